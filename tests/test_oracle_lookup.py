@@ -1,0 +1,141 @@
+"""Pins for the lookup method (Sec. III-B, IV-A, IV-B, V) on the oracle:
+the paper's worked digit example, its packing and ciphertext-count figures,
+the fp64 BSGS schedule against M x, and the encrypted lookup decrypted
+against the cleartext row."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+from tests import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def test_worked_digit_example():
+    """Sec. IV-A worked example: k=16, p=4, i=14 -> (i_0, i_1) = (2, 3)."""
+    g = golden("digit_example.json")
+    assert O.num_digits(g["k"], g["p"]) == g["num_digits"]
+    assert O.digits_of(g["i"], g["p"], g["num_digits"]) == g["digits"]
+    assert sum(d * g["p"] ** j for j, d in enumerate(g["digits"])) == g["i"]
+
+
+def test_uci_packing_slot_count():
+    """Sec. V-C: 5 dense + one-hots of the 8 UCI tables = 28 input slots."""
+    g = golden("uci_packing.json")
+    rng = synth.rng(0)
+    tables = [W.uncompressed_table(rng, k, 4, -1, 1) for k in g["table_rows"]]
+    idx = [k - 1 for k in g["table_rows"]]
+    sel = O.pack_selector(tables, idx)
+    assert g["dense"] + len(sel) == g["slots"]
+    assert sum(sel) == len(g["table_rows"])
+
+
+def test_selector_ciphertext_counts():
+    """ceil(k_t / n) selector ciphertexts (Sec. III-C) for the paper's figures."""
+    g = golden("ciphertext_counts.json")
+    n = g["slots_per_ct"]
+    for row in g["table2"]:
+        assert math.ceil(row["slots"] / n) == row["cts"]
+    crit = g["criteo_rows"]
+    # 33.8e6 rows gives 1032 ciphertexts; the paper rounds to "roughly 1031"
+    assert abs(math.ceil(crit["rows"] / n) - crit["paper_cts"]) <= 1
+    # compression ratio x slots recovers the ~3.38e7 full rows (Table II rows 2-5)
+    for row in g["table2"][1:]:
+        assert abs(row["cr"] * row["slots"] / 3.38e7 - 1) < 0.01
+    t1 = g["table1"]
+    assert t1["p"] * t1["l"] == t1["selector_slots"]
+    assert round(t1["codedhelut_s"] / t1["helrm_s"]) == t1["speedup"]
+
+
+def test_block_diag_matvec_equals_per_table_lookups():
+    """Sec. IV-B: the packed product extracts and concatenates every table's row."""
+    rng = synth.rng(4)
+    tables = [W.compressed_table(rng, 256, 16, 16, -1, 1),
+              W.uncompressed_table(rng, 7, 16, -1, 1),
+              W.compressed_table(rng, 4000, 16, 16, -1, 1)]
+    for _ in range(5):
+        idx = synth.indices(rng, [t.rows for t in tables])
+        y = O.pack_tables(tables) @ O.pack_selector(tables, idx)
+        ref = np.concatenate([t.lookup(i) for t, i in zip(tables, idx)])
+        assert np.allclose(y, ref, atol=1e-12)
+        # compressed row = sum of the digit tables' rows
+        t = tables[0]
+        ds = O.digits_of(idx[0], 16, 2)
+        assert np.allclose(t.lookup(idx[0]), t.C[0][ds[0]] + t.C[1][ds[1]])
+
+
+@pytest.mark.parametrize("n1,radix", [(4, 2), (16, 2), (16, 4), (2, 8), (1, 2)])
+def test_bsgs_schedule_equals_matvec(n1, radix):
+    rng = np.random.default_rng(n1 * 10 + radix)
+    n = 256
+    for rows, cols in [(16, 32), (24, 100), (5, 256), (64, 64)]:
+        M = rng.uniform(-1, 1, (rows, cols))
+        x = rng.uniform(-1, 1, cols)
+        z = O.cleartext_bsgs(M, x, n, n1, radix)
+        assert np.allclose(z[:rows], M @ x, atol=1e-12)
+
+
+def test_fold_stage_shapes():
+    assert O.fold_stages(2048, 16, 2) == [(1024, 2), (512, 2), (256, 2), (128, 2), (64, 2), (32, 2), (16, 2)]
+    assert O.fold_stages(32768, 16, 8) == [(4096, 8), (512, 8), (64, 8), (16, 4)]
+    assert len(O.fold_stages(32768, 16, 2)) == 11
+    assert len(O.fold_stages(32768, 512, 2)) == 6
+
+
+def test_special_matrices_cleartext():
+    n = 64
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1, 1, n)
+    # identity gives the input back; a single shifted diagonal gives rot(x, 3)
+    assert np.allclose(O.cleartext_bsgs(np.eye(8, 8), x[:8], n, 4, 2)[:8], x[:8])
+    S = np.zeros((8, 16))
+    for r in range(8):
+        S[r, r + 3] = 1
+    assert np.allclose(O.cleartext_bsgs(S, x[:16], n, 4, 2)[:8], x[3:11])
+
+
+@pytest.fixture(scope="module")
+def w1():
+    return W.config1(n_queries=2)
+
+
+def test_config1_plan_shape(w1):
+    p = w1.plan
+    assert (w1.M.shape, p.m, p.n1, p.n2) == ((16, 32), 16, 4, 4)
+    assert len(p.stages) == 7
+    assert len(p.coeffs) == 16
+
+
+def test_config1_encrypted_lookup_decrypts_to_row(w1):
+    prm = w1.prm
+    for ct, ref in zip(w1.cts, w1.expected):
+        out = O.lookup(prm, w1.keys, w1.plan, ct)
+        assert out.shape == (2, w1.level, prm.N)
+        got = W.decrypt_slots(w1, out, prm.delta, 16)
+        assert np.max(np.abs(got - ref)) < 1e-4
+
+
+def test_config1_uncompressed_control():
+    w = W.config1(n_queries=1, compressed=False)
+    assert w.M.shape == (16, 256)
+    out = O.lookup(w.prm, w.keys, w.plan, w.cts[0])
+    got = W.decrypt_slots(w, out, w.prm.delta, 16)
+    assert np.max(np.abs(got - w.expected[0])) < 1e-4
+
+
+def test_config1_other_schedules_agree_semantically():
+    for n1, radix in [(16, 2), (2, 8)]:
+        w = W.config1(n_queries=1, n1=n1, radix=radix)
+        out = O.lookup(w.prm, w.keys, w.plan, w.cts[0])
+        got = W.decrypt_slots(w, out, w.prm.delta, 16)
+        assert np.max(np.abs(got - w.expected[0])) < 1e-4

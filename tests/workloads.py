@@ -1,0 +1,76 @@
+"""Oracle-side construction of the synthetic lookup workloads used by the tests.
+
+Everything random comes from ``synth``; every piece of CKKS or lookup
+arithmetic (digits, packing, encoding, keys, encryption) is the oracle's.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, List, Optional
+
+import numpy as np
+
+import synth
+from oracle import oracle as O
+
+
+@dataclass
+class Workload:
+    prm: O.Params
+    tables: List[O.TableSpec]
+    M: np.ndarray
+    plan: O.Plan
+    keys: O.Keys
+    queries: List[List[int]]          # per query: one index per table
+    cts: List[np.ndarray]             # per query: uint64 [2][level+1][N]
+    expected: List[np.ndarray]        # per query: cleartext lookup (concatenated rows)
+    level: int
+    draws: object = None
+
+
+def compressed_table(g, rows: int, d: int, base: int, lo: float, hi: float) -> O.TableSpec:
+    l = O.num_digits(rows, base)
+    C = [synth.uniform_table(g, base, d, lo, hi) for _ in range(l)]
+    return O.TableSpec(rows=rows, d=d, base=base, C=C)
+
+
+def uncompressed_table(g, rows: int, d: int, lo: float, hi: float) -> O.TableSpec:
+    return O.TableSpec(rows=rows, d=d, E=synth.uniform_table(g, rows, d, lo, hi))
+
+
+def build(prm: O.Params, tables: List[O.TableSpec], level: int, n1: int, radix: int,
+          n_queries: int, seed: int = 0, key_seed: int = 0) -> Workload:
+    M = O.pack_tables(tables)
+    plan = O.make_plan(prm, M, level, n1, radix)
+    gals = [O.galois_for_step(k, prm) for k in plan.rotation_steps()]
+    draws = synth.key_draws(key_seed, prm.N, prm.q, prm.p, prm.dnum, gals)
+    keys = O.keygen(prm, draws)
+    g = synth.rng(seed + 1000)
+    queries, cts, expected = [], [], []
+    for _ in range(n_queries):
+        idx = synth.indices(g, [t.rows for t in tables])
+        sel = O.pack_selector(tables, idx)
+        m = O.encode(sel, prm.delta, prm)
+        ct = O.encrypt(prm, keys, m, level, synth.enc_draws(g, prm.N))
+        queries.append(idx)
+        cts.append(ct)
+        expected.append(np.concatenate([t.lookup(i) for t, i in zip(tables, idx)]))
+    return Workload(prm=prm, tables=tables, M=M, plan=plan, keys=keys, queries=queries,
+                    cts=cts, expected=expected, level=level, draws=draws)
+
+
+def config1(n_queries: int = 2, compressed: bool = True, n1: int = 4, radix: int = 2) -> Workload:
+    """Toy ring N=2^12: one 256-row x 16 table, values U[-1,1]; base-16
+    digits (2 digits, 32 selector slots) or an uncompressed 256-slot control."""
+    prm = O.config1_params()
+    g = synth.rng(0)
+    if compressed:
+        t = compressed_table(g, 256, 16, 16, -1.0, 1.0)
+    else:
+        t = uncompressed_table(g, 256, 16, -1.0, 1.0)
+    return build(prm, [t], level=prm.L, n1=n1, radix=radix, n_queries=n_queries)
+
+
+def decrypt_slots(w: Workload, ct: np.ndarray, scale: float, count: int) -> np.ndarray:
+    m = O.decrypt(w.prm, w.keys, ct)
+    return O.decode(m, scale, w.prm)[:count].real
