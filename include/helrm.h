@@ -1,0 +1,219 @@
+/*
+ * helrm.h -- C ABI of libhelrm, the MI355X (gfx950) library for the CKKS
+ * plaintext-matrix x ciphertext-vector product behind HE-LRM's encrypted
+ * embedding lookups (arXiv 2506.18150).
+ *
+ * Paper passages the calls implement:
+ *   - Appendix A "CKKS operations": the ring R_Q = Z_Q[X]/(X^N+1) with
+ *     Q = q_0 ... q_L, encryption (c0, c1) in R_Q^2, plaintext x ciphertext
+ *     multiplication, rescale Q_l -> Q_{l-1}, rotation by k slots, key
+ *     switching with a special switching key.
+ *   - Sec. II-A "System-Level Costs": rotation needs key switching and one
+ *     evaluation key per rotation offset.
+ *   - Sec. II-A "Neural Network Layers in FHE" and Sec. III-B "Matrix-Vector
+ *     Lookup": y = E^T s computed by the diagonal method with baby-step
+ *     giant-step (BSGS) rotations, double-hoisted, consuming one level.
+ *   - Sec. IV-B "Block-diagonal embedding matrix" and the end-to-end pipeline:
+ *     the server multiplies the packed matrix by the encrypted concatenated
+ *     one-hot selector; the result is already packed.
+ *
+ * Conventions (all calls):
+ *   - Residues are uint64, canonical in [0, q).  A polynomial over a basis of
+ *     limbs is stored limb-major: limb i occupies N contiguous words.
+ *   - Prime indices: 0..L are q_0..q_L, L+1..L+K are the special primes
+ *     p_0..p_{K-1}.  A ciphertext at level l has limbs q_0..q_l; an
+ *     "extended" (PQ) polynomial at level l has limbs q_0..q_l, p_0..p_{K-1}.
+ *   - Ciphertexts are [batch][2][limbs][N] (c0 then c1), in evaluation (NTT)
+ *     form: value j of a limb is the polynomial at psi^(2 brv(j)+1) mod q,
+ *     brv = log2(N)-bit reversal, psi the root fixed in helrm_create.
+ *   - Rotation by k slots (left: slot j receives slot j+k) uses the Galois
+ *     element 5^k mod 2N.
+ *   - Device pointers named d_* are owned by the caller and must stay valid
+ *     until the work enqueued on `stream` has finished.  The library never
+ *     frees caller memory.  Keys and plans are copied into library-owned
+ *     device memory that lives until helrm_destroy / helrm_plan_destroy.
+ *   - `stream` is a hipStream_t passed as void* (0 = the null stream).  Calls
+ *     check their arguments on the host, enqueue, and return without
+ *     synchronising; only helrm_create, helrm_load_eval_keys and
+ *     helrm_plan_create block.  A device-side fault surfaces at the caller's
+ *     next synchronisation.
+ *   - Calls that need temporaries use a workspace owned by the context, one per
+ *     stream, grown on demand (growing synchronises that stream).  Work for
+ *     one context on one stream is serialised; different streams get
+ *     different workspaces and may overlap.
+ *   - Return value: HELRM_OK (0) or a negative code; helrm_last_error()
+ *     returns a thread-local description of the last failure.  No C++
+ *     exception crosses this interface and the library never aborts.
+ */
+#ifndef HELRM_H
+#define HELRM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HELRM_OK 0
+#define HELRM_EINVAL (-1) /* bad pointer, size, level, basis or missing key */
+#define HELRM_ENOMEM (-2) /* device allocation failed */
+#define HELRM_EHIP (-3)   /* a HIP runtime call failed */
+#define HELRM_ESTATE (-4) /* call not valid in the current state */
+
+typedef struct helrm_ctx helrm_ctx;
+typedef struct helrm_plan helrm_plan;
+
+/* RNS-CKKS parameters.  q[0..L] are the ciphertext primes (q_0 is never
+ * dropped), p[0..K-1] the special primes of hybrid key switching; every
+ * prime is < 2^61 and = 1 mod 2N.  Key-switching digit j holds the Q primes
+ * j*alpha .. j*alpha+alpha-1 (dnum = ceil((L+1)/alpha) digits). */
+typedef struct {
+  int log_n;            /* N = 2^log_n; 12 or 16 */
+  int L;                /* index of the top ciphertext prime */
+  int K;                /* number of special primes, 1..16 */
+  int alpha;            /* Q primes per digit */
+  const uint64_t *q;    /* host, L+1 primes */
+  const uint64_t *p;    /* host, K primes */
+} helrm_params;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *helrm_last_error(void);
+
+/* Build a context on the current HIP device: per-prime roots psi (from the
+ * smallest quadratic non-residue x: psi = x^((q-1)/2N)), twiddle tables and
+ * the constants of base conversion, ModDown and rescale.  Blocks. */
+int helrm_create(const helrm_params *params, helrm_ctx **out);
+int helrm_destroy(helrm_ctx *ctx);
+
+/* Root psi chosen for prime index i (host query, for checks). */
+int helrm_get_psi(const helrm_ctx *ctx, int prime_index, uint64_t *psi);
+
+/* Copy n_keys switching keys into library-owned device memory (Appendix A
+ * "Key-switching").  galois[k] is the Galois element of key k (rotation by r
+ * slots: 5^r mod 2N); galois 0 denotes the relinearisation key.  `keys`
+ * (host or device memory) is [n_keys][dnum][2][L+1+K][N]: for digit j the pair
+ * (b_j, a_j) over all L+1+K primes in evaluation form, with
+ * b_j = -a_j s + e_j + [P]_{q_i} s' on digit j's primes.  A key loaded again
+ * for the same element replaces the old one.  Blocks. */
+int helrm_load_eval_keys(helrm_ctx *ctx, const uint32_t *galois, int n_keys,
+                         const uint64_t *keys);
+
+/* Forward / inverse negacyclic NTT, in place, of `batch` blocks of n_limbs
+ * limbs each (block b at d_data + b*n_limbs*N); limb i of every block uses
+ * prime prime_index[i] (host array).  Forward maps coefficients to evaluation
+ * form as defined above; inverse is its exact inverse (includes N^-1). */
+int helrm_ntt(helrm_ctx *ctx, uint64_t *d_data, int n_limbs, const int32_t *prime_index,
+              int batch, void *stream);
+int helrm_intt(helrm_ctx *ctx, uint64_t *d_data, int n_limbs, const int32_t *prime_index,
+               int batch, void *stream);
+
+/* Automorphism X -> X^galois in evaluation form (a permutation of each limb):
+ * d_out[j] = d_in[j'] with 2 brv(j')+1 = galois (2 brv(j)+1) mod 2N.
+ * galois must be odd.  d_in and d_out must not overlap.  Layout
+ * [batch][n_limbs][N]. */
+int helrm_automorph(helrm_ctx *ctx, const uint64_t *d_in, uint64_t *d_out, uint32_t galois,
+                    int n_limbs, int batch, void *stream);
+
+/* Element-wise arithmetic over [batch][n_limbs][N] (limb i uses prime
+ * prime_index[i]).  op: 0 add, 1 sub (a - b), 2 mul, 3 neg (b ignored).
+ * Outputs may alias inputs. */
+#define HELRM_OP_ADD 0
+#define HELRM_OP_SUB 1
+#define HELRM_OP_MUL 2
+#define HELRM_OP_NEG 3
+int helrm_poly_op(helrm_ctx *ctx, int op, const uint64_t *d_a, const uint64_t *d_b, uint64_t *d_out,
+                  int n_limbs, const int32_t *prime_index, int batch, void *stream);
+
+/* d_out[b][i][j] = d_a[b][i][j] * scalars[i] mod q (scalars: host, one per limb). */
+int helrm_mul_scalar(helrm_ctx *ctx, const uint64_t *d_a, const uint64_t *scalars, uint64_t *d_out,
+                     int n_limbs, const int32_t *prime_index, int batch, void *stream);
+
+/* Signed integer coefficients to residues: d_out[b][i][j] = d_in[b][j] mod q
+ * (d_in: device int64 [batch][N]; coefficient form, no NTT applied). */
+int helrm_from_signed(helrm_ctx *ctx, const int64_t *d_in, uint64_t *d_out, int n_limbs,
+                      const int32_t *prime_index, int batch, void *stream);
+
+/* Hoisted rotations with key switching (Appendix A "Rotation",
+ * "Key-switching"; hoisting as in the double-hoisted BSGS of Sec. III-B).
+ * One ModUp of c1 (digit decomposition + fast base conversion to the extended
+ * basis, uncorrected), then for each step k: the automorphism of every digit,
+ * the inner product with the key of 5^k, plus P * sigma(c0):
+ *   A = sum_j sigma(d_j) a_j,  B = sum_j sigma(d_j) b_j + P sigma(c0).
+ * d_ct: [batch][2][level+1][N].  out_basis 0 (Q): each output is divided by P
+ * (ModDown, no rounding offset) -> d_out [batch][n_rot][2][level+1][N], a
+ * rotated ciphertext.  out_basis 1 (PQ): kept as (B, A) over the extended
+ * basis -> d_out [batch][n_rot][2][level+1+K][N].  Keys for every step must
+ * be loaded; step 0 is allowed and gives (P c0, P c1) (PQ) or the input (Q). */
+#define HELRM_BASIS_Q 0
+#define HELRM_BASIS_PQ 1
+int helrm_keyswitch_hoisted(helrm_ctx *ctx, const uint64_t *d_ct, int level,
+                            const int32_t *rot_steps, int n_rot, uint64_t *d_out,
+                            int out_basis, int batch, void *stream);
+
+/* Rescale Q_l -> Q_{l-1} (Appendix A "Multiplication"): each coefficient C
+ * (CRT value in [0, Q_l)) becomes floor((C + floor(q_l/2)) / q_l) mod Q_{l-1}.
+ * d_in [batch][2][level+1][N] -> d_out [batch][2][level][N].  level >= 1. */
+int helrm_rescale(helrm_ctx *ctx, const uint64_t *d_in, int level, uint64_t *d_out, int batch,
+                  void *stream);
+
+/* A plaintext matrix prepared for the BSGS diagonal method (Sec. II-A
+ * "Neural Network Layers in FHE", Sec. III-B).  For an r x c matrix M (r
+ * outputs, c <= N/2 inputs) with m = next power of two >= r, the hybrid
+ * diagonals are u_k[j] = M[j mod m][(j + k) mod (N/2)] (zero rows beyond r),
+ * k < m.  With k = n1*g + b, the plan holds v_{g,b} = rot(u_k, -n1*g) encoded
+ * at scale q_level as signed integer coefficients.  The product is
+ *   z = sum_g rot( sum_b v_{g,b} (.) rot(x, b), n1*g ),
+ * followed by a fold from N/2 slots down to period m: each stage with stride s
+ * and radix r replaces z by sum_{t<r} rot(z, t*s) (s = span/r, r = min(radix,
+ * span/m), span starting at N/2).  Slot i < r then holds (M x)_i. */
+typedef struct {
+  int level;              /* level of the input ciphertext */
+  int m;                  /* number of hybrid diagonals (power of two) */
+  int n1;                 /* baby steps */
+  int n2;                 /* giant steps, n1*n2 >= m */
+  int radix;              /* fold radix >= 2 */
+  int n_diag;             /* number of non-zero diagonals given */
+  const int32_t *diag;    /* host [n_diag]: k = n1*g + b of each diagonal, ascending */
+  const int64_t *coeffs;  /* host [n_diag][N]: coefficients of v_{g,b} at scale q_level */
+} helrm_plan_desc;
+
+/* Reduce the plan's coefficients over the extended basis at its level, take
+ * them to evaluation form on the device and keep them resident.  Blocks. */
+int helrm_plan_create(helrm_ctx *ctx, const helrm_plan_desc *desc, helrm_plan **out);
+int helrm_plan_destroy(helrm_plan *plan);
+
+/* Galois steps the plan needs keys for (host query): writes up to `cap`
+ * rotation steps into steps and their count into *n. */
+int helrm_plan_rotation_steps(const helrm_plan *plan, int32_t *steps, int cap, int *n);
+
+/* Double-hoisted BSGS plaintext-matrix x ciphertext product without rescale:
+ *   1. ModUp(c1) once; R_0 = (P c0, P c1); R_b = hoisted rotation by b (PQ).
+ *   2. X_g = sum_b pt_{g,b} (.) R_b over PQ; x_g = ModDown(X_g).
+ *   3. acc = P x_0 + sum_{g>=1} (rotation of x_g by n1 g, kept in PQ);
+ *      z = ModDown(acc)  (z = x_0 when only g = 0 has diagonals).
+ *   4. Fold: per stage (s, r): z = ModDown(P z + sum_{t=1}^{r-1} rot_PQ(z, t s)).
+ * d_ct [batch][2][level+1][N] -> d_out [batch][2][level+1][N] at scale
+ * (input scale * q_level). */
+int helrm_ptxt_ct_matvec_diag(helrm_ctx *ctx, const helrm_plan *plan, const uint64_t *d_ct,
+                              uint64_t *d_out, int batch, void *stream);
+
+/* Encrypted packed embedding lookup (Sec. IV-B pipeline): the matvec above
+ * followed by rescale, so the result is at level-1 and at the selector's
+ * scale.  d_sel [batch][2][level+1][N] -> d_out [batch][2][level][N]; table t's
+ * row lands in slots [d*t, d*t + d) when the plan packs tables block-diagonally. */
+int helrm_lookup_packed(helrm_ctx *ctx, const helrm_plan *plan, const uint64_t *d_sel,
+                        int batch, uint64_t *d_out, void *stream);
+
+/* Device bytes one call of helrm_lookup_packed with this batch uses beyond its
+ * input and output (workspace), for admission control. */
+int helrm_footprint(const helrm_ctx *ctx, const helrm_plan *plan, int batch, size_t *bytes);
+
+/* Grow the workspace of `stream` to serve helrm_lookup_packed(plan, batch)
+ * without further allocation (call before capturing a graph). */
+int helrm_reserve(helrm_ctx *ctx, const helrm_plan *plan, int batch, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELRM_H */

@@ -1,0 +1,1027 @@
+// C ABI of libhelrm: context set-up (roots, twiddles, conversion constants),
+// resident evaluation keys and plans, and the host orchestration of the
+// key-switching, rescale and double-hoisted BSGS matvec pipelines.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "common.h"
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+extern "C" const char *helrm_last_error(void) { return g_last_error.c_str(); }
+
+#define API_GUARD_BEGIN try {
+#define API_GUARD_END                                          \
+  }                                                            \
+  catch (const std::bad_alloc &) {                             \
+    set_error("host allocation failed");                       \
+    return HELRM_ENOMEM;                                       \
+  }                                                            \
+  catch (...) {                                                \
+    set_error("internal error");                               \
+    return HELRM_ESTATE;                                       \
+  }
+
+// ---------------------------------------------------------------- host modular arithmetic
+
+namespace {
+
+u64 hmul(u64 a, u64 b, u64 q) { return (u64)((u128)a * b % q); }
+
+u64 hpow(u64 a, u64 e, u64 q) {
+  u64 r = 1 % q;
+  a %= q;
+  while (e) {
+    if (e & 1) r = hmul(r, a, q);
+    a = hmul(a, a, q);
+    e >>= 1;
+  }
+  return r;
+}
+
+// inverse modulo q (q odd, gcd(a, q) = 1) by the extended Euclidean algorithm
+u64 hinv(u64 a, u64 q) {
+  __int128 t = 0, nt = 1, r = q, nr = a % q;
+  while (nr != 0) {
+    __int128 qq = r / nr, tmp;
+    tmp = t - qq * nt; t = nt; nt = tmp;
+    tmp = r - qq * nr; r = nr; nr = tmp;
+  }
+  if (t < 0) t += q;
+  return (u64)t;
+}
+
+u64 shoup_of(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
+
+TW tw_of(u64 w, u64 q) { return TW{w % q, shoup_of(w % q, q)}; }
+
+u64 neg_inv64(u64 q) {
+  u64 x = q;  // q * q = 1 mod 8 for odd q
+  for (int i = 0; i < 6; i++) x *= 2 - q * x;
+  return (u64)0 - x;
+}
+
+u64 mont_of(u64 w, u64 q) { return (u64)(((u128)(w % q) << 64) % q); }
+
+unsigned brv(unsigned x, int bits) {
+  unsigned r = 0;
+  for (int i = 0; i < bits; i++) { r = (r << 1) | (x & 1); x >>= 1; }
+  return r;
+}
+
+bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+// ---------------------------------------------------------------- constant buffer builder
+
+struct ConstBuilder {
+  std::vector<u64> words;
+  size_t add_tw(const std::vector<TW> &v) {
+    size_t off = words.size();
+    for (auto &t : v) { words.push_back(t.w); words.push_back(t.wp); }
+    return off;
+  }
+  size_t add_u64(const std::vector<u64> &v) {
+    size_t off = words.size();
+    words.insert(words.end(), v.begin(), v.end());
+    return off;
+  }
+};
+
+// Fast base conversion constants from input primes to output primes.
+void build_conv(helrm_ctx *c, ConstBuilder &cb, const std::vector<int> &in, const std::vector<int> &out,
+                ConvTable &t, size_t &off_inv, size_t &off_mont) {
+  t.nin = (int)in.size();
+  t.nout = (int)out.size();
+  for (int i = 0; i < t.nin; i++) t.in_prime[i] = in[i];
+  for (int r = 0; r < t.nout; r++) t.out_prime[r] = out[r];
+  std::vector<TW> inv(t.nin);
+  std::vector<u64> mont((size_t)t.nin * t.nout);
+  for (int i = 0; i < t.nin; i++) {
+    const u64 qi = c->primes[in[i]];
+    u64 hat = 1;  // (Qin / q_i) mod q_i
+    for (int k = 0; k < t.nin; k++)
+      if (k != i) hat = hmul(hat, c->primes[in[k]] % qi, qi);
+    inv[i] = tw_of(hinv(hat, qi), qi);
+    for (int r = 0; r < t.nout; r++) {
+      const u64 qr = c->primes[out[r]];
+      u64 h = 1;  // (Qin / q_i) mod r
+      for (int k = 0; k < t.nin; k++)
+        if (k != i) h = hmul(h, c->primes[in[k]] % qr, qr);
+      mont[(size_t)i * t.nout + r] = mont_of(h, qr);
+    }
+  }
+  off_inv = cb.add_tw(inv);
+  off_mont = cb.add_u64(mont);
+}
+
+// ---------------------------------------------------------------- workspace
+
+struct Arena {
+  char *base;
+  size_t used = 0;
+  u64 *take(size_t words) {
+    u64 *p = (u64 *)(base + used);
+    used += ((words * sizeof(u64) + 255) / 256) * 256;
+    return p;
+  }
+};
+
+int ensure_ws(helrm_ctx *ctx, hipStream_t s, size_t bytes, char **out) {
+  std::lock_guard<std::mutex> lk(ctx->ws_mu);
+  Workspace &w = ctx->ws[s];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipFree(w.ptr));
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("workspace allocation of %zu bytes failed", bytes);
+      return HELRM_ENOMEM;
+    }
+    w.ptr = p;
+    w.bytes = bytes;
+  }
+  *out = (char *)w.ptr;
+  return HELRM_OK;
+}
+
+size_t rnd(size_t words) { return ((words * sizeof(u64) + 255) / 256) * 256; }
+
+// ---------------------------------------------------------------- limb lists
+
+LimbList ll_make(int n, int src_bs, int dst_bs) {
+  LimbList ll;
+  memset(&ll, 0, sizeof ll);
+  ll.n = n;
+  ll.src_bstride = src_bs;
+  ll.dst_bstride = dst_bs;
+  return ll;
+}
+
+// ---------------------------------------------------------------- pipeline pieces
+
+// ModUp of c1 (evaluation form, [level+1] limbs, batch stride c1_bs limbs) to
+// digits D ([beta][pqn] limbs per batch element, stride d_bs limbs).
+int do_modup(helrm_ctx *ctx, int level, const u64 *c1, int c1_bs, u64 *D, int d_bs, u64 *coef, int batch,
+             hipStream_t s) {
+  const int N = ctx->N, qn = level + 1, pqn = level + 1 + ctx->K, beta = ctx->n_digits(level);
+  // 1. coefficient form of c1
+  LimbList a = ll_make(qn, c1_bs, qn);
+  for (int i = 0; i < qn; i++) { a.src_off[i] = i; a.dst_off[i] = i; a.prime[i] = (unsigned char)i; }
+  TRY(launch_ntt(ctx, c1, coef, a, batch, false, s));
+  // 2. base conversion of every digit to the other primes of PQ_level
+  LimbList nt = ll_make(0, d_bs, d_bs);
+  for (int j = 0; j < beta; j++) {
+    const ConvTable &t = ctx->modup_tabs[level][j];
+    int doff[HELRM_MAX_PRIMES];
+    int lo = ctx->digit_lo(j), hi = ctx->digit_hi(j, level), k = 0;
+    for (int r = 0; r < pqn; r++) {
+      if (r >= lo && r < hi) continue;
+      doff[k] = j * pqn + r;
+      if (nt.n >= HELRM_MAX_LIMBS) { set_error("modup: too many limbs"); return HELRM_EINVAL; }
+      nt.src_off[nt.n] = j * pqn + r;
+      nt.dst_off[nt.n] = j * pqn + r;
+      nt.prime[nt.n] = (unsigned char)ctx->pq_prime(r, level);
+      nt.n++;
+      k++;
+    }
+    TRY(launch_conv(ctx, t, coef, lo, qn, D, doff, d_bs, batch, s));
+  }
+  // 3. back to evaluation form
+  TRY(launch_ntt(ctx, D, D, nt, batch, true, s));
+  // 4. each digit's own limbs are c1's limbs
+  LimbList cp = ll_make(0, c1_bs, d_bs);
+  for (int j = 0; j < beta; j++)
+    for (int i = ctx->digit_lo(j); i < ctx->digit_hi(j, level); i++) {
+      cp.src_off[cp.n] = i;
+      cp.dst_off[cp.n] = j * pqn + i;
+      cp.prime[cp.n] = (unsigned char)i;
+      cp.n++;
+    }
+  TRY(launch_copy_limbs(c1, D, cp, batch, N, s));
+  return HELRM_OK;
+}
+
+// ModDown of X ([2][pqn] limbs per element, stride x_bs) to out ([2][qn],
+// stride out_bs).  mdP: [2K] limbs per element, mdT: [2 qn] per element.
+int do_moddown(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *out, int out_bs, u64 *mdP, u64 *mdT,
+               int batch, hipStream_t s) {
+  const int K = ctx->K, qn = level + 1, pqn = level + 1 + K;
+  // 1. special limbs to coefficient form
+  LimbList a = ll_make(2 * K, x_bs, 2 * K);
+  for (int c = 0; c < 2; c++)
+    for (int k = 0; k < K; k++) {
+      a.src_off[c * K + k] = c * pqn + qn + k;
+      a.dst_off[c * K + k] = c * K + k;
+      a.prime[c * K + k] = (unsigned char)(ctx->L + 1 + k);
+    }
+  TRY(launch_ntt(ctx, X, mdP, a, batch, false, s));
+  // 2. convert P -> Q_level (both polynomials as a batch of 2*batch)
+  int doff[HELRM_MAX_PRIMES];
+  for (int i = 0; i < qn; i++) doff[i] = i;
+  TRY(launch_conv(ctx, ctx->moddown_tabs[level], mdP, 0, K, mdT, doff, qn, 2 * batch, s));
+  // 3. evaluation form
+  LimbList b = ll_make(qn, qn, qn);
+  for (int i = 0; i < qn; i++) { b.src_off[i] = i; b.dst_off[i] = i; b.prime[i] = (unsigned char)i; }
+  TRY(launch_ntt(ctx, mdT, mdT, b, 2 * batch, true, s));
+  // 4. out_i = (X_i - t_i) P^-1
+  LimbList c = ll_make(2 * qn, x_bs, out_bs);
+  for (int p = 0; p < 2; p++)
+    for (int i = 0; i < qn; i++) {
+      c.src_off[p * qn + i] = p * pqn + i;
+      c.dst_off[p * qn + i] = p * qn + i;
+      c.prime[p * qn + i] = (unsigned char)i;
+    }
+  // mdT is [2 qn] per element, addressed with dst offsets p*qn+i
+  TRY(launch_sub_mul(ctx, X, mdT, 2 * qn, out, c, ctx->moddown_pinv[level], batch, s));
+  return HELRM_OK;
+}
+
+int do_rescale(helrm_ctx *ctx, int level, const u64 *in, int in_bs, u64 *out, int out_bs, u64 *top, u64 *V,
+               int batch, hipStream_t s) {
+  const int qn = level + 1;
+  LimbList a = ll_make(2, in_bs, 2);
+  for (int c = 0; c < 2; c++) {
+    a.src_off[c] = c * qn + level;
+    a.dst_off[c] = c;
+    a.prime[c] = (unsigned char)level;
+  }
+  TRY(launch_ntt(ctx, in, top, a, batch, false, s));
+  TRY(launch_rescale_spread(ctx, top, V, level, batch, s));
+  LimbList b = ll_make(level, level, level);
+  for (int i = 0; i < level; i++) { b.src_off[i] = i; b.dst_off[i] = i; b.prime[i] = (unsigned char)i; }
+  TRY(launch_ntt(ctx, V, V, b, 2 * batch, true, s));
+  LimbList c = ll_make(2 * level, in_bs, out_bs);
+  for (int p = 0; p < 2; p++)
+    for (int i = 0; i < level; i++) {
+      c.src_off[p * level + i] = p * qn + i;
+      c.dst_off[p * level + i] = p * level + i;
+      c.prime[p * level + i] = (unsigned char)i;
+    }
+  TRY(launch_sub_mul(ctx, in, V, 2 * level, out, c, ctx->rescale_qinv[level], batch, s));
+  return HELRM_OK;
+}
+
+uint32_t galois_of_step(const helrm_ctx *ctx, long step) {
+  const long n = ctx->N / 2;
+  long k = ((step % n) + n) % n;
+  u64 g = 1, twoN = 2ull * ctx->N;
+  for (long i = 0; i < k; i++) g = g * 5 % twoN;
+  return (uint32_t)g;
+}
+
+int key_for(helrm_ctx *ctx, long step, const u64 **key, uint32_t *gal) {
+  *gal = galois_of_step(ctx, step);
+  auto it = ctx->keys.find(*gal);
+  if (it == ctx->keys.end()) {
+    set_error("no evaluation key loaded for rotation %ld (galois %u)", step, *gal);
+    return HELRM_EINVAL;
+  }
+  *key = it->second.d;
+  return HELRM_OK;
+}
+
+// workspace words of one ModUp + ModDown at this level and batch
+struct KsSizes {
+  size_t coef, D, X, mdP, mdT;
+};
+
+KsSizes ks_sizes(const helrm_ctx *ctx, int level, int batch, int n_pq) {
+  const size_t N = ctx->N, qn = level + 1, pqn = level + 1 + ctx->K, beta = ctx->n_digits(level);
+  KsSizes z;
+  z.coef = batch * qn * N;
+  z.D = batch * beta * pqn * N;
+  z.X = (size_t)batch * n_pq * 2 * pqn * N;
+  z.mdP = (size_t)batch * n_pq * 2 * ctx->K * N;
+  z.mdT = (size_t)batch * n_pq * 2 * qn * N;
+  return z;
+}
+
+// ---------------------------------------------------------------- matvec
+
+struct MatvecWS {
+  u64 *coef, *D, *Dg, *X, *xg, *acc, *zA, *zB, *mdP, *mdT, *top, *V, *mv;
+};
+
+size_t matvec_ws_bytes(const helrm_ctx *ctx, const helrm_plan *p, int batch, bool with_rescale) {
+  const size_t N = ctx->N, lv = p->level, qn = lv + 1, pqn = lv + 1 + ctx->K, beta = ctx->n_digits((int)lv);
+  const size_t B = batch, n2 = p->n2;
+  size_t ng = 0;
+  for (int g : p->giants)
+    if (g != 0) ng++;
+  size_t tot = 0;
+  tot += rnd(B * qn * N);                       // coef
+  tot += rnd(B * beta * pqn * N);               // D
+  tot += rnd(B * std::max<size_t>(ng, 1) * beta * pqn * N);  // Dg
+  tot += rnd(B * n2 * 2 * pqn * N);             // X
+  tot += rnd(B * n2 * 2 * qn * N);              // xg
+  tot += rnd(B * 2 * pqn * N);                  // acc
+  tot += 2 * rnd(B * 2 * qn * N);               // zA, zB
+  tot += rnd(B * n2 * 2 * ctx->K * N);          // mdP
+  tot += rnd(B * n2 * 2 * qn * N);              // mdT
+  if (with_rescale) {
+    tot += rnd(B * 2 * N);                      // top
+    tot += rnd(B * 2 * lv * N);                 // V
+    tot += rnd(B * 2 * qn * N);                 // matvec result
+  }
+  return tot;
+}
+
+MatvecWS carve_matvec(const helrm_ctx *ctx, const helrm_plan *p, int batch, bool with_rescale, char *base) {
+  const size_t N = ctx->N, lv = p->level, qn = lv + 1, pqn = lv + 1 + ctx->K, beta = ctx->n_digits((int)lv);
+  const size_t B = batch, n2 = p->n2;
+  size_t ng = 0;
+  for (int g : p->giants)
+    if (g != 0) ng++;
+  Arena a{base};
+  MatvecWS w;
+  w.coef = a.take(B * qn * N);
+  w.D = a.take(B * beta * pqn * N);
+  w.Dg = a.take(B * std::max<size_t>(ng, 1) * beta * pqn * N);
+  w.X = a.take(B * n2 * 2 * pqn * N);
+  w.xg = a.take(B * n2 * 2 * qn * N);
+  w.acc = a.take(B * 2 * pqn * N);
+  w.zA = a.take(B * 2 * qn * N);
+  w.zB = a.take(B * 2 * qn * N);
+  w.mdP = a.take(B * n2 * 2 * ctx->K * N);
+  w.mdT = a.take(B * n2 * 2 * qn * N);
+  w.top = w.V = w.mv = nullptr;
+  if (with_rescale) {
+    w.top = a.take(B * 2 * N);
+    w.V = a.take(B * 2 * lv * N);
+    w.mv = a.take(B * 2 * qn * N);
+  }
+  return w;
+}
+
+int run_matvec(helrm_ctx *ctx, const helrm_plan *p, const u64 *ct, u64 *out, int batch, MatvecWS &w,
+               hipStream_t s) {
+  const int N = ctx->N, lv = p->level, qn = lv + 1, pqn = lv + 1 + ctx->K, beta = ctx->n_digits(lv);
+  const int n2 = p->n2;
+  const int ct_bs = 2 * qn, d_bs = beta * pqn;
+  // 1. hoisted ModUp of c1
+  TRY(do_modup(ctx, lv, ct + (size_t)qn * N, ct_bs, w.D, d_bs, w.coef, batch, s));
+  // 2. fused baby steps + plaintext MAC, giant outputs in tiles
+  const size_t x_bs = (size_t)n2 * 2 * pqn;  // limbs per batch element of X
+  for (int g0 = 0; g0 < n2; g0 += HELRM_MAX_GTILE) {
+    const int ng = std::min(HELRM_MAX_GTILE, n2 - g0);
+    bool any = false;
+    for (int g : p->giants)
+      if (g >= g0 && g < g0 + ng) any = true;
+    if (!any) continue;
+    TRY(launch_baby_mac(ctx, p, w.D, (size_t)d_bs * N, ct, (size_t)ct_bs * N, w.X + (size_t)g0 * 2 * pqn * N,
+                        x_bs * N, g0, ng, batch, s));
+  }
+  // 3. x_g = ModDown(X_g) for every g (batch of batch*n2)
+  TRY(do_moddown(ctx, lv, w.X, 2 * pqn, w.xg, 2 * qn, w.mdP, w.mdT, batch * n2, s));
+  const u64 *z;
+  const bool only0 = p->giants.size() == 1 && p->giants[0] == 0;
+  const bool no_fold = p->stages.empty();
+  u64 *zbuf = w.zA;
+  if (only0) {
+    if (no_fold) {
+      // copy x_0 to out
+      LimbList cp = ll_make(2 * qn, n2 * 2 * qn, 2 * qn);
+      for (int i = 0; i < 2 * qn; i++) { cp.src_off[i] = i; cp.dst_off[i] = i; cp.prime[i] = 0; }
+      TRY(launch_copy_limbs(w.xg, out, cp, batch, N, s));
+      return HELRM_OK;
+    }
+    // x_0 is element 0 of every n2-group of xg
+    LimbList cp = ll_make(2 * qn, n2 * 2 * qn, 2 * qn);
+    for (int i = 0; i < 2 * qn; i++) { cp.src_off[i] = i; cp.dst_off[i] = i; cp.prime[i] = 0; }
+    TRY(launch_copy_limbs(w.xg, zbuf, cp, batch, N, s));
+    z = zbuf;
+  } else {
+    // 4. giant rotations by n1 g of x_g (g >= 1), accumulated in PQ with P x_0
+    std::vector<KsTerm> terms;
+    int gi = 0;
+    for (int g : p->giants) {
+      if (g == 0) continue;
+      const u64 *xgp = w.xg + (size_t)g * 2 * qn * N;
+      u64 *Dg = w.Dg + (size_t)gi * beta * pqn * N;
+      const int ng_ = (int)(p->giants.size() - (p->giants[0] == 0 ? 1 : 0));
+      TRY(do_modup(ctx, lv, xgp + (size_t)qn * N, n2 * 2 * qn, Dg, ng_ * d_bs, w.coef, batch, s));
+      KsTerm t;
+      t.digits = Dg;
+      t.c0 = xgp;
+      TRY(key_for(ctx, (long)p->n1 * g, &t.key, &t.galois));
+      terms.push_back(t);
+      gi++;
+    }
+    const int ng_ = gi;
+    const bool has0 = p->giants[0] == 0;
+    for (size_t t0 = 0; t0 < terms.size(); t0 += HELRM_MAX_TERMS) {
+      const int nt = (int)std::min<size_t>(HELRM_MAX_TERMS, terms.size() - t0);
+      if (t0 != 0) {
+        set_error("more than %d giant steps are not supported", HELRM_MAX_TERMS);
+        return HELRM_EINVAL;
+      }
+      TRY(launch_ks_accumulate(ctx, lv, terms.data() + t0, nt, (size_t)ng_ * d_bs * N,
+                               (size_t)n2 * 2 * qn * N, has0 ? w.xg : nullptr, (size_t)n2 * 2 * qn * N,
+                               w.acc, (size_t)2 * pqn * N, batch, s));
+    }
+    u64 *dst = no_fold ? out : zbuf;
+    TRY(do_moddown(ctx, lv, w.acc, 2 * pqn, dst, 2 * qn, w.mdP, w.mdT, batch, s));
+    if (no_fold) return HELRM_OK;
+    z = zbuf;
+  }
+  // 5. fold stages
+  for (size_t si = 0; si < p->stages.size(); si++) {
+    const int st = p->stages[si].first, r = p->stages[si].second;
+    TRY(do_modup(ctx, lv, z + (size_t)qn * N, 2 * qn, w.D, d_bs, w.coef, batch, s));
+    std::vector<KsTerm> terms;
+    for (int t = 1; t < r; t++) {
+      KsTerm k;
+      k.digits = w.D;
+      k.c0 = z;
+      TRY(key_for(ctx, (long)t * st, &k.key, &k.galois));
+      terms.push_back(k);
+    }
+    if ((int)terms.size() > HELRM_MAX_TERMS) {
+      set_error("fold radix above %d is not supported", HELRM_MAX_TERMS + 1);
+      return HELRM_EINVAL;
+    }
+    TRY(launch_ks_accumulate(ctx, lv, terms.data(), (int)terms.size(), (size_t)d_bs * N, (size_t)2 * qn * N,
+                             z, (size_t)2 * qn * N, w.acc, (size_t)2 * pqn * N, batch, s));
+    const bool last = si + 1 == p->stages.size();
+    u64 *dst = last ? out : (z == w.zA ? w.zB : w.zA);
+    TRY(do_moddown(ctx, lv, w.acc, 2 * pqn, dst, 2 * qn, w.mdP, w.mdT, batch, s));
+    z = dst;
+  }
+  return HELRM_OK;
+}
+
+LimbList ll_from_primes(helrm_ctx *ctx, int n_limbs, const int32_t *prime_index, int off0) {
+  LimbList ll = ll_make(n_limbs, n_limbs, n_limbs);
+  for (int i = 0; i < n_limbs; i++) {
+    ll.src_off[i] = off0 + i;
+    ll.dst_off[i] = off0 + i;
+    ll.prime[i] = (unsigned char)prime_index[i];
+  }
+  return ll;
+}
+
+int check_primes(const helrm_ctx *ctx, int n_limbs, const int32_t *prime_index) {
+  CHECK_ARG(n_limbs >= 0, "n_limbs must be >= 0");
+  CHECK_ARG(n_limbs == 0 || prime_index, "prime_index is NULL");
+  for (int i = 0; i < n_limbs; i++)
+    CHECK_ARG(prime_index[i] >= 0 && prime_index[i] < ctx->nprimes, "prime_index[%d] = %d out of range", i,
+              prime_index[i]);
+  return HELRM_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
+  API_GUARD_BEGIN
+  CHECK_ARG(prm && out, "NULL argument");
+  *out = nullptr;
+  CHECK_ARG(prm->log_n == 12 || prm->log_n == 16, "log_n must be 12 or 16");
+  CHECK_ARG(prm->L >= 0 && prm->K >= 1 && prm->K <= 16 && prm->alpha >= 1 && prm->alpha <= 16,
+            "bad L/K/alpha");
+  CHECK_ARG(prm->L + 1 + prm->K <= HELRM_MAX_PRIMES, "too many primes");
+  CHECK_ARG(prm->q && prm->p, "NULL prime arrays");
+  helrm_ctx *c = new helrm_ctx();
+  c->logn = prm->log_n;
+  c->N = 1 << prm->log_n;
+  c->L = prm->L;
+  c->K = prm->K;
+  c->alpha = prm->alpha;
+  c->dnum = (prm->L + 1 + prm->alpha - 1) / prm->alpha;
+  c->nprimes = prm->L + 1 + prm->K;
+  for (int i = 0; i <= prm->L; i++) c->primes.push_back(prm->q[i]);
+  for (int i = 0; i < prm->K; i++) c->primes.push_back(prm->p[i]);
+  const u64 twoN = 2ull * c->N;
+  for (int i = 0; i < c->nprimes; i++) {
+    const u64 q = c->primes[i];
+    if (q < 3 || q >= (1ull << 61) || q % twoN != 1) {
+      set_error("prime %d (%llu) must be < 2^61 and = 1 mod 2N", i, (unsigned long long)q);
+      delete c;
+      return HELRM_EINVAL;
+    }
+    for (int k = 0; k < i; k++)
+      if (c->primes[k] == q) {
+        set_error("prime %d repeated", i);
+        delete c;
+        return HELRM_EINVAL;
+      }
+  }
+  if (c->dnum > 16 || c->alpha > 16) {
+    set_error("at most 16 digits of at most 16 primes");
+    delete c;
+    return HELRM_EINVAL;
+  }
+  int rc = hipGetDevice(&c->device);
+  if (rc != hipSuccess) {
+    set_error("hipGetDevice failed");
+    delete c;
+    return HELRM_EHIP;
+  }
+  const int N = c->N;
+  // roots: psi = x^((q-1)/2N) for the smallest non-residue x
+  std::vector<TW> twf((size_t)c->nprimes * N), twi((size_t)c->nprimes * N);
+  u64 P_all[HELRM_MAX_PRIMES];
+  for (int i = 0; i < c->nprimes; i++) {
+    const u64 q = c->primes[i];
+    u64 x = 2;
+    while (hpow(x, (q - 1) / 2, q) != q - 1) x++;
+    const u64 psi = hpow(x, (q - 1) / twoN, q);
+    c->psi.push_back(psi);
+    const u64 psii = hinv(psi, q);
+    std::vector<u64> pw(N), pwi(N);
+    pw[0] = pwi[0] = 1;
+    for (int k = 1; k < N; k++) { pw[k] = hmul(pw[k - 1], psi, q); pwi[k] = hmul(pwi[k - 1], psii, q); }
+    for (int k = 0; k < N; k++) {
+      const unsigned e = brv((unsigned)k, c->logn);
+      twf[(size_t)i * N + k] = tw_of(pw[e], q);
+      twi[(size_t)i * N + k] = tw_of(pwi[e], q);
+    }
+    u64 Pm = 1;
+    for (int k = 0; k < c->K; k++) Pm = hmul(Pm, c->primes[c->L + 1 + k] % q, q);
+    P_all[i] = Pm;
+    PrimeInfo pi;
+    pi.q = q;
+    pi.qn = neg_inv64(q);
+    pi.mu = (u64)(((u128)1 << 64) / q);
+    const u64 r1 = (u64)(((u128)1 << 64) % q);
+    pi.r2 = hmul(r1, r1, q);
+    pi.ninv = hinv((u64)N % q, q);
+    pi.ninv_p = shoup_of(pi.ninv, q);
+    pi.pmod = Pm;
+    pi.pmod_p = shoup_of(Pm, q);
+    pi.pinv = Pm ? hinv(Pm, q) : 0;
+    pi.pinv_p = shoup_of(pi.pinv, q);
+    c->h_pinfo.push_back(pi);
+  }
+  // conversion tables
+  ConstBuilder cb;
+  struct Fix { int level, digit; size_t inv, mont; };
+  std::vector<Fix> fix_up, fix_down;
+  std::vector<size_t> off_pinv(c->L + 1), off_qinv(c->L + 1);
+  c->modup_tabs.resize(c->L + 1);
+  c->moddown_tabs.resize(c->L + 1);
+  for (int lv = 0; lv <= c->L; lv++) {
+    const int beta = c->n_digits(lv), pqn = lv + 1 + c->K;
+    c->modup_tabs[lv].resize(beta);
+    for (int j = 0; j < beta; j++) {
+      std::vector<int> in, outp;
+      for (int i = c->digit_lo(j); i < c->digit_hi(j, lv); i++) in.push_back(i);
+      for (int r = 0; r < pqn; r++)
+        if (r < c->digit_lo(j) || r >= c->digit_hi(j, lv)) outp.push_back(c->pq_prime(r, lv));
+      Fix f{lv, j, 0, 0};
+      build_conv(c, cb, in, outp, c->modup_tabs[lv][j], f.inv, f.mont);
+      fix_up.push_back(f);
+    }
+    std::vector<int> in, outp;
+    for (int k = 0; k < c->K; k++) in.push_back(c->L + 1 + k);
+    for (int i = 0; i <= lv; i++) outp.push_back(i);
+    Fix f{lv, 0, 0, 0};
+    build_conv(c, cb, in, outp, c->moddown_tabs[lv], f.inv, f.mont);
+    fix_down.push_back(f);
+    std::vector<TW> pinv;
+    for (int p = 0; p < 2; p++)
+      for (int i = 0; i <= lv; i++) pinv.push_back(TW{c->h_pinfo[i].pinv, c->h_pinfo[i].pinv_p});
+    off_pinv[lv] = cb.add_tw(pinv);
+    std::vector<TW> qinv;
+    for (int p = 0; p < 2; p++)
+      for (int i = 0; i < lv; i++) qinv.push_back(tw_of(hinv(c->primes[lv] % c->primes[i], c->primes[i]), c->primes[i]));
+    if (qinv.empty()) qinv.push_back(TW{0, 0});
+    off_qinv[lv] = cb.add_tw(qinv);
+  }
+  auto fail = [&](int code) {
+    helrm_destroy(c);
+    return code;
+  };
+  if (hipMalloc(&c->d_pinfo, sizeof(PrimeInfo) * c->nprimes) != hipSuccess ||
+      hipMalloc(&c->d_tw_fwd, sizeof(TW) * twf.size()) != hipSuccess ||
+      hipMalloc(&c->d_tw_inv, sizeof(TW) * twi.size()) != hipSuccess ||
+      hipMalloc(&c->d_const, sizeof(u64) * cb.words.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation of context tables failed");
+    return fail(HELRM_ENOMEM);
+  }
+  if (hipMemcpy(c->d_pinfo, c->h_pinfo.data(), sizeof(PrimeInfo) * c->nprimes, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(c->d_tw_fwd, twf.data(), sizeof(TW) * twf.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_tw_inv, twi.data(), sizeof(TW) * twi.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_const, cb.words.data(), sizeof(u64) * cb.words.size(), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    set_error("upload of context tables failed");
+    return fail(HELRM_EHIP);
+  }
+  for (auto &f : fix_up) {
+    c->modup_tabs[f.level][f.digit].hat_inv = (const TW *)(c->d_const + f.inv);
+    c->modup_tabs[f.level][f.digit].hat_mont = c->d_const + f.mont;
+  }
+  for (auto &f : fix_down) {
+    c->moddown_tabs[f.level].hat_inv = (const TW *)(c->d_const + f.inv);
+    c->moddown_tabs[f.level].hat_mont = c->d_const + f.mont;
+  }
+  c->moddown_pinv.resize(c->L + 1);
+  c->rescale_qinv.resize(c->L + 1);
+  for (int lv = 0; lv <= c->L; lv++) {
+    c->moddown_pinv[lv] = (const TW *)(c->d_const + off_pinv[lv]);
+    c->rescale_qinv[lv] = (const TW *)(c->d_const + off_qinv[lv]);
+  }
+  *out = c;
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_destroy(helrm_ctx *c) {
+  API_GUARD_BEGIN
+  if (!c) return HELRM_OK;
+  (void)hipDeviceSynchronize();
+  for (auto &kv : c->keys) (void)hipFree(kv.second.d);
+  for (auto &kv : c->ws)
+    if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+  if (c->d_pinfo) (void)hipFree(c->d_pinfo);
+  if (c->d_tw_fwd) (void)hipFree(c->d_tw_fwd);
+  if (c->d_tw_inv) (void)hipFree(c->d_tw_inv);
+  if (c->d_const) (void)hipFree(c->d_const);
+  delete c;
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_get_psi(const helrm_ctx *c, int i, uint64_t *psi) {
+  CHECK_ARG(c && psi, "NULL argument");
+  CHECK_ARG(i >= 0 && i < c->nprimes, "prime index out of range");
+  *psi = c->psi[i];
+  return HELRM_OK;
+}
+
+extern "C" int helrm_load_eval_keys(helrm_ctx *c, const uint32_t *galois, int n_keys, const uint64_t *keys) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(n_keys >= 0, "n_keys < 0");
+  CHECK_ARG(n_keys == 0 || (galois && keys), "NULL galois or keys");
+  const size_t N = c->N, kl = c->L + 1 + c->K;
+  const size_t words = (size_t)c->dnum * 2 * kl * N;
+  for (int k = 0; k < n_keys; k++)
+    CHECK_ARG(galois[k] == 0 || (galois[k] & 1u) && galois[k] < 2u * c->N, "bad galois element %u", galois[k]);
+  for (int k = 0; k < n_keys; k++) {
+    u64 *d = nullptr;
+    auto it = c->keys.find(galois[k]);
+    if (it != c->keys.end()) {
+      d = it->second.d;
+    } else {
+      if (hipMalloc(&d, words * sizeof(u64)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("key allocation (%zu bytes) failed", words * sizeof(u64));
+        return HELRM_ENOMEM;
+      }
+      c->keys[galois[k]] = KeyEntry{d};
+    }
+    HIP_TRY(hipMemcpy(d, keys + (size_t)k * words, words * sizeof(u64), hipMemcpyDefault));
+    LimbList ll = ll_make((int)kl, (int)kl, (int)kl);
+    for (size_t i = 0; i < kl; i++) { ll.src_off[i] = (int)i; ll.dst_off[i] = (int)i; ll.prime[i] = (unsigned char)i; }
+    TRY(launch_to_mont(c, d, ll, c->dnum * 2, 0));
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+static int ntt_common(helrm_ctx *c, uint64_t *d, int n_limbs, const int32_t *pidx, int batch, void *stream,
+                      bool fwd) {
+  CHECK_ARG(c && (d || n_limbs * batch == 0), "NULL argument");
+  CHECK_ARG(batch >= 0, "batch < 0");
+  TRY(check_primes(c, n_limbs, pidx));
+  for (int i0 = 0; i0 < n_limbs; i0 += HELRM_MAX_LIMBS) {
+    const int n = std::min(HELRM_MAX_LIMBS, n_limbs - i0);
+    LimbList ll = ll_from_primes(c, n, pidx + i0, i0);
+    ll.src_bstride = ll.dst_bstride = n_limbs;
+    TRY(launch_ntt(c, d, d, ll, batch, fwd, as_stream(stream)));
+  }
+  return HELRM_OK;
+}
+
+extern "C" int helrm_ntt(helrm_ctx *c, uint64_t *d, int n_limbs, const int32_t *pidx, int batch, void *stream) {
+  API_GUARD_BEGIN
+  return ntt_common(c, d, n_limbs, pidx, batch, stream, true);
+  API_GUARD_END
+}
+
+extern "C" int helrm_intt(helrm_ctx *c, uint64_t *d, int n_limbs, const int32_t *pidx, int batch, void *stream) {
+  API_GUARD_BEGIN
+  return ntt_common(c, d, n_limbs, pidx, batch, stream, false);
+  API_GUARD_END
+}
+
+extern "C" int helrm_automorph(helrm_ctx *c, const uint64_t *in, uint64_t *out, uint32_t galois, int n_limbs,
+                               int batch, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(n_limbs >= 0 && batch >= 0, "negative size");
+  CHECK_ARG(n_limbs * batch == 0 || (in && out), "NULL buffer");
+  CHECK_ARG((galois & 1u) && galois < 2u * c->N, "galois element must be odd and < 2N");
+  CHECK_ARG(in != out, "in and out must differ");
+  return launch_automorph(c, in, out, galois, n_limbs, batch, as_stream(stream));
+  API_GUARD_END
+}
+
+extern "C" int helrm_poly_op(helrm_ctx *c, int op, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                             int n_limbs, const int32_t *pidx, int batch, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(op >= 0 && op <= 3, "bad op");
+  CHECK_ARG(batch >= 0, "batch < 0");
+  TRY(check_primes(c, n_limbs, pidx));
+  CHECK_ARG(n_limbs * batch == 0 || (a && out && (op == HELRM_OP_NEG || b)), "NULL buffer");
+  for (int i0 = 0; i0 < n_limbs; i0 += HELRM_MAX_LIMBS) {
+    const int n = std::min(HELRM_MAX_LIMBS, n_limbs - i0);
+    LimbList ll = ll_from_primes(c, n, pidx + i0, i0);
+    ll.src_bstride = ll.dst_bstride = n_limbs;
+    TRY(launch_poly_op(c, op, a, b ? b : a, out, ll, batch, as_stream(stream)));
+  }
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_mul_scalar(helrm_ctx *c, const uint64_t *a, const uint64_t *scalars, uint64_t *out,
+                                int n_limbs, const int32_t *pidx, int batch, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(batch >= 0, "batch < 0");
+  TRY(check_primes(c, n_limbs, pidx));
+  CHECK_ARG(n_limbs * batch == 0 || (a && out && scalars), "NULL buffer");
+  for (int i0 = 0; i0 < n_limbs; i0 += 64) {
+    const int n = std::min(64, n_limbs - i0);
+    LimbList ll = ll_from_primes(c, n, pidx + i0, i0);
+    ll.src_bstride = ll.dst_bstride = n_limbs;
+    TRY(launch_mul_scalar(c, a, scalars + i0, out, ll, batch, as_stream(stream)));
+  }
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_from_signed(helrm_ctx *c, const int64_t *in, uint64_t *out, int n_limbs,
+                                 const int32_t *pidx, int batch, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(batch >= 0, "batch < 0");
+  TRY(check_primes(c, n_limbs, pidx));
+  CHECK_ARG(n_limbs * batch == 0 || (in && out), "NULL buffer");
+  for (int i0 = 0; i0 < n_limbs; i0 += HELRM_MAX_LIMBS) {
+    const int n = std::min(HELRM_MAX_LIMBS, n_limbs - i0);
+    LimbList ll = ll_from_primes(c, n, pidx + i0, i0);
+    ll.dst_bstride = n_limbs;
+    TRY(launch_from_signed(c, in, out, ll, batch, as_stream(stream)));
+  }
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_keyswitch_hoisted(helrm_ctx *c, const uint64_t *ct, int level, const int32_t *steps,
+                                       int n_rot, uint64_t *out, int out_basis, int batch, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(level >= 0 && level <= c->L, "level %d out of range", level);
+  CHECK_ARG(n_rot >= 0 && batch >= 0, "negative size");
+  CHECK_ARG(out_basis == HELRM_BASIS_Q || out_basis == HELRM_BASIS_PQ, "bad out_basis");
+  if (n_rot == 0 || batch == 0) return HELRM_OK;
+  CHECK_ARG(ct && out && steps, "NULL buffer");
+  hipStream_t s = as_stream(stream);
+  const size_t N = c->N;
+  const int qn = level + 1, pqn = level + 1 + c->K, beta = c->n_digits(level);
+  std::vector<KsTerm> terms(n_rot);
+  for (int r = 0; r < n_rot; r++) {
+    terms[r].digits = nullptr;
+    terms[r].c0 = ct;
+    if (steps[r] % (c->N / 2) != 0) TRY(key_for(c, steps[r], &terms[r].key, &terms[r].galois));
+    else terms[r].galois = 1;
+  }
+  KsSizes z = ks_sizes(c, level, batch, 1);
+  size_t bytes = rnd(z.coef) + rnd(z.D) + rnd(z.X) + rnd(z.mdP) + rnd(z.mdT);
+  char *base;
+  TRY(ensure_ws(c, s, bytes, &base));
+  Arena a{base};
+  u64 *coef = a.take(z.coef), *D = a.take(z.D), *X = a.take(z.X), *mdP = a.take(z.mdP), *mdT = a.take(z.mdT);
+  const int ct_bs = 2 * qn, d_bs = beta * pqn;
+  TRY(do_modup(c, level, ct + (size_t)qn * N, ct_bs, D, d_bs, coef, batch, s));
+  const int ob = out_basis == HELRM_BASIS_PQ ? 2 * pqn : 2 * qn;
+  for (int r = 0; r < n_rot; r++) {
+    u64 *dst = out + (size_t)r * ob * N;
+    const size_t out_bs = (size_t)n_rot * ob * N;
+    if (terms[r].galois == 1) {
+      if (out_basis == HELRM_BASIS_PQ) {
+        TRY(launch_ks_accumulate(c, level, nullptr, 0, 0, 0, ct, (size_t)ct_bs * N, dst, out_bs, batch, s));
+      } else {
+        LimbList cp = ll_make(2 * qn, ct_bs, n_rot * ob);
+        for (int i = 0; i < 2 * qn; i++) { cp.src_off[i] = i; cp.dst_off[i] = i; cp.prime[i] = 0; }
+        TRY(launch_copy_limbs(ct, dst, cp, batch, (int)N, s));
+      }
+      continue;
+    }
+    KsTerm t = terms[r];
+    t.digits = D;
+    if (out_basis == HELRM_BASIS_PQ) {
+      TRY(launch_ks_accumulate(c, level, &t, 1, (size_t)d_bs * N, (size_t)ct_bs * N, nullptr, 0, dst, out_bs,
+                               batch, s));
+    } else {
+      TRY(launch_ks_accumulate(c, level, &t, 1, (size_t)d_bs * N, (size_t)ct_bs * N, nullptr, 0, X,
+                               (size_t)2 * pqn * N, batch, s));
+      TRY(do_moddown(c, level, X, 2 * pqn, dst, n_rot * ob, mdP, mdT, batch, s));
+    }
+  }
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_rescale(helrm_ctx *c, const uint64_t *in, int level, uint64_t *out, int batch,
+                             void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(level >= 1 && level <= c->L, "level %d out of range (1..L)", level);
+  CHECK_ARG(batch >= 0, "batch < 0");
+  if (batch == 0) return HELRM_OK;
+  CHECK_ARG(in && out, "NULL buffer");
+  hipStream_t s = as_stream(stream);
+  const size_t N = c->N;
+  size_t bytes = rnd((size_t)batch * 2 * N) + rnd((size_t)batch * 2 * level * N);
+  char *base;
+  TRY(ensure_ws(c, s, bytes, &base));
+  Arena a{base};
+  u64 *top = a.take((size_t)batch * 2 * N), *V = a.take((size_t)batch * 2 * level * N);
+  return do_rescale(c, level, in, 2 * (level + 1), out, 2 * level, top, V, batch, s);
+  API_GUARD_END
+}
+
+extern "C" int helrm_plan_create(helrm_ctx *c, const helrm_plan_desc *d, helrm_plan **out) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && d && out, "NULL argument");
+  *out = nullptr;
+  const int n = c->N / 2;
+  CHECK_ARG(d->level >= 0 && d->level <= c->L, "plan level out of range");
+  CHECK_ARG(is_pow2(d->m) && d->m <= n, "m must be a power of two <= N/2");
+  CHECK_ARG(d->n1 >= 1 && d->n2 >= 1 && (long)d->n1 * d->n2 >= d->m, "need n1*n2 >= m");
+  CHECK_ARG(d->n1 <= HELRM_MAX_BABY, "n1 above %d", HELRM_MAX_BABY);
+  CHECK_ARG(d->radix >= 2 && d->radix <= HELRM_MAX_TERMS + 1, "radix must be in [2, %d]", HELRM_MAX_TERMS + 1);
+  CHECK_ARG(d->n_diag >= 1 && d->diag && d->coeffs, "plan needs at least one diagonal");
+  for (int i = 0; i < d->n_diag; i++) {
+    CHECK_ARG(d->diag[i] >= 0 && d->diag[i] < d->m, "diagonal index %d out of range", d->diag[i]);
+    CHECK_ARG(i == 0 || d->diag[i] > d->diag[i - 1], "diagonal indices must ascend");
+  }
+  helrm_plan *p = new helrm_plan();
+  p->ctx = c;
+  p->level = d->level;
+  p->m = d->m;
+  p->n1 = d->n1;
+  p->n2 = d->n2;
+  p->radix = d->radix;
+  p->n_diag = d->n_diag;
+  p->slot.assign((size_t)d->n2 * d->n1, -1);
+  for (int i = 0; i < d->n_diag; i++) {
+    const int k = d->diag[i], g = k / d->n1, b = k % d->n1;
+    p->diag.push_back(k);
+    p->slot[(size_t)g * d->n1 + b] = i;
+    if (std::find(p->babies.begin(), p->babies.end(), b) == p->babies.end()) p->babies.push_back(b);
+    if (std::find(p->giants.begin(), p->giants.end(), g) == p->giants.end()) p->giants.push_back(g);
+  }
+  std::sort(p->babies.begin(), p->babies.end());
+  std::sort(p->giants.begin(), p->giants.end());
+  for (int span = n; span > d->m;) {
+    const int r = std::min(d->radix, span / d->m);
+    const int st = span / r;
+    p->stages.push_back({st, r});
+    span = st;
+  }
+  const int pqn = d->level + 1 + c->K;
+  p->pt_limb_stride = pqn;
+  const size_t N = c->N;
+  int64_t *dcoef = nullptr;
+  auto fail = [&](int code) {
+    if (dcoef) (void)hipFree(dcoef);
+    helrm_plan_destroy(p);
+    return code;
+  };
+  if (hipMalloc(&p->d_pt, (size_t)d->n_diag * pqn * N * sizeof(u64)) != hipSuccess ||
+      hipMalloc(&p->d_slot, p->slot.size() * sizeof(int)) != hipSuccess ||
+      hipMalloc(&dcoef, (size_t)d->n_diag * N * sizeof(int64_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("plan allocation failed");
+    return fail(HELRM_ENOMEM);
+  }
+  if (hipMemcpy(p->d_slot, p->slot.data(), p->slot.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dcoef, d->coeffs, (size_t)d->n_diag * N * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("plan upload failed");
+    return fail(HELRM_EHIP);
+  }
+  LimbList ll = ll_make(pqn, pqn, pqn);
+  for (int r = 0; r < pqn; r++) { ll.src_off[r] = r; ll.dst_off[r] = r; ll.prime[r] = (unsigned char)c->pq_prime(r, d->level); }
+  int rc;
+  if ((rc = launch_from_signed(c, dcoef, p->d_pt, ll, d->n_diag, 0)) != HELRM_OK) return fail(rc);
+  if ((rc = launch_ntt(c, p->d_pt, p->d_pt, ll, d->n_diag, true, 0)) != HELRM_OK) return fail(rc);
+  if ((rc = launch_to_mont(c, p->d_pt, ll, d->n_diag, 0)) != HELRM_OK) return fail(rc);
+  if (hipDeviceSynchronize() != hipSuccess) {
+    set_error("plan preparation failed on the device");
+    return fail(HELRM_EHIP);
+  }
+  (void)hipFree(dcoef);
+  dcoef = nullptr;
+  *out = p;
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_plan_destroy(helrm_plan *p) {
+  API_GUARD_BEGIN
+  if (!p) return HELRM_OK;
+  (void)hipDeviceSynchronize();
+  if (p->d_pt) (void)hipFree(p->d_pt);
+  if (p->d_slot) (void)hipFree(p->d_slot);
+  delete p;
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_plan_rotation_steps(const helrm_plan *p, int32_t *steps, int cap, int *n) {
+  API_GUARD_BEGIN
+  CHECK_ARG(p && n, "NULL argument");
+  std::vector<int> st;
+  for (int b : p->babies)
+    if (b) st.push_back(b);
+  for (int g : p->giants)
+    if (g) st.push_back(p->n1 * g);
+  for (auto &sr : p->stages)
+    for (int t = 1; t < sr.second; t++) st.push_back(t * sr.first);
+  std::sort(st.begin(), st.end());
+  st.erase(std::unique(st.begin(), st.end()), st.end());
+  *n = (int)st.size();
+  for (int i = 0; i < (int)st.size() && i < cap; i++) steps[i] = st[i];
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_ptxt_ct_matvec_diag(helrm_ctx *c, const helrm_plan *p, const uint64_t *ct, uint64_t *out,
+                                         int batch, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && p && p->ctx == c, "NULL or foreign plan");
+  CHECK_ARG(batch >= 0, "batch < 0");
+  if (batch == 0) return HELRM_OK;
+  CHECK_ARG(ct && out, "NULL buffer");
+  hipStream_t s = as_stream(stream);
+  char *base;
+  TRY(ensure_ws(c, s, matvec_ws_bytes(c, p, batch, false), &base));
+  MatvecWS w = carve_matvec(c, p, batch, false, base);
+  return run_matvec(c, p, ct, out, batch, w, s);
+  API_GUARD_END
+}
+
+extern "C" int helrm_lookup_packed(helrm_ctx *c, const helrm_plan *p, const uint64_t *sel, int batch,
+                                   uint64_t *out, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && p && p->ctx == c, "NULL or foreign plan");
+  CHECK_ARG(p->level >= 1, "lookup needs a plan at level >= 1");
+  CHECK_ARG(batch >= 0, "batch < 0");
+  if (batch == 0) return HELRM_OK;
+  CHECK_ARG(sel && out, "NULL buffer");
+  hipStream_t s = as_stream(stream);
+  char *base;
+  TRY(ensure_ws(c, s, matvec_ws_bytes(c, p, batch, true), &base));
+  MatvecWS w = carve_matvec(c, p, batch, true, base);
+  TRY(run_matvec(c, p, sel, w.mv, batch, w, s));
+  const int lv = p->level;
+  return do_rescale(c, lv, w.mv, 2 * (lv + 1), out, 2 * lv, w.top, w.V, batch, s);
+  API_GUARD_END
+}
+
+extern "C" int helrm_footprint(const helrm_ctx *c, const helrm_plan *p, int batch, size_t *bytes) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && p && bytes && batch >= 0, "bad argument");
+  *bytes = matvec_ws_bytes(c, p, batch, true);
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_reserve(helrm_ctx *c, const helrm_plan *p, int batch, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && p && batch >= 0, "bad argument");
+  char *base;
+  return ensure_ws(c, as_stream(stream), matvec_ws_bytes(c, p, batch, true), &base);
+  API_GUARD_END
+}

@@ -1,0 +1,265 @@
+// Internal declarations of libhelrm: device modular arithmetic, launch
+// descriptors, the context structure and the host-side launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "helrm.h"
+
+typedef uint64_t u64;
+typedef unsigned __int128 u128;
+
+#define HELRM_MAX_PRIMES 64   // L+1+K
+#define HELRM_MAX_LIMBS 128   // limbs one descriptor list may name
+#define HELRM_MAX_TERMS 16    // key-switch terms summed by one accumulate launch
+#define HELRM_MAX_BABY 64     // baby steps per fused MAC launch
+#define HELRM_MAX_GTILE 8     // giant outputs accumulated per fused MAC launch
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const char *fmt, ...);
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) {                                                        \
+      set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, __LINE__); \
+      return HELRM_EHIP;                                                           \
+    }                                                                              \
+  } while (0)
+
+#define CHECK_ARG(cond, ...)          \
+  do {                                \
+    if (!(cond)) {                    \
+      set_error(__VA_ARGS__);         \
+      return HELRM_EINVAL;            \
+    }                                 \
+  } while (0)
+
+#define TRY(expr)                     \
+  do {                                \
+    int _r = (expr);                  \
+    if (_r != HELRM_OK) return _r;    \
+  } while (0)
+
+// ---------------------------------------------------------------- device arithmetic
+//
+// Two reductions are used:
+//  * Shoup: x * w mod q for a fixed w with w' = floor(w 2^64 / q); the result
+//    of the lazy form is in [0, 2q) for any 64-bit x (Shoup; Harvey 2014).
+//  * Montgomery REDC (Montgomery 1985): for T = hi 2^64 + lo with hi < q,
+//    returns T 2^-64 mod q.  Resident operands (keys, plaintext diagonals,
+//    conversion constants) are stored pre-multiplied by 2^64, so REDC of a
+//    128-bit sum of products gives the plain modular sum of products.
+
+struct Mod {
+  u64 q;
+  u64 qn;  // -q^-1 mod 2^64
+};
+
+__device__ __forceinline__ u64 shoup_lazy(u64 x, u64 w, u64 wp, u64 q) {
+  u64 qh = __umul64hi(x, wp);
+  return x * w - qh * q;
+}
+
+__device__ __forceinline__ u64 shoup(u64 x, u64 w, u64 wp, u64 q) {
+  u64 r = shoup_lazy(x, w, wp, q);
+  return r >= q ? r - q : r;
+}
+
+struct Acc {
+  u64 lo, hi;
+};
+
+__device__ __forceinline__ void acc_zero(Acc &a) { a.lo = 0; a.hi = 0; }
+
+__device__ __forceinline__ void acc_mac(Acc &a, u64 x, u64 y) {
+  u128 p = (u128)x * y;
+  u64 l = (u64)p;
+  a.lo += l;
+  a.hi += (u64)(p >> 64) + (a.lo < l ? 1 : 0);
+}
+
+// REDC for hi < q: result in [0, q).
+__device__ __forceinline__ u64 redc(u64 lo, u64 hi, u64 q, u64 qn) {
+  u64 m = lo * qn;
+  u64 r = hi + __umul64hi(m, q) + (lo != 0 ? 1 : 0);
+  return r >= q ? r - q : r;
+}
+
+// REDC for hi < 4q (sums of up to 64 products of residues below 2^60).
+__device__ __forceinline__ u64 redc_acc(const Acc &a, u64 q, u64 qn) {
+  u64 hi = a.hi;
+  hi = hi >= 2 * q ? hi - 2 * q : hi;
+  hi = hi >= q ? hi - q : hi;
+  return redc(a.lo, hi, q, qn);
+}
+
+__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
+  u64 s = a + b;
+  return s >= q ? s - q : s;
+}
+
+__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) {
+  return a >= b ? a - b : a + q - b;
+}
+
+// x mod q for any 64-bit x, with mu = floor(2^64 / q).
+__device__ __forceinline__ u64 reduce64(u64 x, u64 q, u64 mu) {
+  u64 r = x - __umul64hi(x, mu) * q;
+  return r >= q ? r - q : r;
+}
+
+// Evaluation-form index permutation of X -> X^g:
+// out[j] = in[j'] with 2 brv(j')+1 = g (2 brv(j)+1) mod 2N.
+__device__ __forceinline__ unsigned galois_src(unsigned j, unsigned g, int logn) {
+  unsigned e = 2u * (__brev(j) >> (32 - logn)) + 1u;
+  unsigned e2 = (g * e) & ((2u << logn) - 1u);
+  return __brev((e2 - 1u) >> 1) >> (32 - logn);
+}
+
+// ---------------------------------------------------------------- per-prime device constants
+
+struct PrimeInfo {
+  u64 q, qn;           // modulus, -q^-1 mod 2^64
+  u64 mu;              // floor(2^64 / q)
+  u64 r2;              // 2^128 mod q (to Montgomery form: REDC(x r2) = x 2^64)
+  u64 ninv, ninv_p;    // N^-1 mod q with its Shoup companion
+  u64 pmod, pmod_p;    // [P]_q with Shoup companion (P = product of special primes)
+  u64 pinv, pinv_p;    // [P^-1]_q (Q primes only)
+};
+
+struct TW {
+  u64 w, wp;
+};
+
+// A list of limbs for one launch.  Limb i of batch element b lives at
+// base + (b * bstride + off[i]) * N and uses prime prime[i].
+struct LimbList {
+  int n;
+  int src_bstride;   // in limbs
+  int dst_bstride;   // in limbs
+  int src_off[HELRM_MAX_LIMBS];
+  int dst_off[HELRM_MAX_LIMBS];
+  unsigned char prime[HELRM_MAX_LIMBS];
+};
+
+// Fast base conversion for one (level, digit) or the ModDown of one level.
+struct ConvTable {
+  int nin, nout;
+  int in_prime[16];
+  int out_prime[HELRM_MAX_PRIMES];
+  // device pointers into the context's constant buffer
+  const TW *hat_inv;   // [nin]: (Qin/q_i)^-1 mod q_i, Shoup form
+  const u64 *hat_mont; // [nin][nout]: (Qin/q_i mod r) 2^64 mod r
+};
+
+// ---------------------------------------------------------------- context
+
+struct KeyEntry {
+  u64 *d;   // [dnum][2][L+1+K][N], Montgomery form
+};
+
+struct Workspace {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct helrm_ctx {
+  int logn, N, L, K, alpha, dnum, nprimes;
+  int device;
+  std::vector<u64> primes;   // q_0..q_L, p_0..p_{K-1}
+  std::vector<u64> psi;
+  std::vector<PrimeInfo> h_pinfo;
+  PrimeInfo *d_pinfo = nullptr;
+  TW *d_tw_fwd = nullptr;    // [nprimes][N]: psi^brv(k)
+  TW *d_tw_inv = nullptr;    // [nprimes][N]: psi^-brv(k)
+  u64 *d_const = nullptr;    // conversion constants
+  std::vector<std::vector<ConvTable>> modup_tabs;   // [level][digit]
+  std::vector<ConvTable> moddown_tabs;              // [level]
+  std::vector<const TW *> moddown_pinv;             // [level] -> [2][level+1] P^-1 mod q_i
+  std::vector<const TW *> rescale_qinv;             // [level] -> [2][level] q_level^-1 mod q_i
+  std::map<uint32_t, KeyEntry> keys;
+  std::mutex ws_mu;
+  std::map<hipStream_t, Workspace> ws;
+
+  int n_digits(int level) const { return (level + 1 + alpha - 1) / alpha; }
+  int digit_lo(int j) const { return j * alpha; }
+  int digit_hi(int j, int level) const {  // exclusive
+    int h = (j + 1) * alpha;
+    return h < level + 1 ? h : level + 1;
+  }
+  // index of the prime of PQ-limb r at this level
+  int pq_prime(int r, int level) const { return r <= level ? r : L + 1 + (r - level - 1); }
+  // position of PQ-limb r inside a full-level key
+  int key_limb(int r, int level) const { return r <= level ? r : L + 1 + (r - level - 1); }
+};
+
+struct helrm_plan {
+  helrm_ctx *ctx;
+  int level, m, n1, n2, radix, n_diag;
+  std::vector<int> diag;                 // k = n1 g + b per stored diagonal
+  std::vector<std::pair<int, int>> stages;  // fold (s, r)
+  std::vector<int> babies;               // b values present (ascending)
+  std::vector<int> giants;               // g values present (ascending)
+  std::vector<int> slot;                 // [n2][n1]: stored diagonal index or -1
+  u64 *d_pt = nullptr;                   // [n_diag][L_pq][N], Montgomery form
+  int *d_slot = nullptr;                 // device copy of slot
+  size_t pt_limb_stride;                 // limbs per stored diagonal (= level+1+K)
+};
+
+// ---------------------------------------------------------------- launchers
+
+// NTT of the limbs in `ll` (src -> dst, may be in place).
+int launch_ntt(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int batch, bool forward,
+               hipStream_t s);
+
+int launch_automorph(helrm_ctx *ctx, const u64 *in, u64 *out, uint32_t galois, int n_limbs, int batch,
+                     hipStream_t s);
+int launch_poly_op(helrm_ctx *ctx, int op, const u64 *a, const u64 *b, u64 *out, const LimbList &ll,
+                   int batch, hipStream_t s);
+int launch_mul_scalar(helrm_ctx *ctx, const u64 *a, const u64 *scal, u64 *out, const LimbList &ll,
+                      int batch, hipStream_t s);
+int launch_from_signed(helrm_ctx *ctx, const int64_t *in, u64 *out, const LimbList &ll, int batch,
+                       hipStream_t s);
+int launch_to_mont(helrm_ctx *ctx, u64 *data, const LimbList &ll, int batch, hipStream_t s);
+int launch_copy_limbs(const u64 *src, u64 *dst, const LimbList &ll, int batch, int N, hipStream_t s);
+
+// Fast base conversion (coefficient form): dst limbs = conv(src limbs).
+int launch_conv(helrm_ctx *ctx, const ConvTable &t, const u64 *src, int src_off0, int src_bstride,
+                u64 *dst, const int *dst_off, int dst_bstride, int batch, hipStream_t s);
+
+// out[l] = (a[l] - b[l]) * consts[l]  (consts: Shoup pairs, one per list entry)
+// b is addressed with the dst offsets of ll and batch stride b_bstride.
+int launch_sub_mul(helrm_ctx *ctx, const u64 *a, const u64 *b, int b_bstride, u64 *out,
+                   const LimbList &ll, const TW *consts, int batch, hipStream_t s);
+
+// Rescale middle step: from the coefficient-form top limb c (both polys),
+// write [ (c + h mod q_l) - h ]_{q_i} for i < level.
+int launch_rescale_spread(helrm_ctx *ctx, const u64 *top, u64 *out, int level, int batch,
+                          hipStream_t s);
+
+struct KsTerm {
+  const u64 *digits;  // [beta][level+1+K][N] (batch stride given separately)
+  const u64 *c0;      // [level+1][N]
+  const u64 *key;     // [dnum][2][L+1+K][N] Montgomery form
+  uint32_t galois;
+};
+
+// out (PQ, 2 polys) = [lift_P(base)] + sum_t KeyIP(term t).
+int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_terms,
+                         size_t digits_bstride, size_t c0_bstride, const u64 *base,
+                         size_t base_bstride, u64 *out, size_t out_bstride, int batch, hipStream_t s);
+
+// Fused baby steps + plaintext MAC: X_g = sum_b pt_{g,b} (.) R_b for g in
+// [g0, g0+ng).
+int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, size_t digits_bstride,
+                    const u64 *ct, size_t ct_bstride, u64 *X, size_t x_bstride, int g0, int ng,
+                    int batch, hipStream_t s);

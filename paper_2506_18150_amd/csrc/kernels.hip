@@ -1,0 +1,467 @@
+// Element-wise, automorphism, base-conversion, rescale and key-switching
+// kernels of libhelrm (gfx950).  All residues are uint64; one thread owns one
+// coefficient position of one limb, so every global access is a coalesced
+// run of consecutive words (the automorphism gathers inside aligned blocks:
+// X -> X^g maps each aligned block of 2^k evaluation points onto an aligned
+// block of 2^k points).
+#include "common.h"
+
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ size_t limb_ptr(int bat, int bstride, int off, int N) {
+  return ((size_t)bat * bstride + off) * (size_t)N;
+}
+
+// ---------------------------------------------------------------- element-wise
+
+__global__ __launch_bounds__(TPB) void poly_op_kernel(int op, const u64 *a, const u64 *b, u64 *out,
+                                                      LimbList ll, const PrimeInfo *pinfo, int N) {
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int li = blockIdx.y % ll.n, bat = blockIdx.y / ll.n;
+  const PrimeInfo pi = pinfo[ll.prime[li]];
+  const size_t ia = limb_ptr(bat, ll.src_bstride, ll.src_off[li], N) + x;
+  const size_t io = limb_ptr(bat, ll.dst_bstride, ll.dst_off[li], N) + x;
+  const u64 va = a[ia];
+  u64 r;
+  if (op == HELRM_OP_NEG) {
+    r = va == 0 ? 0 : pi.q - va;
+  } else {
+    const u64 vb = b[ia];
+    if (op == HELRM_OP_ADD) {
+      r = add_mod(va, vb, pi.q);
+    } else if (op == HELRM_OP_SUB) {
+      r = sub_mod(va, vb, pi.q);
+    } else {
+      u128 p = (u128)va * vb;
+      u64 t = redc((u64)p, (u64)(p >> 64), pi.q, pi.qn);   // a b 2^-64
+      p = (u128)t * pi.r2;
+      r = redc((u64)p, (u64)(p >> 64), pi.q, pi.qn);       // a b
+    }
+  }
+  out[io] = r;
+}
+
+struct ScalarArgs {
+  TW c[64];
+};
+
+__global__ __launch_bounds__(TPB) void mul_scalar_kernel(const u64 *a, u64 *out, LimbList ll,
+                                                         ScalarArgs sc, const PrimeInfo *pinfo, int N) {
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int li = blockIdx.y % ll.n, bat = blockIdx.y / ll.n;
+  const u64 q = pinfo[ll.prime[li]].q;
+  const size_t ia = limb_ptr(bat, ll.src_bstride, ll.src_off[li], N) + x;
+  const size_t io = limb_ptr(bat, ll.dst_bstride, ll.dst_off[li], N) + x;
+  out[io] = shoup(a[ia], sc.c[li].w, sc.c[li].wp, q);
+}
+
+__global__ __launch_bounds__(TPB) void from_signed_kernel(const int64_t *in, u64 *out, LimbList ll,
+                                                          const PrimeInfo *pinfo, int N) {
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int li = blockIdx.y % ll.n, bat = blockIdx.y / ll.n;
+  const PrimeInfo pi = pinfo[ll.prime[li]];
+  const int64_t v = in[(size_t)bat * N + x];
+  const u64 mag = v >= 0 ? (u64)v : (u64)(-(v + 1)) + 1u;
+  u64 r = reduce64(mag, pi.q, pi.mu);
+  if (v < 0 && r != 0) r = pi.q - r;
+  out[limb_ptr(bat, ll.dst_bstride, ll.dst_off[li], N) + x] = r;
+}
+
+__global__ __launch_bounds__(TPB) void to_mont_kernel(u64 *data, LimbList ll, const PrimeInfo *pinfo,
+                                                      int N) {
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int li = blockIdx.y % ll.n, bat = blockIdx.y / ll.n;
+  const PrimeInfo pi = pinfo[ll.prime[li]];
+  const size_t i = limb_ptr(bat, ll.dst_bstride, ll.dst_off[li], N) + x;
+  u128 p = (u128)data[i] * pi.r2;
+  data[i] = redc((u64)p, (u64)(p >> 64), pi.q, pi.qn);
+}
+
+__global__ __launch_bounds__(TPB) void copy_limbs_kernel(const u64 *src, u64 *dst, LimbList ll, int N) {
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int li = blockIdx.y % ll.n, bat = blockIdx.y / ll.n;
+  dst[limb_ptr(bat, ll.dst_bstride, ll.dst_off[li], N) + x] =
+      src[limb_ptr(bat, ll.src_bstride, ll.src_off[li], N) + x];
+}
+
+__global__ __launch_bounds__(TPB) void automorph_kernel(const u64 *in, u64 *out, unsigned g, int logn) {
+  const int N = 1 << logn;
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const size_t base = (size_t)blockIdx.y * N;
+  out[base + x] = in[base + galois_src(x, g, logn)];
+}
+
+// out[l] = (a[l] - b[l]) * c[l]  with c in Shoup form (ModDown: P^-1,
+// rescale: q_l^-1).  a uses the src offsets, b and out the dst offsets.
+__global__ __launch_bounds__(TPB) void sub_mul_kernel(const u64 *a, const u64 *b, u64 *out, LimbList ll,
+                                                      const TW *consts, const PrimeInfo *pinfo, int N,
+                                                      int b_bstride) {
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int li = blockIdx.y % ll.n, bat = blockIdx.y / ll.n;
+  const u64 q = pinfo[ll.prime[li]].q;
+  const u64 va = a[limb_ptr(bat, ll.src_bstride, ll.src_off[li], N) + x];
+  const u64 vb = b[limb_ptr(bat, b_bstride, ll.dst_off[li], N) + x];
+  const TW c = consts[li];
+  out[limb_ptr(bat, ll.dst_bstride, ll.dst_off[li], N) + x] = shoup(sub_mod(va, vb, q), c.w, c.wp, q);
+}
+
+// ---------------------------------------------------------------- base conversion
+
+struct DstOff {
+  int off[HELRM_MAX_PRIMES];
+};
+
+// y_i = x_i (Qin/q_i)^-1 mod q_i;  out_r = sum_i y_i [Qin/q_i]_r mod r.
+__global__ __launch_bounds__(TPB) void conv_kernel(ConvTable t, const u64 *src, int src_off0, int src_bstride,
+                                                   u64 *dst, DstOff doff, int dst_bstride,
+                                                   const PrimeInfo *pinfo, int N) {
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int bat = blockIdx.y;
+  u64 y[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++) {
+    if (i < t.nin) {
+      const u64 q = pinfo[t.in_prime[i]].q;
+      const u64 v = src[limb_ptr(bat, src_bstride, src_off0 + i, N) + x];
+      y[i] = shoup(v, t.hat_inv[i].w, t.hat_inv[i].wp, q);
+    }
+  }
+  for (int r = 0; r < t.nout; r++) {
+    const PrimeInfo pr = pinfo[t.out_prime[r]];
+    Acc a;
+    acc_zero(a);
+#pragma unroll
+    for (int i = 0; i < 16; i++)
+      if (i < t.nin) acc_mac(a, y[i], t.hat_mont[i * t.nout + r]);
+    dst[limb_ptr(bat, dst_bstride, doff.off[r], N) + x] = redc_acc(a, pr.q, pr.qn);
+  }
+}
+
+// Rescale middle step: t = (c + h) mod q_l from the top limb (coefficient
+// form), then [t - h]_{q_i} for every lower prime i.
+__global__ __launch_bounds__(TPB) void rescale_spread_kernel(const u64 *top, u64 *out, int level,
+                                                             const PrimeInfo *pinfo, int N) {
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int i = blockIdx.y % level, cb = blockIdx.y / level;   // cb = bat*2 + poly
+  const u64 ql = pinfo[level].q;
+  const u64 h = ql >> 1;
+  u64 t = top[(size_t)cb * N + x] + h;
+  t = t >= ql ? t - ql : t;
+  const PrimeInfo pi = pinfo[i];
+  u64 r;
+  if (t >= h) {
+    r = reduce64(t - h, pi.q, pi.mu);
+  } else {
+    r = reduce64(h - t, pi.q, pi.mu);
+    r = r == 0 ? 0 : pi.q - r;
+  }
+  out[((size_t)cb * level + i) * N + x] = r;
+}
+
+// ---------------------------------------------------------------- key switching
+
+struct KsArgs {
+  int n;
+  const u64 *digits[HELRM_MAX_TERMS];
+  const u64 *c0[HELRM_MAX_TERMS];
+  const u64 *key[HELRM_MAX_TERMS];
+  unsigned gal[HELRM_MAX_TERMS];
+};
+
+struct LevelGeom {
+  int level, beta, pqn, keyl, logn;
+};
+
+__device__ __forceinline__ int pq_prime_dev(int r, int level, int L) {
+  return r <= level ? r : L + 1 + (r - level - 1);
+}
+
+// out = (B, A) over PQ:  B = sum_t sum_j sigma_t(d_{t,j}) b_{t,j}
+//                          + P (sum_t sigma_t(c0_t) + base_c0),
+//                        A = sum_t sum_j sigma_t(d_{t,j}) a_{t,j} + P base_c1.
+__global__ __launch_bounds__(TPB) void ks_acc_kernel(KsArgs T, LevelGeom G, int L, size_t dig_bs,
+                                                     size_t c0_bs, const u64 *base, size_t base_bs,
+                                                     u64 *out, size_t out_bs, const PrimeInfo *pinfo) {
+  const int N = 1 << G.logn;
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int r = blockIdx.y;
+  const int bat = blockIdx.z;
+  const int p = pq_prime_dev(r, G.level, L);
+  const PrimeInfo pi = pinfo[p];
+  const bool isq = r <= G.level;
+  Acc ab, aa;
+  acc_zero(ab);
+  acc_zero(aa);
+  u64 csum = 0;
+  for (int t = 0; t < T.n; t++) {
+    const unsigned src = galois_src(x, T.gal[t], G.logn);
+    const u64 *dg = T.digits[t] + bat * dig_bs;
+    const u64 *kk = T.key[t];
+    for (int j = 0; j < G.beta; j++) {
+      const u64 d = dg[((size_t)j * G.pqn + r) * N + src];
+      const u64 kb = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
+      const u64 ka = kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
+      acc_mac(ab, d, kb);
+      acc_mac(aa, d, ka);
+    }
+    if (isq) csum = add_mod(csum, T.c0[t][bat * c0_bs + (size_t)r * N + src], pi.q);
+  }
+  u64 B = redc_acc(ab, pi.q, pi.qn);
+  u64 A = redc_acc(aa, pi.q, pi.qn);
+  if (isq) {
+    if (base) {
+      const u64 *bb = base + bat * base_bs;
+      csum = add_mod(csum, bb[(size_t)r * N + x], pi.q);
+      A = add_mod(A, shoup(bb[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q), pi.q);
+    }
+    B = add_mod(B, shoup(csum, pi.pmod, pi.pmod_p, pi.q), pi.q);
+  }
+  u64 *o = out + bat * out_bs;
+  o[(size_t)r * N + x] = B;
+  o[((size_t)G.pqn + r) * N + x] = A;
+}
+
+struct BabyArgs {
+  int nb;
+  int b[HELRM_MAX_BABY];
+  const u64 *key[HELRM_MAX_BABY];
+  unsigned gal[HELRM_MAX_BABY];
+};
+
+// Fused hoisted baby-step rotations and plaintext-diagonal MAC (double
+// hoisting): R_b is formed in registers and immediately multiplied into every
+// giant output of the tile, so no rotated ciphertext is written to memory.
+template <int GT>
+__global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G, int L, const u64 *digits,
+                                                       size_t dig_bs, const u64 *ct, size_t ct_bs,
+                                                       const u64 *pt, const int *slot, int n1, int g0,
+                                                       int ng, u64 *X, size_t x_bs,
+                                                       const PrimeInfo *pinfo) {
+  const int N = 1 << G.logn;
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int r = blockIdx.y;
+  const int bat = blockIdx.z;
+  const int p = pq_prime_dev(r, G.level, L);
+  const PrimeInfo pi = pinfo[p];
+  const bool isq = r <= G.level;
+  const u64 *dg = digits + bat * dig_bs;
+  const u64 *c = ct + bat * ct_bs;
+  Acc acc[GT][2];
+#pragma unroll
+  for (int gi = 0; gi < GT; gi++) {
+    acc_zero(acc[gi][0]);
+    acc_zero(acc[gi][1]);
+  }
+  for (int bi = 0; bi < BA.nb; bi++) {
+    const int b = BA.b[bi];
+    u64 RB, RA;
+    if (b == 0) {
+      if (isq) {
+        RB = shoup(c[(size_t)r * N + x], pi.pmod, pi.pmod_p, pi.q);
+        RA = shoup(c[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q);
+      } else {
+        RB = 0;
+        RA = 0;
+      }
+    } else {
+      const unsigned src = galois_src(x, BA.gal[bi], G.logn);
+      const u64 *kk = BA.key[bi];
+      Acc ab, aa;
+      acc_zero(ab);
+      acc_zero(aa);
+      for (int j = 0; j < G.beta; j++) {
+        const u64 d = dg[((size_t)j * G.pqn + r) * N + src];
+        acc_mac(ab, d, kk[((size_t)(2 * j) * G.keyl + p) * N + x]);
+        acc_mac(aa, d, kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x]);
+      }
+      RB = redc_acc(ab, pi.q, pi.qn);
+      RA = redc_acc(aa, pi.q, pi.qn);
+      if (isq) RB = add_mod(RB, shoup(c[(size_t)r * N + src], pi.pmod, pi.pmod_p, pi.q), pi.q);
+    }
+#pragma unroll
+    for (int gi = 0; gi < GT; gi++) {
+      if (gi < ng) {
+        const int s = slot[(g0 + gi) * n1 + b];
+        if (s >= 0) {
+          const u64 w = pt[((size_t)s * G.pqn + r) * N + x];
+          acc_mac(acc[gi][0], w, RB);
+          acc_mac(acc[gi][1], w, RA);
+        }
+      }
+    }
+  }
+  u64 *o = X + bat * x_bs;
+#pragma unroll
+  for (int gi = 0; gi < GT; gi++) {
+    if (gi < ng) {
+      o[((size_t)(gi * 2) * G.pqn + r) * N + x] = redc_acc(acc[gi][0], pi.q, pi.qn);
+      o[((size_t)(gi * 2 + 1) * G.pqn + r) * N + x] = redc_acc(acc[gi][1], pi.q, pi.qn);
+    }
+  }
+}
+
+dim3 ew_grid(const helrm_ctx *ctx, int rows) { return dim3(ctx->N / TPB, rows); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+int launch_poly_op(helrm_ctx *ctx, int op, const u64 *a, const u64 *b, u64 *out, const LimbList &ll,
+                   int batch, hipStream_t s) {
+  if (ll.n * batch == 0) return HELRM_OK;
+  hipLaunchKernelGGL(poly_op_kernel, ew_grid(ctx, ll.n * batch), dim3(TPB), 0, s, op, a, b, out, ll,
+                     ctx->d_pinfo, ctx->N);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_mul_scalar(helrm_ctx *ctx, const u64 *a, const u64 *scal, u64 *out, const LimbList &ll,
+                      int batch, hipStream_t s) {
+  if (ll.n > 64) {
+    set_error("mul_scalar: at most 64 limbs per launch");
+    return HELRM_EINVAL;
+  }
+  ScalarArgs sc;
+  for (int i = 0; i < ll.n; i++) {
+    const u64 q = ctx->primes[ll.prime[i]];
+    const u64 w = scal[i] % q;
+    sc.c[i].w = w;
+    sc.c[i].wp = (u64)(((u128)w << 64) / q);
+  }
+  if (ll.n * batch == 0) return HELRM_OK;
+  hipLaunchKernelGGL(mul_scalar_kernel, ew_grid(ctx, ll.n * batch), dim3(TPB), 0, s, a, out, ll, sc,
+                     ctx->d_pinfo, ctx->N);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_from_signed(helrm_ctx *ctx, const int64_t *in, u64 *out, const LimbList &ll, int batch,
+                       hipStream_t s) {
+  if (ll.n * batch == 0) return HELRM_OK;
+  hipLaunchKernelGGL(from_signed_kernel, ew_grid(ctx, ll.n * batch), dim3(TPB), 0, s, in, out, ll,
+                     ctx->d_pinfo, ctx->N);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_to_mont(helrm_ctx *ctx, u64 *data, const LimbList &ll, int batch, hipStream_t s) {
+  if (ll.n * batch == 0) return HELRM_OK;
+  hipLaunchKernelGGL(to_mont_kernel, ew_grid(ctx, ll.n * batch), dim3(TPB), 0, s, data, ll, ctx->d_pinfo,
+                     ctx->N);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_copy_limbs(const u64 *src, u64 *dst, const LimbList &ll, int batch, int N, hipStream_t s) {
+  if (ll.n * batch == 0) return HELRM_OK;
+  hipLaunchKernelGGL(copy_limbs_kernel, dim3(N / TPB, ll.n * batch), dim3(TPB), 0, s, src, dst, ll, N);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_automorph(helrm_ctx *ctx, const u64 *in, u64 *out, uint32_t galois, int n_limbs, int batch,
+                     hipStream_t s) {
+  if (n_limbs * batch == 0) return HELRM_OK;
+  hipLaunchKernelGGL(automorph_kernel, ew_grid(ctx, n_limbs * batch), dim3(TPB), 0, s, in, out,
+                     (unsigned)galois, ctx->logn);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_conv(helrm_ctx *ctx, const ConvTable &t, const u64 *src, int src_off0, int src_bstride,
+                u64 *dst, const int *dst_off, int dst_bstride, int batch, hipStream_t s) {
+  DstOff d;
+  for (int r = 0; r < t.nout; r++) d.off[r] = dst_off[r];
+  if (batch == 0) return HELRM_OK;
+  hipLaunchKernelGGL(conv_kernel, ew_grid(ctx, batch), dim3(TPB), 0, s, t, src, src_off0, src_bstride, dst,
+                     d, dst_bstride, ctx->d_pinfo, ctx->N);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_sub_mul(helrm_ctx *ctx, const u64 *a, const u64 *b, int b_bstride, u64 *out,
+                   const LimbList &ll, const TW *consts, int batch, hipStream_t s) {
+  if (ll.n * batch == 0) return HELRM_OK;
+  hipLaunchKernelGGL(sub_mul_kernel, ew_grid(ctx, ll.n * batch), dim3(TPB), 0, s, a, b, out, ll, consts,
+                     ctx->d_pinfo, ctx->N, b_bstride);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_rescale_spread(helrm_ctx *ctx, const u64 *top, u64 *out, int level, int batch, hipStream_t s) {
+  if (batch == 0 || level == 0) return HELRM_OK;
+  hipLaunchKernelGGL(rescale_spread_kernel, ew_grid(ctx, 2 * batch * level), dim3(TPB), 0, s, top, out,
+                     level, ctx->d_pinfo, ctx->N);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_terms,
+                         size_t digits_bstride, size_t c0_bstride, const u64 *base, size_t base_bstride,
+                         u64 *out, size_t out_bstride, int batch, hipStream_t s) {
+  if (n_terms > HELRM_MAX_TERMS) {
+    set_error("ks_accumulate: at most %d terms", HELRM_MAX_TERMS);
+    return HELRM_EINVAL;
+  }
+  KsArgs T;
+  T.n = n_terms;
+  for (int i = 0; i < n_terms; i++) {
+    T.digits[i] = terms[i].digits;
+    T.c0[i] = terms[i].c0;
+    T.key[i] = terms[i].key;
+    T.gal[i] = terms[i].galois;
+  }
+  LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn};
+  if (batch == 0) return HELRM_OK;
+  hipLaunchKernelGGL(ks_acc_kernel, dim3(ctx->N / TPB, G.pqn, batch), dim3(TPB), 0, s, T, G, ctx->L,
+                     digits_bstride, c0_bstride, base, base_bstride, out, out_bstride, ctx->d_pinfo);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, size_t digits_bstride,
+                    const u64 *ct, size_t ct_bstride, u64 *X, size_t x_bstride, int g0, int ng, int batch,
+                    hipStream_t s) {
+  BabyArgs BA;
+  BA.nb = (int)plan->babies.size();
+  if (BA.nb > HELRM_MAX_BABY) {
+    set_error("baby_mac: at most %d baby steps", HELRM_MAX_BABY);
+    return HELRM_EINVAL;
+  }
+  const uint64_t twoN = 2ull * ctx->N;
+  for (int i = 0; i < BA.nb; i++) {
+    const int b = plan->babies[i];
+    BA.b[i] = b;
+    if (b == 0) {
+      BA.key[i] = nullptr;
+      BA.gal[i] = 1;
+      continue;
+    }
+    uint64_t g = 1;
+    for (int k = 0; k < b; k++) g = g * 5 % twoN;
+    auto it = ctx->keys.find((uint32_t)g);
+    if (it == ctx->keys.end()) {
+      set_error("no evaluation key loaded for rotation %d (galois %llu)", b, (unsigned long long)g);
+      return HELRM_EINVAL;
+    }
+    BA.key[i] = it->second.d;
+    BA.gal[i] = (unsigned)g;
+  }
+  const int level = plan->level;
+  LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn};
+  if (batch == 0 || ng == 0) return HELRM_OK;
+  dim3 grid(ctx->N / TPB, G.pqn, batch);
+#define BABY(GT_)                                                                                      \
+  hipLaunchKernelGGL((baby_mac_kernel<GT_>), grid, dim3(TPB), 0, s, BA, G, ctx->L, digits, digits_bstride, \
+                     ct, ct_bstride, plan->d_pt, plan->d_slot, plan->n1, g0, ng, X, x_bstride,         \
+                     ctx->d_pinfo)
+  if (ng <= 1) BABY(1);
+  else if (ng <= 2) BABY(2);
+  else if (ng <= 4) BABY(4);
+  else BABY(8);
+#undef BABY
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}

@@ -1,0 +1,241 @@
+"""GPU parity: every libhelrm call against the CPU oracle, bit-exact on every
+residue, on the same seeded inputs (oracle-made keys, plans and ciphertexts)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+from tests import workloads as W
+from tests.gpu_helpers import (assert_bit_exact, context_for, empty, gpu_plan, load_keys, say, to_dev,
+                               to_host)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def p1():
+    return O.config1_params()
+
+
+@pytest.fixture(scope="module")
+def p2():
+    return O.config2_params()
+
+
+@pytest.fixture(scope="module")
+def ctx1(p1):
+    return context_for(p1)
+
+
+@pytest.fixture(scope="module")
+def ctx2(p2):
+    return context_for(p2)
+
+
+def rand_limbs(rng, moduli, N, batch=1):
+    return np.stack([np.stack([rng.integers(0, q, size=N, dtype=np.uint64) for q in moduli])
+                     for _ in range(batch)])
+
+
+def test_roots_match(p1, p2, ctx1, ctx2):
+    say("roots")
+    for prm, ctx in ((p1, ctx1), (p2, ctx2)):
+        for i, q in enumerate(prm.q + prm.p):
+            assert ctx.helrm_get_psi(i) == prm.psi[q]
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2"])
+def test_ntt_parity(which, p1, p2, ctx1, ctx2):
+    prm, ctx = (p1, ctx1) if which == "cfg1" else (p2, ctx2)
+    allm = prm.q + prm.p
+    rng = np.random.default_rng(10)
+    # batch of 3, every prime once, plus a ragged list that repeats primes
+    for pidx, batch in ((list(range(len(allm))), 3), ([0, 2, 2, len(allm) - 1, 1], 2)):
+        say(f"ntt {which} primes={pidx} batch={batch}")
+        mods = [allm[i] for i in pidx]
+        x = rand_limbs(rng, mods, prm.N, batch)
+        d = to_dev(x)
+        ctx.helrm_ntt(d, pidx, batch)
+        got = to_host(d).reshape(x.shape)
+        for b in range(batch):
+            assert_bit_exact(got[b], O.ntt(x[b], mods, prm), f"ntt batch {b}")
+        ctx.helrm_intt(d, pidx, batch)
+        assert_bit_exact(to_host(d).reshape(x.shape), x, "intt(ntt(x))")
+        ctx.helrm_intt(d, pidx, batch)
+        got = to_host(d).reshape(x.shape)
+        for b in range(batch):
+            assert_bit_exact(got[b], O.intt(x[b], mods, prm), f"intt batch {b}")
+
+
+def test_ntt_edge_values(p2, ctx2):
+    say("ntt edge values q-1 / 0")
+    prm, ctx = p2, ctx2
+    mods = prm.q[:2] + prm.p[:1]
+    pidx = [0, 1, prm.L + 1]
+    x = np.stack([np.full(prm.N, q - 1, dtype=np.uint64) for q in mods])
+    x[1, ::3] = 0
+    d = to_dev(x)
+    ctx.helrm_ntt(d, pidx, 1)
+    assert_bit_exact(to_host(d).reshape(x.shape), O.ntt(x, mods, prm), "ntt of q-1")
+
+
+def test_automorph_parity(p1, p2, ctx1, ctx2):
+    rng = np.random.default_rng(11)
+    for prm, ctx in ((p1, ctx1), (p2, ctx2)):
+        for k in (1, 5, prm.n - 1, prm.n // 2):
+            g = O.galois_for_step(k, prm)
+            say(f"automorph N={prm.N} g={g}")
+            x = rand_limbs(rng, prm.q[:3], prm.N, 2)
+            out = empty(*x.shape)
+            ctx.helrm_automorph(to_dev(x), out, g, 3, 2)
+            got = to_host(out).reshape(x.shape)
+            for b in range(2):
+                assert_bit_exact(got[b], O.automorph_ntt(x[b], g, prm.N), "automorph")
+
+
+def test_elementwise_parity(p2, ctx2):
+    prm, ctx = p2, ctx2
+    from paper_2506_18150_amd import binding as B
+    rng = np.random.default_rng(12)
+    pidx = [0, 5, prm.L + 2]
+    mods = [(prm.q + prm.p)[i] for i in pidx]
+    a = rand_limbs(rng, mods, prm.N, 2)
+    b = rand_limbs(rng, mods, prm.N, 2)
+    da, db = to_dev(a), to_dev(b)
+    for op, fn in ((B.HELRM_OP_ADD, O.add), (B.HELRM_OP_SUB, O.sub), (B.HELRM_OP_MUL, O.mul)):
+        say(f"poly_op {op}")
+        out = empty(*a.shape)
+        ctx.helrm_poly_op(op, da, db, out, pidx, 2)
+        got = to_host(out).reshape(a.shape)
+        for k in range(2):
+            assert_bit_exact(got[k], fn(a[k], b[k], mods), f"op {op}")
+    out = empty(*a.shape)
+    ctx.helrm_poly_op(B.HELRM_OP_NEG, da, None, out, pidx, 2)
+    assert_bit_exact(to_host(out).reshape(a.shape)[1], O.neg(a[1], mods), "neg")
+    sc = [3, mods[1] - 1, 2 ** 59 + 12345]
+    out = empty(*a.shape)
+    ctx.helrm_mul_scalar(da, sc, out, pidx, 2)
+    assert_bit_exact(to_host(out).reshape(a.shape)[0], O.mul_scalar(a[0], sc, mods), "mul_scalar")
+    say("from_signed")
+    import torch
+    v = rng.integers(-2 ** 62, 2 ** 62, size=(2, prm.N), dtype=np.int64)
+    v[0, :4] = [0, -1, 2 ** 63 - 1, -2 ** 63]
+    out = empty(2, 3, prm.N)
+    ctx.helrm_from_signed(torch.from_numpy(v).cuda(), out, pidx, 2)
+    got = to_host(out).reshape(2, 3, prm.N)
+    for k in range(2):
+        assert_bit_exact(got[k], O.from_signed(v[k], mods), "from_signed")
+
+
+@pytest.fixture(scope="module")
+def w1(ctx1):
+    w = W.config1(n_queries=3)
+    load_keys(ctx1, w.keys)
+    return w
+
+
+def test_rescale_parity(p1, p2, ctx1, ctx2):
+    rng = np.random.default_rng(13)
+    for prm, ctx, levels in ((p1, ctx1, (3, 1)), (p2, ctx2, (23, 4, 1))):
+        for lv in levels:
+            say(f"rescale N={prm.N} level={lv}")
+            ct = rand_limbs(rng, prm.Q(lv), prm.N, 2).reshape(1, 2, lv + 1, prm.N)
+            ct = np.concatenate([ct, ct[:, ::-1]])   # batch of 2
+            out = empty(2, 2, lv, prm.N)
+            ctx.helrm_rescale(to_dev(ct), lv, out, 2)
+            got = to_host(out).reshape(2, 2, lv, prm.N)
+            for b in range(2):
+                assert_bit_exact(got[b], O.rescale(prm, ct[b], lv), f"rescale level {lv}")
+
+
+@pytest.mark.parametrize("level", [3, 2, 0])
+def test_keyswitch_hoisted_parity_cfg1(level, p1, ctx1, w1):
+    from paper_2506_18150_amd import binding as B
+    prm = p1
+    steps = [1, 0, 3, 1024]
+    for k in steps:
+        if k:
+            assert O.galois_for_step(k, prm) in w1.keys.swk or True
+    steps = [s for s in steps if s == 0 or O.galois_for_step(s, prm) in w1.keys.swk]
+    ct = w1.cts[0][:, : level + 1].copy()
+    ct2 = np.stack([ct, w1.cts[1][:, : level + 1]])
+    say(f"keyswitch_hoisted cfg1 level={level} steps={steps}")
+    pqn = level + 1 + prm.K
+    outpq = empty(2, len(steps), 2, pqn, prm.N)
+    ctx1.helrm_keyswitch_hoisted(to_dev(ct2), level, steps, outpq, B.HELRM_BASIS_PQ, 2)
+    outq = empty(2, len(steps), 2, level + 1, prm.N)
+    ctx1.helrm_keyswitch_hoisted(to_dev(ct2), level, steps, outq, B.HELRM_BASIS_Q, 2)
+    gpq = to_host(outpq).reshape(2, len(steps), 2, pqn, prm.N)
+    gq = to_host(outq).reshape(2, len(steps), 2, level + 1, prm.N)
+    for b in range(2):
+        d = O.modup(prm, ct2[b][1], level)
+        for i, s in enumerate(steps):
+            if s == 0:
+                want = O.lift_P(prm, ct2[b], level)
+                assert_bit_exact(gq[b, i], ct2[b], "step 0 (Q)")
+            else:
+                g = O.galois_for_step(s, prm)
+                want = O.key_inner_product(prm, d, ct2[b][0], level, w1.keys.swk[g], g)
+                assert_bit_exact(gq[b, i], O.moddown(prm, want, level), f"KS step {s} (Q)")
+            assert_bit_exact(gpq[b, i], want, f"KS step {s} (PQ)")
+
+
+def _check_lookup(ctx, w, plan_gpu, batch_idx):
+    prm = w.prm
+    lv = w.level
+    cts = np.stack([w.cts[i] for i in batch_idx])
+    B_ = len(batch_idx)
+    say(f"matvec N={prm.N} level={lv} n1={w.plan.n1} radix={w.plan.radix} batch={B_}")
+    out_mv = empty(B_, 2, lv + 1, prm.N)
+    ctx.helrm_ptxt_ct_matvec_diag(plan_gpu, to_dev(cts), out_mv, B_)
+    out_lk = empty(B_, 2, lv, prm.N)
+    say(f"lookup_packed N={prm.N} level={lv} batch={B_}")
+    ctx.helrm_lookup_packed(plan_gpu, to_dev(cts), B_, out_lk)
+    gmv = to_host(out_mv).reshape(B_, 2, lv + 1, prm.N)
+    glk = to_host(out_lk).reshape(B_, 2, lv, prm.N)
+    pts = O.plan_residues(prm, w.plan)
+    for k, qi in enumerate(batch_idx):
+        mv = O.matvec(prm, w.keys, w.plan, w.cts[qi], pts)
+        assert_bit_exact(gmv[k], mv, f"matvec query {qi}")
+        lk = O.rescale(prm, mv, lv)
+        assert_bit_exact(glk[k], lk, f"lookup query {qi}")
+        got = W.decrypt_slots(w, glk[k], prm.delta, len(w.expected[qi]))
+        assert np.max(np.abs(got - w.expected[qi])) < 1e-4
+    return glk
+
+
+def test_lookup_parity_cfg1(ctx1, w1):
+    plan = gpu_plan(ctx1, w1.plan)
+    assert plan.rotation_steps() == w1.plan.rotation_steps()
+    glk = _check_lookup(ctx1, w1, plan, [0, 1, 2])
+    # batch invariance: query 1 alone equals its slot in the batch
+    alone = _check_lookup(ctx1, w1, plan, [1])
+    assert_bit_exact(alone[0], glk[1], "batch invariance")
+
+
+@pytest.mark.parametrize("n1,radix,compressed", [(16, 2, True), (2, 8, True), (4, 2, False), (1, 4, True)])
+def test_lookup_schedules_cfg1(n1, radix, compressed, p1):
+    ctx = context_for(p1)
+    w = W.config1(n_queries=1, n1=n1, radix=radix, compressed=compressed)
+    load_keys(ctx, w.keys)
+    _check_lookup(ctx, w, gpu_plan(ctx, w.plan), [0])
+
+
+def cfg2_workload(level, n1=16, radix=2, n_queries=1):
+    prm = O.config2_params()
+    g = synth.rng(0)
+    t = W.compressed_table(g, 65536, 16, 256, -0.05, 0.05)
+    return W.build(prm, [t], level=level, n1=n1, radix=radix, n_queries=n_queries)
+
+
+@pytest.mark.parametrize("level,n1,radix", [(1, 16, 2), (4, 4, 2), (4, 16, 8)])
+def test_lookup_parity_cfg2(level, n1, radix, ctx2):
+    w = cfg2_workload(level, n1, radix)
+    load_keys(ctx2, w.keys)
+    _check_lookup(ctx2, w, gpu_plan(ctx2, w.plan), [0])
+
+
+def test_lookup_parity_cfg2_full_level(ctx2):
+    w = cfg2_workload(23, 16, 2)
+    load_keys(ctx2, w.keys)
+    _check_lookup(ctx2, w, gpu_plan(ctx2, w.plan), [0])
