@@ -213,6 +213,21 @@ int helrm_footprint(const helrm_ctx *ctx, const helrm_plan *plan, int batch, siz
  * without further allocation (call before capturing a graph). */
 int helrm_reserve(helrm_ctx *ctx, const helrm_plan *plan, int batch, void *stream);
 
+/* Kernel timing for measurement.  While enabled, every launch of the timed
+ * kernel classes records a pair of HIP events on its stream (enabling or
+ * disabling synchronises the device and clears earlier records).  Classes:
+ * "ntt_fwd_col", "ntt_fwd_blk", "ntt_inv_blk", "ntt_inv_col" (the two passes
+ * of each transform), "conv" (fast base conversion), "ks_acc" (key inner
+ * product + automorphism), "baby_mac" (fused baby steps and plaintext MAC),
+ * "sub_mul" (ModDown / rescale finish).  helrm_timing_read waits for the
+ * recorded launches of one class and returns their summed duration (ms), the
+ * launch count, and the algorithmic bytes and modular products those launches
+ * process (each kernel's minimum HBM traffic: every operand read once, every
+ * result written once). */
+int helrm_timing_enable(helrm_ctx *ctx, int enable);
+int helrm_timing_read(helrm_ctx *ctx, const char *kernel, double *ms, int64_t *launches, double *bytes,
+                      double *ops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,7 +50,7 @@ EXPORTS = [
     "helrm_ntt", "helrm_intt", "helrm_automorph", "helrm_poly_op", "helrm_mul_scalar",
     "helrm_from_signed", "helrm_keyswitch_hoisted", "helrm_rescale", "helrm_plan_create",
     "helrm_plan_destroy", "helrm_plan_rotation_steps", "helrm_ptxt_ct_matvec_diag",
-    "helrm_lookup_packed", "helrm_footprint", "helrm_reserve",
+    "helrm_lookup_packed", "helrm_footprint", "helrm_reserve", "helrm_timing_enable", "helrm_timing_read",
 ]
 
 _lib = None
@@ -84,6 +84,10 @@ def lib() -> ctypes.CDLL:
     L.helrm_lookup_packed.argtypes = [_vp, _vp, _vp, _c_int, _vp, _vp]
     L.helrm_footprint.argtypes = [_vp, _vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.helrm_reserve.argtypes = [_vp, _vp, _c_int, _vp]
+    L.helrm_timing_enable.argtypes = [_vp, _c_int]
+    L.helrm_timing_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
     for name in EXPORTS[1:]:
         getattr(L, name).restype = _c_int
     _lib = L
@@ -218,6 +222,16 @@ class Context:
 
     def helrm_reserve(self, plan: "Plan", batch: int, stream=None):
         _check(lib().helrm_reserve(self.h, plan.h, batch, _stream(stream)))
+
+    def helrm_timing_enable(self, enable: bool):
+        _check(lib().helrm_timing_enable(self.h, 1 if enable else 0))
+
+    def helrm_timing_read(self, kernel: str):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        by, ops = ctypes.c_double(), ctypes.c_double()
+        _check(lib().helrm_timing_read(self.h, kernel.encode(), ctypes.byref(ms), ctypes.byref(n),
+                                       ctypes.byref(by), ctypes.byref(ops)))
+        return {"ms": ms.value, "launches": int(n.value), "bytes": by.value, "ops": ops.value}
 
 
 class Plan:

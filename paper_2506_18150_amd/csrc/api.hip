@@ -37,6 +37,40 @@ extern "C" const char *helrm_last_error(void) { return g_last_error.c_str(); }
     return HELRM_ESTATE;                                       \
   }
 
+// ---------------------------------------------------------------- kernel timing
+
+hipEvent_t timing_event(helrm_ctx *ctx) {
+  std::lock_guard<std::mutex> lk(ctx->tmu);
+  if (!ctx->evpool.empty()) {
+    hipEvent_t e = ctx->evpool.back();
+    ctx->evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void timing_push(helrm_ctx *ctx, int k, hipEvent_t a, hipEvent_t b, double bytes, double ops) {
+  std::lock_guard<std::mutex> lk(ctx->tmu);
+  ctx->trecs.push_back(TimingRec{k, a, b, bytes, ops});
+}
+
+static const char *const kTimedNames[TK_COUNT] = {"ntt_fwd_col", "ntt_fwd_blk", "ntt_inv_blk", "ntt_inv_col",
+                                                  "conv",        "ks_acc",      "baby_mac",    "sub_mul"};
+
+static void timing_clear(helrm_ctx *ctx) {
+  std::vector<hipEvent_t> seen;
+  for (auto &r : ctx->trecs) {
+    seen.push_back(r.a);
+    seen.push_back(r.b);
+  }
+  std::sort(seen.begin(), seen.end());
+  seen.erase(std::unique(seen.begin(), seen.end()), seen.end());
+  for (auto e : seen) ctx->evpool.push_back(e);
+  ctx->trecs.clear();
+}
+
 // ---------------------------------------------------------------- host modular arithmetic
 
 namespace {
@@ -190,36 +224,35 @@ int do_modup(helrm_ctx *ctx, int level, const u64 *c1, int c1_bs, u64 *D, int d_
   LimbList a = ll_make(qn, c1_bs, qn);
   for (int i = 0; i < qn; i++) { a.src_off[i] = i; a.dst_off[i] = i; a.prime[i] = (unsigned char)i; }
   TRY(launch_ntt(ctx, c1, coef, a, batch, false, s));
-  // 2. base conversion of every digit to the other primes of PQ_level
+  // 2. base conversion of every digit to the other primes of PQ_level; the
+  //    digit's own limbs are c1's limbs (copied in evaluation form)
   LimbList nt = ll_make(0, d_bs, d_bs);
+  ConvSpec specs[HELRM_MAX_CONV_JOBS];
+  CHECK_ARG(beta <= HELRM_MAX_CONV_JOBS, "modup: at most %d digits", HELRM_MAX_CONV_JOBS);
   for (int j = 0; j < beta; j++) {
-    const ConvTable &t = ctx->modup_tabs[level][j];
-    int doff[HELRM_MAX_PRIMES];
-    int lo = ctx->digit_lo(j), hi = ctx->digit_hi(j, level), k = 0;
+    ConvSpec &sp = specs[j];
+    sp.t = &ctx->modup_tabs[level][j];
+    const int lo = ctx->digit_lo(j), hi = ctx->digit_hi(j, level);
+    sp.src_off0 = lo;
+    int k = 0;
     for (int r = 0; r < pqn; r++) {
       if (r >= lo && r < hi) continue;
-      doff[k] = j * pqn + r;
+      sp.dst_off[k++] = j * pqn + r;
       if (nt.n >= HELRM_MAX_LIMBS) { set_error("modup: too many limbs"); return HELRM_EINVAL; }
       nt.src_off[nt.n] = j * pqn + r;
       nt.dst_off[nt.n] = j * pqn + r;
       nt.prime[nt.n] = (unsigned char)ctx->pq_prime(r, level);
       nt.n++;
-      k++;
     }
-    TRY(launch_conv(ctx, t, coef, lo, qn, D, doff, d_bs, batch, s));
+    sp.ncopy = hi - lo;
+    for (int i = lo; i < hi; i++) {
+      sp.copy_src_off[i - lo] = i;
+      sp.copy_dst_off[i - lo] = j * pqn + i;
+    }
   }
+  TRY(launch_conv(ctx, specs, beta, coef, qn, c1, c1_bs, D, d_bs, batch, s));
   // 3. back to evaluation form
   TRY(launch_ntt(ctx, D, D, nt, batch, true, s));
-  // 4. each digit's own limbs are c1's limbs
-  LimbList cp = ll_make(0, c1_bs, d_bs);
-  for (int j = 0; j < beta; j++)
-    for (int i = ctx->digit_lo(j); i < ctx->digit_hi(j, level); i++) {
-      cp.src_off[cp.n] = i;
-      cp.dst_off[cp.n] = j * pqn + i;
-      cp.prime[cp.n] = (unsigned char)i;
-      cp.n++;
-    }
-  TRY(launch_copy_limbs(c1, D, cp, batch, N, s));
   return HELRM_OK;
 }
 
@@ -238,23 +271,26 @@ int do_moddown(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *out, int 
     }
   TRY(launch_ntt(ctx, X, mdP, a, batch, false, s));
   // 2. convert P -> Q_level (both polynomials as a batch of 2*batch)
-  int doff[HELRM_MAX_PRIMES];
-  for (int i = 0; i < qn; i++) doff[i] = i;
-  TRY(launch_conv(ctx, ctx->moddown_tabs[level], mdP, 0, K, mdT, doff, qn, 2 * batch, s));
-  // 3. evaluation form
+  ConvSpec sp;
+  sp.t = &ctx->moddown_tabs[level];
+  sp.src_off0 = 0;
+  for (int i = 0; i < qn; i++) sp.dst_off[i] = i;
+  sp.ncopy = 0;
+  TRY(launch_conv(ctx, &sp, 1, mdP, K, nullptr, 0, mdT, qn, 2 * batch, s));
+  // 3. evaluation form, fused with 4. out_i = (X_i - t_i) P^-1
   LimbList b = ll_make(qn, qn, qn);
   for (int i = 0; i < qn; i++) { b.src_off[i] = i; b.dst_off[i] = i; b.prime[i] = (unsigned char)i; }
-  TRY(launch_ntt(ctx, mdT, mdT, b, 2 * batch, true, s));
-  // 4. out_i = (X_i - t_i) P^-1
-  LimbList c = ll_make(2 * qn, x_bs, out_bs);
-  for (int p = 0; p < 2; p++)
-    for (int i = 0; i < qn; i++) {
-      c.src_off[p * qn + i] = p * pqn + i;
-      c.dst_off[p * qn + i] = p * qn + i;
-      c.prime[p * qn + i] = (unsigned char)i;
-    }
-  // mdT is [2 qn] per element, addressed with dst offsets p*qn+i
-  TRY(launch_sub_mul(ctx, X, mdT, 2 * qn, out, c, ctx->moddown_pinv[level], batch, s));
+  NttEpi e;
+  e.a = X;
+  e.out = out;
+  e.c = ctx->moddown_pinv[level];
+  e.inner = 2;
+  e.a_bs = x_bs;
+  e.a_cs = pqn;
+  e.out_bs = out_bs;
+  e.out_cs = qn;
+  for (int i = 0; i < qn; i++) { e.a_off[i] = i; e.out_off[i] = i; }
+  TRY(launch_ntt_epi(ctx, mdT, mdT, b, 2 * batch, true, s, e));
   return HELRM_OK;
 }
 
@@ -271,15 +307,18 @@ int do_rescale(helrm_ctx *ctx, int level, const u64 *in, int in_bs, u64 *out, in
   TRY(launch_rescale_spread(ctx, top, V, level, batch, s));
   LimbList b = ll_make(level, level, level);
   for (int i = 0; i < level; i++) { b.src_off[i] = i; b.dst_off[i] = i; b.prime[i] = (unsigned char)i; }
-  TRY(launch_ntt(ctx, V, V, b, 2 * batch, true, s));
-  LimbList c = ll_make(2 * level, in_bs, out_bs);
-  for (int p = 0; p < 2; p++)
-    for (int i = 0; i < level; i++) {
-      c.src_off[p * level + i] = p * qn + i;
-      c.dst_off[p * level + i] = p * level + i;
-      c.prime[p * level + i] = (unsigned char)i;
-    }
-  TRY(launch_sub_mul(ctx, in, V, 2 * level, out, c, ctx->rescale_qinv[level], batch, s));
+  // evaluation form fused with out_i = (c_i - v_i) q_l^-1
+  NttEpi e;
+  e.a = in;
+  e.out = out;
+  e.c = ctx->rescale_qinv[level];
+  e.inner = 2;
+  e.a_bs = in_bs;
+  e.a_cs = qn;
+  e.out_bs = out_bs;
+  e.out_cs = level;
+  for (int i = 0; i < level; i++) { e.a_off[i] = i; e.out_off[i] = i; }
+  TRY(launch_ntt_epi(ctx, V, V, b, 2 * batch, true, s, e));
   return HELRM_OK;
 }
 
@@ -655,6 +694,8 @@ extern "C" int helrm_destroy(helrm_ctx *c) {
   API_GUARD_BEGIN
   if (!c) return HELRM_OK;
   (void)hipDeviceSynchronize();
+  timing_clear(c);
+  for (auto e : c->evpool) (void)hipEventDestroy(e);
   for (auto &kv : c->keys) (void)hipFree(kv.second.d);
   for (auto &kv : c->ws)
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
@@ -1023,5 +1064,43 @@ extern "C" int helrm_reserve(helrm_ctx *c, const helrm_plan *p, int batch, void 
   CHECK_ARG(c && p && batch >= 0, "bad argument");
   char *base;
   return ensure_ws(c, as_stream(stream), matvec_ws_bytes(c, p, batch, true), &base);
+  API_GUARD_END
+}
+
+extern "C" int helrm_timing_enable(helrm_ctx *c, int enable) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  HIP_TRY(hipDeviceSynchronize());
+  std::lock_guard<std::mutex> lk(c->tmu);
+  timing_clear(c);
+  c->timing = enable != 0;
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_timing_read(helrm_ctx *c, const char *kernel, double *ms, int64_t *launches, double *bytes,
+                                 double *ops) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && kernel && ms && launches && bytes && ops, "NULL argument");
+  int k = -1;
+  for (int i = 0; i < TK_COUNT; i++)
+    if (strcmp(kernel, kTimedNames[i]) == 0) k = i;
+  CHECK_ARG(k >= 0, "unknown kernel class '%s'", kernel);
+  std::lock_guard<std::mutex> lk(c->tmu);
+  *ms = 0;
+  *launches = 0;
+  *bytes = 0;
+  *ops = 0;
+  for (auto &r : c->trecs) {
+    if (r.k != k) continue;
+    HIP_TRY(hipEventSynchronize(r.b));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+    *ms += t;
+    *launches += 1;
+    *bytes += r.bytes;
+    *ops += r.ops;
+  }
+  return HELRM_OK;
   API_GUARD_END
 }

@@ -21,6 +21,7 @@ typedef unsigned __int128 u128;
 #define HELRM_MAX_TERMS 16    // key-switch terms summed by one accumulate launch
 #define HELRM_MAX_BABY 64     // baby steps per fused MAC launch
 #define HELRM_MAX_GTILE 8     // giant outputs accumulated per fused MAC launch
+#define HELRM_MAX_CONV_JOBS 4 // base conversions per launch
 
 // ---------------------------------------------------------------- errors
 
@@ -172,6 +173,25 @@ struct Workspace {
   size_t bytes = 0;
 };
 
+// Kernel classes that can be timed with HIP events (helrm_timing_*).
+enum TimedKernel {
+  TK_NTT_FWD_COL = 0,
+  TK_NTT_FWD_BLK,
+  TK_NTT_INV_BLK,
+  TK_NTT_INV_COL,
+  TK_CONV,
+  TK_KS_ACC,
+  TK_BABY_MAC,
+  TK_SUB_MUL,
+  TK_COUNT
+};
+
+struct TimingRec {
+  int k;
+  hipEvent_t a, b;
+  double bytes, ops;   // algorithmic bytes moved and modular products of this launch
+};
+
 struct helrm_ctx {
   int logn, N, L, K, alpha, dnum, nprimes;
   int device;
@@ -189,6 +209,10 @@ struct helrm_ctx {
   std::map<uint32_t, KeyEntry> keys;
   std::mutex ws_mu;
   std::map<hipStream_t, Workspace> ws;
+  bool timing = false;
+  std::mutex tmu;
+  std::vector<TimingRec> trecs;
+  std::vector<hipEvent_t> evpool;
 
   int n_digits(int level) const { return (level + 1 + alpha - 1) / alpha; }
   int digit_lo(int j) const { return j * alpha; }
@@ -215,11 +239,55 @@ struct helrm_plan {
   size_t pt_limb_stride;                 // limbs per stored diagonal (= level+1+K)
 };
 
+// ---------------------------------------------------------------- timing
+
+hipEvent_t timing_event(helrm_ctx *ctx);
+void timing_push(helrm_ctx *ctx, int k, hipEvent_t a, hipEvent_t b, double bytes, double ops);
+
+// Records a HIP event pair around one launch when timing is enabled.
+struct KTimer {
+  helrm_ctx *c;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  KTimer(helrm_ctx *ctx, hipStream_t st) : c(ctx), s(st) {
+    if (c->timing) {
+      a = timing_event(c);
+      (void)hipEventRecord(a, s);
+    }
+  }
+  // close the current interval as kernel class k and open the next one
+  void lap(int k, double bytes, double ops) {
+    if (!a) return;
+    hipEvent_t b = timing_event(c);
+    (void)hipEventRecord(b, s);
+    timing_push(c, k, a, b, bytes, ops);
+    a = b;
+  }
+};
+
 // ---------------------------------------------------------------- launchers
+
+#define HELRM_MAX_EPI 64
+
+// Fused finish of a forward NTT: instead of storing y = NTT(x), store
+// out = (a - y) * c[i] for list entry i.  The transform's batch index splits
+// into (outer, inner) = (bat / inner, bat % inner); a and out limbs live at
+// outer * bs + inner * cs + off[i].
+struct NttEpi {
+  const u64 *a = nullptr;
+  u64 *out = nullptr;
+  const TW *c = nullptr;
+  int inner = 1;
+  int a_bs = 0, a_cs = 0, out_bs = 0, out_cs = 0;
+  int a_off[HELRM_MAX_EPI] = {};
+  int out_off[HELRM_MAX_EPI] = {};
+};
 
 // NTT of the limbs in `ll` (src -> dst, may be in place).
 int launch_ntt(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int batch, bool forward,
                hipStream_t s);
+int launch_ntt_epi(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int batch, bool forward,
+                   hipStream_t s, const NttEpi &epi);
 
 int launch_automorph(helrm_ctx *ctx, const u64 *in, u64 *out, uint32_t galois, int n_limbs, int batch,
                      hipStream_t s);
@@ -232,9 +300,19 @@ int launch_from_signed(helrm_ctx *ctx, const int64_t *in, u64 *out, const LimbLi
 int launch_to_mont(helrm_ctx *ctx, u64 *data, const LimbList &ll, int batch, hipStream_t s);
 int launch_copy_limbs(const u64 *src, u64 *dst, const LimbList &ll, int batch, int N, hipStream_t s);
 
-// Fast base conversion (coefficient form): dst limbs = conv(src limbs).
-int launch_conv(helrm_ctx *ctx, const ConvTable &t, const u64 *src, int src_off0, int src_bstride,
-                u64 *dst, const int *dst_off, int dst_bstride, int batch, hipStream_t s);
+// One fast base conversion (coefficient form) of a launch: inputs are the
+// consecutive limbs src_off0.. of src, outputs go to dst_off[r]; ncopy limbs
+// are copied unchanged from copy_src (evaluation-form own limbs of a digit).
+struct ConvSpec {
+  const ConvTable *t;
+  int src_off0;
+  int dst_off[HELRM_MAX_PRIMES];
+  int ncopy;
+  int copy_src_off[16];
+  int copy_dst_off[16];
+};
+int launch_conv(helrm_ctx *ctx, const ConvSpec *specs, int nspecs, const u64 *src, int src_bstride,
+                const u64 *copy_src, int copy_bstride, u64 *dst, int dst_bstride, int batch, hipStream_t s);
 
 // out[l] = (a[l] - b[l]) * consts[l]  (consts: Shoup pairs, one per list entry)
 // b is addressed with the dst offsets of ll and batch stride b_bstride.

@@ -4,6 +4,10 @@
 // run of consecutive words (the automorphism gathers inside aligned blocks:
 // X -> X^g maps each aligned block of 2^k evaluation points onto an aligned
 // block of 2^k points).
+#include <string.h>
+
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -109,34 +113,64 @@ __global__ __launch_bounds__(TPB) void sub_mul_kernel(const u64 *a, const u64 *b
 
 // ---------------------------------------------------------------- base conversion
 
-struct DstOff {
-  int off[HELRM_MAX_PRIMES];
+// One base conversion job of a launch: the input limbs are consecutive
+// (src_off0 + i), the outputs go to arbitrary limb offsets; optionally the
+// job also copies `ncopy` limbs unchanged (ModUp: each digit's own limbs,
+// already in evaluation form, from copy_src).
+struct ConvJob {
+  ConvTable t;
+  int src_off0;
+  int dst_off[HELRM_MAX_PRIMES];
+  int ncopy;
+  int copy_src_off[16];
+  int copy_dst_off[16];
 };
 
+struct ConvJobs {
+  int njobs;
+  int nchunks;       // output chunks per job (the last one also copies)
+  ConvJob j[HELRM_MAX_CONV_JOBS];
+};
+
+constexpr int CONV_TPB = 256;
+
 // y_i = x_i (Qin/q_i)^-1 mod q_i;  out_r = sum_i y_i [Qin/q_i]_r mod r.
-__global__ __launch_bounds__(TPB) void conv_kernel(ConvTable t, const u64 *src, int src_off0, int src_bstride,
-                                                   u64 *dst, DstOff doff, int dst_bstride,
-                                                   const PrimeInfo *pinfo, int N) {
-  const int x = blockIdx.x * TPB + threadIdx.x;
-  const int bat = blockIdx.y;
-  u64 y[16];
-#pragma unroll
-  for (int i = 0; i < 16; i++) {
-    if (i < t.nin) {
-      const u64 q = pinfo[t.in_prime[i]].q;
-      const u64 v = src[limb_ptr(bat, src_bstride, src_off0 + i, N) + x];
-      y[i] = shoup(v, t.hat_inv[i].w, t.hat_inv[i].wp, q);
-    }
+// One thread per coefficient computes every output, so each input residue
+// is read once; the [NIN][nout] constant matrix is staged in LDS and read as
+// broadcasts.  Grid: (N/CONV_TPB, 1, batch * njobs).
+template <int NIN>
+__global__ __launch_bounds__(CONV_TPB) void conv_kernel(const ConvJobs J, const u64 *src, int src_bstride,
+                                                        const u64 *copy_src, int copy_bstride, u64 *dst,
+                                                        int dst_bstride, const PrimeInfo *pinfo, int N) {
+  __shared__ u64 cm[NIN * HELRM_MAX_PRIMES];
+  __shared__ u64 oq[HELRM_MAX_PRIMES], oqn[HELRM_MAX_PRIMES];
+  const int x = blockIdx.x * CONV_TPB + threadIdx.x;
+  const int job = blockIdx.z % J.njobs, bat = blockIdx.z / J.njobs;
+  const ConvJob &jb = J.j[job];
+  const int nout = jb.t.nout;
+  for (int k = threadIdx.x; k < NIN * nout; k += CONV_TPB) cm[k] = jb.t.hat_mont[k];
+  for (int k = threadIdx.x; k < nout; k += CONV_TPB) {
+    oq[k] = pinfo[jb.t.out_prime[k]].q;
+    oqn[k] = pinfo[jb.t.out_prime[k]].qn;
   }
-  for (int r = 0; r < t.nout; r++) {
-    const PrimeInfo pr = pinfo[t.out_prime[r]];
+  u64 y[NIN];
+#pragma unroll
+  for (int i = 0; i < NIN; i++) {
+    const u64 q = pinfo[jb.t.in_prime[i]].q;
+    const u64 v = src[limb_ptr(bat, src_bstride, jb.src_off0 + i, N) + x];
+    y[i] = shoup(v, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, q);
+  }
+  __syncthreads();
+  for (int r = 0; r < nout; r++) {
     Acc a;
     acc_zero(a);
 #pragma unroll
-    for (int i = 0; i < 16; i++)
-      if (i < t.nin) acc_mac(a, y[i], t.hat_mont[i * t.nout + r]);
-    dst[limb_ptr(bat, dst_bstride, doff.off[r], N) + x] = redc_acc(a, pr.q, pr.qn);
+    for (int i = 0; i < NIN; i++) acc_mac(a, y[i], cm[i * nout + r]);
+    dst[limb_ptr(bat, dst_bstride, jb.dst_off[r], N) + x] = redc_acc(a, oq[r], oqn[r]);
   }
+  for (int c = 0; c < jb.ncopy; c++)
+    dst[limb_ptr(bat, dst_bstride, jb.copy_dst_off[c], N) + x] =
+        copy_src[limb_ptr(bat, copy_bstride, jb.copy_src_off[c], N) + x];
 }
 
 // Rescale middle step: t = (c + h) mod q_l from the top limb (coefficient
@@ -370,22 +404,79 @@ int launch_automorph(helrm_ctx *ctx, const u64 *in, u64 *out, uint32_t galois, i
   return HELRM_OK;
 }
 
-int launch_conv(helrm_ctx *ctx, const ConvTable &t, const u64 *src, int src_off0, int src_bstride,
-                u64 *dst, const int *dst_off, int dst_bstride, int batch, hipStream_t s) {
-  DstOff d;
-  for (int r = 0; r < t.nout; r++) d.off[r] = dst_off[r];
-  if (batch == 0) return HELRM_OK;
-  hipLaunchKernelGGL(conv_kernel, ew_grid(ctx, batch), dim3(TPB), 0, s, t, src, src_off0, src_bstride, dst,
-                     d, dst_bstride, ctx->d_pinfo, ctx->N);
-  HIP_TRY(hipGetLastError());
+int launch_conv(helrm_ctx *ctx, const ConvSpec *specs, int nspecs, const u64 *src, int src_bstride,
+                const u64 *copy_src, int copy_bstride, u64 *dst, int dst_bstride, int batch, hipStream_t s) {
+  if (nspecs > HELRM_MAX_CONV_JOBS) {
+    set_error("conv: at most %d jobs per launch", HELRM_MAX_CONV_JOBS);
+    return HELRM_EINVAL;
+  }
+  if (batch == 0 || nspecs == 0) return HELRM_OK;
+  // jobs of one launch share the input count; split by it
+  int done = 0;
+  while (done < nspecs) {
+    const int nin = specs[done].t->nin;
+    int end = done;
+    while (end < nspecs && specs[end].t->nin == nin) end++;
+    ConvJobs J;
+    memset(&J, 0, sizeof J);
+    J.njobs = end - done;
+    J.nchunks = 1;
+    double words = 0, macs = 0;
+    for (int k = done; k < end; k++) {
+      const ConvSpec &sp = specs[k];
+      ConvJob &jb = J.j[k - done];
+      jb.t = *sp.t;
+      jb.src_off0 = sp.src_off0;
+      for (int r = 0; r < sp.t->nout; r++) jb.dst_off[r] = sp.dst_off[r];
+      jb.ncopy = sp.ncopy;
+      for (int c = 0; c < sp.ncopy; c++) {
+        jb.copy_src_off[c] = sp.copy_src_off[c];
+        jb.copy_dst_off[c] = sp.copy_dst_off[c];
+      }
+      words += sp.t->nin + sp.t->nout + 2.0 * sp.ncopy;
+      macs += (double)sp.t->nin * sp.t->nout;
+    }
+    dim3 grid(ctx->N / CONV_TPB, 1, batch * J.njobs);
+    KTimer tm(ctx, s);
+#define CONV(NIN_)                                                                                    \
+  hipLaunchKernelGGL((conv_kernel<NIN_>), grid, dim3(CONV_TPB), 0, s, J, src, src_bstride, copy_src,  \
+                     copy_bstride, dst, dst_bstride, ctx->d_pinfo, ctx->N)
+    switch (nin) {
+      case 1: CONV(1); break;
+      case 2: CONV(2); break;
+      case 3: CONV(3); break;
+      case 4: CONV(4); break;
+      case 5: CONV(5); break;
+      case 6: CONV(6); break;
+      case 7: CONV(7); break;
+      case 8: CONV(8); break;
+      case 9: CONV(9); break;
+      case 10: CONV(10); break;
+      case 11: CONV(11); break;
+      case 12: CONV(12); break;
+      case 13: CONV(13); break;
+      case 14: CONV(14); break;
+      case 15: CONV(15); break;
+      case 16: CONV(16); break;
+      default:
+        set_error("conv: %d inputs unsupported", nin);
+        return HELRM_EINVAL;
+    }
+#undef CONV
+    tm.lap(TK_CONV, words * 8.0 * ctx->N * batch, macs * ctx->N * batch);
+    HIP_TRY(hipGetLastError());
+    done = end;
+  }
   return HELRM_OK;
 }
 
 int launch_sub_mul(helrm_ctx *ctx, const u64 *a, const u64 *b, int b_bstride, u64 *out,
                    const LimbList &ll, const TW *consts, int batch, hipStream_t s) {
   if (ll.n * batch == 0) return HELRM_OK;
+  KTimer tm(ctx, s);
   hipLaunchKernelGGL(sub_mul_kernel, ew_grid(ctx, ll.n * batch), dim3(TPB), 0, s, a, b, out, ll, consts,
                      ctx->d_pinfo, ctx->N, b_bstride);
+  tm.lap(TK_SUB_MUL, 24.0 * ctx->N * ll.n * batch, (double)ctx->N * ll.n * batch);
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
 }
@@ -415,8 +506,14 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
   }
   LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn};
   if (batch == 0) return HELRM_OK;
+  // per coefficient of a Q limb: terms * 3 beta words (digit, key b, key a) + terms c0 words
+  // + 2 base words + 2 output words; special limbs: no c0 / base words.
+  const double qn = level + 1, K = ctx->K, nt = n_terms, beta = G.beta;
+  const double wq = nt * 3 * beta + nt + (base ? 2 : 0) + 2, wp = nt * 3 * beta + 2;
+  KTimer tm(ctx, s);
   hipLaunchKernelGGL(ks_acc_kernel, dim3(ctx->N / TPB, G.pqn, batch), dim3(TPB), 0, s, T, G, ctx->L,
                      digits_bstride, c0_bstride, base, base_bstride, out, out_bstride, ctx->d_pinfo);
+  tm.lap(TK_KS_ACC, 8.0 * ctx->N * batch * (qn * wq + K * wp), 2.0 * nt * beta * ctx->N * batch * (qn + K));
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
 }
@@ -453,6 +550,16 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn};
   if (batch == 0 || ng == 0) return HELRM_OK;
   dim3 grid(ctx->N / TPB, G.pqn, batch);
+  // per coefficient: rotated babies read beta digits + 2 beta key words (+ c0 on Q limbs),
+  // b = 0 reads c0, c1 (Q limbs); each present diagonal one plaintext word; 2 ng outputs.
+  double npt = 0;
+  for (int gi = 0; gi < ng; gi++)
+    for (int b : plan->babies)
+      if (plan->slot[(size_t)(g0 + gi) * plan->n1 + b] >= 0) npt++;
+  const double nrot = BA.nb - (plan->babies[0] == 0 ? 1 : 0), has0 = plan->babies[0] == 0 ? 1 : 0;
+  const double qn = level + 1, K = ctx->K, beta = G.beta;
+  const double wq = nrot * (3 * beta + 1) + 2 * has0 + npt + 2 * ng, wp = nrot * 3 * beta + npt + 2 * ng;
+  KTimer tm(ctx, s);
 #define BABY(GT_)                                                                                      \
   hipLaunchKernelGGL((baby_mac_kernel<GT_>), grid, dim3(TPB), 0, s, BA, G, ctx->L, digits, digits_bstride, \
                      ct, ct_bstride, plan->d_pt, plan->d_slot, plan->n1, g0, ng, X, x_bstride,         \
@@ -462,6 +569,8 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   else if (ng <= 4) BABY(4);
   else BABY(8);
 #undef BABY
+  tm.lap(TK_BABY_MAC, 8.0 * ctx->N * batch * (qn * wq + K * wp),
+         (2.0 * nrot * beta + 2.0 * npt) * ctx->N * batch * (qn + K));
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
 }

@@ -8,7 +8,7 @@
 // A limb of N = R*R points (R = E*E, E = 2^H) is transformed in two passes:
 //   * "column" pass: the R sub-transforms {c + R r : r < R} (stride R),
 //   * "block"  pass: the R contiguous blocks {R b + s : s < R}.
-// Each workgroup owns W = 256/E sub-transforms; each thread holds E residues
+// Each workgroup owns W sub-transforms; each thread holds E residues
 // in registers and runs H butterfly stages on them, the workgroup exchanges
 // the residues through LDS (swizzled against bank conflicts) and the thread
 // runs the other H stages.  Global loads and stores are coalesced: in the
@@ -35,32 +35,34 @@ __device__ __forceinline__ void gs_bfly(u64 &x, u64 &y, const TW &t, u64 q, u64 
   y = shoup_lazy(D, t.w, t.wp, q);
 }
 
-template <int H>
+// Workgroup shape of one pass.  The column pass keeps WC consecutive columns
+// per workgroup (WC words per row contiguous in HBM); the block pass keeps WB
+// blocks.  Small workgroups let a launch of a few limbs fill 256 CUs.
+template <int H, bool COLS>
 struct Shape {
-  static constexpr int E = 1 << H;       // residues per thread
-  static constexpr int R = E * E;        // sub-transform length
-  static constexpr int N = R * R;        // ring degree
-  static constexpr int W = 256 / E;      // sub-transforms per workgroup
-  static constexpr int WPL = R / W;      // workgroups per limb
-  static constexpr int PAD = 16;
-  static constexpr int LDS_BLK = W * (R + PAD);
-  static constexpr int LDS_COL = R * W + E * PAD;
-  static constexpr int LDS = LDS_BLK > LDS_COL ? LDS_BLK : LDS_COL;
+  static constexpr int E = 1 << H;                    // residues per thread
+  static constexpr int R = E * E;                     // sub-transform length
+  static constexpr int N = R * R;                     // ring degree
+  static constexpr int W = COLS ? 16 : 8;             // sub-transforms per workgroup
+  static constexpr int T = W * E;                     // threads per workgroup
+  static constexpr int WPL = R / W;                   // workgroups per limb
+  // column pass: row stride E*W + W keeps the lane groups of a wave on
+  // distinct bank halves; block pass: stride R + 16 plus an XOR swizzle.
+  static constexpr int LDS = COLS ? (R * W + E * W) : (W * (R + 16));
 };
 
 // LDS index of element s of sub-transform w (block pass): XOR-swizzle the
 // high H bits into the low H bits so both access patterns spread over banks.
 template <int H>
 __device__ __forceinline__ int blk_idx(int w, int s) {
-  using S = Shape<H>;
-  return w * (S::R + S::PAD) + (s ^ ((s >> H) & (S::E - 1)));
+  constexpr int E = 1 << H, R = E * E;
+  return w * (R + 16) + (s ^ ((s >> H) & (E - 1)));
 }
 
-// LDS index of element r of column w (column pass).
-template <int H>
+// LDS index of element r of column w (column pass, W columns per workgroup).
+template <int H, int W>
 __device__ __forceinline__ int col_idx(int w, int r) {
-  using S = Shape<H>;
-  return r * S::W + w + (r >> H) * S::PAD;
+  return r * W + w + (r >> H) * W;
 }
 
 // Forward stages on x[] in the "A" layout (element u + E k): global stage
@@ -135,10 +137,11 @@ __device__ __forceinline__ void inv_phase_a(u64 (&x)[1 << H], const TW *tw, int 
 // second (in place, final reduction).  INV: block pass first, column pass
 // second (in place, times N^-1).
 template <int H, bool FWD, bool COLS>
-__global__ __launch_bounds__(256) void ntt_pass_kernel(const u64 *src, u64 *dst, LimbList ll,
-                                                       const TW *__restrict__ twtab,
-                                                       const PrimeInfo *__restrict__ pinfo) {
-  using S = Shape<H>;
+__global__ __launch_bounds__((Shape<H, COLS>::T)) void ntt_pass_kernel(const u64 *src, u64 *dst, LimbList ll,
+                                                                     const TW *__restrict__ twtab,
+                                                                     const PrimeInfo *__restrict__ pinfo,
+                                                                     const NttEpi epi) {
+  using S = Shape<H, COLS>;
   constexpr int E = S::E, R = S::R, N = S::N, W = S::W, WPL = S::WPL;
   __shared__ u64 lds[S::LDS];
 
@@ -163,10 +166,10 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(const u64 *src, u64 *dst,
       for (int k = 0; k < E; k++) x[k] = in[c + R * (u + E * k)];
       fwd_phase_a<H>(x, tw, 1, q);
 #pragma unroll
-      for (int k = 0; k < E; k++) lds[col_idx<H>(w, u + E * k)] = x[k];
+      for (int k = 0; k < E; k++) lds[col_idx<H, W>(w, u + E * k)] = x[k];
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < E; k++) x[k] = lds[col_idx<H>(w, E * u + k)];
+      for (int k = 0; k < E; k++) x[k] = lds[col_idx<H, W>(w, E * u + k)];
       fwd_phase_b<H>(x, tw, 1, u, q);
 #pragma unroll
       for (int k = 0; k < E; k++) out[c + R * (E * u + k)] = x[k];
@@ -176,10 +179,10 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(const u64 *src, u64 *dst,
       for (int k = 0; k < E; k++) x[k] = in[c + R * (E * u + k)];
       inv_phase_b<H>(x, tw, 1, u, q);
 #pragma unroll
-      for (int k = 0; k < E; k++) lds[col_idx<H>(w, E * u + k)] = x[k];
+      for (int k = 0; k < E; k++) lds[col_idx<H, W>(w, E * u + k)] = x[k];
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < E; k++) x[k] = lds[col_idx<H>(w, u + E * k)];
+      for (int k = 0; k < E; k++) x[k] = lds[col_idx<H, W>(w, u + E * k)];
       inv_phase_a<H>(x, tw, 1, q);
       const u64 ni = pinfo[p].ninv, nip = pinfo[p].ninv_p;
 #pragma unroll
@@ -206,12 +209,29 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(const u64 *src, u64 *dst,
       for (int k = 0; k < E; k++) lds[blk_idx<H>(w, E * u + k)] = x[k];
       __syncthreads();
       const u64 q2 = 2 * q;
+      if (epi.a) {
+        // fused finish: out = (a - NTT(x)) * c  (ModDown: c = P^-1, rescale: c = q_l^-1)
+        const int bo = bat / epi.inner, bi = bat % epi.inner;
+        const u64 *ea = epi.a + ((size_t)bo * epi.a_bs + (size_t)bi * epi.a_cs + epi.a_off[li]) * (size_t)N +
+                        (size_t)R * b;
+        u64 *eo = epi.out + ((size_t)bo * epi.out_bs + (size_t)bi * epi.out_cs + epi.out_off[li]) * (size_t)N +
+                  (size_t)R * b;
+        const TW c = epi.c[li];
 #pragma unroll
-      for (int k = 0; k < E; k++) {
-        u64 v = lds[blk_idx<H>(w, u + E * k)];
-        v = v >= q2 ? v - q2 : v;
-        v = v >= q ? v - q : v;
-        ob[u + E * k] = v;
+        for (int k = 0; k < E; k++) {
+          u64 v = lds[blk_idx<H>(w, u + E * k)];
+          v = v >= q2 ? v - q2 : v;
+          v = v >= q ? v - q : v;
+          eo[u + E * k] = shoup(sub_mod(ea[u + E * k], v, q), c.w, c.wp, q);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < E; k++) {
+          u64 v = lds[blk_idx<H>(w, u + E * k)];
+          v = v >= q2 ? v - q2 : v;
+          v = v >= q ? v - q : v;
+          ob[u + E * k] = v;
+        }
       }
     } else {
 #pragma unroll
@@ -235,23 +255,33 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(const u64 *src, u64 *dst,
 
 template <int H>
 int launch_ntt_h(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int batch, bool forward,
-                 hipStream_t s) {
-  using S = Shape<H>;
+                 hipStream_t s, const NttEpi &epi) {
+  using S = Shape<H, true>;
+  using SC = Shape<H, true>;
+  using SB = Shape<H, false>;
   LimbList second = ll;
   for (int i = 0; i < ll.n; i++) second.src_off[i] = ll.dst_off[i];
   second.src_bstride = ll.dst_bstride;
-  const int grid = ll.n * batch * S::WPL;
-  if (grid == 0) return HELRM_OK;
+  const int gc = ll.n * batch * SC::WPL, gb = ll.n * batch * SB::WPL;
+  if (gc == 0) return HELRM_OK;
+  // per pass and limb: N words read and written, (N/2) log2(R) butterflies
+  const double limbs = (double)ll.n * batch;
+  const double bytes = limbs * 16.0 * S::N, ops = limbs * (S::N / 2) * (2 * H);
+  KTimer tm(ctx, s);
   if (forward) {
-    hipLaunchKernelGGL((ntt_pass_kernel<H, true, true>), dim3(grid), dim3(256), 0, s, src, dst, ll,
-                       ctx->d_tw_fwd, ctx->d_pinfo);
-    hipLaunchKernelGGL((ntt_pass_kernel<H, true, false>), dim3(grid), dim3(256), 0, s, dst, dst,
-                       second, ctx->d_tw_fwd, ctx->d_pinfo);
+    hipLaunchKernelGGL((ntt_pass_kernel<H, true, true>), dim3(gc), dim3(SC::T), 0, s, src, dst, ll,
+                       ctx->d_tw_fwd, ctx->d_pinfo, NttEpi{});
+    tm.lap(TK_NTT_FWD_COL, bytes, ops);
+    hipLaunchKernelGGL((ntt_pass_kernel<H, true, false>), dim3(gb), dim3(SB::T), 0, s, dst, dst,
+                       second, ctx->d_tw_fwd, ctx->d_pinfo, epi);
+    tm.lap(TK_NTT_FWD_BLK, epi.a ? bytes * 1.5 : bytes, ops);
   } else {
-    hipLaunchKernelGGL((ntt_pass_kernel<H, false, false>), dim3(grid), dim3(256), 0, s, src, dst, ll,
-                       ctx->d_tw_inv, ctx->d_pinfo);
-    hipLaunchKernelGGL((ntt_pass_kernel<H, false, true>), dim3(grid), dim3(256), 0, s, dst, dst,
-                       second, ctx->d_tw_inv, ctx->d_pinfo);
+    hipLaunchKernelGGL((ntt_pass_kernel<H, false, false>), dim3(gb), dim3(SB::T), 0, s, src, dst, ll,
+                       ctx->d_tw_inv, ctx->d_pinfo, NttEpi{});
+    tm.lap(TK_NTT_INV_BLK, bytes, ops);
+    hipLaunchKernelGGL((ntt_pass_kernel<H, false, true>), dim3(gc), dim3(SC::T), 0, s, dst, dst,
+                       second, ctx->d_tw_inv, ctx->d_pinfo, NttEpi{});
+    tm.lap(TK_NTT_INV_COL, bytes, ops);
   }
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
@@ -261,8 +291,17 @@ int launch_ntt_h(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, i
 
 int launch_ntt(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int batch, bool forward,
                hipStream_t s) {
-  if (ctx->logn == 16) return launch_ntt_h<4>(ctx, src, dst, ll, batch, forward, s);
-  if (ctx->logn == 12) return launch_ntt_h<3>(ctx, src, dst, ll, batch, forward, s);
+  return launch_ntt_epi(ctx, src, dst, ll, batch, forward, s, NttEpi{});
+}
+
+int launch_ntt_epi(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int batch, bool forward,
+                   hipStream_t s, const NttEpi &epi) {
+  if (epi.a && (!forward || ll.n > HELRM_MAX_EPI)) {
+    set_error("NTT epilogue: forward transforms of at most %d limbs only", HELRM_MAX_EPI);
+    return HELRM_EINVAL;
+  }
+  if (ctx->logn == 16) return launch_ntt_h<4>(ctx, src, dst, ll, batch, forward, s, epi);
+  if (ctx->logn == 12) return launch_ntt_h<3>(ctx, src, dst, ll, batch, forward, s, epi);
   set_error("unsupported log_n %d (12 or 16)", ctx->logn);
   return HELRM_EINVAL;
 }

@@ -1,0 +1,71 @@
+"""Host-side pieces of the product (parameter rule, encoding, planner,
+selector) against the oracle's independent implementations and against the
+paper's worked example -- CPU only."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+from paper_2506_18150_amd import encoding, params, planner
+
+
+def test_param_sets_match_oracle_rule():
+    for mine, theirs in ((params.toy(), O.config1_params()), (params.n16(), O.config2_params())):
+        assert mine.q == theirs.q and mine.p == theirs.p
+        assert (mine.N, mine.L, mine.K, mine.alpha, mine.dnum) == (theirs.N, theirs.L, theirs.K, theirs.alpha,
+                                                                  theirs.dnum)
+
+
+@pytest.mark.parametrize("N", [64, 4096])
+def test_encoding_matches_oracle(N):
+    prm = O.make_params(N=N, L=1, K=1, alpha=1)
+    rng = np.random.default_rng(N)
+    for scale in (2.0 ** 40, float(prm.q[1])):
+        z = rng.uniform(-1, 1, N // 2)
+        mine = encoding.encode(z, scale, N)
+        theirs = O.encode(z, scale, prm)
+        # two different FFT routes: rounding may differ only at exact .5 ties
+        assert np.max(np.abs(mine - theirs)) <= 1
+        assert np.mean(mine != theirs) < 1e-3
+        back = encoding.decode(mine, scale, N)
+        assert np.max(np.abs(back.real - z)) < 1e-9
+
+
+def test_digits_worked_example():
+    assert planner.n_digits(16, 4) == 2 and planner.digits(14, 4, 2) == [2, 3]
+    assert planner.n_digits(65536, 256) == 2 and planner.n_digits(65537, 256) == 3
+    assert planner.n_digits(1, 256) == 1
+
+
+def test_plan_matches_oracle_diagonals():
+    rng = synth.rng(3)
+    M = rng.uniform(-1, 1, (24, 300))
+    for n1 in (4, 16):
+        m, n2, vals = planner.bsgs_diagonals(M, 512, n1)
+        om, on2, ovals = O.bsgs_plan_values(M, 512, n1)
+        assert (m, n2) == (om, on2)
+        assert sorted(vals) == sorted(g * n1 + b for (g, b) in ovals)
+        for (g, b), v in ovals.items():
+            assert np.array_equal(vals[g * n1 + b], v)
+    assert planner.fold_stages(32768, 16, 8) == O.fold_stages(32768, 16, 8)
+
+
+def test_selector_and_rows_match_oracle():
+    g = synth.rng(5)
+    parts = [synth.uniform_table(g, 16, 4, -1, 1) for _ in range(3)]
+    E = synth.uniform_table(g, 7, 4, -1, 1)
+    mine = [planner.Table(rows=4000, d=4, base=16, parts=parts), planner.Table(rows=7, d=4, full=E)]
+    theirs = [O.TableSpec(rows=4000, d=4, base=16, C=parts), O.TableSpec(rows=7, d=4, E=E)]
+    assert np.array_equal(planner.packed_matrix(mine), O.pack_tables(theirs))
+    for idx in ([0, 0], [3999, 6], [1234, 3]):
+        assert np.array_equal(planner.packed_selector(mine, idx), O.pack_selector(theirs, idx))
+        assert np.allclose(np.concatenate([t.row(i) for t, i in zip(mine, idx)]),
+                           np.concatenate([t.lookup(i) for t, i in zip(theirs, idx)]))
+
+
+def test_plan_spec_rotation_steps():
+    M = np.ones((16, 512))
+    spec = planner.make_plan(M, 1 << 16, 23, 2.0 ** 40, 16, 2)
+    assert spec.m == 16 and spec.n2 == 1 and len(spec.stages) == 11
+    assert len(spec.rotation_steps()) == 26
+    assert planner.compress_rule(501, 500) and not planner.compress_rule(500, 500)
