@@ -36,6 +36,29 @@ KERNEL_SYMBOL = {
 }
 
 
+PMC_PROFILES = {"ks_acc": "profiles/ks_acc_kernel_w2_level23_radix8_pmc.json"}
+
+
+def measured_traffic(kernel: str, level: int, radix: int, n1: int, batch: int):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE counter
+    runs (scaled by the copy-kernel calibration), or None when there is no
+    such record for this kernel and workload or the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    path = PMC_PROFILES.get(kernel)
+    if not path or (level, radix, n1, batch) != (23, 8, 16, 1):
+        return None
+    try:
+        with open(os.path.join(ROOT, path)) as f:
+            rec = json.load(f)
+        src = b"".join(open(os.path.join(ROOT, p), "rb").read() for p in rec["source_files"])
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,6 +70,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the run, copy a 1 GiB buffer 3 times (reference kernel for HBM counters)")
     return ap.parse_args()
 
 
@@ -171,12 +196,13 @@ def main():
                 continue
             table[k] = {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
                         "avg_us": 1e3 * v["ms"] / v["launches"], "GB/s": v["bytes"] / (v["ms"] * 1e6),
-                        "Gmodmul/s": v["ops"] / (v["ms"] * 1e6)}
+                        "Gmodmul/s": v["ops"] / (v["ms"] * 1e6), "bytes_per_launch": v["bytes"] / v["launches"]}
         dom = max(table, key=lambda k: table[k]["ms_per_step"])
         d = table[dom]
         res["roofline"] = {"kernel": KERNEL_SYMBOL[dom], "bound": "hbm", "achieved": d["GB/s"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["GB/s"] / HBM_PEAK_GBS,
-                           "traffic": None, "avg_us": d["avg_us"]}
+                           "traffic": measured_traffic(dom, args.level, args.radix, args.n1, B),
+                           "avg_us": d["avg_us"], "algorithmic_bytes_per_launch": d["bytes_per_launch"]}
         ks = table.get("ks_acc")
         if ks:
             res["roofline_keyswitch"] = {"kernel": KERNEL_SYMBOL["ks_acc"], "bound": "hbm",
@@ -185,6 +211,14 @@ def main():
         limb_ntts = (kt["ntt_fwd_col"]["ops"] + kt["ntt_inv_blk"]["ops"]) / ((prm.N // 2) * 8) / args.steps
         res["ntts_per_s"] = limb_ntts * (1e3 / ms_per_step)
         res["kernels"] = {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in table.items()}
+
+    if args.calibrate_copy:
+        a = torch.zeros(1 << 27, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        res["copy_calibration_bytes"] = 1 << 30
 
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(args.level, args.n1, args.radix)
