@@ -639,18 +639,30 @@ def next_pow2(x: int) -> int:
     return p
 
 
-def hybrid_diagonals(M: np.ndarray, n: int) -> Tuple[int, np.ndarray]:
-    """u_k[j] = M'[j mod m][(j+k) mod n] for k < m, M' = M zero-padded to m x n,
-    m = next_pow2(rows).  sum_k u_k * rot(x, k), folded over the m-periodic
-    copies, equals M x in slots [0, rows)."""
+def hybrid_diagonals(M: np.ndarray, n: int, sign: int = 1) -> Tuple[int, np.ndarray]:
+    """u_k[j] = M'[j mod m][(j + sign k) mod n] for k < m, M' = M zero-padded to
+    m x n, m = next_pow2(rows).  sum_k u_k * rot(x, sign k), folded over the
+    m-periodic copies, equals M x in slots [0, rows)."""
     rows, cols = M.shape
-    assert cols <= n
+    assert cols <= n and sign in (1, -1)
     m = next_pow2(rows)
     Mp = np.zeros((m, n))
     Mp[:rows, :cols] = M
     j = np.arange(n)
-    U = np.stack([Mp[j % m, (j + k) % n] for k in range(m)])
+    U = np.stack([Mp[j % m, (j + sign * k) % n] for k in range(m)])
     return m, U
+
+
+def fold_span(M: np.ndarray, n: int, sign: int) -> int:
+    """Slots the fold must cover.  With sign -1, u_k[j] is non-zero only for
+    j - k in [0, cols), so every partial sum lies in [0, cols + m - 1) and the
+    fold can stop at the next power of two above that; with sign +1 the
+    partial sums wrap around and the fold covers all n slots."""
+    rows, cols = M.shape
+    m = next_pow2(rows)
+    if sign == 1:
+        return n
+    return min(n, next_pow2(cols + m - 1))
 
 
 def rot(x: np.ndarray, k: int) -> np.ndarray:
@@ -673,7 +685,9 @@ def fold_stages(n: int, m: int, radix: int) -> List[Tuple[int, int]]:
 
 @dataclass
 class Plan:
-    """BSGS matvec schedule over the hybrid diagonals of one packed matrix."""
+    """BSGS matvec schedule over the hybrid diagonals of one packed matrix.
+    sign = +1 rotates by +b and +n1 g, sign = -1 by -b and -n1 g; the fold
+    runs from `span` slots down to period m."""
     m: int
     n1: int
     n2: int
@@ -682,6 +696,8 @@ class Plan:
     rows: int
     coeffs: Dict[Tuple[int, int], np.ndarray]   # (g, b) -> int64 [N], encoded at scale q_level
     stages: List[Tuple[int, int]] = field(default_factory=list)
+    sign: int = 1
+    span: int = 0
 
     def baby_steps(self) -> List[int]:
         return sorted({b for (_, b) in self.coeffs})
@@ -690,39 +706,40 @@ class Plan:
         return sorted({g for (g, _) in self.coeffs})
 
     def rotation_steps(self) -> List[int]:
-        st = set(b for b in self.baby_steps() if b != 0)
-        st |= {self.n1 * g for g in self.giant_steps() if g != 0}
+        st = set(self.sign * b for b in self.baby_steps() if b != 0)
+        st |= {self.sign * self.n1 * g for g in self.giant_steps() if g != 0}
         for s, r in self.stages:
             st |= {t * s for t in range(1, r)}
         return sorted(st)
 
 
-def bsgs_plan_values(M: np.ndarray, n: int, n1: int) -> Tuple[int, int, Dict[Tuple[int, int], np.ndarray]]:
-    """Pre-rotated diagonals v_{g,b} = rot(u_{n1 g + b}, -n1 g) for every
-    non-zero hybrid diagonal, so that sum_g rot(sum_b v_{g,b} rot(x, b), n1 g)
-    = sum_k u_k rot(x, k)."""
-    m, U = hybrid_diagonals(M, n)
+def bsgs_plan_values(M: np.ndarray, n: int, n1: int, sign: int = 1) -> Tuple[int, int, Dict[Tuple[int, int], np.ndarray]]:
+    """Pre-rotated diagonals v_{g,b} = rot(u_{n1 g + b}, -sign n1 g) for every
+    non-zero hybrid diagonal, so that
+    sum_g rot(sum_b v_{g,b} rot(x, sign b), sign n1 g) = sum_k u_k rot(x, sign k)."""
+    m, U = hybrid_diagonals(M, n, sign)
     n2 = -(-m // n1)
     vals = {}
     for k in range(m):
         if not np.any(U[k]):
             continue
         g, b = divmod(k, n1)
-        vals[(g, b)] = rot(U[k], -n1 * g)
+        vals[(g, b)] = rot(U[k], -sign * n1 * g)
     return m, n2, vals
 
 
-def make_plan(prm: Params, M: np.ndarray, level: int, n1: int, radix: int = 2) -> Plan:
-    m, n2, vals = bsgs_plan_values(M, prm.n, n1)
+def make_plan(prm: Params, M: np.ndarray, level: int, n1: int, radix: int = 2, sign: int = 1) -> Plan:
+    m, n2, vals = bsgs_plan_values(M, prm.n, n1, sign)
     scale = prm.q[level]
     coeffs = {gb: encode(v, scale, prm) for gb, v in vals.items()}
+    span = fold_span(M, prm.n, sign)
     return Plan(m=m, n1=n1, n2=n2, radix=radix, level=level, rows=M.shape[0], coeffs=coeffs,
-                stages=fold_stages(prm.n, m, radix))
+                stages=fold_stages(span, m, radix), sign=sign, span=span)
 
 
-def cleartext_bsgs(M: np.ndarray, x: np.ndarray, n: int, n1: int, radix: int) -> np.ndarray:
+def cleartext_bsgs(M: np.ndarray, x: np.ndarray, n: int, n1: int, radix: int, sign: int = 1) -> np.ndarray:
     """fp64 replay of the schedule: the BSGS sum followed by the fold."""
-    m, n2, vals = bsgs_plan_values(M, n, n1)
+    m, n2, vals = bsgs_plan_values(M, n, n1, sign)
     xs = np.zeros(n)
     xs[: len(x)] = x
     z = np.zeros(n)
@@ -730,9 +747,9 @@ def cleartext_bsgs(M: np.ndarray, x: np.ndarray, n: int, n1: int, radix: int) ->
         inner = np.zeros(n)
         for b in range(n1):
             if (g, b) in vals:
-                inner += vals[(g, b)] * rot(xs, b)
-        z += rot(inner, n1 * g)
-    for s, r in fold_stages(n, m, radix):
+                inner += vals[(g, b)] * rot(xs, sign * b)
+        z += rot(inner, sign * n1 * g)
+    for s, r in fold_stages(fold_span(M, n, sign), m, radix):
         z = sum(rot(z, t * s) for t in range(r))
     return z
 
@@ -748,9 +765,9 @@ def plan_residues(prm: Params, plan: Plan) -> Dict[Tuple[int, int], np.ndarray]:
 def matvec(prm: Params, keys: Keys, plan: Plan, ct: np.ndarray,
            pts: Optional[Dict[Tuple[int, int], np.ndarray]] = None) -> np.ndarray:
     """Double-hoisted BSGS plaintext-matrix x ciphertext product (no rescale).
-      1. ModUp(c1) once; R_0 = (P c0, P c1); R_b = hoisted rotation by b in PQ.
+      1. ModUp(c1) once; R_0 = (P c0, P c1); R_b = hoisted rotation by sign b in PQ.
       2. X_g = sum_b pt_{g,b} * R_b over PQ; x_g = ModDown(X_g).
-      3. acc = P x_0 + sum_{g>=1} [rotation of x_g by n1 g, kept in PQ];
+      3. acc = P x_0 + sum_{g>=1} [rotation of x_g by sign n1 g, kept in PQ];
          z = ModDown(acc)  (z = x_0 when there is one giant step).
       4. Fold: per stage (s, r), z = ModDown(P z + sum_{t=1}^{r-1} rot_PQ(z, t s))."""
     lv = plan.level
@@ -764,7 +781,7 @@ def matvec(prm: Params, keys: Keys, plan: Plan, ct: np.ndarray,
         if b == 0:
             R[0] = lift_P(prm, ct, lv)
         else:
-            g = galois_for_step(b, prm)
+            g = galois_for_step(plan.sign * b, prm)
             R[b] = key_inner_product(prm, d, ct[0], lv, keys.swk[g], g)
     xs = {}
     for g in plan.giant_steps():
@@ -784,7 +801,7 @@ def matvec(prm: Params, keys: Keys, plan: Plan, ct: np.ndarray,
             if g == 0:
                 Y = lift_P(prm, xs[0], lv)
             else:
-                gal = galois_for_step(plan.n1 * g, prm)
+                gal = galois_for_step(plan.sign * plan.n1 * g, prm)
                 dg = modup(prm, xs[g][1], lv)
                 Y = key_inner_product(prm, dg, xs[g][0], lv, keys.swk[gal], gal)
             for c in range(2):

@@ -74,15 +74,30 @@ def test_block_diag_matvec_equals_per_table_lookups():
         assert np.allclose(t.lookup(idx[0]), t.C[0][ds[0]] + t.C[1][ds[1]])
 
 
+@pytest.mark.parametrize("sign", [1, -1])
 @pytest.mark.parametrize("n1,radix", [(4, 2), (16, 2), (16, 4), (2, 8), (1, 2)])
-def test_bsgs_schedule_equals_matvec(n1, radix):
+def test_bsgs_schedule_equals_matvec(n1, radix, sign):
     rng = np.random.default_rng(n1 * 10 + radix)
     n = 256
-    for rows, cols in [(16, 32), (24, 100), (5, 256), (64, 64)]:
+    for rows, cols in [(16, 32), (24, 100), (5, 256 - 8), (64, 64)]:
         M = rng.uniform(-1, 1, (rows, cols))
         x = rng.uniform(-1, 1, cols)
-        z = O.cleartext_bsgs(M, x, n, n1, radix)
+        z = O.cleartext_bsgs(M, x, n, n1, radix, sign)
         assert np.allclose(z[:rows], M @ x, atol=1e-12)
+
+
+def test_window_span():
+    """With rotations by -k every partial sum of the diagonal method lies in
+    [0, cols + m - 1), so the fold can stop at the next power of two."""
+    assert O.fold_span(np.zeros((16, 512)), 32768, -1) == 1024
+    assert O.fold_span(np.zeros((16, 512)), 32768, 1) == 32768
+    assert O.fold_span(np.zeros((416, 19968)), 32768, -1) == 32768
+    rng = np.random.default_rng(5)
+    M = rng.uniform(-1, 1, (16, 40))
+    m, U = O.hybrid_diagonals(M, 256, -1)
+    for k in range(m):
+        nz = np.nonzero(U[k])[0]
+        assert nz.min() >= k and nz.max() < 40 + k
 
 
 def test_fold_stage_shapes():
@@ -134,8 +149,8 @@ def test_config1_uncompressed_control():
 
 
 def test_config1_other_schedules_agree_semantically():
-    for n1, radix in [(16, 2), (2, 8)]:
-        w = W.config1(n_queries=1, n1=n1, radix=radix)
+    for n1, radix, sign in [(16, 2, 1), (2, 8, 1), (4, 2, -1), (16, 8, -1)]:
+        w = W.config1(n_queries=1, n1=n1, radix=radix, sign=sign)
         out = O.lookup(w.prm, w.keys, w.plan, w.cts[0])
         got = W.decrypt_slots(w, out, w.prm.delta, 16)
         assert np.max(np.abs(got - w.expected[0])) < 1e-4
