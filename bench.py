@@ -39,14 +39,14 @@ KERNEL_SYMBOL = {
 PMC_PROFILES = {"ks_acc": "profiles/ks_acc_kernel_w2_level23_radix8_pmc.json"}
 
 
-def measured_traffic(kernel: str, level: int, radix: int, n1: int, batch: int):
+def measured_traffic(kernel: str, level: int, radix: int, n1: int, batch: int, sign: int):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE counter
     runs (scaled by the copy-kernel calibration), or None when there is no
     such record for this kernel and workload or the kernel source changed
     since the counters were taken."""
     import hashlib
     path = PMC_PROFILES.get(kernel)
-    if not path or (level, radix, n1, batch) != (23, 8, 16, 1):
+    if not path or (level, radix, n1, batch, sign) != (23, 8, 16, 1, 1):
         return None
     try:
         with open(os.path.join(ROOT, path)) as f:
@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--n1", type=int, default=16)
     ap.add_argument("--radix", type=int, default=8)
     ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--sign", type=int, default=-1, choices=[1, -1],
+                    help="direction of the diagonal rotations; -1 lets the fold stop at the occupied window")
+    ap.add_argument("--graph", action="store_true", help="replay one captured HIP graph per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -81,7 +84,7 @@ def w2_tables(synth, planner):
     return [planner.Table(rows=65536, d=16, base=256, parts=parts)]
 
 
-def cpu_baseline(level: int, n1: int, radix: int):
+def cpu_baseline(level: int, n1: int, radix: int, sign: int):
     """The CPU oracle on one lookup of the same workload (keys, plan encoding
     and encryption untimed)."""
     import numpy as np
@@ -94,7 +97,7 @@ def cpu_baseline(level: int, n1: int, radix: int):
     g = synth.rng(0)
     C = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(2)]
     t = O.TableSpec(rows=65536, d=16, base=256, C=C)
-    plan = O.make_plan(prm, O.pack_tables([t]), level, n1, radix)
+    plan = O.make_plan(prm, O.pack_tables([t]), level, n1, radix, sign)
     gals = [O.galois_for_step(k, prm) for k in plan.rotation_steps()]
     keys = O.keygen(prm, synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals))
     qg = synth.rng(1)
@@ -109,7 +112,7 @@ def cpu_baseline(level: int, n1: int, radix: int):
     err = float(np.max(np.abs(got - t.lookup(idx[0]))))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / dt, "unit": "lookups/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 lookup of the same workload (level {level}, n1={n1}, radix {radix}); "
+            "sample": f"1 lookup of the same workload (level {level}, n1={n1}, radix {radix}, sign {sign}); "
                       f"{dt:.2f} s; decrypted max error {err:.1e}; keygen/encoding untimed"}
 
 
@@ -130,7 +133,7 @@ def main():
     tables = w2_tables(synth, planner)
     t0 = time.time()
     sess = LookupSession(prm, tables, args.level, args.n1, args.radix,
-                         lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals))
+                         lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals), sign=args.sign)
     setup_s = time.time() - t0
     B = args.batch
     qg = synth.rng(1)
@@ -142,10 +145,25 @@ def main():
     for _ in range(args.warmup):
         sess.lookup(sel, out, stream)
     torch.cuda.synchronize()
+    step = lambda: sess.lookup(sel, out, stream)
+    if args.graph:
+        cap = torch.cuda.Stream()
+        sess.ctx.helrm_reserve(sess.plan, B, cap)
+        cap.wait_stream(stream)
+        with torch.cuda.stream(cap):
+            sess.lookup(sel, out, cap)
+        stream.wait_stream(cap)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=cap):
+            sess.lookup(sel, out, cap)
+        graph.replay()
+        torch.cuda.synchronize()
+        step = graph.replay
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     ev[0].record(stream)
     for k in range(args.steps):
-        sess.lookup(sel, out, stream)
+        step()
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
@@ -173,9 +191,11 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": f"w2: N=2^16, L=23, dnum=3, K=8; 1 table 65536x16 as 2 base-256 digit tables; "
-                               f"selector at level {args.level}; n1={args.n1}, fold radix {args.radix}; "
-                               f"batch {B} ciphertext(s) per call",
-                   "level": args.level, "batch": B, "n1": args.n1, "radix": args.radix},
+                               f"selector at level {args.level}; n1={args.n1}, fold radix {args.radix}, "
+                               f"rotation sign {args.sign} (fold span {sess.spec.span}); "
+                               f"batch {B} ciphertext(s) per call" + (", HIP graph replay" if args.graph else ""),
+                   "level": args.level, "batch": B, "n1": args.n1, "radix": args.radix, "sign": args.sign,
+                   "fold_span": sess.spec.span, "graph": args.graph},
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
         "key_switches_per_s": {"hoisted": n_hoisted * value, "full": n_full * value,
                                "per_lookup": {"hoisted": n_hoisted, "full": n_full}},
@@ -201,7 +221,7 @@ def main():
         d = table[dom]
         res["roofline"] = {"kernel": KERNEL_SYMBOL[dom], "bound": "hbm", "achieved": d["GB/s"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["GB/s"] / HBM_PEAK_GBS,
-                           "traffic": measured_traffic(dom, args.level, args.radix, args.n1, B),
+                           "traffic": measured_traffic(dom, args.level, args.radix, args.n1, B, args.sign),
                            "avg_us": d["avg_us"], "algorithmic_bytes_per_launch": d["bytes_per_launch"]}
         ks = table.get("ks_acc")
         if ks:
@@ -221,7 +241,7 @@ def main():
         res["copy_calibration_bytes"] = 1 << 30
 
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.level, args.n1, args.radix)
+        res["cpu_baseline"] = cpu_baseline(args.level, args.n1, args.radix, args.sign)
     print(json.dumps(res))
 
 

@@ -159,14 +159,18 @@ int helrm_rescale(helrm_ctx *ctx, const uint64_t *d_in, int level, uint64_t *d_o
 
 /* A plaintext matrix prepared for the BSGS diagonal method (Sec. II-A
  * "Neural Network Layers in FHE", Sec. III-B).  For an r x c matrix M (r
- * outputs, c <= N/2 inputs) with m = next power of two >= r, the hybrid
- * diagonals are u_k[j] = M[j mod m][(j + k) mod (N/2)] (zero rows beyond r),
- * k < m.  With k = n1*g + b, the plan holds v_{g,b} = rot(u_k, -n1*g) encoded
- * at scale q_level as signed integer coefficients.  The product is
- *   z = sum_g rot( sum_b v_{g,b} (.) rot(x, b), n1*g ),
- * followed by a fold from N/2 slots down to period m: each stage with stride s
- * and radix r replaces z by sum_{t<r} rot(z, t*s) (s = span/r, r = min(radix,
- * span/m), span starting at N/2).  Slot i < r then holds (M x)_i. */
+ * outputs, c <= N/2 inputs) with m = next power of two >= r and a direction
+ * sign = +1 or -1, the hybrid diagonals are
+ * u_k[j] = M[j mod m][(j + sign*k) mod (N/2)] (zero rows beyond r), k < m.
+ * With k = n1*g + b, the plan holds v_{g,b} = rot(u_k, -sign*n1*g) encoded at
+ * scale q_level as signed integer coefficients.  The product is
+ *   z = sum_g rot( sum_b v_{g,b} (.) rot(x, sign*b), sign*n1*g ),
+ * followed by a fold from `fold_span` slots down to period m: each stage with
+ * stride s and radix r replaces z by sum_{t<r} rot(z, t*s) (s = span/r,
+ * r = min(radix, span/m), span starting at fold_span).  Slot i < r then holds
+ * (M x)_i.  With sign = +1 the fold must cover all N/2 slots; with sign = -1
+ * every partial sum lies in [0, c + m - 1), so any power of two >= c + m - 1
+ * is a valid fold_span. */
 typedef struct {
   int level;              /* level of the input ciphertext */
   int m;                  /* number of hybrid diagonals (power of two) */
@@ -176,6 +180,8 @@ typedef struct {
   int n_diag;             /* number of non-zero diagonals given */
   const int32_t *diag;    /* host [n_diag]: k = n1*g + b of each diagonal, ascending */
   const int64_t *coeffs;  /* host [n_diag][N]: coefficients of v_{g,b} at scale q_level */
+  int sign;               /* +1 or -1: direction of the baby and giant rotations */
+  int fold_span;          /* power of two in [m, N/2]; 0 means N/2 */
 } helrm_plan_desc;
 
 /* Reduce the plan's coefficients over the extended basis at its level, take
@@ -188,9 +194,9 @@ int helrm_plan_destroy(helrm_plan *plan);
 int helrm_plan_rotation_steps(const helrm_plan *plan, int32_t *steps, int cap, int *n);
 
 /* Double-hoisted BSGS plaintext-matrix x ciphertext product without rescale:
- *   1. ModUp(c1) once; R_0 = (P c0, P c1); R_b = hoisted rotation by b (PQ).
+ *   1. ModUp(c1) once; R_0 = (P c0, P c1); R_b = hoisted rotation by sign*b (PQ).
  *   2. X_g = sum_b pt_{g,b} (.) R_b over PQ; x_g = ModDown(X_g).
- *   3. acc = P x_0 + sum_{g>=1} (rotation of x_g by n1 g, kept in PQ);
+ *   3. acc = P x_0 + sum_{g>=1} (rotation of x_g by sign*n1*g, kept in PQ);
  *      z = ModDown(acc)  (z = x_0 when only g = 0 has diagonals).
  *   4. Fold: per stage (s, r): z = ModDown(P z + sum_{t=1}^{r-1} rot_PQ(z, t s)).
  * d_ct [batch][2][level+1][N] -> d_out [batch][2][level+1][N] at scale

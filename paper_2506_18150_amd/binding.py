@@ -42,7 +42,8 @@ class helrm_params(ctypes.Structure):
 
 class helrm_plan_desc(ctypes.Structure):
     _fields_ = [("level", _c_int), ("m", _c_int), ("n1", _c_int), ("n2", _c_int),
-                ("radix", _c_int), ("n_diag", _c_int), ("diag", _i32p), ("coeffs", _i64p)]
+                ("radix", _c_int), ("n_diag", _c_int), ("diag", _i32p), ("coeffs", _i64p),
+                ("sign", _c_int), ("fold_span", _c_int)]
 
 
 EXPORTS = [
@@ -200,11 +201,11 @@ class Context:
         _check(lib().helrm_rescale(self.h, _ptr(d_in), level, _ptr(d_out), batch, _stream(stream)))
 
     def helrm_plan_create(self, level: int, m: int, n1: int, n2: int, radix: int,
-                          diag: Sequence[int], coeffs: np.ndarray) -> "Plan":
+                          diag: Sequence[int], coeffs: np.ndarray, sign: int = 1, fold_span: int = 0) -> "Plan":
         da, pd = _i32(diag)
         co = np.ascontiguousarray(coeffs, dtype=np.int64)
         assert co.shape == (len(da), self.N)
-        desc = helrm_plan_desc(level, m, n1, n2, radix, len(da), pd, co.ctypes.data_as(_i64p))
+        desc = helrm_plan_desc(level, m, n1, n2, radix, len(da), pd, co.ctypes.data_as(_i64p), sign, fold_span)
         h = ctypes.c_void_p()
         _check(lib().helrm_plan_create(self.h, ctypes.byref(desc), ctypes.byref(h)))
         return Plan(self, h, level, m, n1, n2, radix)

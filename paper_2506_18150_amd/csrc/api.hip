@@ -464,7 +464,7 @@ int run_matvec(helrm_ctx *ctx, const helrm_plan *p, const u64 *ct, u64 *out, int
       KsTerm t;
       t.digits = Dg;
       t.c0 = xgp;
-      TRY(key_for(ctx, (long)p->n1 * g, &t.key, &t.galois));
+      TRY(key_for(ctx, (long)p->sign * p->n1 * g, &t.key, &t.galois));
       terms.push_back(t);
       gi++;
     }
@@ -923,6 +923,9 @@ extern "C" int helrm_plan_create(helrm_ctx *c, const helrm_plan_desc *d, helrm_p
   CHECK_ARG(d->n1 <= HELRM_MAX_BABY, "n1 above %d", HELRM_MAX_BABY);
   CHECK_ARG(d->radix >= 2 && d->radix <= HELRM_MAX_TERMS + 1, "radix must be in [2, %d]", HELRM_MAX_TERMS + 1);
   CHECK_ARG(d->n_diag >= 1 && d->diag && d->coeffs, "plan needs at least one diagonal");
+  CHECK_ARG(d->sign == 1 || d->sign == -1, "sign must be +1 or -1");
+  const int span = d->fold_span == 0 ? n : d->fold_span;
+  CHECK_ARG(is_pow2(span) && span >= d->m && span <= n, "fold_span must be a power of two in [m, N/2]");
   for (int i = 0; i < d->n_diag; i++) {
     CHECK_ARG(d->diag[i] >= 0 && d->diag[i] < d->m, "diagonal index %d out of range", d->diag[i]);
     CHECK_ARG(i == 0 || d->diag[i] > d->diag[i - 1], "diagonal indices must ascend");
@@ -935,6 +938,8 @@ extern "C" int helrm_plan_create(helrm_ctx *c, const helrm_plan_desc *d, helrm_p
   p->n2 = d->n2;
   p->radix = d->radix;
   p->n_diag = d->n_diag;
+  p->sign = d->sign;
+  p->span = span;
   p->slot.assign((size_t)d->n2 * d->n1, -1);
   for (int i = 0; i < d->n_diag; i++) {
     const int k = d->diag[i], g = k / d->n1, b = k % d->n1;
@@ -945,11 +950,11 @@ extern "C" int helrm_plan_create(helrm_ctx *c, const helrm_plan_desc *d, helrm_p
   }
   std::sort(p->babies.begin(), p->babies.end());
   std::sort(p->giants.begin(), p->giants.end());
-  for (int span = n; span > d->m;) {
-    const int r = std::min(d->radix, span / d->m);
-    const int st = span / r;
+  for (int sp = span; sp > d->m;) {
+    const int r = std::min(d->radix, sp / d->m);
+    const int st = sp / r;
     p->stages.push_back({st, r});
-    span = st;
+    sp = st;
   }
   const int pqn = d->level + 1 + c->K;
   p->pt_limb_stride = pqn;
@@ -1005,9 +1010,9 @@ extern "C" int helrm_plan_rotation_steps(const helrm_plan *p, int32_t *steps, in
   CHECK_ARG(p && n, "NULL argument");
   std::vector<int> st;
   for (int b : p->babies)
-    if (b) st.push_back(b);
+    if (b) st.push_back(p->sign * b);
   for (int g : p->giants)
-    if (g) st.push_back(p->n1 * g);
+    if (g) st.push_back(p->sign * p->n1 * g);
   for (auto &sr : p->stages)
     for (int t = 1; t < sr.second; t++) st.push_back(t * sr.first);
   std::sort(st.begin(), st.end());

@@ -228,7 +228,7 @@ struct helrm_ctx {
 
 struct helrm_plan {
   helrm_ctx *ctx;
-  int level, m, n1, n2, radix, n_diag;
+  int level, m, n1, n2, radix, n_diag, sign, span;
   std::vector<int> diag;                 // k = n1 g + b per stored diagonal
   std::vector<std::pair<int, int>> stages;  // fold (s, r)
   std::vector<int> babies;               // b values present (ascending)

@@ -212,49 +212,102 @@ __device__ __forceinline__ int pq_prime_dev(int r, int level, int L) {
   return r <= level ? r : L + 1 + (r - level - 1);
 }
 
+// Workgroup order for kernels whose operands (keys, plaintexts) are shared by
+// every ciphertext of a batch: a group is one (256-coefficient block, limb)
+// pair and a tile is BT ciphertexts of the batch.  Workgroup L runs on XCD
+// L mod 8 (round-robin dispatch); the mapping sends all tiles of a group to
+// the same XCD back to back, so the group's key and plaintext words come from
+// HBM once and from that XCD's L2 afterwards.
+struct TileMap {
+  int xb, r, tile;
+};
+
+__device__ __forceinline__ TileMap tile_map(int L, int nx, int ntiles) {
+  const int xcd = L & 7, k = L >> 3;
+  const int tile = k % ntiles;
+  const int grp = (k / ntiles) * 8 + xcd;
+  TileMap m;
+  m.xb = grp % nx;
+  m.r = grp / nx;
+  m.tile = tile;
+  return m;
+}
+
+constexpr int MAXBETA = 4;   // digits per key switch handled in registers
+
 // out = (B, A) over PQ:  B = sum_t sum_j sigma_t(d_{t,j}) b_{t,j}
 //                          + P (sum_t sigma_t(c0_t) + base_c0),
 //                        A = sum_t sum_j sigma_t(d_{t,j}) a_{t,j} + P base_c1.
-__global__ __launch_bounds__(TPB) void ks_acc_kernel(KsArgs T, LevelGeom G, int L, size_t dig_bs,
-                                                     size_t c0_bs, const u64 *base, size_t base_bs,
-                                                     u64 *out, size_t out_bs, const PrimeInfo *pinfo) {
+// Each thread owns one coefficient of one limb for BT ciphertexts; the key
+// words of a rotation are loaded once and used for all BT.
+template <int BT>
+__global__ __launch_bounds__(TPB) void ks_acc_kernel(KsArgs T, LevelGeom G, int L, int batch, int ntiles,
+                                                     size_t dig_bs, size_t c0_bs, const u64 *base,
+                                                     size_t base_bs, u64 *out, size_t out_bs,
+                                                     const PrimeInfo *pinfo) {
   const int N = 1 << G.logn;
-  const int x = blockIdx.x * TPB + threadIdx.x;
-  const int r = blockIdx.y;
-  const int bat = blockIdx.z;
+  const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles);
+  const int x = tm.xb * TPB + threadIdx.x;
+  const int r = tm.r;
+  const int b0 = tm.tile * BT;
   const int p = pq_prime_dev(r, G.level, L);
   const PrimeInfo pi = pinfo[p];
   const bool isq = r <= G.level;
-  Acc ab, aa;
-  acc_zero(ab);
-  acc_zero(aa);
-  u64 csum = 0;
+  Acc ab[BT], aa[BT];
+  u64 csum[BT];
+#pragma unroll
+  for (int k = 0; k < BT; k++) {
+    acc_zero(ab[k]);
+    acc_zero(aa[k]);
+    csum[k] = 0;
+  }
   for (int t = 0; t < T.n; t++) {
     const unsigned src = galois_src(x, T.gal[t], G.logn);
-    const u64 *dg = T.digits[t] + bat * dig_bs;
     const u64 *kk = T.key[t];
-    for (int j = 0; j < G.beta; j++) {
-      const u64 d = dg[((size_t)j * G.pqn + r) * N + src];
-      const u64 kb = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
-      const u64 ka = kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
-      acc_mac(ab, d, kb);
-      acc_mac(aa, d, ka);
+    u64 kb[MAXBETA], ka[MAXBETA];
+#pragma unroll
+    for (int j = 0; j < MAXBETA; j++) {
+      if (j < G.beta) {
+        kb[j] = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
+        ka[j] = kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
+      }
     }
-    if (isq) csum = add_mod(csum, T.c0[t][bat * c0_bs + (size_t)r * N + src], pi.q);
-  }
-  u64 B = redc_acc(ab, pi.q, pi.qn);
-  u64 A = redc_acc(aa, pi.q, pi.qn);
-  if (isq) {
-    if (base) {
-      const u64 *bb = base + bat * base_bs;
-      csum = add_mod(csum, bb[(size_t)r * N + x], pi.q);
-      A = add_mod(A, shoup(bb[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q), pi.q);
+#pragma unroll
+    for (int k = 0; k < BT; k++) {
+      const int bat = b0 + k;
+      if (bat < batch) {
+        const u64 *dg = T.digits[t] + bat * dig_bs;
+#pragma unroll
+        for (int j = 0; j < MAXBETA; j++) {
+          if (j < G.beta) {
+            const u64 d = dg[((size_t)j * G.pqn + r) * N + src];
+            acc_mac(ab[k], d, kb[j]);
+            acc_mac(aa[k], d, ka[j]);
+          }
+        }
+        if (isq) csum[k] = add_mod(csum[k], T.c0[t][bat * c0_bs + (size_t)r * N + src], pi.q);
+      }
     }
-    B = add_mod(B, shoup(csum, pi.pmod, pi.pmod_p, pi.q), pi.q);
   }
-  u64 *o = out + bat * out_bs;
-  o[(size_t)r * N + x] = B;
-  o[((size_t)G.pqn + r) * N + x] = A;
+#pragma unroll
+  for (int k = 0; k < BT; k++) {
+    const int bat = b0 + k;
+    if (bat >= batch) break;
+    u64 B = redc_acc(ab[k], pi.q, pi.qn);
+    u64 A = redc_acc(aa[k], pi.q, pi.qn);
+    u64 cs = csum[k];
+    if (isq) {
+      if (base) {
+        const u64 *bb = base + bat * base_bs;
+        cs = add_mod(cs, bb[(size_t)r * N + x], pi.q);
+        A = add_mod(A, shoup(bb[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q), pi.q);
+      }
+      B = add_mod(B, shoup(cs, pi.pmod, pi.pmod_p, pi.q), pi.q);
+    }
+    u64 *o = out + bat * out_bs;
+    o[(size_t)r * N + x] = B;
+    o[((size_t)G.pqn + r) * N + x] = A;
+  }
 }
 
 struct BabyArgs {
@@ -267,71 +320,112 @@ struct BabyArgs {
 // Fused hoisted baby-step rotations and plaintext-diagonal MAC (double
 // hoisting): R_b is formed in registers and immediately multiplied into every
 // giant output of the tile, so no rotated ciphertext is written to memory.
-template <int GT>
-__global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G, int L, const u64 *digits,
-                                                       size_t dig_bs, const u64 *ct, size_t ct_bs,
-                                                       const u64 *pt, const int *slot, int n1, int g0,
-                                                       int ng, u64 *X, size_t x_bs,
+// Each thread serves BT ciphertexts: key and plaintext words are loaded once
+// per rotation and reused for all of them.
+template <int GT, int BT>
+__global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G, int L, int batch, int ntiles,
+                                                       const u64 *digits, size_t dig_bs, const u64 *ct,
+                                                       size_t ct_bs, const u64 *pt, const int *slot, int n1,
+                                                       int g0, int ng, u64 *X, size_t x_bs,
                                                        const PrimeInfo *pinfo) {
   const int N = 1 << G.logn;
-  const int x = blockIdx.x * TPB + threadIdx.x;
-  const int r = blockIdx.y;
-  const int bat = blockIdx.z;
+  const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles);
+  const int x = tm.xb * TPB + threadIdx.x;
+  const int r = tm.r;
+  const int b0 = tm.tile * BT;
   const int p = pq_prime_dev(r, G.level, L);
   const PrimeInfo pi = pinfo[p];
   const bool isq = r <= G.level;
-  const u64 *dg = digits + bat * dig_bs;
-  const u64 *c = ct + bat * ct_bs;
-  Acc acc[GT][2];
+  Acc acc[BT][GT][2];
 #pragma unroll
-  for (int gi = 0; gi < GT; gi++) {
-    acc_zero(acc[gi][0]);
-    acc_zero(acc[gi][1]);
-  }
-  for (int bi = 0; bi < BA.nb; bi++) {
-    const int b = BA.b[bi];
-    u64 RB, RA;
-    if (b == 0) {
-      if (isq) {
-        RB = shoup(c[(size_t)r * N + x], pi.pmod, pi.pmod_p, pi.q);
-        RA = shoup(c[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q);
-      } else {
-        RB = 0;
-        RA = 0;
-      }
-    } else {
-      const unsigned src = galois_src(x, BA.gal[bi], G.logn);
-      const u64 *kk = BA.key[bi];
-      Acc ab, aa;
-      acc_zero(ab);
-      acc_zero(aa);
-      for (int j = 0; j < G.beta; j++) {
-        const u64 d = dg[((size_t)j * G.pqn + r) * N + src];
-        acc_mac(ab, d, kk[((size_t)(2 * j) * G.keyl + p) * N + x]);
-        acc_mac(aa, d, kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x]);
-      }
-      RB = redc_acc(ab, pi.q, pi.qn);
-      RA = redc_acc(aa, pi.q, pi.qn);
-      if (isq) RB = add_mod(RB, shoup(c[(size_t)r * N + src], pi.pmod, pi.pmod_p, pi.q), pi.q);
-    }
+  for (int k = 0; k < BT; k++)
 #pragma unroll
     for (int gi = 0; gi < GT; gi++) {
+      acc_zero(acc[k][gi][0]);
+      acc_zero(acc[k][gi][1]);
+    }
+  for (int bi = 0; bi < BA.nb; bi++) {
+    const int b = BA.b[bi];
+    u64 w[GT];
+    bool any = false;
+#pragma unroll
+    for (int gi = 0; gi < GT; gi++) {
+      w[gi] = 0;
       if (gi < ng) {
         const int s = slot[(g0 + gi) * n1 + b];
         if (s >= 0) {
-          const u64 w = pt[((size_t)s * G.pqn + r) * N + x];
-          acc_mac(acc[gi][0], w, RB);
-          acc_mac(acc[gi][1], w, RA);
+          w[gi] = pt[((size_t)s * G.pqn + r) * N + x];
+          any = true;
+        }
+      }
+    }
+    if (!any) continue;
+    if (b == 0) {
+#pragma unroll
+      for (int k = 0; k < BT; k++) {
+        const int bat = b0 + k;
+        if (bat < batch && isq) {
+          const u64 *c = ct + bat * ct_bs;
+          const u64 RB = shoup(c[(size_t)r * N + x], pi.pmod, pi.pmod_p, pi.q);
+          const u64 RA = shoup(c[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q);
+#pragma unroll
+          for (int gi = 0; gi < GT; gi++) {
+            acc_mac(acc[k][gi][0], w[gi], RB);
+            acc_mac(acc[k][gi][1], w[gi], RA);
+          }
+        }
+      }
+      continue;
+    }
+    const unsigned src = galois_src(x, BA.gal[bi], G.logn);
+    const u64 *kk = BA.key[bi];
+    u64 kb[MAXBETA], ka[MAXBETA];
+#pragma unroll
+    for (int j = 0; j < MAXBETA; j++) {
+      if (j < G.beta) {
+        kb[j] = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
+        ka[j] = kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < BT; k++) {
+      const int bat = b0 + k;
+      if (bat < batch) {
+        const u64 *dg = digits + bat * dig_bs;
+        Acc ab, aa;
+        acc_zero(ab);
+        acc_zero(aa);
+#pragma unroll
+        for (int j = 0; j < MAXBETA; j++) {
+          if (j < G.beta) {
+            const u64 d = dg[((size_t)j * G.pqn + r) * N + src];
+            acc_mac(ab, d, kb[j]);
+            acc_mac(aa, d, ka[j]);
+          }
+        }
+        u64 RB = redc_acc(ab, pi.q, pi.qn);
+        const u64 RA = redc_acc(aa, pi.q, pi.qn);
+        if (isq)
+          RB = add_mod(RB, shoup(ct[bat * ct_bs + (size_t)r * N + src], pi.pmod, pi.pmod_p, pi.q), pi.q);
+#pragma unroll
+        for (int gi = 0; gi < GT; gi++) {
+          acc_mac(acc[k][gi][0], w[gi], RB);
+          acc_mac(acc[k][gi][1], w[gi], RA);
         }
       }
     }
   }
-  u64 *o = X + bat * x_bs;
 #pragma unroll
-  for (int gi = 0; gi < GT; gi++) {
-    if (gi < ng) {
-      o[((size_t)(gi * 2) * G.pqn + r) * N + x] = redc_acc(acc[gi][0], pi.q, pi.qn);
-      o[((size_t)(gi * 2 + 1) * G.pqn + r) * N + x] = redc_acc(acc[gi][1], pi.q, pi.qn);
+  for (int k = 0; k < BT; k++) {
+    const int bat = b0 + k;
+    if (bat >= batch) break;
+    u64 *o = X + bat * x_bs;
+#pragma unroll
+    for (int gi = 0; gi < GT; gi++) {
+      if (gi < ng) {
+        o[((size_t)(gi * 2) * G.pqn + r) * N + x] = redc_acc(acc[k][gi][0], pi.q, pi.qn);
+        o[((size_t)(gi * 2 + 1) * G.pqn + r) * N + x] = redc_acc(acc[k][gi][1], pi.q, pi.qn);
+      }
     }
   }
 }
@@ -489,6 +583,12 @@ int launch_rescale_spread(helrm_ctx *ctx, const u64 *top, u64 *out, int level, i
   return HELRM_OK;
 }
 
+int pick_bt(int batch, int cap) {
+  int bt = 1;
+  while (bt < cap && bt < batch) bt *= 2;
+  return bt;
+}
+
 int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_terms,
                          size_t digits_bstride, size_t c0_bstride, const u64 *base, size_t base_bstride,
                          u64 *out, size_t out_bstride, int batch, hipStream_t s) {
@@ -505,15 +605,31 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
     T.gal[i] = terms[i].galois;
   }
   LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn};
+  if (G.beta > MAXBETA) {
+    set_error("key switching with %d digits (at most %d)", G.beta, MAXBETA);
+    return HELRM_EINVAL;
+  }
   if (batch == 0) return HELRM_OK;
   // per coefficient of a Q limb: terms * 3 beta words (digit, key b, key a) + terms c0 words
-  // + 2 base words + 2 output words; special limbs: no c0 / base words.
-  const double qn = level + 1, K = ctx->K, nt = n_terms, beta = G.beta;
-  const double wq = nt * 3 * beta + nt + (base ? 2 : 0) + 2, wp = nt * 3 * beta + 2;
+  // + 2 base words + 2 output words; special limbs: no c0 / base words.  Keys count once per
+  // launch, the rest once per ciphertext.
+  const double qn = level + 1, K = ctx->K, nt = n_terms, beta = G.beta, B = batch;
+  const double words = qn * (nt * 2 * beta + B * (nt * beta + nt + (base ? 2 : 0) + 2)) +
+                       K * (nt * 2 * beta + B * (nt * beta + 2));
+  const int bt = pick_bt(batch, 4);
+  const int ntiles = (batch + bt - 1) / bt;
+  const int grid = (ctx->N / TPB) * G.pqn * ntiles;
   KTimer tm(ctx, s);
-  hipLaunchKernelGGL(ks_acc_kernel, dim3(ctx->N / TPB, G.pqn, batch), dim3(TPB), 0, s, T, G, ctx->L,
-                     digits_bstride, c0_bstride, base, base_bstride, out, out_bstride, ctx->d_pinfo);
-  tm.lap(TK_KS_ACC, 8.0 * ctx->N * batch * (qn * wq + K * wp), 2.0 * nt * beta * ctx->N * batch * (qn + K));
+#define KSACC(BT_)                                                                                     \
+  hipLaunchKernelGGL((ks_acc_kernel<BT_>), dim3(grid), dim3(TPB), 0, s, T, G, ctx->L, batch, ntiles,   \
+                     digits_bstride, c0_bstride, base, base_bstride, out, out_bstride, ctx->d_pinfo)
+  switch (bt) {
+    case 1: KSACC(1); break;
+    case 2: KSACC(2); break;
+    default: KSACC(4); break;
+  }
+#undef KSACC
+  tm.lap(TK_KS_ACC, 8.0 * ctx->N * words, 2.0 * nt * beta * ctx->N * B * (qn + K));
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
 }
@@ -537,7 +653,9 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
       continue;
     }
     uint64_t g = 1;
-    for (int k = 0; k < b; k++) g = g * 5 % twoN;
+    const int n = ctx->N / 2;
+    const int e = ((plan->sign * b) % n + n) % n;
+    for (int k = 0; k < e; k++) g = g * 5 % twoN;
     auto it = ctx->keys.find((uint32_t)g);
     if (it == ctx->keys.end()) {
       set_error("no evaluation key loaded for rotation %d (galois %llu)", b, (unsigned long long)g);
@@ -548,29 +666,43 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   }
   const int level = plan->level;
   LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn};
+  if (G.beta > MAXBETA) {
+    set_error("key switching with %d digits (at most %d)", G.beta, MAXBETA);
+    return HELRM_EINVAL;
+  }
   if (batch == 0 || ng == 0) return HELRM_OK;
-  dim3 grid(ctx->N / TPB, G.pqn, batch);
-  // per coefficient: rotated babies read beta digits + 2 beta key words (+ c0 on Q limbs),
-  // b = 0 reads c0, c1 (Q limbs); each present diagonal one plaintext word; 2 ng outputs.
+  // algorithmic words per coefficient: keys and plaintexts once per launch, the rest per ciphertext
   double npt = 0;
   for (int gi = 0; gi < ng; gi++)
     for (int b : plan->babies)
       if (plan->slot[(size_t)(g0 + gi) * plan->n1 + b] >= 0) npt++;
   const double nrot = BA.nb - (plan->babies[0] == 0 ? 1 : 0), has0 = plan->babies[0] == 0 ? 1 : 0;
-  const double qn = level + 1, K = ctx->K, beta = G.beta;
-  const double wq = nrot * (3 * beta + 1) + 2 * has0 + npt + 2 * ng, wp = nrot * 3 * beta + npt + 2 * ng;
+  const double qn = level + 1, K = ctx->K, beta = G.beta, B = batch;
+  const double words = qn * (nrot * 2 * beta + npt + B * (nrot * (beta + 1) + 2 * has0 + 2 * ng)) +
+                       K * (nrot * 2 * beta + npt + B * (nrot * beta + 2 * ng));
+  const int gt = ng <= 1 ? 1 : ng <= 2 ? 2 : ng <= 4 ? 4 : 8;
+  const int bt = pick_bt(batch, gt >= 4 ? 1 : gt == 2 ? 2 : 4);
+  const int ntiles = (batch + bt - 1) / bt;
+  const int grid = (ctx->N / TPB) * G.pqn * ntiles;
   KTimer tm(ctx, s);
-#define BABY(GT_)                                                                                      \
-  hipLaunchKernelGGL((baby_mac_kernel<GT_>), grid, dim3(TPB), 0, s, BA, G, ctx->L, digits, digits_bstride, \
-                     ct, ct_bstride, plan->d_pt, plan->d_slot, plan->n1, g0, ng, X, x_bstride,         \
-                     ctx->d_pinfo)
-  if (ng <= 1) BABY(1);
-  else if (ng <= 2) BABY(2);
-  else if (ng <= 4) BABY(4);
-  else BABY(8);
+#define BABY(GT_, BT_)                                                                                   \
+  hipLaunchKernelGGL((baby_mac_kernel<GT_, BT_>), dim3(grid), dim3(TPB), 0, s, BA, G, ctx->L, batch,      \
+                     ntiles, digits, digits_bstride, ct, ct_bstride, plan->d_pt, plan->d_slot, plan->n1,  \
+                     g0, ng, X, x_bstride, ctx->d_pinfo)
+  if (gt == 1) {
+    if (bt == 1) BABY(1, 1);
+    else if (bt == 2) BABY(1, 2);
+    else BABY(1, 4);
+  } else if (gt == 2) {
+    if (bt == 1) BABY(2, 1);
+    else BABY(2, 2);
+  } else if (gt == 4) {
+    BABY(4, 1);
+  } else {
+    BABY(8, 1);
+  }
 #undef BABY
-  tm.lap(TK_BABY_MAC, 8.0 * ctx->N * batch * (qn * wq + K * wp),
-         (2.0 * nrot * beta + 2.0 * npt) * ctx->N * batch * (qn + K));
+  tm.lap(TK_BABY_MAC, 8.0 * ctx->N * words, (2.0 * nrot * beta + 2.0 * npt) * ctx->N * B * (qn + K));
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
 }

@@ -103,8 +103,9 @@ def fold_stages(n: int, m: int, radix: int) -> List[Tuple[int, int]]:
     return out
 
 
-def bsgs_diagonals(M: np.ndarray, n: int, n1: int) -> Tuple[int, int, Dict[int, np.ndarray]]:
-    """Non-zero hybrid diagonals, pre-rotated for BSGS, keyed by k = n1 g + b."""
+def bsgs_diagonals(M: np.ndarray, n: int, n1: int, sign: int = 1) -> Tuple[int, int, Dict[int, np.ndarray]]:
+    """Non-zero hybrid diagonals u_k[j] = M[j mod m][(j + sign k) mod n],
+    pre-rotated for BSGS (v = rot(u_k, -sign n1 g)), keyed by k = n1 g + b."""
     rows, cols = M.shape
     if cols > n:
         raise ValueError(f"matrix has {cols} columns, more than the {n} slots")
@@ -115,12 +116,20 @@ def bsgs_diagonals(M: np.ndarray, n: int, n1: int) -> Tuple[int, int, Dict[int, 
     R[:rows, :cols] = M
     out = {}
     for k in range(m):
-        u = R[j % m, (j + k) % n]
+        u = R[j % m, (j + sign * k) % n]
         if not u.any():
             continue
         g = k // n1
-        out[k] = np.roll(u, n1 * g)     # rot(u, -n1 g)
+        out[k] = np.roll(u, sign * n1 * g)     # rot(u, -sign n1 g)
     return m, n2, out
+
+
+def fold_span(rows: int, cols: int, n: int, sign: int) -> int:
+    """With sign -1 the partial sums occupy [0, cols + m - 1) without wrapping,
+    so the fold only has to cover the next power of two above that."""
+    if sign == 1:
+        return n
+    return min(n, next_pow2(cols + next_pow2(rows) - 1))
 
 
 @dataclass
@@ -134,27 +143,31 @@ class PlanSpec:
     coeffs: np.ndarray            # int64 [n_diag][N]
     rows: int
     stages: List[Tuple[int, int]] = field(default_factory=list)
+    sign: int = 1
+    span: int = 0
 
     def rotation_steps(self) -> List[int]:
         st = set()
         for k in self.diag:
             g, b = divmod(k, self.n1)
             if b:
-                st.add(b)
+                st.add(self.sign * b)
             if g:
-                st.add(self.n1 * g)
+                st.add(self.sign * self.n1 * g)
         for s, r in self.stages:
             st.update(t * s for t in range(1, r))
         return sorted(st)
 
 
-def make_plan(M: np.ndarray, N: int, level: int, scale: float, n1: int, radix: int = 2) -> PlanSpec:
+def make_plan(M: np.ndarray, N: int, level: int, scale: float, n1: int, radix: int = 2,
+              sign: int = -1) -> PlanSpec:
     n = N // 2
-    m, n2, vals = bsgs_diagonals(M, n, n1)
+    m, n2, vals = bsgs_diagonals(M, n, n1, sign)
     diag = sorted(vals)
     coeffs = np.stack([encoding.encode(vals[k], scale, N) for k in diag]) if diag else np.zeros((0, N), np.int64)
+    span = fold_span(M.shape[0], M.shape[1], n, sign)
     return PlanSpec(level=level, m=m, n1=n1, n2=n2, radix=radix, diag=diag, coeffs=coeffs,
-                    rows=M.shape[0], stages=fold_stages(n, m, radix))
+                    rows=M.shape[0], stages=fold_stages(span, m, radix), sign=sign, span=span)
 
 
 def galois(step: int, N: int) -> int:

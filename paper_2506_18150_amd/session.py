@@ -20,7 +20,7 @@ from .params import ParamSet
 
 class LookupSession:
     def __init__(self, prm: ParamSet, tables: Sequence[planner.Table], level: int, n1: int, radix: int,
-                 key_draws_fn, ctx: Optional[Context] = None):
+                 key_draws_fn, ctx: Optional[Context] = None, sign: int = -1):
         """key_draws_fn(galois_list) -> key draws (secret, public-key and
         switching-key randomness) for those Galois elements."""
         self.prm = prm
@@ -28,9 +28,10 @@ class LookupSession:
         self.level = level
         self.ctx = ctx or Context(prm.log_n, prm.q, prm.p, prm.alpha)
         self.M = planner.packed_matrix(self.tables)
-        self.spec = planner.make_plan(self.M, prm.N, level, float(prm.q[level]), n1, radix)
+        self.spec = planner.make_plan(self.M, prm.N, level, float(prm.q[level]), n1, radix, sign)
         self.plan: Plan = self.ctx.helrm_plan_create(level, self.spec.m, self.spec.n1, self.spec.n2,
-                                                     self.spec.radix, self.spec.diag, self.spec.coeffs)
+                                                     self.spec.radix, self.spec.diag, self.spec.coeffs,
+                                                     self.spec.sign, self.spec.span)
         steps = self.plan.rotation_steps()
         assert steps == self.spec.rotation_steps()
         self.galois = [planner.galois(s, prm.N) for s in steps]

@@ -31,7 +31,8 @@ def load_keys(ctx, keys: O.Keys):
 def gpu_plan(ctx, plan: O.Plan):
     diag = sorted(g * plan.n1 + b for (g, b) in plan.coeffs)
     coeffs = np.stack([plan.coeffs[divmod(k, plan.n1)] for k in diag])
-    return ctx.helrm_plan_create(plan.level, plan.m, plan.n1, plan.n2, plan.radix, diag, coeffs)
+    return ctx.helrm_plan_create(plan.level, plan.m, plan.n1, plan.n2, plan.radix, diag, coeffs,
+                                 plan.sign, plan.span)
 
 
 def to_dev(a: np.ndarray):

@@ -213,29 +213,75 @@ def test_lookup_parity_cfg1(ctx1, w1):
     assert_bit_exact(alone[0], glk[1], "batch invariance")
 
 
-@pytest.mark.parametrize("n1,radix,compressed", [(16, 2, True), (2, 8, True), (4, 2, False), (1, 4, True)])
-def test_lookup_schedules_cfg1(n1, radix, compressed, p1):
+@pytest.mark.parametrize("n1,radix,compressed,sign", [(16, 2, True, 1), (2, 8, True, 1), (4, 2, False, 1),
+                                                       (1, 4, True, 1), (4, 2, True, -1), (16, 8, False, -1)])
+def test_lookup_schedules_cfg1(n1, radix, compressed, sign, p1):
     ctx = context_for(p1)
-    w = W.config1(n_queries=1, n1=n1, radix=radix, compressed=compressed)
+    w = W.config1(n_queries=1, n1=n1, radix=radix, compressed=compressed, sign=sign)
     load_keys(ctx, w.keys)
     _check_lookup(ctx, w, gpu_plan(ctx, w.plan), [0])
 
 
-def cfg2_workload(level, n1=16, radix=2, n_queries=1):
+def cfg2_workload(level, n1=16, radix=2, n_queries=1, sign=1):
     prm = O.config2_params()
     g = synth.rng(0)
     t = W.compressed_table(g, 65536, 16, 256, -0.05, 0.05)
-    return W.build(prm, [t], level=level, n1=n1, radix=radix, n_queries=n_queries)
+    return W.build(prm, [t], level=level, n1=n1, radix=radix, n_queries=n_queries, sign=sign)
 
 
-@pytest.mark.parametrize("level,n1,radix", [(1, 16, 2), (4, 4, 2), (4, 16, 8)])
-def test_lookup_parity_cfg2(level, n1, radix, ctx2):
-    w = cfg2_workload(level, n1, radix)
+@pytest.mark.parametrize("level,n1,radix,sign", [(1, 16, 2, 1), (4, 4, 2, 1), (4, 16, 8, 1), (4, 16, 8, -1),
+                                                 (1, 4, 4, -1)])
+def test_lookup_parity_cfg2(level, n1, radix, sign, ctx2):
+    w = cfg2_workload(level, n1, radix, sign=sign)
     load_keys(ctx2, w.keys)
     _check_lookup(ctx2, w, gpu_plan(ctx2, w.plan), [0])
 
 
-def test_lookup_parity_cfg2_full_level(ctx2):
-    w = cfg2_workload(23, 16, 2)
+@pytest.mark.parametrize("radix,sign", [(2, 1), (8, -1)])
+def test_lookup_parity_cfg2_full_level(radix, sign, ctx2):
+    w = cfg2_workload(23, 16, radix, sign=sign)
     load_keys(ctx2, w.keys)
     _check_lookup(ctx2, w, gpu_plan(ctx2, w.plan), [0])
+
+
+def test_lookup_batched_ragged_cfg2(ctx2):
+    """Batch of 5 at level 1 (tiles of 4 plus a ragged tail of 1): every
+    ciphertext bit-exact against the oracle and identical to its batch-1 result."""
+    w = cfg2_workload(1, 16, 8, n_queries=5)
+    load_keys(ctx2, w.keys)
+    plan = gpu_plan(ctx2, w.plan)
+    glk = _check_lookup(ctx2, w, plan, [0, 1, 2, 3, 4])
+    for i in (0, 4):
+        alone = _check_lookup(ctx2, w, plan, [i])
+        assert_bit_exact(alone[0], glk[i], f"batch invariance query {i}")
+
+
+def test_graph_capture_replays(ctx1, w1):
+    """The batched lookup captured in a HIP graph: every replay (with eager
+    work and synchronisation between replays) equals the eager result."""
+    import torch
+    plan = gpu_plan(ctx1, w1.plan)
+    B_ = 3
+    cts = to_dev(np.stack(w1.cts[:B_]))
+    eager = empty(B_, 2, w1.level, w1.prm.N)
+    ctx1.helrm_lookup_packed(plan, cts, B_, eager)
+    want = to_host(eager)
+    s = torch.cuda.Stream()
+    out = empty(B_, 2, w1.level, w1.prm.N)
+    ctx1.helrm_reserve(plan, B_, s)
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ctx1.helrm_lookup_packed(plan, cts, B_, out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    say("graph capture of lookup_packed batch=3")
+    with torch.cuda.graph(g, stream=s):
+        ctx1.helrm_lookup_packed(plan, cts, B_, out)
+    for rep in range(4):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert_bit_exact(to_host(out), want, f"graph replay {rep}")
+        ctx1.helrm_lookup_packed(plan, cts, B_, eager)   # eager work between replays
+        torch.cuda.synchronize()

@@ -40,14 +40,16 @@ def test_digits_worked_example():
 def test_plan_matches_oracle_diagonals():
     rng = synth.rng(3)
     M = rng.uniform(-1, 1, (24, 300))
-    for n1 in (4, 16):
-        m, n2, vals = planner.bsgs_diagonals(M, 512, n1)
-        om, on2, ovals = O.bsgs_plan_values(M, 512, n1)
+    for n1, sign in ((4, 1), (16, 1), (4, -1), (16, -1)):
+        m, n2, vals = planner.bsgs_diagonals(M, 512, n1, sign)
+        om, on2, ovals = O.bsgs_plan_values(M, 512, n1, sign)
         assert (m, n2) == (om, on2)
         assert sorted(vals) == sorted(g * n1 + b for (g, b) in ovals)
         for (g, b), v in ovals.items():
             assert np.array_equal(vals[g * n1 + b], v)
     assert planner.fold_stages(32768, 16, 8) == O.fold_stages(32768, 16, 8)
+    for sign in (1, -1):
+        assert planner.fold_span(24, 300, 512, sign) == O.fold_span(M, 512, sign)
 
 
 def test_selector_and_rows_match_oracle():
@@ -65,7 +67,11 @@ def test_selector_and_rows_match_oracle():
 
 def test_plan_spec_rotation_steps():
     M = np.ones((16, 512))
-    spec = planner.make_plan(M, 1 << 16, 23, 2.0 ** 40, 16, 2)
+    spec = planner.make_plan(M, 1 << 16, 23, 2.0 ** 40, 16, 2, sign=1)
     assert spec.m == 16 and spec.n2 == 1 and len(spec.stages) == 11
     assert len(spec.rotation_steps()) == 26
+    spec = planner.make_plan(M, 1 << 16, 23, 2.0 ** 40, 16, 8, sign=-1)
+    assert spec.span == 1024 and spec.stages == [(128, 8), (16, 8)]
+    assert spec.rotation_steps()[:15] == list(range(-15, 0))
+    assert len(spec.rotation_steps()) == 15 + 14
     assert planner.compress_rule(501, 500) and not planner.compress_rule(500, 500)

@@ -39,9 +39,9 @@ def uncompressed_table(g, rows: int, d: int, lo: float, hi: float) -> O.TableSpe
 
 
 def build(prm: O.Params, tables: List[O.TableSpec], level: int, n1: int, radix: int,
-          n_queries: int, seed: int = 0, key_seed: int = 0) -> Workload:
+          n_queries: int, seed: int = 0, key_seed: int = 0, sign: int = 1) -> Workload:
     M = O.pack_tables(tables)
-    plan = O.make_plan(prm, M, level, n1, radix)
+    plan = O.make_plan(prm, M, level, n1, radix, sign)
     gals = [O.galois_for_step(k, prm) for k in plan.rotation_steps()]
     draws = synth.key_draws(key_seed, prm.N, prm.q, prm.p, prm.dnum, gals)
     keys = O.keygen(prm, draws)
@@ -59,7 +59,7 @@ def build(prm: O.Params, tables: List[O.TableSpec], level: int, n1: int, radix: 
                     cts=cts, expected=expected, level=level, draws=draws)
 
 
-def config1(n_queries: int = 2, compressed: bool = True, n1: int = 4, radix: int = 2) -> Workload:
+def config1(n_queries: int = 2, compressed: bool = True, n1: int = 4, radix: int = 2, sign: int = 1) -> Workload:
     """Toy ring N=2^12: one 256-row x 16 table, values U[-1,1]; base-16
     digits (2 digits, 32 selector slots) or an uncompressed 256-slot control."""
     prm = O.config1_params()
@@ -68,7 +68,7 @@ def config1(n_queries: int = 2, compressed: bool = True, n1: int = 4, radix: int
         t = compressed_table(g, 256, 16, 16, -1.0, 1.0)
     else:
         t = uncompressed_table(g, 256, 16, -1.0, 1.0)
-    return build(prm, [t], level=prm.L, n1=n1, radix=radix, n_queries=n_queries)
+    return build(prm, [t], level=prm.L, n1=n1, radix=radix, n_queries=n_queries, sign=sign)
 
 
 def decrypt_slots(w: Workload, ct: np.ndarray, scale: float, count: int) -> np.ndarray:
