@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark: encrypted packed embedding lookups on one MI355X.
 
-Default workload ("w2"): N = 2^16, 24 ciphertext primes (60 + 23 x 40 bits),
-dnum = 3 with 8 special 60-bit primes; one 65,536-row x 16 table stored as two
-256 x 16 digit tables (base 256, values U[-0.05, 0.05]); one selector
-ciphertext per call at level 23; double-hoisted BSGS (n1 = 16 baby steps)
-with a fold of the given radix, then rescale.  A step is one
-helrm_lookup_packed call over one batch of selector ciphertexts already
-resident in HBM.  Inputs are seeded synthetic data of the paper's shapes.
+Workloads (seeded synthetic data of the paper's shapes):
+  w2  N = 2^16, 24 ciphertext primes (60 + 23 x 40 bits), dnum = 3 with 8
+      special 60-bit primes; one 65,536-row x 16 table stored as two 256 x 16
+      digit tables (base 256, values U[-0.05, 0.05]); selector at level 23.
+  w3  same parameters; 26 tables with log-uniform row counts in [4, 1e7]
+      (~3.4e7 rows), 16-dim, base 256 (tables of at most 256 rows stay
+      uncompressed), all packed block-diagonally into one selector ciphertext
+      per query; batch of 64 queries.
+A step is one helrm_lookup_packed call over one batch of selector ciphertexts
+already resident in HBM; a lookup is one (query, table) embedding row.
 
-After the timed region the same steps run again with per-kernel HIP-event
-timing enabled in the library; the dominant kernel's algorithmic bytes over
-its measured time give the roofline entry.  The CPU oracle is then timed on
-one lookup of the same workload (cpu_baseline).
+The schedule (n1, fold radix, rotation direction, kernel tiles) comes from the
+autotuner's record for this workload shape when there is one
+(paper_2506_18150_amd/tuned.json), else the defaults below; --autotune
+re-measures it first.  After the timed region the same steps run again with
+per-kernel HIP-event timing in the library: the dominant kernel's algorithmic
+bytes over its measured time give the roofline entry.  The CPU oracle is then
+timed on one lookup of the same workload (cpu_baseline).
 
 Prints one JSON line.
 """
@@ -34,27 +40,28 @@ KERNEL_SYMBOL = {
     "ntt_inv_blk": "ntt_pass_kernel<4, false, false>", "ntt_inv_col": "ntt_pass_kernel<4, false, true>",
     "conv": "conv_kernel", "ks_acc": "ks_acc_kernel", "baby_mac": "baby_mac_kernel", "sub_mul": "sub_mul_kernel",
 }
-
-
+DEFAULTS = {"w2": dict(n1=16, radix=8, sign=-1, batch=1), "w3": dict(n1=64, radix=8, sign=-1, batch=64)}
 PMC_PROFILES = {"ks_acc": "profiles/ks_acc_kernel_w2_level23_radix8_pmc.json"}
 
 
-def measured_traffic(kernel: str, level: int, radix: int, n1: int, batch: int, sign: int):
+def measured_traffic(kernel: str, workload: str, level: int, radix: int, n1: int, batch: int, sign: int):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE counter
     runs (scaled by the copy-kernel calibration), or None when there is no
     such record for this kernel and workload or the kernel source changed
     since the counters were taken."""
     import hashlib
     path = PMC_PROFILES.get(kernel)
-    if not path or (level, radix, n1, batch, sign) != (23, 8, 16, 1, 1):
+    if not path:
         return None
     try:
         with open(os.path.join(ROOT, path)) as f:
             rec = json.load(f)
         src = b"".join(open(os.path.join(ROOT, p), "rb").read() for p in rec["source_files"])
-    except OSError:
+    except (OSError, KeyError):
         return None
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    if rec.get("config") != dict(workload=workload, level=level, radix=radix, n1=n1, batch=batch, sign=sign):
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -64,29 +71,55 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="w2", choices=["w2", "w3"])
     ap.add_argument("--level", type=int, default=23)
-    ap.add_argument("--n1", type=int, default=16)
-    ap.add_argument("--radix", type=int, default=8)
-    ap.add_argument("--batch", type=int, default=1)
-    ap.add_argument("--sign", type=int, default=-1, choices=[1, -1],
+    ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--n1", type=int, default=None)
+    ap.add_argument("--radix", type=int, default=None)
+    ap.add_argument("--sign", type=int, default=None, choices=[1, -1],
                     help="direction of the diagonal rotations; -1 lets the fold stop at the occupied window")
+    ap.add_argument("--ks-tile", type=int, default=None)
+    ap.add_argument("--baby-tile", type=int, default=None)
+    ap.add_argument("--autotune", action="store_true", help="measure candidate schedules first")
+    ap.add_argument("--autotune-out", default=None, help="write the tuning record to this file")
     ap.add_argument("--graph", action="store_true", help="replay one captured HIP graph per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the request loop (26 tables in groups, Poisson arrivals) instead of the step loop")
+    ap.add_argument("--rates", default="5,20,50,100,200", help="arrival rates (requests/s) for --serve")
+    ap.add_argument("--requests", type=int, default=200, help="requests per rate for --serve")
+    ap.add_argument("--group-size", type=int, default=4)
+    ap.add_argument("--max-batch", type=int, default=16)
+    ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the run, copy a 1 GiB buffer 3 times (reference kernel for HBM counters)")
     return ap.parse_args()
 
 
-def w2_tables(synth, planner):
+def make_tables(workload: str, synth, planner):
+    """Seeded synthetic tables.  w2: one 65,536-row table as two base-256
+    digit tables.  w3: 26 tables with log-uniform row counts (the first seed
+    whose total lies in [3.0e7, 3.8e7])."""
     g = synth.rng(0)
-    parts = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(2)]
-    return [planner.Table(rows=65536, d=16, base=256, parts=parts)]
+    if workload == "w2":
+        parts = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(2)]
+        return [planner.Table(rows=65536, d=16, base=256, parts=parts)]
+    _, counts = synth.criteo_like_row_counts()
+    tables = []
+    for k in counts:
+        if k <= 256:
+            tables.append(planner.Table(rows=k, d=16, full=synth.uniform_table(g, k, 16, -0.05, 0.05)))
+        else:
+            nd = planner.n_digits(k, 256)
+            parts = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(nd)]
+            tables.append(planner.Table(rows=k, d=16, base=256, parts=parts))
+    return tables
 
 
-def cpu_baseline(level: int, n1: int, radix: int, sign: int):
-    """The CPU oracle on one lookup of the same workload (keys, plan encoding
-    and encryption untimed)."""
+def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int):
+    """The CPU oracle on one selector ciphertext of the same workload (keys,
+    plan encoding and encryption untimed)."""
     import numpy as np
 
     import synth
@@ -95,25 +128,117 @@ def cpu_baseline(level: int, n1: int, radix: int, sign: int):
     O.build()
     prm = O.config2_params()
     g = synth.rng(0)
-    C = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(2)]
-    t = O.TableSpec(rows=65536, d=16, base=256, C=C)
-    plan = O.make_plan(prm, O.pack_tables([t]), level, n1, radix, sign)
+    if workload == "w2":
+        C = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(2)]
+        tables = [O.TableSpec(rows=65536, d=16, base=256, C=C)]
+    else:
+        _, counts = synth.criteo_like_row_counts()
+        tables = []
+        for k in counts:
+            if k <= 256:
+                tables.append(O.TableSpec(rows=k, d=16, E=synth.uniform_table(g, k, 16, -0.05, 0.05)))
+            else:
+                C = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(O.num_digits(k, 256))]
+                tables.append(O.TableSpec(rows=k, d=16, base=256, C=C))
+    plan = O.make_plan(prm, O.pack_tables(tables), level, n1, radix, sign)
     gals = [O.galois_for_step(k, prm) for k in plan.rotation_steps()]
     keys = O.keygen(prm, synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals))
     qg = synth.rng(1)
-    idx = synth.indices(qg, [t.rows])
-    ct = O.encrypt(prm, keys, O.encode(O.pack_selector([t], idx), prm.delta, prm), level,
+    idx = synth.indices(qg, [t.rows for t in tables])
+    ct = O.encrypt(prm, keys, O.encode(O.pack_selector(tables, idx), prm.delta, prm), level,
                    synth.enc_draws(qg, prm.N))
     pts = O.plan_residues(prm, plan)
     t0 = time.perf_counter()
     out = O.lookup(prm, keys, plan, ct, pts)
     dt = time.perf_counter() - t0
-    got = O.decode(O.decrypt(prm, keys, out), prm.delta, prm)[:16].real
-    err = float(np.max(np.abs(got - t.lookup(idx[0]))))
+    rows = len(tables) * 16
+    got = O.decode(O.decrypt(prm, keys, out), prm.delta, prm)[:rows].real
+    ref = np.concatenate([t.lookup(i) for t, i in zip(tables, idx)])
+    err = float(np.max(np.abs(got - ref)))
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / dt, "unit": "lookups/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 lookup of the same workload (level {level}, n1={n1}, radix {radix}, sign {sign}); "
-                      f"{dt:.2f} s; decrypted max error {err:.1e}; keygen/encoding untimed"}
+    return {"value": len(tables) / dt, "unit": "lookups/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 selector ciphertext ({len(tables)} lookups) of the same workload (level {level}, "
+                      f"n1={n1}, radix {radix}, sign {sign}); {dt:.2f} s; decrypted max error {err:.1e}; "
+                      f"keygen/encoding untimed"}
+
+
+def serve_bench(args):
+    """The request loop on the 26-table set: tables in fixed groups of
+    --group-size, one selector ciphertext per touched group, Poisson arrivals,
+    each request touching r ~ U{1..26} distinct tables.  Selector ciphertexts
+    wait in pinned host memory (a pool per group, encrypted before the run:
+    cost is data-oblivious) and are copied in and out by the loop.  Compared
+    with the plain per-request path: one stream, one ciphertext per call."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_18150_amd import params, planner
+    from paper_2506_18150_amd.serving import GpuExecutor, RealClock, Request, Server
+    from paper_2506_18150_amd.session import GroupedDeployment
+
+    prm = params.n16()
+    tables = make_tables("w3", synth, planner)
+    t0 = time.time()
+    dep = GroupedDeployment(prm, tables, args.group_size, args.level, args.n1 or 16, args.radix or 8,
+                            lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals),
+                            sign=args.sign or -1)
+    eg = synth.rng(11)
+    pool = []
+    for g, grp in enumerate(dep.groups):
+        cts = []
+        for _ in range(4):
+            touched = {t: int(eg.integers(0, tables[t].rows)) for t in grp}
+            cts.append(dep.encrypt_group(g, touched, synth.enc_draws(eg, prm.N)).cpu().pin_memory())
+        pool.append(cts)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    total = torch.cuda.get_device_properties(0).total_memory
+    static = dep.key_bytes + dep.plan_bytes
+    out = {"rates": []}
+    rg = synth.rng(12)
+    for rate in [float(x) for x in args.rates.split(",")]:
+        arr = synth.poisson_arrivals(rg, rate, args.requests)
+        specs = []
+        for i in range(args.requests):
+            r = int(rg.integers(1, len(tables) + 1))
+            ts = rg.choice(len(tables), size=r, replace=False)
+            groups = sorted({dep.group_of(int(t)) for t in ts})
+            specs.append((float(arr[i]), r, [(g, pool[g][int(rg.integers(0, len(pool[g])))]) for g in groups]))
+        row = {"rate": rate}
+        for mode, streams, mb in (("served", args.streams, args.max_batch), ("plain", 1, 1)):
+            ex = GpuExecutor(dep.ctx, dep.plans, args.level, prm.N, n_streams=streams, max_batch=mb,
+                             static_bytes=static)
+            srv = Server(ex, RealClock(), len(dep.groups), hbm_budget=int(total * 0.9), max_batch=mb,
+                         admit_timeout=30.0)
+            reqs = [Request(rid=i, arrival=a, units=u) for i, (a, _, u) in enumerate(specs)]
+            rep = srv.run(reqs)
+            looked = sum(specs[r.rid][1] for r in srv.completed)
+            rep["lookups_per_s"] = looked / rep["span_s"] if rep["span_s"] > 0 else 0.0
+            row[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in rep.items()}
+            del ex, srv
+            torch.cuda.synchronize()
+        out["rates"].append(row)
+    best = max(out["rates"], key=lambda r: r["served"]["lookups_per_s"])
+    res = {
+        "metric": "served encrypted lookups/s",
+        "value": best["served"]["lookups_per_s"],
+        "unit": "lookups/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"w5: 26 tables (w3 set) in {len(dep.groups)} groups of {args.group_size}, "
+                               f"selectors at level {args.level}, Poisson arrivals, {args.requests} requests per "
+                               f"rate, r ~ U{{1..26}} tables per request; served: {args.streams} streams, batches "
+                               f"of up to {args.max_batch}; plain: 1 stream, 1 ciphertext per call",
+                   "level": args.level, "group_size": args.group_size},
+        "latency_ms": {"p50": best["served"]["p50_ms"], "p99": best["served"]["p99_ms"]},
+        "serving": out,
+        "setup_s": round(setup_s, 1),
+        "resident_bytes": {"keys": dep.key_bytes, "plans": dep.plan_bytes},
+    }
+    print(json.dumps(res))
 
 
 def main():
@@ -121,21 +246,46 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU benchmark: run with --gpus 1 (multi-GPU is not built)"}))
         sys.exit(2)
+    if args.serve:
+        return serve_bench(args)
     import numpy as np
     import torch
 
     import synth
-    from paper_2506_18150_amd import params, planner
+    from paper_2506_18150_amd import autotune, params, planner
     from paper_2506_18150_amd.session import LookupSession
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     prm = params.n16()
-    tables = w2_tables(synth, planner)
+    tables = make_tables(args.workload, synth, planner)
+    M = planner.packed_matrix(tables)
+    dflt = DEFAULTS[args.workload]
+    B = args.batch or dflt["batch"]
+    key_fn = lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals)
+    tune_rec = None
+    if args.autotune:
+        eg = synth.rng(7)
+        cands = None
+        if args.workload == "w3":
+            cands = [autotune.Schedule(n1, r, -1) for n1 in (32, 64) for r in (4, 8)]
+        tune_rec = autotune.tune(prm, tables, args.level, B, key_fn, lambda: synth.enc_draws(eg, prm.N),
+                                 schedules=cands, steps=3)
+        if args.autotune_out:
+            autotune.record(tune_rec, args.autotune_out)
+    sched = autotune.tuned_schedule(prm.N, prm.L, args.level, M.shape[0], M.shape[1], B)
+    if tune_rec is not None:
+        b = tune_rec["best"]
+        sched = autotune.Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"])
+    if sched is None:
+        sched = autotune.Schedule(dflt["n1"], dflt["radix"], dflt["sign"])
+    n1 = args.n1 or sched.n1
+    radix = args.radix or sched.radix
+    sign = args.sign or sched.sign
     t0 = time.time()
-    sess = LookupSession(prm, tables, args.level, args.n1, args.radix,
-                         lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals), sign=args.sign)
+    sess = LookupSession(prm, tables, args.level, n1, radix, key_fn, sign=sign)
+    sess.ctx.helrm_set_tuning("ks_tile", args.ks_tile or sched.ks_tile)
+    sess.ctx.helrm_set_tuning("baby_tile", args.baby_tile or sched.baby_tile)
     setup_s = time.time() - t0
-    B = args.batch
     qg = synth.rng(1)
     idx = [synth.indices(qg, [t.rows for t in tables]) for _ in range(B)]
     sel = sess.encrypt(idx, [synth.enc_draws(qg, prm.N) for _ in range(B)])
@@ -173,10 +323,10 @@ def main():
     lookups_per_step = B * len(tables)
     value = lookups_per_step / (ms_per_step / 1e3)
 
-    # key switches per lookup: hoisted (baby steps) and full (giant steps + fold)
     spec = sess.spec
     n_hoisted = sum(1 for b in sorted({k % spec.n1 for k in spec.diag}) if b)
     n_full = sum(1 for g in sorted({k // spec.n1 for k in spec.diag}) if g) + sum(r - 1 for _, r in spec.stages)
+    cts_per_s = B / (ms_per_step / 1e3)
     res = {
         "metric": "encrypted lookups/s",
         "value": value,
@@ -190,18 +340,21 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"w2: N=2^16, L=23, dnum=3, K=8; 1 table 65536x16 as 2 base-256 digit tables; "
-                               f"selector at level {args.level}; n1={args.n1}, fold radix {args.radix}, "
-                               f"rotation sign {args.sign} (fold span {sess.spec.span}); "
-                               f"batch {B} ciphertext(s) per call" + (", HIP graph replay" if args.graph else ""),
-                   "level": args.level, "batch": B, "n1": args.n1, "radix": args.radix, "sign": args.sign,
-                   "fold_span": sess.spec.span, "graph": args.graph},
+        "config": {"workload": f"{args.workload}: N=2^16, L=23, dnum=3, K=8; {len(tables)} table(s), packed "
+                               f"{M.shape[0]}x{M.shape[1]}; selector at level {args.level}; n1={n1}, fold radix "
+                               f"{radix}, rotation sign {sign} (fold span {spec.span}); batch {B} ciphertext(s) per "
+                               f"call" + (", HIP graph replay" if args.graph else ""),
+                   "name": args.workload, "level": args.level, "batch": B, "tables": len(tables), "n1": n1,
+                   "radix": radix, "sign": sign, "fold_span": spec.span, "graph": args.graph,
+                   "ks_tile": args.ks_tile or sched.ks_tile, "baby_tile": args.baby_tile or sched.baby_tile},
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
-        "key_switches_per_s": {"hoisted": n_hoisted * value, "full": n_full * value,
-                               "per_lookup": {"hoisted": n_hoisted, "full": n_full}},
+        "key_switches_per_s": {"hoisted": n_hoisted * cts_per_s, "full": n_full * cts_per_s,
+                               "per_ciphertext": {"hoisted": n_hoisted, "full": n_full}},
         "max_abs_err": err,
         "setup_s": round(setup_s, 2),
     }
+    if tune_rec is not None:
+        res["autotune"] = {"best": tune_rec["best"], "candidates": len(tune_rec["results"])}
 
     if not args.no_kernel_timing:
         sess.ctx.helrm_timing_enable(True)
@@ -221,13 +374,15 @@ def main():
         d = table[dom]
         res["roofline"] = {"kernel": KERNEL_SYMBOL[dom], "bound": "hbm", "achieved": d["GB/s"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["GB/s"] / HBM_PEAK_GBS,
-                           "traffic": measured_traffic(dom, args.level, args.radix, args.n1, B, args.sign),
+                           "traffic": measured_traffic(dom, args.workload, args.level, radix, n1, B, sign),
                            "avg_us": d["avg_us"], "algorithmic_bytes_per_launch": d["bytes_per_launch"]}
         ks = table.get("ks_acc")
         if ks:
             res["roofline_keyswitch"] = {"kernel": KERNEL_SYMBOL["ks_acc"], "bound": "hbm",
                                          "achieved": ks["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                         "frac": ks["GB/s"] / HBM_PEAK_GBS, "avg_us": ks["avg_us"]}
+                                         "frac": ks["GB/s"] / HBM_PEAK_GBS, "avg_us": ks["avg_us"],
+                                         "traffic": measured_traffic("ks_acc", args.workload, args.level, radix,
+                                                                     n1, B, sign)}
         limb_ntts = (kt["ntt_fwd_col"]["ops"] + kt["ntt_inv_blk"]["ops"]) / ((prm.N // 2) * 8) / args.steps
         res["ntts_per_s"] = limb_ntts * (1e3 / ms_per_step)
         res["kernels"] = {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in table.items()}
@@ -241,7 +396,7 @@ def main():
         res["copy_calibration_bytes"] = 1 << 30
 
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args.level, args.n1, args.radix, args.sign)
+        res["cpu_baseline"] = cpu_baseline(args.workload, args.level, n1, radix, sign)
     print(json.dumps(res))
 
 

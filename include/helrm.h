@@ -234,6 +234,13 @@ int helrm_timing_enable(helrm_ctx *ctx, int enable);
 int helrm_timing_read(helrm_ctx *ctx, const char *kernel, double *ms, int64_t *launches, double *bytes,
                       double *ops);
 
+/* Schedule knobs set by the autotuner.  "ks_tile" and "baby_tile" cap how many
+ * ciphertexts of a batch one thread serves in the key inner product and the
+ * fused baby-step kernel (1, 2 or 4; default 4): larger tiles read each key
+ * and plaintext word fewer times, smaller tiles use fewer registers.  Results
+ * do not depend on the knobs. */
+int helrm_set_tuning(helrm_ctx *ctx, const char *knob, int value);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,142 @@
+"""Schedule autotuner.
+
+For one packed matrix, level and batch size it measures candidate schedules
+on the device -- baby steps n1, fold radix, rotation direction (which fixes
+the fold span) -- and the key-switch / baby-step kernel tiles, and keeps the
+fastest.  Every candidate computes the same product (the schedules differ
+only in rotation bookkeeping and are each replayed bit-exactly by the
+oracle), so the choice is purely a timing decision.  Results are stored per
+workload shape in ``tuned.json`` next to this file and looked up by
+``tuned_schedule``.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from dataclasses import dataclass
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import encoding, planner
+
+TUNED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
+def shape_key(N: int, L: int, level: int, rows: int, cols: int, batch: int) -> str:
+    return f"N{N}_L{L}_level{level}_{rows}x{cols}_batch{batch}"
+
+
+@dataclass
+class Schedule:
+    n1: int
+    radix: int
+    sign: int
+    ks_tile: int = 4
+    baby_tile: int = 4
+
+
+def candidate_schedules(rows: int, cols: int, n: int, n1s=(4, 8, 16, 32, 64), radices=(4, 8, 16),
+                        signs=(-1, 1)) -> List[Schedule]:
+    m = planner.next_pow2(rows)
+    out = []
+    for sign in signs:
+        for n1 in n1s:
+            if n1 > m or n1 > 64:
+                continue
+            for r in radices:
+                out.append(Schedule(n1, r, sign))
+    return out
+
+
+def tuned_schedule(N: int, L: int, level: int, rows: int, cols: int, batch: int,
+                   path: str = TUNED_PATH) -> Optional[Schedule]:
+    try:
+        with open(path) as f:
+            db = json.load(f)
+    except OSError:
+        return None
+    rec = db.get(shape_key(N, L, level, rows, cols, batch))
+    if rec is None:
+        return None
+    b = rec["best"]
+    return Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"])
+
+
+def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
+         schedules: Optional[Sequence[Schedule]] = None, tiles: Iterable[int] = (1, 2, 4),
+         steps: int = 5, log=None) -> Dict:
+    """Measure every schedule (and tile pair when batch > 1) and return
+    {"best": {...}, "results": [...]}.  key_draws_fn(galois) and
+    enc_draws_fn() supply the randomness."""
+    import torch
+
+    from .binding import Context
+    from .client import Client
+
+    ctx = Context(prm.log_n, prm.q, prm.p, prm.alpha)
+    M = planner.packed_matrix(tables)
+    rows, cols = M.shape
+    if schedules is None:
+        schedules = candidate_schedules(rows, cols, prm.n)
+    specs = []
+    steps_union = set()
+    for sc in schedules:
+        spec = planner.make_plan(M, prm.N, level, float(prm.q[level]), sc.n1, sc.radix, sc.sign)
+        specs.append((sc, spec))
+        steps_union.update(spec.rotation_steps())
+    gals = sorted({planner.galois(s, prm.N) for s in steps_union})
+    client = Client(ctx, prm)
+    client.keygen(key_draws_fn(gals), gals)
+    idx = [[0 for _ in tables] for _ in range(batch)]
+    cts = []
+    for q in idx:
+        m = encoding.encode(planner.packed_selector(tables, q), prm.delta, prm.N)
+        cts.append(client.encrypt(m, level, enc_draws_fn()))
+    sel = torch.stack(cts).contiguous()
+    out = torch.zeros(batch, 2, level, prm.N, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    tile_pairs = [(4, 4)] if batch == 1 else [(a, b) for a in tiles for b in tiles]
+    results = []
+    for sc, spec in specs:
+        plan = ctx.helrm_plan_create(level, spec.m, spec.n1, spec.n2, spec.radix, spec.diag, spec.coeffs,
+                                     spec.sign, spec.span)
+        ctx.helrm_reserve(plan, batch, stream)
+        for kt, bt in tile_pairs:
+            ctx.helrm_set_tuning("ks_tile", kt)
+            ctx.helrm_set_tuning("baby_tile", bt)
+            ctx.helrm_lookup_packed(plan, sel, batch, out, stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                ctx.helrm_lookup_packed(plan, sel, batch, out, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            rec = {"n1": sc.n1, "radix": sc.radix, "sign": sc.sign, "span": spec.span, "ks_tile": kt,
+                   "baby_tile": bt, "ms_per_batch": ms, "lookups_per_s": batch * len(tables) / (ms / 1e3),
+                   "keys": len(spec.rotation_steps())}
+            results.append(rec)
+            if log:
+                log(rec)
+        plan.close()
+    best = min(results, key=lambda r: r["ms_per_batch"])
+    ctx.close()
+    return {"key": shape_key(prm.N, prm.L, level, rows, cols, batch), "best": best, "results": results,
+            "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+
+
+def record(result: Dict, path: str = TUNED_PATH) -> None:
+    try:
+        with open(path) as f:
+            db = json.load(f)
+    except OSError:
+        db = {}
+    db[result["key"]] = {"best": result["best"], "when": result["when"],
+                         "candidates": len(result["results"])}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)

@@ -52,6 +52,7 @@ EXPORTS = [
     "helrm_from_signed", "helrm_keyswitch_hoisted", "helrm_rescale", "helrm_plan_create",
     "helrm_plan_destroy", "helrm_plan_rotation_steps", "helrm_ptxt_ct_matvec_diag",
     "helrm_lookup_packed", "helrm_footprint", "helrm_reserve", "helrm_timing_enable", "helrm_timing_read",
+    "helrm_set_tuning",
 ]
 
 _lib = None
@@ -86,6 +87,7 @@ def lib() -> ctypes.CDLL:
     L.helrm_footprint.argtypes = [_vp, _vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.helrm_reserve.argtypes = [_vp, _vp, _c_int, _vp]
     L.helrm_timing_enable.argtypes = [_vp, _c_int]
+    L.helrm_set_tuning.argtypes = [_vp, ctypes.c_char_p, _c_int]
     L.helrm_timing_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]
@@ -223,6 +225,9 @@ class Context:
 
     def helrm_reserve(self, plan: "Plan", batch: int, stream=None):
         _check(lib().helrm_reserve(self.h, plan.h, batch, _stream(stream)))
+
+    def helrm_set_tuning(self, knob: str, value: int):
+        _check(lib().helrm_set_tuning(self.h, knob.encode(), int(value)))
 
     def helrm_timing_enable(self, enable: bool):
         _check(lib().helrm_timing_enable(self.h, 1 if enable else 0))

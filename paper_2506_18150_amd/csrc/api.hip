@@ -1109,3 +1109,19 @@ extern "C" int helrm_timing_read(helrm_ctx *c, const char *kernel, double *ms, i
   return HELRM_OK;
   API_GUARD_END
 }
+
+extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && knob, "NULL argument");
+  CHECK_ARG(value == 1 || value == 2 || value == 4, "tile must be 1, 2 or 4");
+  if (strcmp(knob, "ks_tile") == 0) {
+    c->tune_ks_tile = value;
+  } else if (strcmp(knob, "baby_tile") == 0) {
+    c->tune_baby_tile = value;
+  } else {
+    set_error("unknown tuning knob '%s'", knob);
+    return HELRM_EINVAL;
+  }
+  return HELRM_OK;
+  API_GUARD_END
+}

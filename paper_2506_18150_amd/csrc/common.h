@@ -209,6 +209,8 @@ struct helrm_ctx {
   std::map<uint32_t, KeyEntry> keys;
   std::mutex ws_mu;
   std::map<hipStream_t, Workspace> ws;
+  int tune_ks_tile = 4;      // ciphertexts per thread in ks_acc (1, 2, 4)
+  int tune_baby_tile = 4;    // ciphertexts per thread in baby_mac when one giant output (1, 2, 4)
   bool timing = false;
   std::mutex tmu;
   std::vector<TimingRec> trecs;

@@ -616,7 +616,7 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
   const double qn = level + 1, K = ctx->K, nt = n_terms, beta = G.beta, B = batch;
   const double words = qn * (nt * 2 * beta + B * (nt * beta + nt + (base ? 2 : 0) + 2)) +
                        K * (nt * 2 * beta + B * (nt * beta + 2));
-  const int bt = pick_bt(batch, 4);
+  const int bt = pick_bt(batch, ctx->tune_ks_tile);
   const int ntiles = (batch + bt - 1) / bt;
   const int grid = (ctx->N / TPB) * G.pqn * ntiles;
   KTimer tm(ctx, s);
@@ -681,7 +681,7 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   const double words = qn * (nrot * 2 * beta + npt + B * (nrot * (beta + 1) + 2 * has0 + 2 * ng)) +
                        K * (nrot * 2 * beta + npt + B * (nrot * beta + 2 * ng));
   const int gt = ng <= 1 ? 1 : ng <= 2 ? 2 : ng <= 4 ? 4 : 8;
-  const int bt = pick_bt(batch, gt >= 4 ? 1 : gt == 2 ? 2 : 4);
+  const int bt = pick_bt(batch, gt >= 4 ? 1 : gt == 2 ? std::min(2, ctx->tune_baby_tile) : ctx->tune_baby_tile);
   const int ntiles = (batch + bt - 1) / bt;
   const int grid = (ctx->N / TPB) * G.pqn * ntiles;
   KTimer tm(ctx, s);

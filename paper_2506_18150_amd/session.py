@@ -67,3 +67,64 @@ class LookupSession:
 
     def cleartext(self, idx: Sequence[int]) -> np.ndarray:
         return np.concatenate([t.row(i) for t, i in zip(self.tables, idx)])
+
+
+class GroupedDeployment:
+    """Tables split into fixed groups of consecutive tables, one packed plan
+    per group, all sharing one context and one resident key set (the union of
+    the groups' rotation keys).  A request touching some tables sends one
+    selector ciphertext per touched group; untouched tables of a touched group
+    get an all-zero one-hot block (their rows come out as zeros)."""
+
+    def __init__(self, prm: ParamSet, tables: Sequence[planner.Table], group_size: int, level: int, n1: int,
+                 radix: int, key_draws_fn, sign: int = -1):
+        self.prm, self.level = prm, level
+        self.tables = list(tables)
+        self.groups = [list(range(i, min(i + group_size, len(tables)))) for i in range(0, len(tables), group_size)]
+        self.ctx = Context(prm.log_n, prm.q, prm.p, prm.alpha)
+        self.specs, self.plans = [], []
+        steps = set()
+        for grp in self.groups:
+            M = planner.packed_matrix([self.tables[t] for t in grp])
+            m = planner.next_pow2(M.shape[0])
+            spec = planner.make_plan(M, prm.N, level, float(prm.q[level]), min(n1, m), radix, sign)
+            self.specs.append(spec)
+            self.plans.append(self.ctx.helrm_plan_create(level, spec.m, spec.n1, spec.n2, spec.radix, spec.diag,
+                                                         spec.coeffs, spec.sign, spec.span))
+            steps.update(spec.rotation_steps())
+        self.galois = sorted({planner.galois(s, prm.N) for s in steps})
+        self.client = Client(self.ctx, prm)
+        self.client.keygen(key_draws_fn(self.galois), self.galois)
+        kl = prm.L + 1 + prm.K
+        self.key_bytes = len(self.galois) * prm.dnum * 2 * kl * prm.N * 8
+        self.plan_bytes = sum(len(sp.diag) * (level + 1 + prm.K) * prm.N * 8 for sp in self.specs)
+
+    def group_of(self, table: int) -> int:
+        for g, grp in enumerate(self.groups):
+            if table in grp:
+                return g
+        raise ValueError(table)
+
+    def selector(self, g: int, touched: dict) -> np.ndarray:
+        """Packed one-hots of group g; touched maps table -> index."""
+        parts = []
+        for t in self.groups[g]:
+            tb = self.tables[t]
+            parts.append(tb.one_hot(touched[t]) if t in touched else np.zeros(tb.width))
+        return np.concatenate(parts)
+
+    def encrypt_group(self, g: int, touched: dict, ed) -> torch.Tensor:
+        m = encoding.encode(self.selector(g, touched), self.prm.delta, self.prm.N)
+        return self.client.encrypt(m, self.level, ed)
+
+    def decrypt_group(self, g: int, out: torch.Tensor) -> np.ndarray:
+        m = self.client.decrypt(out.reshape(2, self.level, self.prm.N))
+        rows = 16 * len(self.groups[g])
+        return encoding.decode(m, self.prm.delta, self.prm.N)[:rows].real
+
+    def cleartext_group(self, g: int, touched: dict) -> np.ndarray:
+        out = []
+        for t in self.groups[g]:
+            tb = self.tables[t]
+            out.append(tb.row(touched[t]) if t in touched else np.zeros(tb.d))
+        return np.concatenate(out)
