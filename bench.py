@@ -41,7 +41,8 @@ KERNEL_SYMBOL = {
     "conv": "conv_kernel", "ks_acc": "ks_acc_kernel", "baby_mac": "baby_mac_kernel", "sub_mul": "sub_mul_kernel",
 }
 DEFAULTS = {"w2": dict(n1=16, radix=8, sign=-1, batch=1), "w3": dict(n1=64, radix=8, sign=-1, batch=64)}
-PMC_PROFILES = {"ks_acc": "profiles/ks_acc_kernel_w2_level23_radix8_pmc.json"}
+PMC_PROFILES = {"ks_acc": "profiles/ks_acc_kernel_w2_level23_pmc.json",
+                "baby_mac": "profiles/baby_mac_kernel_w2_level23_pmc.json"}
 
 
 def measured_traffic(kernel: str, workload: str, level: int, radix: int, n1: int, batch: int, sign: int):
@@ -85,6 +86,8 @@ def parse():
     ap.add_argument("--graph", action="store_true", help="replay one captured HIP graph per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--batched", type=int, default=8,
+                    help="also time this batch size on the same plan and keys (0 to skip)")
     ap.add_argument("--serve", action="store_true",
                     help="run the request loop (26 tables in groups, Poisson arrivals) instead of the step loop")
     ap.add_argument("--rates", default="5,20,50,100,200", help="arrival rates (requests/s) for --serve")
@@ -355,6 +358,31 @@ def main():
     }
     if tune_rec is not None:
         res["autotune"] = {"best": tune_rec["best"], "candidates": len(tune_rec["results"])}
+
+    if args.batched and args.batched != B:
+        Bb = args.batched
+        bg = synth.rng(2)
+        bidx = [synth.indices(bg, [t.rows for t in tables]) for _ in range(Bb)]
+        bsel = sess.encrypt(bidx, [synth.enc_draws(bg, prm.N) for _ in range(Bb)])
+        bout = sess.new_output(Bb)
+        sess.ctx.helrm_reserve(sess.plan, Bb, stream)
+        for _ in range(2):
+            sess.lookup(bsel, bout, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        nb = max(3, args.steps // 4)
+        e0.record(stream)
+        for _ in range(nb):
+            sess.lookup(bsel, bout, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bms = e0.elapsed_time(e1) / nb
+        brows = sess.decrypt_rows(bout)
+        berr = max(float(np.max(np.abs(brows[b] - sess.cleartext(bidx[b])))) for b in range(Bb))
+        res["batched"] = {"batch": Bb, "steps": nb, "ms_per_step": bms,
+                          "lookups_per_s": Bb * len(tables) / (bms / 1e3), "max_abs_err": berr,
+                          "vs_plain": (Bb * len(tables) / (bms / 1e3)) / value}
+        del bsel, bout
 
     if not args.no_kernel_timing:
         sess.ctx.helrm_timing_enable(True)

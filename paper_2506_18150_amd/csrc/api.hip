@@ -613,7 +613,15 @@ extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
     pi.pmod_p = shoup_of(Pm, q);
     pi.pinv = Pm ? hinv(Pm, q) : 0;
     pi.pinv_p = shoup_of(pi.pinv, q);
+    pi.qd = (double)q;
+    pi.qinv_d = 1.0 / (double)q;
+    pi.ninv_d = (double)pi.ninv;
     c->h_pinfo.push_back(pi);
+  }
+  std::vector<double> twdf(twf.size()), twdi(twi.size());
+  for (size_t k = 0; k < twf.size(); k++) {
+    twdf[k] = (double)twf[k].w;
+    twdi[k] = (double)twi[k].w;
   }
   // conversion tables
   ConstBuilder cb;
@@ -657,6 +665,8 @@ extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
   if (hipMalloc(&c->d_pinfo, sizeof(PrimeInfo) * c->nprimes) != hipSuccess ||
       hipMalloc(&c->d_tw_fwd, sizeof(TW) * twf.size()) != hipSuccess ||
       hipMalloc(&c->d_tw_inv, sizeof(TW) * twi.size()) != hipSuccess ||
+      hipMalloc(&c->d_twd_fwd, sizeof(double) * twf.size()) != hipSuccess ||
+      hipMalloc(&c->d_twd_inv, sizeof(double) * twi.size()) != hipSuccess ||
       hipMalloc(&c->d_const, sizeof(u64) * cb.words.size()) != hipSuccess) {
     (void)hipGetLastError();
     set_error("device allocation of context tables failed");
@@ -666,6 +676,8 @@ extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
           hipSuccess ||
       hipMemcpy(c->d_tw_fwd, twf.data(), sizeof(TW) * twf.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_tw_inv, twi.data(), sizeof(TW) * twi.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_twd_fwd, twdf.data(), sizeof(double) * twdf.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_twd_inv, twdi.data(), sizeof(double) * twdi.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_const, cb.words.data(), sizeof(u64) * cb.words.size(), hipMemcpyHostToDevice) !=
           hipSuccess) {
     set_error("upload of context tables failed");
@@ -702,6 +714,8 @@ extern "C" int helrm_destroy(helrm_ctx *c) {
   if (c->d_pinfo) (void)hipFree(c->d_pinfo);
   if (c->d_tw_fwd) (void)hipFree(c->d_tw_fwd);
   if (c->d_tw_inv) (void)hipFree(c->d_tw_inv);
+  if (c->d_twd_fwd) (void)hipFree(c->d_twd_fwd);
+  if (c->d_twd_inv) (void)hipFree(c->d_twd_inv);
   if (c->d_const) (void)hipFree(c->d_const);
   delete c;
   return HELRM_OK;

@@ -135,6 +135,8 @@ struct PrimeInfo {
   u64 ninv, ninv_p;    // N^-1 mod q with its Shoup companion
   u64 pmod, pmod_p;    // [P]_q with Shoup companion (P = product of special primes)
   u64 pinv, pinv_p;    // [P^-1]_q (Q primes only)
+  double qd, qinv_d;   // q and 1/q as doubles (fp64 NTT path, q < 2^45)
+  double ninv_d;       // N^-1 mod q as a double
 };
 
 struct TW {
@@ -201,6 +203,8 @@ struct helrm_ctx {
   PrimeInfo *d_pinfo = nullptr;
   TW *d_tw_fwd = nullptr;    // [nprimes][N]: psi^brv(k)
   TW *d_tw_inv = nullptr;    // [nprimes][N]: psi^-brv(k)
+  double *d_twd_fwd = nullptr;  // the same twiddles as doubles (exact for q < 2^45)
+  double *d_twd_inv = nullptr;
   u64 *d_const = nullptr;    // conversion constants
   std::vector<std::vector<ConvTable>> modup_tabs;   // [level][digit]
   std::vector<ConvTable> moddown_tabs;              // [level]

@@ -15,7 +15,8 @@
 // column pass consecutive lanes own consecutive columns, in the block pass
 // consecutive lanes own consecutive elements.  Butterflies are Harvey's lazy
 // ones (values in [0,4q) forward, [0,2q) inverse) with Shoup twiddle
-// products; only the last pass reduces to [0,q).
+// products for 60-bit primes and exact fp64 products for primes below 2^45;
+// only the last pass reduces to [0,q).
 #include "common.h"
 
 namespace {
@@ -65,128 +66,163 @@ __device__ __forceinline__ int col_idx(int w, int r) {
   return r * W + w + (r >> H) * W;
 }
 
+// ---------------------------------------------------------------- arithmetic policies
+//
+// IntA: residues as uint64 with Shoup twiddle products (any prime < 2^61).
+// FltA: residues as fp64 for primes below 2^45, where every lazy value
+// (< 4q < 2^47) and every twiddle is an exact double.  a*w mod q is computed
+// exactly: h = fl(a w) and l = fma(a, w, -h) give a w = h + l exactly; the
+// quotient estimate qq = floor(h * (1/q)) is off by at most one, so
+// r = fma(-qq, q, h) + l (both steps exact) lies in (-q, 2q) and one
+// correction brings it to [0, 2q).  fp64 FMA runs at full rate on gfx950,
+// four times the rate of the 32-bit integer multiplies the Shoup product needs.
+
+struct IntA {
+  using V = u64;
+  u64 q, q2;
+  const TW *tw;
+  __device__ __forceinline__ V load(u64 x) const { return x; }
+  __device__ __forceinline__ u64 bits(V v) const { return v; }
+  __device__ __forceinline__ V unbits(u64 b) const { return b; }
+  __device__ __forceinline__ void ct(V &x, V &y, int idx) const { ct_bfly(x, y, tw[idx], q, q2); }
+  __device__ __forceinline__ void gs(V &x, V &y, int idx) const { gs_bfly(x, y, tw[idx], q, q2); }
+  // [0, 4q) -> [0, q)
+  __device__ __forceinline__ u64 canon(V v) const {
+    v = v >= q2 ? v - q2 : v;
+    return v >= q ? v - q : v;
+  }
+  __device__ __forceinline__ u64 scale(V v, const PrimeInfo &pi) const { return shoup(v, pi.ninv, pi.ninv_p, q); }
+};
+
+struct FltA {
+  using V = double;
+  double q, q2, qinv;
+  const double *tw;
+  __device__ __forceinline__ V load(u64 x) const { return (double)x; }
+  __device__ __forceinline__ u64 bits(V v) const { return (u64)__double_as_longlong(v); }
+  __device__ __forceinline__ V unbits(u64 b) const { return __longlong_as_double((long long)b); }
+  // a * w mod q in [0, 2q) for 0 <= a < 4q, 0 <= w < q
+  __device__ __forceinline__ double mm(double a, double w) const {
+#pragma clang fp contract(off)
+    const double h = a * w;
+    const double l = __fma_rn(a, w, -h);
+    const double qq = floor(h * qinv);
+    double r = __fma_rn(-qq, q, h) + l;
+    return r < 0.0 ? r + q : r;
+  }
+  __device__ __forceinline__ void ct(V &x, V &y, int idx) const {
+#pragma clang fp contract(off)
+    const double X = x >= q2 ? x - q2 : x;
+    const double T = mm(y, tw[idx]);
+    x = X + T;
+    y = (X - T) + q2;
+  }
+  __device__ __forceinline__ void gs(V &x, V &y, int idx) const {
+#pragma clang fp contract(off)
+    double S = x + y;
+    S = S >= q2 ? S - q2 : S;
+    const double D = (x - y) + q2;
+    x = S;
+    y = mm(D, tw[idx]);
+  }
+  __device__ __forceinline__ u64 canon(V v) const {
+    v = v >= q2 ? v - q2 : v;
+    v = v >= q ? v - q : v;
+    return (u64)v;
+  }
+  __device__ __forceinline__ u64 scale(V v, const PrimeInfo &pi) const {
+    double r = mm(v, pi.ninv_d);
+    return (u64)(r >= q ? r - q : r);
+  }
+};
+
 // Forward stages on x[] in the "A" layout (element u + E k): global stage
 // multiplier m = E/(2h), twiddle index m f + k/(2h).
-template <int H>
-__device__ __forceinline__ void fwd_phase_a(u64 (&x)[1 << H], const TW *tw, int f, u64 q) {
+template <int H, class A>
+__device__ __forceinline__ void fwd_phase_a(typename A::V (&x)[1 << H], const A &ar, int f) {
   constexpr int E = 1 << H;
-  const u64 q2 = 2 * q;
 #pragma unroll
   for (int h = E / 2; h >= 1; h >>= 1) {
 #pragma unroll
-    for (int k = 0; k < E; k++) {
-      if ((k & h) == 0) {
-        const TW t = tw[(E / (2 * h)) * f + k / (2 * h)];
-        ct_bfly(x[k], x[k + h], t, q, q2);
-      }
-    }
+    for (int k = 0; k < E; k++)
+      if ((k & h) == 0) ar.ct(x[k], x[k + h], (E / (2 * h)) * f + k / (2 * h));
   }
 }
 
 // Forward stages in the "B" layout (element E u + k): m = R/(2h), twiddle
 // index m f + u E/(2h) + k/(2h).
-template <int H>
-__device__ __forceinline__ void fwd_phase_b(u64 (&x)[1 << H], const TW *tw, int f, int u, u64 q) {
+template <int H, class A>
+__device__ __forceinline__ void fwd_phase_b(typename A::V (&x)[1 << H], const A &ar, int f, int u) {
   constexpr int E = 1 << H, R = E * E;
-  const u64 q2 = 2 * q;
 #pragma unroll
   for (int h = E / 2; h >= 1; h >>= 1) {
 #pragma unroll
-    for (int k = 0; k < E; k++) {
-      if ((k & h) == 0) {
-        const TW t = tw[(R / (2 * h)) * f + u * (E / (2 * h)) + k / (2 * h)];
-        ct_bfly(x[k], x[k + h], t, q, q2);
-      }
-    }
+    for (int k = 0; k < E; k++)
+      if ((k & h) == 0) ar.ct(x[k], x[k + h], (R / (2 * h)) * f + u * (E / (2 * h)) + k / (2 * h));
   }
 }
 
-template <int H>
-__device__ __forceinline__ void inv_phase_b(u64 (&x)[1 << H], const TW *tw, int f, int u, u64 q) {
+template <int H, class A>
+__device__ __forceinline__ void inv_phase_b(typename A::V (&x)[1 << H], const A &ar, int f, int u) {
   constexpr int E = 1 << H, R = E * E;
-  const u64 q2 = 2 * q;
 #pragma unroll
   for (int h = 1; h <= E / 2; h <<= 1) {
 #pragma unroll
-    for (int k = 0; k < E; k++) {
-      if ((k & h) == 0) {
-        const TW t = tw[(R / (2 * h)) * f + u * (E / (2 * h)) + k / (2 * h)];
-        gs_bfly(x[k], x[k + h], t, q, q2);
-      }
-    }
+    for (int k = 0; k < E; k++)
+      if ((k & h) == 0) ar.gs(x[k], x[k + h], (R / (2 * h)) * f + u * (E / (2 * h)) + k / (2 * h));
   }
 }
 
-template <int H>
-__device__ __forceinline__ void inv_phase_a(u64 (&x)[1 << H], const TW *tw, int f, u64 q) {
+template <int H, class A>
+__device__ __forceinline__ void inv_phase_a(typename A::V (&x)[1 << H], const A &ar, int f) {
   constexpr int E = 1 << H;
-  const u64 q2 = 2 * q;
 #pragma unroll
   for (int h = 1; h <= E / 2; h <<= 1) {
 #pragma unroll
-    for (int k = 0; k < E; k++) {
-      if ((k & h) == 0) {
-        const TW t = tw[(E / (2 * h)) * f + k / (2 * h)];
-        gs_bfly(x[k], x[k + h], t, q, q2);
-      }
-    }
+    for (int k = 0; k < E; k++)
+      if ((k & h) == 0) ar.gs(x[k], x[k + h], (E / (2 * h)) * f + k / (2 * h));
   }
 }
 
-// One pass of the transform.  FWD: column pass first (src -> dst), block pass
-// second (in place, final reduction).  INV: block pass first, column pass
-// second (in place, times N^-1).
-template <int H, bool FWD, bool COLS>
-__global__ __launch_bounds__((Shape<H, COLS>::T)) void ntt_pass_kernel(const u64 *src, u64 *dst, LimbList ll,
-                                                                     const TW *__restrict__ twtab,
-                                                                     const PrimeInfo *__restrict__ pinfo,
-                                                                     const NttEpi epi) {
+// The body of one pass for one arithmetic policy.
+template <int H, bool FWD, bool COLS, class A>
+__device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 *in, u64 *out, int part, int bat,
+                                          int li, const PrimeInfo &pi, const NttEpi &epi) {
   using S = Shape<H, COLS>;
-  constexpr int E = S::E, R = S::R, N = S::N, W = S::W, WPL = S::WPL;
-  __shared__ u64 lds[S::LDS];
-
+  constexpr int E = S::E, R = S::R, N = S::N, W = S::W;
+  using V = typename A::V;
   const int tid = threadIdx.x;
-  const int limb_lin = blockIdx.x / WPL;
-  const int part = blockIdx.x % WPL;
-  const int bat = limb_lin / ll.n;
-  const int li = limb_lin - bat * ll.n;
-  const u64 *in = src + ((size_t)bat * ll.src_bstride + ll.src_off[li]) * (size_t)N;
-  u64 *out = dst + ((size_t)bat * ll.dst_bstride + ll.dst_off[li]) * (size_t)N;
-  const int p = ll.prime[li];
-  const u64 q = pinfo[p].q;
-  const TW *tw = twtab + (size_t)p * N;
-
-  u64 x[E];
+  V x[E];
   if (COLS) {
     const int w = tid % W, u = tid / W;
     const int c = part * W + w;
     if (FWD) {
       // first forward pass: stages m = 1 .. R/2 on column c
 #pragma unroll
-      for (int k = 0; k < E; k++) x[k] = in[c + R * (u + E * k)];
-      fwd_phase_a<H>(x, tw, 1, q);
+      for (int k = 0; k < E; k++) x[k] = ar.load(in[c + R * (u + E * k)]);
+      fwd_phase_a<H>(x, ar, 1);
 #pragma unroll
-      for (int k = 0; k < E; k++) lds[col_idx<H, W>(w, u + E * k)] = x[k];
+      for (int k = 0; k < E; k++) lds[col_idx<H, W>(w, u + E * k)] = ar.bits(x[k]);
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < E; k++) x[k] = lds[col_idx<H, W>(w, E * u + k)];
-      fwd_phase_b<H>(x, tw, 1, u, q);
+      for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[col_idx<H, W>(w, E * u + k)]);
+      fwd_phase_b<H>(x, ar, 1, u);
+      // lazy values in [0, 4q) go to memory as integers
 #pragma unroll
-      for (int k = 0; k < E; k++) out[c + R * (E * u + k)] = x[k];
+      for (int k = 0; k < E; k++) out[c + R * (E * u + k)] = (u64)x[k];
     } else {
       // last inverse pass: stages m = R/2 .. 1 on column c, then N^-1
 #pragma unroll
-      for (int k = 0; k < E; k++) x[k] = in[c + R * (E * u + k)];
-      inv_phase_b<H>(x, tw, 1, u, q);
+      for (int k = 0; k < E; k++) x[k] = ar.load(in[c + R * (E * u + k)]);
+      inv_phase_b<H>(x, ar, 1, u);
 #pragma unroll
-      for (int k = 0; k < E; k++) lds[col_idx<H, W>(w, E * u + k)] = x[k];
+      for (int k = 0; k < E; k++) lds[col_idx<H, W>(w, E * u + k)] = ar.bits(x[k]);
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < E; k++) x[k] = lds[col_idx<H, W>(w, u + E * k)];
-      inv_phase_a<H>(x, tw, 1, q);
-      const u64 ni = pinfo[p].ninv, nip = pinfo[p].ninv_p;
+      for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[col_idx<H, W>(w, u + E * k)]);
+      inv_phase_a<H>(x, ar, 1);
 #pragma unroll
-      for (int k = 0; k < E; k++) out[c + R * (u + E * k)] = shoup(x[k], ni, nip, q);
+      for (int k = 0; k < E; k++) out[c + R * (u + E * k)] = ar.scale(x[k], pi);
     }
   } else {
     const int u = tid % E, w = tid / E;
@@ -195,20 +231,20 @@ __global__ __launch_bounds__((Shape<H, COLS>::T)) void ntt_pass_kernel(const u64
     const u64 *ib = in + (size_t)R * b;
     u64 *ob = out + (size_t)R * b;
 #pragma unroll
-    for (int k = 0; k < E; k++) x[k] = ib[u + E * k];
+    for (int k = 0; k < E; k++) x[k] = ar.load(ib[u + E * k]);
     if (FWD) {
-      fwd_phase_a<H>(x, tw, f, q);
+      fwd_phase_a<H>(x, ar, f);
 #pragma unroll
-      for (int k = 0; k < E; k++) lds[blk_idx<H>(w, u + E * k)] = x[k];
+      for (int k = 0; k < E; k++) lds[blk_idx<H>(w, u + E * k)] = ar.bits(x[k]);
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < E; k++) x[k] = lds[blk_idx<H>(w, E * u + k)];
-      fwd_phase_b<H>(x, tw, f, u, q);
+      for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[blk_idx<H>(w, E * u + k)]);
+      fwd_phase_b<H>(x, ar, f, u);
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < E; k++) lds[blk_idx<H>(w, E * u + k)] = x[k];
+      for (int k = 0; k < E; k++) lds[blk_idx<H>(w, E * u + k)] = ar.bits(x[k]);
       __syncthreads();
-      const u64 q2 = 2 * q;
+      const u64 q = pi.q;
       if (epi.a) {
         // fused finish: out = (a - NTT(x)) * c  (ModDown: c = P^-1, rescale: c = q_l^-1)
         const int bo = bat / epi.inner, bi = bat % epi.inner;
@@ -219,37 +255,60 @@ __global__ __launch_bounds__((Shape<H, COLS>::T)) void ntt_pass_kernel(const u64
         const TW c = epi.c[li];
 #pragma unroll
         for (int k = 0; k < E; k++) {
-          u64 v = lds[blk_idx<H>(w, u + E * k)];
-          v = v >= q2 ? v - q2 : v;
-          v = v >= q ? v - q : v;
+          const u64 v = ar.canon(ar.unbits(lds[blk_idx<H>(w, u + E * k)]));
           eo[u + E * k] = shoup(sub_mod(ea[u + E * k], v, q), c.w, c.wp, q);
         }
       } else {
 #pragma unroll
-        for (int k = 0; k < E; k++) {
-          u64 v = lds[blk_idx<H>(w, u + E * k)];
-          v = v >= q2 ? v - q2 : v;
-          v = v >= q ? v - q : v;
-          ob[u + E * k] = v;
-        }
+        for (int k = 0; k < E; k++) ob[u + E * k] = ar.canon(ar.unbits(lds[blk_idx<H>(w, u + E * k)]));
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < E; k++) lds[blk_idx<H>(w, u + E * k)] = x[k];
+      for (int k = 0; k < E; k++) lds[blk_idx<H>(w, u + E * k)] = ar.bits(x[k]);
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < E; k++) x[k] = lds[blk_idx<H>(w, E * u + k)];
-      inv_phase_b<H>(x, tw, f, u, q);
+      for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[blk_idx<H>(w, E * u + k)]);
+      inv_phase_b<H>(x, ar, f, u);
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < E; k++) lds[blk_idx<H>(w, E * u + k)] = x[k];
+      for (int k = 0; k < E; k++) lds[blk_idx<H>(w, E * u + k)] = ar.bits(x[k]);
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < E; k++) x[k] = lds[blk_idx<H>(w, u + E * k)];
-      inv_phase_a<H>(x, tw, f, q);
+      for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[blk_idx<H>(w, u + E * k)]);
+      inv_phase_a<H>(x, ar, f);
+      // values in [0, 2q) go to memory as integers
 #pragma unroll
-      for (int k = 0; k < E; k++) ob[u + E * k] = x[k];
+      for (int k = 0; k < E; k++) ob[u + E * k] = (u64)x[k];
     }
+  }
+}
+
+// One pass of the transform.  FWD: column pass first (src -> dst), block pass
+// second (in place, final reduction).  INV: block pass first, column pass
+// second (in place, times N^-1).  Primes below 2^45 take the fp64 path.
+template <int H, bool FWD, bool COLS>
+__global__ __launch_bounds__((Shape<H, COLS>::T)) void ntt_pass_kernel(const u64 *src, u64 *dst, LimbList ll,
+                                                                     const TW *__restrict__ twtab,
+                                                                     const double *__restrict__ twdtab,
+                                                                     const PrimeInfo *__restrict__ pinfo,
+                                                                     const NttEpi epi) {
+  using S = Shape<H, COLS>;
+  constexpr int N = S::N, WPL = S::WPL;
+  __shared__ u64 lds[S::LDS];
+  const int limb_lin = blockIdx.x / WPL;
+  const int part = blockIdx.x % WPL;
+  const int bat = limb_lin / ll.n;
+  const int li = limb_lin - bat * ll.n;
+  const u64 *in = src + ((size_t)bat * ll.src_bstride + ll.src_off[li]) * (size_t)N;
+  u64 *out = dst + ((size_t)bat * ll.dst_bstride + ll.dst_off[li]) * (size_t)N;
+  const int p = ll.prime[li];
+  const PrimeInfo pi = pinfo[p];
+  if (pi.q < (1ull << 45)) {
+    FltA ar{pi.qd, 2.0 * pi.qd, pi.qinv_d, twdtab + (size_t)p * N};
+    pass_body<H, FWD, COLS>(ar, lds, in, out, part, bat, li, pi, epi);
+  } else {
+    IntA ar{pi.q, 2 * pi.q, twtab + (size_t)p * N};
+    pass_body<H, FWD, COLS>(ar, lds, in, out, part, bat, li, pi, epi);
   }
 }
 
@@ -270,17 +329,17 @@ int launch_ntt_h(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, i
   KTimer tm(ctx, s);
   if (forward) {
     hipLaunchKernelGGL((ntt_pass_kernel<H, true, true>), dim3(gc), dim3(SC::T), 0, s, src, dst, ll,
-                       ctx->d_tw_fwd, ctx->d_pinfo, NttEpi{});
+                       ctx->d_tw_fwd, ctx->d_twd_fwd, ctx->d_pinfo, NttEpi{});
     tm.lap(TK_NTT_FWD_COL, bytes, ops);
     hipLaunchKernelGGL((ntt_pass_kernel<H, true, false>), dim3(gb), dim3(SB::T), 0, s, dst, dst,
-                       second, ctx->d_tw_fwd, ctx->d_pinfo, epi);
+                       second, ctx->d_tw_fwd, ctx->d_twd_fwd, ctx->d_pinfo, epi);
     tm.lap(TK_NTT_FWD_BLK, epi.a ? bytes * 1.5 : bytes, ops);
   } else {
     hipLaunchKernelGGL((ntt_pass_kernel<H, false, false>), dim3(gb), dim3(SB::T), 0, s, src, dst, ll,
-                       ctx->d_tw_inv, ctx->d_pinfo, NttEpi{});
+                       ctx->d_tw_inv, ctx->d_twd_inv, ctx->d_pinfo, NttEpi{});
     tm.lap(TK_NTT_INV_BLK, bytes, ops);
     hipLaunchKernelGGL((ntt_pass_kernel<H, false, true>), dim3(gc), dim3(SC::T), 0, s, dst, dst,
-                       second, ctx->d_tw_inv, ctx->d_pinfo, NttEpi{});
+                       second, ctx->d_tw_inv, ctx->d_twd_inv, ctx->d_pinfo, NttEpi{});
     tm.lap(TK_NTT_INV_COL, bytes, ops);
   }
   HIP_TRY(hipGetLastError());
