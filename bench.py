@@ -45,22 +45,46 @@ PMC_PROFILES = {"ks_acc": "profiles/ks_acc_kernel_w2_level23_pmc.json",
                 "baby_mac": "profiles/baby_mac_kernel_w2_level23_pmc.json"}
 
 
+def kernel_source(path: str, name: str) -> str:
+    """Text of the kernel `name` in `path`: from its template line to the
+    brace that closes its body."""
+    with open(os.path.join(ROOT, path)) as f:
+        text = f.read()
+    at = text.index(f" void {name}(")
+    start = text.rfind("\ntemplate", 0, at)
+    start = at if start < 0 or "}" in text[start:at] else start
+    depth, i = 0, text.index("{", at)
+    while True:
+        depth += {"{": 1, "}": -1}.get(text[i], 0)
+        if depth == 0:
+            return text[start:i + 1]
+        i += 1
+
+
+def kernel_hash(rec) -> str:
+    """sha256 over the kernel's own text plus the shared device header."""
+    import hashlib
+    h = hashlib.sha256(kernel_source(rec["kernel_file"], rec["kernel"]).encode())
+    for p in rec["headers"]:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel: str, workload: str, level: int, radix: int, n1: int, batch: int, sign: int):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE counter
     runs (scaled by the copy-kernel calibration), or None when there is no
-    such record for this kernel and workload or the kernel source changed
-    since the counters were taken."""
-    import hashlib
+    such record for this kernel and workload or the kernel (or the device
+    header it uses) changed since the counters were taken."""
     path = PMC_PROFILES.get(kernel)
     if not path:
         return None
     try:
         with open(os.path.join(ROOT, path)) as f:
             rec = json.load(f)
-        src = b"".join(open(os.path.join(ROOT, p), "rb").read() for p in rec["source_files"])
-    except (OSError, KeyError):
-        return None
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        if kernel_hash(rec) != rec["source_sha256"]:
+            return None
+    except (OSError, KeyError, ValueError):
         return None
     if rec.get("config") != dict(workload=workload, level=level, radix=radix, n1=n1, batch=batch, sign=sign):
         return None
@@ -81,6 +105,7 @@ def parse():
                     help="direction of the diagonal rotations; -1 lets the fold stop at the occupied window")
     ap.add_argument("--ks-tile", type=int, default=None)
     ap.add_argument("--baby-tile", type=int, default=None)
+    ap.add_argument("--baby-share", type=int, default=None)
     ap.add_argument("--autotune", action="store_true", help="measure candidate schedules first")
     ap.add_argument("--autotune-out", default=None, help="write the tuning record to this file")
     ap.add_argument("--graph", action="store_true", help="replay one captured HIP graph per step")
@@ -272,13 +297,13 @@ def main():
         if args.workload == "w3":
             cands = [autotune.Schedule(n1, r, -1) for n1 in (32, 64) for r in (4, 8)]
         tune_rec = autotune.tune(prm, tables, args.level, B, key_fn, lambda: synth.enc_draws(eg, prm.N),
-                                 schedules=cands, steps=3)
+                                 schedules=cands)
         if args.autotune_out:
             autotune.record(tune_rec, args.autotune_out)
     sched = autotune.tuned_schedule(prm.N, prm.L, args.level, M.shape[0], M.shape[1], B)
     if tune_rec is not None:
         b = tune_rec["best"]
-        sched = autotune.Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"])
+        sched = autotune.Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b["baby_share"])
     if sched is None:
         sched = autotune.Schedule(dflt["n1"], dflt["radix"], dflt["sign"])
     n1 = args.n1 or sched.n1
@@ -288,6 +313,8 @@ def main():
     sess = LookupSession(prm, tables, args.level, n1, radix, key_fn, sign=sign)
     sess.ctx.helrm_set_tuning("ks_tile", args.ks_tile or sched.ks_tile)
     sess.ctx.helrm_set_tuning("baby_tile", args.baby_tile or sched.baby_tile)
+    share = args.baby_share or sched.baby_share
+    sess.ctx.helrm_set_tuning("baby_share", share)
     setup_s = time.time() - t0
     qg = synth.rng(1)
     idx = [synth.indices(qg, [t.rows for t in tables]) for _ in range(B)]
@@ -349,7 +376,8 @@ def main():
                                f"call" + (", HIP graph replay" if args.graph else ""),
                    "name": args.workload, "level": args.level, "batch": B, "tables": len(tables), "n1": n1,
                    "radix": radix, "sign": sign, "fold_span": spec.span, "graph": args.graph,
-                   "ks_tile": args.ks_tile or sched.ks_tile, "baby_tile": args.baby_tile or sched.baby_tile},
+                   "ks_tile": args.ks_tile or sched.ks_tile, "baby_tile": args.baby_tile or sched.baby_tile,
+                   "baby_share": share},
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
         "key_switches_per_s": {"hoisted": n_hoisted * cts_per_s, "full": n_full * cts_per_s,
                                "per_ciphertext": {"hoisted": n_hoisted, "full": n_full}},
@@ -400,7 +428,10 @@ def main():
                         "Gmodmul/s": v["ops"] / (v["ms"] * 1e6), "bytes_per_launch": v["bytes"] / v["launches"]}
         dom = max(table, key=lambda k: table[k]["ms_per_step"])
         d = table[dom]
-        res["roofline"] = {"kernel": KERNEL_SYMBOL[dom], "bound": "hbm", "achieved": d["GB/s"],
+        symbol = dict(KERNEL_SYMBOL)
+        if B >= 2 and spec.n2 >= 2 and share >= 2:
+            symbol["baby_mac"] = "baby_mac_shared_kernel"
+        res["roofline"] = {"kernel": symbol[dom], "bound": "hbm", "achieved": d["GB/s"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["GB/s"] / HBM_PEAK_GBS,
                            "traffic": measured_traffic(dom, args.workload, args.level, radix, n1, B, sign),
                            "avg_us": d["avg_us"], "algorithmic_bytes_per_launch": d["bytes_per_launch"]}

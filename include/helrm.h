@@ -237,8 +237,12 @@ int helrm_timing_read(helrm_ctx *ctx, const char *kernel, double *ms, int64_t *l
 /* Schedule knobs set by the autotuner.  "ks_tile" and "baby_tile" cap how many
  * ciphertexts of a batch one thread serves in the key inner product and the
  * fused baby-step kernel (1, 2 or 4; default 4): larger tiles read each key
- * and plaintext word fewer times, smaller tiles use fewer registers.  Results
- * do not depend on the knobs. */
+ * and plaintext word fewer times, smaller tiles use fewer registers.
+ * "baby_share" (1, 2, 4 or 8; default 8) is the number of ciphertexts one
+ * workgroup of the fused baby-step kernel serves when a launch has several
+ * giant outputs and a batch (each plaintext word is then read once per that
+ * many ciphertexts); 1 turns that kernel off.  Results do not depend on the
+ * knobs.  Errors: HELRM_EINVAL for an unknown knob or value. */
 int helrm_set_tuning(helrm_ctx *ctx, const char *knob, int value);
 
 #ifdef __cplusplus

@@ -35,6 +35,7 @@ class Schedule:
     sign: int
     ks_tile: int = 4
     baby_tile: int = 4
+    baby_share: int = 8
 
 
 def candidate_schedules(rows: int, cols: int, n: int, n1s=(4, 8, 16, 32, 64), radices=(4, 8, 16),
@@ -61,13 +62,13 @@ def tuned_schedule(N: int, L: int, level: int, rows: int, cols: int, batch: int,
     if rec is None:
         return None
     b = rec["best"]
-    return Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"])
+    return Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b.get("baby_share", 8))
 
 
 def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
          schedules: Optional[Sequence[Schedule]] = None, tiles: Iterable[int] = (1, 2, 4),
-         steps: int = 5, log=None) -> Dict:
-    """Measure every schedule (and tile pair when batch > 1) and return
+         shares: Iterable[int] = (2, 4, 8), steps: int = 10, warmup: int = 2, log=None) -> Dict:
+    """Measure every schedule (and its kernel knobs when batch > 1) and return
     {"best": {...}, "results": [...]}.  key_draws_fn(galois) and
     enc_draws_fn() supply the randomness."""
     import torch
@@ -97,16 +98,23 @@ def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
     sel = torch.stack(cts).contiguous()
     out = torch.zeros(batch, 2, level, prm.N, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
-    tile_pairs = [(4, 4)] if batch == 1 else [(a, b) for a in tiles for b in tiles]
     results = []
     for sc, spec in specs:
         plan = ctx.helrm_plan_create(level, spec.m, spec.n1, spec.n2, spec.radix, spec.diag, spec.coeffs,
                                      spec.sign, spec.span)
         ctx.helrm_reserve(plan, batch, stream)
-        for kt, bt in tile_pairs:
+        if batch == 1:
+            knobs = [(4, 4, 8)]
+        elif spec.n2 == 1:   # one giant output: the per-thread baby-step tile matters
+            knobs = [(a, b, 8) for a in tiles for b in tiles]
+        else:                # several giant outputs: the workgroup-shared kernel's width matters
+            knobs = [(a, 4, c) for a in tiles for c in shares]
+        for kt, bt, sh in knobs:
             ctx.helrm_set_tuning("ks_tile", kt)
             ctx.helrm_set_tuning("baby_tile", bt)
-            ctx.helrm_lookup_packed(plan, sel, batch, out, stream)
+            ctx.helrm_set_tuning("baby_share", sh)
+            for _ in range(warmup):
+                ctx.helrm_lookup_packed(plan, sel, batch, out, stream)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
@@ -116,7 +124,7 @@ def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
             rec = {"n1": sc.n1, "radix": sc.radix, "sign": sc.sign, "span": spec.span, "ks_tile": kt,
-                   "baby_tile": bt, "ms_per_batch": ms, "lookups_per_s": batch * len(tables) / (ms / 1e3),
+                   "baby_tile": bt, "baby_share": sh, "ms_per_batch": ms, "lookups_per_s": batch * len(tables) / (ms / 1e3),
                    "keys": len(spec.rotation_steps())}
             results.append(rec)
             if log:

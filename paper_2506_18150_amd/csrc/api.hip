@@ -322,14 +322,6 @@ int do_rescale(helrm_ctx *ctx, int level, const u64 *in, int in_bs, u64 *out, in
   return HELRM_OK;
 }
 
-uint32_t galois_of_step(const helrm_ctx *ctx, long step) {
-  const long n = ctx->N / 2;
-  long k = ((step % n) + n) % n;
-  u64 g = 1, twoN = 2ull * ctx->N;
-  for (long i = 0; i < k; i++) g = g * 5 % twoN;
-  return (uint32_t)g;
-}
-
 int key_for(helrm_ctx *ctx, long step, const u64 **key, uint32_t *gal) {
   *gal = galois_of_step(ctx, step);
   auto it = ctx->keys.find(*gal);
@@ -1127,11 +1119,12 @@ extern "C" int helrm_timing_read(helrm_ctx *c, const char *kernel, double *ms, i
 extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
   API_GUARD_BEGIN
   CHECK_ARG(c && knob, "NULL argument");
-  CHECK_ARG(value == 1 || value == 2 || value == 4, "tile must be 1, 2 or 4");
-  if (strcmp(knob, "ks_tile") == 0) {
-    c->tune_ks_tile = value;
-  } else if (strcmp(knob, "baby_tile") == 0) {
-    c->tune_baby_tile = value;
+  if (strcmp(knob, "ks_tile") == 0 || strcmp(knob, "baby_tile") == 0) {
+    CHECK_ARG(value == 1 || value == 2 || value == 4, "%s must be 1, 2 or 4", knob);
+    (knob[0] == 'k' ? c->tune_ks_tile : c->tune_baby_tile) = value;
+  } else if (strcmp(knob, "baby_share") == 0) {
+    CHECK_ARG(value == 1 || value == 2 || value == 4 || value == 8, "baby_share must be 1, 2, 4 or 8");
+    c->tune_baby_share = value;
   } else {
     set_error("unknown tuning knob '%s'", knob);
     return HELRM_EINVAL;

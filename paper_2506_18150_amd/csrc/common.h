@@ -103,6 +103,52 @@ __device__ __forceinline__ u64 redc_acc(const Acc &a, u64 q, u64 qn) {
   return redc(a.lo, hi, q, qn);
 }
 
+// Multiply-accumulate policies for sums of at most 64 products of residues,
+// finished by one REDC.  Both give the same canonical result, REDC(exact sum).
+//
+// WideMac: 128-bit lazy sum, any residue below 2^60.
+struct WideMac {
+  using Op = u64;
+  Acc a;
+  static __device__ __forceinline__ Op prep(u64 v) { return v; }
+  __device__ __forceinline__ void zero() { acc_zero(a); }
+  __device__ __forceinline__ void mac(Op x, Op y) { acc_mac(a, x, y); }
+  __device__ __forceinline__ u64 finish(u64 q, u64 qn) const { return redc_acc(a, q, qn); }
+};
+
+// SplitMac: residues below 2^40 split into 20-bit halves x = x0 + 2^20 x1;
+// x y = x0 y0 + 2^20 ((x0+x1)(y0+y1) - x0 y0 - x1 y1) + 2^40 x1 y1 (Karatsuba),
+// so a product costs three 32x32->64 multiply-adds into three 64-bit sums
+// that cannot overflow (64 products: below 2^46, 2^46, 2^48).  The exact sum
+// (below 2^86, so its high word is below q) is rebuilt once, then REDC.
+struct Half20 {
+  uint32_t lo, hi, sum;
+};
+struct SplitMac {
+  using Op = Half20;
+  u64 s0, s1, sm;
+  static __device__ __forceinline__ Op prep(u64 v) {
+    Half20 h;
+    h.lo = (uint32_t)v & 0xFFFFFu;
+    h.hi = (uint32_t)(v >> 20);
+    h.sum = h.lo + h.hi;
+    return h;
+  }
+  __device__ __forceinline__ void zero() { s0 = s1 = sm = 0; }
+  __device__ __forceinline__ void mac(const Op &x, const Op &y) {
+    s0 += (u64)x.lo * y.lo;
+    s1 += (u64)x.hi * y.hi;
+    sm += (u64)x.sum * y.sum;
+  }
+  __device__ __forceinline__ u64 finish(u64 q, u64 qn) const {
+    const u64 mid = sm - s0 - s1;
+    u128 s = (u128)s0 + ((u128)mid << 20) + ((u128)s1 << 40);
+    return redc((u64)s, (u64)(s >> 64), q, qn);
+  }
+};
+
+constexpr u64 SPLIT_MAC_LIMIT = 1ull << 40;   // SplitMac needs every residue below this
+
 __device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
   u64 s = a + b;
   return s >= q ? s - q : s;
@@ -215,6 +261,7 @@ struct helrm_ctx {
   std::map<hipStream_t, Workspace> ws;
   int tune_ks_tile = 4;      // ciphertexts per thread in ks_acc (1, 2, 4)
   int tune_baby_tile = 4;    // ciphertexts per thread in baby_mac when one giant output (1, 2, 4)
+  int tune_baby_share = 8;   // ciphertexts per workgroup in baby_mac with several giant outputs (1 = off, 2, 4, 8)
   bool timing = false;
   std::mutex tmu;
   std::vector<TimingRec> trecs;
@@ -336,6 +383,17 @@ struct KsTerm {
   const u64 *key;     // [dnum][2][L+1+K][N] Montgomery form
   uint32_t galois;
 };
+
+// 5^(step mod n) mod 2N by square-and-multiply (2N is a power of two).
+inline uint32_t galois_of_step(const helrm_ctx *ctx, long step) {
+  const long n = ctx->N / 2;
+  unsigned long k = (unsigned long)(((step % n) + n) % n);
+  const u64 mask = 2ull * ctx->N - 1;
+  u64 g = 1, b = 5;
+  for (; k; k >>= 1, b = b * b & mask)
+    if (k & 1) g = g * b & mask;
+  return (uint32_t)g;
+}
 
 // out (PQ, 2 polys) = [lift_P(base)] + sum_t KeyIP(term t).
 int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_terms,

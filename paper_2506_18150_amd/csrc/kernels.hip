@@ -239,8 +239,97 @@ constexpr int MAXBETA = 4;   // digits per key switch handled in registers
 //                          + P (sum_t sigma_t(c0_t) + base_c0),
 //                        A = sum_t sum_j sigma_t(d_{t,j}) a_{t,j} + P base_c1.
 // Each thread owns one coefficient of one limb for BT ciphertexts; the key
-// words of a rotation are loaded once and used for all BT.
-template <int BT>
+// words of a rotation are loaded once and used for all BT.  The loads of the
+// next term are issued before the products of the current one.
+template <int BT, int BETA>
+struct KsIn {
+  u64 kb[BETA], ka[BETA], d[BT][BETA], c0[BT];
+};
+
+template <int BT, int BETA, class M>
+__device__ __forceinline__ void ks_acc_body(const KsArgs &T, const LevelGeom &G, int batch, int x, int r, int b0,
+                                            int p, const PrimeInfo &pi, size_t dig_bs, size_t c0_bs,
+                                            const u64 *base, size_t base_bs, u64 *out, size_t out_bs) {
+  const int N = 1 << G.logn;
+  const bool isq = r <= G.level;
+  const int nct = min(BT, batch - b0);
+  M ab[BT], aa[BT];
+  u64 csum[BT];
+#pragma unroll
+  for (int k = 0; k < BT; k++) {
+    ab[k].zero();
+    aa[k].zero();
+    csum[k] = 0;
+  }
+  auto load = [&](KsIn<BT, BETA> &in, int t) {
+    const unsigned src = galois_src(x, T.gal[t], G.logn);
+    const u64 *kk = T.key[t];
+#pragma unroll
+    for (int j = 0; j < BETA; j++) {
+      in.kb[j] = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
+      in.ka[j] = kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
+    }
+#pragma unroll
+    for (int k = 0; k < BT; k++) {
+      if (k < nct) {
+        const u64 *dg = T.digits[t] + (b0 + k) * dig_bs;
+#pragma unroll
+        for (int j = 0; j < BETA; j++) in.d[k][j] = dg[((size_t)j * G.pqn + r) * N + src];
+        in.c0[k] = isq ? T.c0[t][(b0 + k) * c0_bs + (size_t)r * N + src] : 0;
+      }
+    }
+  };
+  auto step = [&](const KsIn<BT, BETA> &in) {
+    typename M::Op kb[BETA], ka[BETA];
+#pragma unroll
+    for (int j = 0; j < BETA; j++) {
+      kb[j] = M::prep(in.kb[j]);
+      ka[j] = M::prep(in.ka[j]);
+    }
+#pragma unroll
+    for (int k = 0; k < BT; k++) {
+      if (k < nct) {
+#pragma unroll
+        for (int j = 0; j < BETA; j++) {
+          const auto d = M::prep(in.d[k][j]);
+          ab[k].mac(d, kb[j]);
+          aa[k].mac(d, ka[j]);
+        }
+        if (isq) csum[k] = add_mod(csum[k], in.c0[k], pi.q);
+      }
+    }
+  };
+  KsIn<BT, BETA> A, B;
+  if (T.n > 0) load(A, 0);
+  for (int t = 0; t < T.n; t += 2) {
+    if (t + 1 < T.n) load(B, t + 1);
+    step(A);
+    if (t + 1 >= T.n) break;
+    if (t + 2 < T.n) load(A, t + 2);
+    step(B);
+  }
+#pragma unroll
+  for (int k = 0; k < BT; k++) {
+    if (k >= nct) break;
+    const int bat = b0 + k;
+    u64 Bv = ab[k].finish(pi.q, pi.qn);
+    u64 Av = aa[k].finish(pi.q, pi.qn);
+    u64 cs = csum[k];
+    if (isq) {
+      if (base) {
+        const u64 *bb = base + bat * base_bs;
+        cs = add_mod(cs, bb[(size_t)r * N + x], pi.q);
+        Av = add_mod(Av, shoup(bb[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q), pi.q);
+      }
+      Bv = add_mod(Bv, shoup(cs, pi.pmod, pi.pmod_p, pi.q), pi.q);
+    }
+    u64 *o = out + bat * out_bs;
+    o[(size_t)r * N + x] = Bv;
+    o[((size_t)G.pqn + r) * N + x] = Av;
+  }
+}
+
+template <int BT, int BETA>
 __global__ __launch_bounds__(TPB) void ks_acc_kernel(KsArgs T, LevelGeom G, int L, int batch, int ntiles,
                                                      size_t dig_bs, size_t c0_bs, const u64 *base,
                                                      size_t base_bs, u64 *out, size_t out_bs,
@@ -248,186 +337,365 @@ __global__ __launch_bounds__(TPB) void ks_acc_kernel(KsArgs T, LevelGeom G, int 
   const int N = 1 << G.logn;
   const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles);
   const int x = tm.xb * TPB + threadIdx.x;
-  const int r = tm.r;
-  const int b0 = tm.tile * BT;
-  const int p = pq_prime_dev(r, G.level, L);
+  const int p = pq_prime_dev(tm.r, G.level, L);
   const PrimeInfo pi = pinfo[p];
-  const bool isq = r <= G.level;
-  Acc ab[BT], aa[BT];
-  u64 csum[BT];
-#pragma unroll
-  for (int k = 0; k < BT; k++) {
-    acc_zero(ab[k]);
-    acc_zero(aa[k]);
-    csum[k] = 0;
-  }
-  for (int t = 0; t < T.n; t++) {
-    const unsigned src = galois_src(x, T.gal[t], G.logn);
-    const u64 *kk = T.key[t];
-    u64 kb[MAXBETA], ka[MAXBETA];
-#pragma unroll
-    for (int j = 0; j < MAXBETA; j++) {
-      if (j < G.beta) {
-        kb[j] = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
-        ka[j] = kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < BT; k++) {
-      const int bat = b0 + k;
-      if (bat < batch) {
-        const u64 *dg = T.digits[t] + bat * dig_bs;
-#pragma unroll
-        for (int j = 0; j < MAXBETA; j++) {
-          if (j < G.beta) {
-            const u64 d = dg[((size_t)j * G.pqn + r) * N + src];
-            acc_mac(ab[k], d, kb[j]);
-            acc_mac(aa[k], d, ka[j]);
-          }
-        }
-        if (isq) csum[k] = add_mod(csum[k], T.c0[t][bat * c0_bs + (size_t)r * N + src], pi.q);
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < BT; k++) {
-    const int bat = b0 + k;
-    if (bat >= batch) break;
-    u64 B = redc_acc(ab[k], pi.q, pi.qn);
-    u64 A = redc_acc(aa[k], pi.q, pi.qn);
-    u64 cs = csum[k];
-    if (isq) {
-      if (base) {
-        const u64 *bb = base + bat * base_bs;
-        cs = add_mod(cs, bb[(size_t)r * N + x], pi.q);
-        A = add_mod(A, shoup(bb[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q), pi.q);
-      }
-      B = add_mod(B, shoup(cs, pi.pmod, pi.pmod_p, pi.q), pi.q);
-    }
-    u64 *o = out + bat * out_bs;
-    o[(size_t)r * N + x] = B;
-    o[((size_t)G.pqn + r) * N + x] = A;
-  }
+  if (pi.q < SPLIT_MAC_LIMIT)
+    ks_acc_body<BT, BETA, SplitMac>(T, G, batch, x, tm.r, tm.tile * BT, p, pi, dig_bs, c0_bs, base, base_bs, out,
+                                    out_bs);
+  else
+    ks_acc_body<BT, BETA, WideMac>(T, G, batch, x, tm.r, tm.tile * BT, p, pi, dig_bs, c0_bs, base, base_bs, out,
+                                   out_bs);
 }
 
+// Rotation steps of one fused baby-step launch, compacted on the host: only
+// baby steps that some giant output of the launch uses are listed.
 struct BabyArgs {
-  int nb;
-  int b[HELRM_MAX_BABY];
-  const u64 *key[HELRM_MAX_BABY];
-  unsigned gal[HELRM_MAX_BABY];
+  int nrot;                                        // rotation steps (b > 0)
+  int has0;                                        // b = 0 contributes
+  short slot0[HELRM_MAX_GTILE];                    // plaintext of (g0 + gi, b = 0), -1: none
+  unsigned gal[HELRM_MAX_BABY];                    // Galois element of each step
+  const u64 *key[HELRM_MAX_BABY];                  // its evaluation key
+  short slot[HELRM_MAX_BABY][HELRM_MAX_GTILE];     // plaintext of (g0 + gi, step), -1: none
+};
+
+// Loads of one rotation step for BT ciphertexts and GT giant outputs.
+template <int GT, int BT, int BETA>
+struct StepIn {
+  u64 kb[BETA], ka[BETA], d[BT][BETA], c0[BT], w[GT];
 };
 
 // Fused hoisted baby-step rotations and plaintext-diagonal MAC (double
 // hoisting): R_b is formed in registers and immediately multiplied into every
 // giant output of the tile, so no rotated ciphertext is written to memory.
 // Each thread serves BT ciphertexts: key and plaintext words are loaded once
-// per rotation and reused for all of them.
-template <int GT, int BT>
-__global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G, int L, int batch, int ntiles,
-                                                       const u64 *digits, size_t dig_bs, const u64 *ct,
-                                                       size_t ct_bs, const u64 *pt, const int *slot, int n1,
-                                                       int g0, int ng, u64 *X, size_t x_bs,
-                                                       const PrimeInfo *pinfo) {
+// per rotation and reused for all of them.  The loads of the next rotation
+// step are issued before the products of the current one.  M is the
+// multiply-accumulate policy (SplitMac on limbs whose prime is below 2^40,
+// WideMac otherwise); BETA is the number of key-switching digits.
+template <int GT, int BT, int BETA, class M>
+__device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeom &G, int batch, int x, int r,
+                                              int b0, int p, const PrimeInfo &pi, const u64 *digits,
+                                              size_t dig_bs, const u64 *ct, size_t ct_bs, const u64 *pt, int ng,
+                                              u64 *X, size_t x_bs) {
   const int N = 1 << G.logn;
-  const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles);
-  const int x = tm.xb * TPB + threadIdx.x;
-  const int r = tm.r;
-  const int b0 = tm.tile * BT;
-  const int p = pq_prime_dev(r, G.level, L);
-  const PrimeInfo pi = pinfo[p];
   const bool isq = r <= G.level;
-  Acc acc[BT][GT][2];
+  const int nct = min(BT, batch - b0);
+  M acc[BT][GT][2];
 #pragma unroll
   for (int k = 0; k < BT; k++)
 #pragma unroll
     for (int gi = 0; gi < GT; gi++) {
-      acc_zero(acc[k][gi][0]);
-      acc_zero(acc[k][gi][1]);
+      acc[k][gi][0].zero();
+      acc[k][gi][1].zero();
     }
-  for (int bi = 0; bi < BA.nb; bi++) {
-    const int b = BA.b[bi];
-    u64 w[GT];
-    bool any = false;
+  if (BA.has0 && isq) {
+    typename M::Op w[GT];
 #pragma unroll
     for (int gi = 0; gi < GT; gi++) {
-      w[gi] = 0;
-      if (gi < ng) {
-        const int s = slot[(g0 + gi) * n1 + b];
-        if (s >= 0) {
-          w[gi] = pt[((size_t)s * G.pqn + r) * N + x];
-          any = true;
-        }
-      }
-    }
-    if (!any) continue;
-    if (b == 0) {
-#pragma unroll
-      for (int k = 0; k < BT; k++) {
-        const int bat = b0 + k;
-        if (bat < batch && isq) {
-          const u64 *c = ct + bat * ct_bs;
-          const u64 RB = shoup(c[(size_t)r * N + x], pi.pmod, pi.pmod_p, pi.q);
-          const u64 RA = shoup(c[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q);
-#pragma unroll
-          for (int gi = 0; gi < GT; gi++) {
-            acc_mac(acc[k][gi][0], w[gi], RB);
-            acc_mac(acc[k][gi][1], w[gi], RA);
-          }
-        }
-      }
-      continue;
-    }
-    const unsigned src = galois_src(x, BA.gal[bi], G.logn);
-    const u64 *kk = BA.key[bi];
-    u64 kb[MAXBETA], ka[MAXBETA];
-#pragma unroll
-    for (int j = 0; j < MAXBETA; j++) {
-      if (j < G.beta) {
-        kb[j] = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
-        ka[j] = kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
-      }
+      const int s = gi < ng ? BA.slot0[gi] : -1;
+      w[gi] = M::prep(s >= 0 ? pt[((size_t)s * G.pqn + r) * N + x] : 0);
     }
 #pragma unroll
     for (int k = 0; k < BT; k++) {
-      const int bat = b0 + k;
-      if (bat < batch) {
-        const u64 *dg = digits + bat * dig_bs;
-        Acc ab, aa;
-        acc_zero(ab);
-        acc_zero(aa);
-#pragma unroll
-        for (int j = 0; j < MAXBETA; j++) {
-          if (j < G.beta) {
-            const u64 d = dg[((size_t)j * G.pqn + r) * N + src];
-            acc_mac(ab, d, kb[j]);
-            acc_mac(aa, d, ka[j]);
-          }
-        }
-        u64 RB = redc_acc(ab, pi.q, pi.qn);
-        const u64 RA = redc_acc(aa, pi.q, pi.qn);
-        if (isq)
-          RB = add_mod(RB, shoup(ct[bat * ct_bs + (size_t)r * N + src], pi.pmod, pi.pmod_p, pi.q), pi.q);
+      if (k < nct) {
+        const u64 *c = ct + (b0 + k) * ct_bs;
+        const auto RB = M::prep(shoup(c[(size_t)r * N + x], pi.pmod, pi.pmod_p, pi.q));
+        const auto RA = M::prep(shoup(c[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q));
 #pragma unroll
         for (int gi = 0; gi < GT; gi++) {
-          acc_mac(acc[k][gi][0], w[gi], RB);
-          acc_mac(acc[k][gi][1], w[gi], RA);
+          acc[k][gi][0].mac(w[gi], RB);
+          acc[k][gi][1].mac(w[gi], RA);
         }
       }
     }
+  }
+  auto load = [&](StepIn<GT, BT, BETA> &in, int i) {
+    const unsigned src = galois_src(x, BA.gal[i], G.logn);
+    const u64 *kk = BA.key[i];
+#pragma unroll
+    for (int j = 0; j < BETA; j++) {
+      in.kb[j] = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
+      in.ka[j] = kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
+    }
+#pragma unroll
+    for (int k = 0; k < BT; k++) {
+      if (k < nct) {
+        const u64 *dg = digits + (b0 + k) * dig_bs;
+#pragma unroll
+        for (int j = 0; j < BETA; j++) in.d[k][j] = dg[((size_t)j * G.pqn + r) * N + src];
+        in.c0[k] = isq ? ct[(b0 + k) * ct_bs + (size_t)r * N + src] : 0;
+      }
+    }
+#pragma unroll
+    for (int gi = 0; gi < GT; gi++) {
+      const int s = gi < ng ? BA.slot[i][gi] : -1;
+      in.w[gi] = s >= 0 ? pt[((size_t)s * G.pqn + r) * N + x] : 0;
+    }
+  };
+  auto step = [&](const StepIn<GT, BT, BETA> &in) {
+    typename M::Op w[GT], kb[BETA], ka[BETA];
+#pragma unroll
+    for (int gi = 0; gi < GT; gi++) w[gi] = M::prep(in.w[gi]);
+#pragma unroll
+    for (int j = 0; j < BETA; j++) {
+      kb[j] = M::prep(in.kb[j]);
+      ka[j] = M::prep(in.ka[j]);
+    }
+#pragma unroll
+    for (int k = 0; k < BT; k++) {
+      if (k < nct) {
+        M ab, aa;
+        ab.zero();
+        aa.zero();
+#pragma unroll
+        for (int j = 0; j < BETA; j++) {
+          const auto d = M::prep(in.d[k][j]);
+          ab.mac(d, kb[j]);
+          aa.mac(d, ka[j]);
+        }
+        u64 rb = ab.finish(pi.q, pi.qn);
+        const auto RA = M::prep(aa.finish(pi.q, pi.qn));
+        if (isq) rb = add_mod(rb, shoup(in.c0[k], pi.pmod, pi.pmod_p, pi.q), pi.q);
+        const auto RB = M::prep(rb);
+#pragma unroll
+        for (int gi = 0; gi < GT; gi++) {
+          acc[k][gi][0].mac(w[gi], RB);
+          acc[k][gi][1].mac(w[gi], RA);
+        }
+      }
+    }
+  };
+  StepIn<GT, BT, BETA> A, B;
+  if (BA.nrot > 0) load(A, 0);
+  for (int i = 0; i < BA.nrot; i += 2) {
+    if (i + 1 < BA.nrot) load(B, i + 1);
+    step(A);
+    if (i + 1 >= BA.nrot) break;
+    if (i + 2 < BA.nrot) load(A, i + 2);
+    step(B);
   }
 #pragma unroll
   for (int k = 0; k < BT; k++) {
-    const int bat = b0 + k;
-    if (bat >= batch) break;
-    u64 *o = X + bat * x_bs;
+    if (k >= nct) break;
+    u64 *o = X + (b0 + k) * x_bs;
 #pragma unroll
     for (int gi = 0; gi < GT; gi++) {
       if (gi < ng) {
-        o[((size_t)(gi * 2) * G.pqn + r) * N + x] = redc_acc(acc[k][gi][0], pi.q, pi.qn);
-        o[((size_t)(gi * 2 + 1) * G.pqn + r) * N + x] = redc_acc(acc[k][gi][1], pi.q, pi.qn);
+        o[((size_t)(gi * 2) * G.pqn + r) * N + x] = acc[k][gi][0].finish(pi.q, pi.qn);
+        o[((size_t)(gi * 2 + 1) * G.pqn + r) * N + x] = acc[k][gi][1].finish(pi.q, pi.qn);
       }
     }
   }
+}
+
+template <int GT, int BT, int BETA>
+__global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G, int L, int batch, int ntiles,
+                                                       const u64 *digits, size_t dig_bs, const u64 *ct,
+                                                       size_t ct_bs, const u64 *pt, int ng, u64 *X, size_t x_bs,
+                                                       const PrimeInfo *pinfo) {
+  const int N = 1 << G.logn;
+  const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles);
+  const int x = tm.xb * TPB + threadIdx.x;
+  const int p = pq_prime_dev(tm.r, G.level, L);
+  const PrimeInfo pi = pinfo[p];
+  if (pi.q < SPLIT_MAC_LIMIT)
+    baby_mac_body<GT, BT, BETA, SplitMac>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs, ct, ct_bs,
+                                          pt, ng, X, x_bs);
+  else
+    baby_mac_body<GT, BT, BETA, WideMac>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs, ct, ct_bs,
+                                         pt, ng, X, x_bs);
+}
+
+// The same product for launches with several giant outputs and a batch.  A
+// workgroup of W wavefronts serves W ciphertexts on one 64-coefficient block
+// of one limb.  Per baby step, wavefront w forms R_b of ciphertext w and puts
+// it in LDS; then wavefront w multiplies its GPW giant outputs' plaintext
+// words into R_b of all W ciphertexts.  Each plaintext word is read once per
+// workgroup (W ciphertexts), each key word by W wavefronts of one CU at the
+// same time (the repeats hit the CU's cache), and the accumulators spread
+// over the workgroup: W * GPW * 2 per thread.  LDS holds R_b as the policy
+// packs it (SplitMac: both 20-bit halves in one word).  The loads of the next
+// rotation step are issued before the current step's barrier and products.
+struct WidePack {
+  static __device__ __forceinline__ u64 pack(u64 v) { return v; }
+  static __device__ __forceinline__ u64 unpack(u64 v) { return v; }
+};
+struct SplitPack {
+  static __device__ __forceinline__ u64 pack(u64 v) { return (v & 0xFFFFFull) | ((v >> 20) << 32); }
+  static __device__ __forceinline__ Half20 unpack(u64 v) {
+    Half20 h;
+    h.lo = (uint32_t)v;
+    h.hi = (uint32_t)(v >> 32);
+    h.sum = h.lo + h.hi;
+    return h;
+  }
+};
+template <class M> struct PackOf;
+template <> struct PackOf<WideMac> { using T = WidePack; };
+template <> struct PackOf<SplitMac> { using T = SplitPack; };
+
+template <int GPW, int BETA>
+struct WaveIn {
+  u64 kb[BETA], ka[BETA], d[BETA], c0, w[GPW];
+};
+
+template <int W, int GPW, int BETA, class M>
+__device__ __forceinline__ void baby_shared_body(u64 (*R)[W][2][64], const BabyArgs &BA, const LevelGeom &G,
+                                                 int batch, int x, int lane, int w, int r, int b0, int p,
+                                                 const PrimeInfo &pi, const u64 *digits, size_t dig_bs,
+                                                 const u64 *ct, size_t ct_bs, const u64 *pt, int ng, u64 *X,
+                                                 size_t x_bs) {
+  using Pk = typename PackOf<M>::T;
+  const int N = 1 << G.logn;
+  const int nct = min(W, batch - b0);
+  const bool isq = r <= G.level;
+  const bool mine = w < nct;                // this wavefront forms R_b of ciphertext b0 + w
+  const int gw = w * GPW;                   // its first giant output (relative to g0)
+  const u64 *c = ct + (b0 + (mine ? w : 0)) * ct_bs;
+  const u64 *dg = digits + (b0 + (mine ? w : 0)) * dig_bs;
+  M acc[W][GPW][2];
+#pragma unroll
+  for (int k = 0; k < W; k++)
+#pragma unroll
+    for (int gi = 0; gi < GPW; gi++) {
+      acc[k][gi][0].zero();
+      acc[k][gi][1].zero();
+    }
+  auto macs = [&](u64 (*Rb)[2][64], const u64 *wraw) {
+    typename M::Op wv[GPW];
+#pragma unroll
+    for (int gi = 0; gi < GPW; gi++) wv[gi] = M::prep(wraw[gi]);
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+      if (k < nct) {
+        const auto RB = Pk::unpack(Rb[k][0][lane]);
+        const auto RA = Pk::unpack(Rb[k][1][lane]);
+#pragma unroll
+        for (int gi = 0; gi < GPW; gi++) {
+          acc[k][gi][0].mac(wv[gi], RB);
+          acc[k][gi][1].mac(wv[gi], RA);
+        }
+      }
+    }
+  };
+  int buf = 0;
+  if (BA.has0 && isq) {   // R_0 = P (c0, c1); it vanishes on the special limbs
+    u64 w0[GPW];
+#pragma unroll
+    for (int gi = 0; gi < GPW; gi++) {
+      const int s = gw + gi < ng ? BA.slot0[gw + gi] : -1;
+      w0[gi] = s >= 0 ? pt[((size_t)s * G.pqn + r) * N + x] : 0;
+    }
+    if (mine) {
+      R[0][w][0][lane] = Pk::pack(shoup(c[(size_t)r * N + x], pi.pmod, pi.pmod_p, pi.q));
+      R[0][w][1][lane] = Pk::pack(shoup(c[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q));
+    }
+    __syncthreads();
+    macs(R[0], w0);
+    buf = 1;
+  }
+  // One set of registers per wavefront for the step inputs: the key, digit
+  // and c0 words of step i+1 are requested as soon as R_b of step i is in
+  // LDS, the plaintext words of step i+1 as soon as those of step i are
+  // converted, so both loads overlap the barrier and products of step i.
+  WaveIn<GPW, BETA> in;
+  auto load_r = [&](int i) {
+    if (mine) {
+      const unsigned src = galois_src(x, BA.gal[i], G.logn);
+      const u64 *kk = BA.key[i];
+#pragma unroll
+      for (int j = 0; j < BETA; j++) {
+        in.kb[j] = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
+        in.ka[j] = kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
+        in.d[j] = dg[((size_t)j * G.pqn + r) * N + src];
+      }
+      in.c0 = isq ? c[(size_t)r * N + src] : 0;
+    }
+  };
+  auto load_w = [&](int i) {
+#pragma unroll
+    for (int gi = 0; gi < GPW; gi++) {
+      const int s = gw + gi < ng ? BA.slot[i][gw + gi] : -1;
+      in.w[gi] = s >= 0 ? pt[((size_t)s * G.pqn + r) * N + x] : 0;
+    }
+  };
+  if (BA.nrot > 0) {
+    load_r(0);
+    load_w(0);
+  }
+  for (int i = 0; i < BA.nrot; i++) {
+    if (mine) {
+      M ab, aa;
+      ab.zero();
+      aa.zero();
+#pragma unroll
+      for (int j = 0; j < BETA; j++) {
+        const auto d = M::prep(in.d[j]);
+        ab.mac(d, M::prep(in.kb[j]));
+        aa.mac(d, M::prep(in.ka[j]));
+      }
+      u64 RB = ab.finish(pi.q, pi.qn);
+      const u64 RA = aa.finish(pi.q, pi.qn);
+      if (isq) RB = add_mod(RB, shoup(in.c0, pi.pmod, pi.pmod_p, pi.q), pi.q);
+      R[buf][w][0][lane] = Pk::pack(RB);
+      R[buf][w][1][lane] = Pk::pack(RA);
+    }
+    if (i + 1 < BA.nrot) load_r(i + 1);
+    __syncthreads();
+    typename M::Op wv[GPW];
+#pragma unroll
+    for (int gi = 0; gi < GPW; gi++) wv[gi] = M::prep(in.w[gi]);
+    if (i + 1 < BA.nrot) load_w(i + 1);
+#pragma unroll
+    for (int k = 0; k < W; k++) {
+      if (k < nct) {
+        const auto RB = Pk::unpack(R[buf][k][0][lane]);
+        const auto RA = Pk::unpack(R[buf][k][1][lane]);
+#pragma unroll
+        for (int gi = 0; gi < GPW; gi++) {
+          acc[k][gi][0].mac(wv[gi], RB);
+          acc[k][gi][1].mac(wv[gi], RA);
+        }
+      }
+    }
+    // the next step writes the other buffer; the one after that comes only
+    // after the next barrier, which every wavefront passes once done here
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int k = 0; k < W; k++) {
+    if (k >= nct) break;
+    u64 *o = X + (b0 + k) * x_bs;
+#pragma unroll
+    for (int gi = 0; gi < GPW; gi++) {
+      const int g = gw + gi;
+      if (g < ng) {
+        o[((size_t)(g * 2) * G.pqn + r) * N + x] = acc[k][gi][0].finish(pi.q, pi.qn);
+        o[((size_t)(g * 2 + 1) * G.pqn + r) * N + x] = acc[k][gi][1].finish(pi.q, pi.qn);
+      }
+    }
+  }
+}
+
+template <int W, int GPW, int BETA>
+__global__ __launch_bounds__(64 * W) void baby_mac_shared_kernel(BabyArgs BA, LevelGeom G, int L, int batch,
+                                                                 int ntiles, const u64 *digits, size_t dig_bs,
+                                                                 const u64 *ct, size_t ct_bs, const u64 *pt,
+                                                                 int ng, u64 *X, size_t x_bs,
+                                                                 const PrimeInfo *pinfo) {
+  __shared__ u64 R[2][W][2][64];
+  const int N = 1 << G.logn;
+  const TileMap tm = tile_map(blockIdx.x, N / 64, ntiles);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int x = tm.xb * 64 + lane;
+  const int p = pq_prime_dev(tm.r, G.level, L);
+  const PrimeInfo pi = pinfo[p];
+  if (pi.q < SPLIT_MAC_LIMIT)
+    baby_shared_body<W, GPW, BETA, SplitMac>(R, BA, G, batch, x, lane, w, tm.r, tm.tile * W, p, pi, digits,
+                                             dig_bs, ct, ct_bs, pt, ng, X, x_bs);
+  else
+    baby_shared_body<W, GPW, BETA, WideMac>(R, BA, G, batch, x, lane, w, tm.r, tm.tile * W, p, pi, digits,
+                                            dig_bs, ct, ct_bs, pt, ng, X, x_bs);
 }
 
 dim3 ew_grid(const helrm_ctx *ctx, int rows) { return dim3(ctx->N / TPB, rows); }
@@ -605,8 +873,8 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
     T.gal[i] = terms[i].galois;
   }
   LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn};
-  if (G.beta > MAXBETA) {
-    set_error("key switching with %d digits (at most %d)", G.beta, MAXBETA);
+  if (G.beta > MAXBETA || G.beta < 1) {
+    set_error("key switching with %d digits (1 to %d supported)", G.beta, MAXBETA);
     return HELRM_EINVAL;
   }
   if (batch == 0) return HELRM_OK;
@@ -620,14 +888,22 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
   const int ntiles = (batch + bt - 1) / bt;
   const int grid = (ctx->N / TPB) * G.pqn * ntiles;
   KTimer tm(ctx, s);
-#define KSACC(BT_)                                                                                     \
-  hipLaunchKernelGGL((ks_acc_kernel<BT_>), dim3(grid), dim3(TPB), 0, s, T, G, ctx->L, batch, ntiles,   \
-                     digits_bstride, c0_bstride, base, base_bstride, out, out_bstride, ctx->d_pinfo)
-  switch (bt) {
-    case 1: KSACC(1); break;
-    case 2: KSACC(2); break;
-    default: KSACC(4); break;
+#define KSACC(BT_, BETA_)                                                                              \
+  hipLaunchKernelGGL((ks_acc_kernel<BT_, BETA_>), dim3(grid), dim3(TPB), 0, s, T, G, ctx->L, batch,     \
+                     ntiles, digits_bstride, c0_bstride, base, base_bstride, out, out_bstride, ctx->d_pinfo)
+#define KSACC_B(BT_)                      \
+  switch (G.beta) {                       \
+    case 1: KSACC(BT_, 1); break;         \
+    case 2: KSACC(BT_, 2); break;         \
+    case 3: KSACC(BT_, 3); break;         \
+    default: KSACC(BT_, 4); break;        \
   }
+  switch (bt) {
+    case 1: KSACC_B(1); break;
+    case 2: KSACC_B(2); break;
+    default: KSACC_B(4); break;
+  }
+#undef KSACC_B
 #undef KSACC
   tm.lap(TK_KS_ACC, 8.0 * ctx->N * words, 2.0 * nt * beta * ctx->N * B * (qn + K));
   HIP_TRY(hipGetLastError());
@@ -637,71 +913,113 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
 int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, size_t digits_bstride,
                     const u64 *ct, size_t ct_bstride, u64 *X, size_t x_bstride, int g0, int ng, int batch,
                     hipStream_t s) {
-  BabyArgs BA;
-  BA.nb = (int)plan->babies.size();
-  if (BA.nb > HELRM_MAX_BABY) {
-    set_error("baby_mac: at most %d baby steps", HELRM_MAX_BABY);
+  if (ng > HELRM_MAX_GTILE) {
+    set_error("baby_mac: at most %d giant outputs per launch", HELRM_MAX_GTILE);
     return HELRM_EINVAL;
   }
-  const uint64_t twoN = 2ull * ctx->N;
-  for (int i = 0; i < BA.nb; i++) {
-    const int b = plan->babies[i];
-    BA.b[i] = b;
+  BabyArgs BA;
+  BA.nrot = 0;
+  BA.has0 = 0;
+  for (int gi = 0; gi < HELRM_MAX_GTILE; gi++) BA.slot0[gi] = -1;
+  double npt = 0;
+  for (int b : plan->babies) {
+    short sl[HELRM_MAX_GTILE];
+    bool any = false;
+    for (int gi = 0; gi < HELRM_MAX_GTILE; gi++) {
+      sl[gi] = gi < ng ? (short)plan->slot[(size_t)(g0 + gi) * plan->n1 + b] : (short)-1;
+      if (sl[gi] >= 0) {
+        any = true;
+        npt++;
+      }
+    }
+    if (!any) continue;
     if (b == 0) {
-      BA.key[i] = nullptr;
-      BA.gal[i] = 1;
+      BA.has0 = 1;
+      for (int gi = 0; gi < HELRM_MAX_GTILE; gi++) BA.slot0[gi] = sl[gi];
       continue;
     }
-    uint64_t g = 1;
-    const int n = ctx->N / 2;
-    const int e = ((plan->sign * b) % n + n) % n;
-    for (int k = 0; k < e; k++) g = g * 5 % twoN;
-    auto it = ctx->keys.find((uint32_t)g);
+    if (BA.nrot >= HELRM_MAX_BABY) {
+      set_error("baby_mac: at most %d baby steps", HELRM_MAX_BABY);
+      return HELRM_EINVAL;
+    }
+    const uint32_t g = galois_of_step(ctx, (long)plan->sign * b);
+    auto it = ctx->keys.find(g);
     if (it == ctx->keys.end()) {
       set_error("no evaluation key loaded for rotation %d (galois %llu)", b, (unsigned long long)g);
       return HELRM_EINVAL;
     }
+    const int i = BA.nrot++;
     BA.key[i] = it->second.d;
     BA.gal[i] = (unsigned)g;
+    for (int gi = 0; gi < HELRM_MAX_GTILE; gi++) BA.slot[i][gi] = sl[gi];
   }
   const int level = plan->level;
   LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn};
-  if (G.beta > MAXBETA) {
-    set_error("key switching with %d digits (at most %d)", G.beta, MAXBETA);
+  if (G.beta > MAXBETA || G.beta < 1) {
+    set_error("key switching with %d digits (1 to %d supported)", G.beta, MAXBETA);
     return HELRM_EINVAL;
   }
-  if (batch == 0 || ng == 0) return HELRM_OK;
+  if (batch == 0 || ng == 0 || (BA.nrot == 0 && !BA.has0)) return HELRM_OK;
   // algorithmic words per coefficient: keys and plaintexts once per launch, the rest per ciphertext
-  double npt = 0;
-  for (int gi = 0; gi < ng; gi++)
-    for (int b : plan->babies)
-      if (plan->slot[(size_t)(g0 + gi) * plan->n1 + b] >= 0) npt++;
-  const double nrot = BA.nb - (plan->babies[0] == 0 ? 1 : 0), has0 = plan->babies[0] == 0 ? 1 : 0;
+  const double nrot = BA.nrot, has0 = BA.has0;
   const double qn = level + 1, K = ctx->K, beta = G.beta, B = batch;
   const double words = qn * (nrot * 2 * beta + npt + B * (nrot * (beta + 1) + 2 * has0 + 2 * ng)) +
                        K * (nrot * 2 * beta + npt + B * (nrot * beta + 2 * ng));
   const int gt = ng <= 1 ? 1 : ng <= 2 ? 2 : ng <= 4 ? 4 : 8;
-  const int bt = pick_bt(batch, gt >= 4 ? 1 : gt == 2 ? std::min(2, ctx->tune_baby_tile) : ctx->tune_baby_tile);
-  const int ntiles = (batch + bt - 1) / bt;
-  const int grid = (ctx->N / TPB) * G.pqn * ntiles;
   KTimer tm(ctx, s);
-#define BABY(GT_, BT_)                                                                                   \
-  hipLaunchKernelGGL((baby_mac_kernel<GT_, BT_>), dim3(grid), dim3(TPB), 0, s, BA, G, ctx->L, batch,      \
-                     ntiles, digits, digits_bstride, ct, ct_bstride, plan->d_pt, plan->d_slot, plan->n1,  \
-                     g0, ng, X, x_bstride, ctx->d_pinfo)
-  if (gt == 1) {
-    if (bt == 1) BABY(1, 1);
-    else if (bt == 2) BABY(1, 2);
-    else BABY(1, 4);
-  } else if (gt == 2) {
-    if (bt == 1) BABY(2, 1);
-    else BABY(2, 2);
-  } else if (gt == 4) {
-    BABY(4, 1);
-  } else {
-    BABY(8, 1);
+  if (ng >= 2 && batch >= 2 && ctx->tune_baby_share >= 2) {
+    // several giant outputs and a batch: W ciphertexts per workgroup
+    const int W = pick_bt(batch, ctx->tune_baby_share);
+    const int gpw = (ng + W - 1) / W;
+    const int ntiles = (batch + W - 1) / W;
+    const int grid = (ctx->N / 64) * G.pqn * ntiles;
+#define BABYS(W_, GPW_, BETA_)                                                                           \
+  hipLaunchKernelGGL((baby_mac_shared_kernel<W_, GPW_, BETA_>), dim3(grid), dim3(64 * W_), 0, s, BA, G,  \
+                     ctx->L, batch, ntiles, digits, digits_bstride, ct, ct_bstride, plan->d_pt, ng, X,     \
+                     x_bstride, ctx->d_pinfo)
+#define BABYS_B(W_, GPW_)                     \
+  switch (G.beta) {                           \
+    case 1: BABYS(W_, GPW_, 1); break;        \
+    case 2: BABYS(W_, GPW_, 2); break;        \
+    case 3: BABYS(W_, GPW_, 3); break;        \
+    default: BABYS(W_, GPW_, 4); break;       \
   }
+    if (W == 8) {
+      BABYS_B(8, 1);
+    } else if (W == 4) {
+      if (gpw == 1) BABYS_B(4, 1) else BABYS_B(4, 2)
+    } else {
+      if (gpw == 1) BABYS_B(2, 1) else if (gpw == 2) BABYS_B(2, 2) else BABYS_B(2, 4)
+    }
+#undef BABYS_B
+#undef BABYS
+  } else {
+    const int bt = pick_bt(batch, gt >= 4 ? 1 : gt == 2 ? std::min(2, ctx->tune_baby_tile) : ctx->tune_baby_tile);
+    const int ntiles = (batch + bt - 1) / bt;
+    const int grid = (ctx->N / TPB) * G.pqn * ntiles;
+#define BABY(GT_, BT_, BETA_)                                                                            \
+  hipLaunchKernelGGL((baby_mac_kernel<GT_, BT_, BETA_>), dim3(grid), dim3(TPB), 0, s, BA, G, ctx->L,      \
+                     batch, ntiles, digits, digits_bstride, ct, ct_bstride, plan->d_pt, ng, X, x_bstride,  \
+                     ctx->d_pinfo)
+#define BABY_B(GT_, BT_)                      \
+  switch (G.beta) {                           \
+    case 1: BABY(GT_, BT_, 1); break;         \
+    case 2: BABY(GT_, BT_, 2); break;         \
+    case 3: BABY(GT_, BT_, 3); break;         \
+    default: BABY(GT_, BT_, 4); break;        \
+  }
+    if (gt == 1) {
+      if (bt == 1) BABY_B(1, 1) else if (bt == 2) BABY_B(1, 2) else BABY_B(1, 4)
+    } else if (gt == 2) {
+      if (bt == 1) BABY_B(2, 1) else BABY_B(2, 2)
+    } else if (gt == 4) {
+      BABY_B(4, 1);
+    } else {
+      BABY_B(8, 1);
+    }
+#undef BABY_B
 #undef BABY
+  }
   tm.lap(TK_BABY_MAC, 8.0 * ctx->N * words, (2.0 * nrot * beta + 2.0 * npt) * ctx->N * B * (qn + K));
   HIP_TRY(hipGetLastError());
   return HELRM_OK;

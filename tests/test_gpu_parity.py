@@ -256,6 +256,42 @@ def test_lookup_batched_ragged_cfg2(ctx2):
         assert_bit_exact(alone[0], glk[i], f"batch invariance query {i}")
 
 
+@pytest.mark.parametrize("n1", [2, 4, 8])
+def test_lookup_shared_baby_kernel_cfg1(n1, p1):
+    """Batches of 5 with 8, 4 and 2 giant outputs through the workgroup-shared
+    baby-step kernel at every tile width (2, 4, 8 ciphertexts per workgroup:
+    ragged tiles and a tile wider than the batch) and through the per-thread
+    kernel (share 1): bit-exact against the oracle each time."""
+    ctx = context_for(p1)
+    w = W.config1(n_queries=5, n1=n1, radix=2, sign=-1)
+    load_keys(ctx, w.keys)
+    plan = gpu_plan(ctx, w.plan)
+    for share in (1, 2, 4, 8):
+        say(f"baby_share={share} n1={n1}")
+        ctx.helrm_set_tuning("baby_share", share)
+        _check_lookup(ctx, w, plan, [0, 1, 2, 3, 4])
+    ctx.helrm_set_tuning("baby_share", 8)
+
+
+def test_lookup_multitable_batched_cfg2(ctx2):
+    """Four tables of uneven packing (three base-256 compressed, one 100-row
+    uncompressed: 64 outputs, m = 64, four giant outputs) at level 1, batch 5,
+    rotations by -k: every ciphertext bit-exact and decrypting to its rows."""
+    prm = O.config2_params()
+    g = synth.rng(0)
+    tables = [W.compressed_table(g, 65536, 16, 256, -0.05, 0.05),
+              W.uncompressed_table(g, 100, 16, -0.05, 0.05),
+              W.compressed_table(g, 300000, 16, 256, -0.05, 0.05),
+              W.compressed_table(g, 1000, 16, 256, -0.05, 0.05)]
+    w = W.build(prm, tables, level=1, n1=16, radix=8, n_queries=5, sign=-1)
+    assert w.plan.m == 64 and w.plan.n2 == 4
+    load_keys(ctx2, w.keys)
+    plan = gpu_plan(ctx2, w.plan)
+    glk = _check_lookup(ctx2, w, plan, [0, 1, 2, 3, 4])
+    alone = _check_lookup(ctx2, w, plan, [3])
+    assert_bit_exact(alone[0], glk[3], "batch invariance query 3")
+
+
 def test_graph_capture_replays(ctx1, w1):
     """The batched lookup captured in a HIP graph: every replay (with eager
     work and synchronisation between replays) equals the eager result."""
