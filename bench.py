@@ -41,8 +41,7 @@ KERNEL_SYMBOL = {
     "conv": "conv_kernel", "ks_acc": "ks_acc_kernel", "baby_mac": "baby_mac_kernel", "sub_mul": "sub_mul_kernel",
 }
 DEFAULTS = {"w2": dict(n1=16, radix=8, sign=-1, batch=1), "w3": dict(n1=64, radix=8, sign=-1, batch=64)}
-PMC_PROFILES = {"ks_acc": "profiles/ks_acc_kernel_w2_level23_pmc.json",
-                "baby_mac": "profiles/baby_mac_kernel_w2_level23_pmc.json"}
+PMC_DIR = "profiles"   # *_pmc.json: FETCH_SIZE / WRITE_SIZE records, one per kernel and workload
 
 
 def kernel_source(path: str, name: str) -> str:
@@ -71,24 +70,25 @@ def kernel_hash(rec) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str, level: int, radix: int, n1: int, batch: int, sign: int):
-    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE counter
-    runs (scaled by the copy-kernel calibration), or None when there is no
-    such record for this kernel and workload or the kernel (or the device
-    header it uses) changed since the counters were taken."""
-    path = PMC_PROFILES.get(kernel)
-    if not path:
-        return None
-    try:
-        with open(os.path.join(ROOT, path)) as f:
-            rec = json.load(f)
-        if kernel_hash(rec) != rec["source_sha256"]:
-            return None
-    except (OSError, KeyError, ValueError):
-        return None
-    if rec.get("config") != dict(workload=workload, level=level, radix=radix, n1=n1, batch=batch, sign=sign):
-        return None
-    return rec["traffic_bytes_per_launch"]
+def measured_traffic(symbol: str, config: dict):
+    """HBM bytes per launch of kernel `symbol` from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (scaled by the copy-kernel calibration) for this
+    exact workload configuration, or None when there is no such record or the
+    kernel (or the device header it uses) changed since the counters were
+    taken."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, PMC_DIR, "*_pmc.json"))):
+        try:
+            with open(path) as f:
+                rec = json.load(f)
+            if rec.get("kernel") != symbol or rec.get("config") != config:
+                continue
+            if kernel_hash(rec) != rec["source_sha256"]:
+                return None
+        except (OSError, KeyError, ValueError):
+            continue
+        return rec["traffic_bytes_per_launch"]
+    return None
 
 
 def parse():
@@ -394,6 +394,10 @@ def main():
         bsel = sess.encrypt(bidx, [synth.enc_draws(bg, prm.N) for _ in range(Bb)])
         bout = sess.new_output(Bb)
         sess.ctx.helrm_reserve(sess.plan, Bb, stream)
+        bs = autotune.tuned_schedule(prm.N, prm.L, args.level, M.shape[0], M.shape[1], Bb)
+        if bs is not None and (bs.n1, bs.radix, bs.sign) == (n1, radix, sign):
+            for knob, v in (("ks_tile", bs.ks_tile), ("baby_tile", bs.baby_tile), ("baby_share", bs.baby_share)):
+                sess.ctx.helrm_set_tuning(knob, v)
         for _ in range(2):
             sess.lookup(bsel, bout, stream)
         torch.cuda.synchronize()
@@ -407,6 +411,9 @@ def main():
         bms = e0.elapsed_time(e1) / nb
         brows = sess.decrypt_rows(bout)
         berr = max(float(np.max(np.abs(brows[b] - sess.cleartext(bidx[b])))) for b in range(Bb))
+        for knob, v in (("ks_tile", args.ks_tile or sched.ks_tile), ("baby_tile", args.baby_tile or sched.baby_tile),
+                        ("baby_share", share)):
+            sess.ctx.helrm_set_tuning(knob, v)
         res["batched"] = {"batch": Bb, "steps": nb, "ms_per_step": bms,
                           "lookups_per_s": Bb * len(tables) / (bms / 1e3), "max_abs_err": berr,
                           "vs_plain": (Bb * len(tables) / (bms / 1e3)) / value}
@@ -431,17 +438,17 @@ def main():
         symbol = dict(KERNEL_SYMBOL)
         if B >= 2 and spec.n2 >= 2 and share >= 2:
             symbol["baby_mac"] = "baby_mac_shared_kernel"
+        pmc_cfg = dict(workload=args.workload, level=args.level, radix=radix, n1=n1, batch=B, sign=sign)
         res["roofline"] = {"kernel": symbol[dom], "bound": "hbm", "achieved": d["GB/s"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["GB/s"] / HBM_PEAK_GBS,
-                           "traffic": measured_traffic(dom, args.workload, args.level, radix, n1, B, sign),
+                           "traffic": measured_traffic(symbol[dom], pmc_cfg),
                            "avg_us": d["avg_us"], "algorithmic_bytes_per_launch": d["bytes_per_launch"]}
         ks = table.get("ks_acc")
         if ks:
             res["roofline_keyswitch"] = {"kernel": KERNEL_SYMBOL["ks_acc"], "bound": "hbm",
                                          "achieved": ks["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                          "frac": ks["GB/s"] / HBM_PEAK_GBS, "avg_us": ks["avg_us"],
-                                         "traffic": measured_traffic("ks_acc", args.workload, args.level, radix,
-                                                                     n1, B, sign)}
+                                         "traffic": measured_traffic(symbol["ks_acc"], pmc_cfg)}
         limb_ntts = (kt["ntt_fwd_col"]["ops"] + kt["ntt_inv_blk"]["ops"]) / ((prm.N // 2) * 8) / args.steps
         res["ntts_per_s"] = limb_ntts * (1e3 / ms_per_step)
         res["kernels"] = {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in table.items()}

@@ -66,8 +66,8 @@ def tuned_schedule(N: int, L: int, level: int, rows: int, cols: int, batch: int,
 
 
 def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
-         schedules: Optional[Sequence[Schedule]] = None, tiles: Iterable[int] = (1, 2, 4),
-         shares: Iterable[int] = (2, 4, 8), steps: int = 10, warmup: int = 2, log=None) -> Dict:
+         schedules: Optional[Sequence[Schedule]] = None, tiles: Iterable[int] = (2, 4),
+         shares: Iterable[int] = (4, 8), steps: int = 10, warmup: int = 2, log=None) -> Dict:
     """Measure every schedule (and its kernel knobs when batch > 1) and return
     {"best": {...}, "results": [...]}.  key_draws_fn(galois) and
     enc_draws_fn() supply the randomness."""
