@@ -19,6 +19,10 @@ Paper sections followed (arXiv 2506.18150):
     parameterization": base-p digits, y = sum_j C_j[i_j].
   * Sec. IV-B "Block-diagonal embedding matrix": M = block_diag(W_t), the
     selector is the concatenation of per-table one-hots.
+  * Sec. II-B / Sec. V-C: the small DLRM (dense features and embedding
+    lookups into bottom and top MLPs with a square activation), built from
+    the same matvec, ciphertext products with relinearisation, plaintext
+    additions and level alignment.
 
 The paper leaves the following open; this oracle takes these readings (the
 GPU library must take the same ones for bit-exact parity):
@@ -557,6 +561,61 @@ def hoisted_rotations(prm: Params, keys: Keys, ct: np.ndarray, level: int,
     return out
 
 
+# ------------------------------------------------------------------ ciphertext products (App. A "Multiplication")
+
+def tensor(prm: Params, a: np.ndarray, b: np.ndarray, level: int) -> np.ndarray:
+    """(a0 + a1 s)(b0 + b1 s) = d0 + d1 s + d2 s^2 with d0 = a0 b0,
+    d1 = a0 b1 + a1 b0, d2 = a1 b1, pointwise in evaluation form over Q_level.
+    Returns [3][level+1][N]."""
+    Q = prm.Q(level)
+    d0 = mul(a[0], b[0], Q)
+    d1 = add(mul(a[0], b[1], Q), mul(a[1], b[0], Q), Q)
+    d2 = mul(a[1], b[1], Q)
+    return np.stack([d0, d1, d2])
+
+
+def relinearize(prm: Params, keys: Keys, d: np.ndarray, level: int) -> np.ndarray:
+    """Switch d2 from s^2 to s with the relinearisation key and add (d0, d1):
+    ModDown(P (d0, d1) + sum_j ModUp(d2)_j (b_j, a_j)).  P (d0, d1) vanishes
+    modulo every special prime, so adding it before the ModDown gives the same
+    residues as adding (d0, d1) after it."""
+    PQ = prm.PQ(level)
+    digits = modup(prm, d[2], level)
+    zero = np.zeros((level + 1, prm.N), dtype=np.uint64)
+    X = key_inner_product(prm, digits, zero, level, keys.relin, 1)
+    Lp = lift_P(prm, d[:2], level)
+    for c in range(2):
+        X[c] = add(X[c], Lp[c], PQ)
+    return moddown(prm, X, level)
+
+
+def mul_relin(prm: Params, keys: Keys, a: np.ndarray, b: np.ndarray, level: int) -> np.ndarray:
+    """Ciphertext product followed by relinearisation (no rescale)."""
+    return relinearize(prm, keys, tensor(prm, a, b, level), level)
+
+
+def add_plain(prm: Params, ct: np.ndarray, pt: np.ndarray, level: int) -> np.ndarray:
+    """(c0 + pt, c1): pt is [level+1][N] residues in evaluation form."""
+    Q = prm.Q(level)
+    return np.stack([add(ct[0], pt, Q), ct[1].copy()])
+
+
+def add_ct(prm: Params, a: np.ndarray, b: np.ndarray, level: int) -> np.ndarray:
+    Q = prm.Q(level)
+    return np.stack([add(a[0], b[0], Q), add(a[1], b[1], Q)])
+
+
+def mod_drop(ct: np.ndarray, level: int) -> np.ndarray:
+    """Drop the primes above q_level (the same ciphertext modulo Q_level)."""
+    return np.ascontiguousarray(ct[:, : level + 1])
+
+
+def plain_residues(prm: Params, z, scale: float, level: int) -> np.ndarray:
+    """Slot vector z encoded at `scale`, as residues over Q_level in evaluation form."""
+    Q = prm.Q(level)
+    return ntt(from_signed(encode(z, scale, prm), Q), Q, prm)
+
+
 # ------------------------------------------------------------------ cleartext model (Sec. IV)
 
 def num_digits(k: int, p: int) -> int:
@@ -728,9 +787,12 @@ def bsgs_plan_values(M: np.ndarray, n: int, n1: int, sign: int = 1) -> Tuple[int
     return m, n2, vals
 
 
-def make_plan(prm: Params, M: np.ndarray, level: int, n1: int, radix: int = 2, sign: int = 1) -> Plan:
+def make_plan(prm: Params, M: np.ndarray, level: int, n1: int, radix: int = 2, sign: int = 1,
+              scale: Optional[float] = None) -> Plan:
+    """Plaintext diagonals encoded at `scale` (default q_level, which keeps the
+    product at the input's scale after the rescale)."""
     m, n2, vals = bsgs_plan_values(M, prm.n, n1, sign)
-    scale = prm.q[level]
+    scale = prm.q[level] if scale is None else scale
     coeffs = {gb: encode(v, scale, prm) for gb, v in vals.items()}
     span = fold_span(M, prm.n, sign)
     return Plan(m=m, n1=n1, n2=n2, radix=radix, level=level, rows=M.shape[0], coeffs=coeffs,
@@ -822,3 +884,152 @@ def matvec(prm: Params, keys: Keys, plan: Plan, ct: np.ndarray,
 def lookup(prm: Params, keys: Keys, plan: Plan, ct: np.ndarray, pts=None) -> np.ndarray:
     """Encrypted lookup: matvec followed by one rescale (consumes one level)."""
     return rescale(prm, matvec(prm, keys, plan, ct, pts), plan.level)
+
+
+# ------------------------------------------------------------------ small DLRM (Sec. II-B, Sec. V-C)
+
+@dataclass
+class SmallDLRM:
+    """Dense features and uncompressed embedding tables (Sec. II-B): a bottom
+    MLP on the dense features, the embedding rows of every table, and a top MLP
+    on the concatenation [embedding rows; bottom output].  Every hidden layer is
+    followed by the square activation (the degree-2 polynomial the paper uses
+    for its small model, Sec. V-C); the last top layer gives the logit."""
+    tables: List[TableSpec]
+    bottom: List[Tuple[np.ndarray, np.ndarray]]     # (W, b) per layer
+    top: List[Tuple[np.ndarray, np.ndarray]]
+    n_dense: int
+
+    @property
+    def emb_dim(self) -> int:
+        return sum(t.d for t in self.tables)
+
+    def input_slots(self, dense: np.ndarray, idx: Sequence[int]) -> np.ndarray:
+        """Packed input: dense features in slots [0, n_dense), then the one-hots."""
+        return np.concatenate([np.asarray(dense, dtype=float), pack_selector(self.tables, idx)])
+
+
+def dlrm_cleartext(model: SmallDLRM, dense: np.ndarray, idx: Sequence[int]) -> np.ndarray:
+    """fp64 forward pass: the reference the decrypted logit is compared with."""
+    h = np.asarray(dense, dtype=float)
+    for W, b in model.bottom:
+        h = (W @ h + b) ** 2
+    e = np.concatenate([t.lookup(i) for t, i in zip(model.tables, idx)])
+    z = np.concatenate([e, h])
+    for k, (W, b) in enumerate(model.top):
+        z = W @ z + b
+        if k + 1 < len(model.top):
+            z = z ** 2
+    return z
+
+
+@dataclass
+class DLRMLayout:
+    """The model's layers as matrices over slot vectors.  The embedding matrix
+    reads the one-hot slots and writes rows [0, E); the last bottom layer is
+    padded to write rows [E, E+H); both have E+H rows, so both products are
+    exact (zero) in every slot of [0, next_pow2(E+H)) they do not write and
+    their sum is the concatenation."""
+    emb: np.ndarray
+    bottom: List[np.ndarray]
+    bias_bottom: List[np.ndarray]
+    top: List[np.ndarray]
+    bias_top: List[np.ndarray]
+
+
+def dlrm_layout(model: SmallDLRM) -> DLRMLayout:
+    E = model.emb_dim
+    H = model.bottom[-1][0].shape[0]
+    width = model.n_dense + sum(t.width for t in model.tables)
+    emb = np.zeros((E + H, width))
+    emb[:E, model.n_dense:] = pack_tables(model.tables)
+    bottom, bb = [], []
+    for k, (W, b) in enumerate(model.bottom):
+        if k + 1 < len(model.bottom):
+            bottom.append(np.array(W, dtype=float))
+            bb.append(np.array(b, dtype=float))
+        else:
+            M = np.zeros((E + H, W.shape[1]))
+            M[E:] = W
+            bv = np.zeros(E + H)
+            bv[E:] = b
+            bottom.append(M)
+            bb.append(bv)
+    return DLRMLayout(emb=emb, bottom=bottom, bias_bottom=bb,
+                      top=[np.array(W, dtype=float) for W, _ in model.top],
+                      bias_top=[np.array(b, dtype=float) for _, b in model.top])
+
+
+@dataclass
+class DLRMSchedule:
+    """Plans, bias plaintexts and levels of the encrypted forward pass.  Every
+    matvec's plaintexts are encoded at scale S_out q_l / S_in, so its output
+    after the rescale is at S_out (Delta, except the embedding product, whose
+    output is put at the scale of the bottom output so the two can be added).
+    A square multiplies the scale S into S^2 / q_l."""
+    level0: int
+    emb: Plan
+    bottom: List[Plan]
+    bias_bottom: List[np.ndarray]
+    top: List[Plan]
+    bias_top: List[np.ndarray]
+    concat_level: int
+    concat_scale: float
+    out_level: int
+
+    def plans(self) -> List[Plan]:
+        return [self.emb] + self.bottom + self.top
+
+    def rotation_steps(self) -> List[int]:
+        return sorted({k for p in self.plans() for k in p.rotation_steps()})
+
+
+def dlrm_schedule(prm: Params, model: SmallDLRM, level0: int, n1: int = 16, radix: int = 8,
+                  sign: int = -1) -> DLRMSchedule:
+    lay = dlrm_layout(model)
+    delta = float(prm.delta)
+    lv, S = level0, delta
+
+    def plan_for(M, level, s_in, s_out):
+        m = next_pow2(M.shape[0])
+        return make_plan(prm, M, level, min(n1, m), radix, sign, scale=s_out * prm.q[level] / s_in)
+
+    bottom, bb = [], []
+    for M, bv in zip(lay.bottom, lay.bias_bottom):
+        bottom.append(plan_for(M, lv, S, delta))
+        lv -= 1
+        S = delta
+        bb.append(plain_residues(prm, bv, S, lv))
+        S = S * S / prm.q[lv]          # square, then rescale by q_lv
+        lv -= 1
+    concat_level, concat_scale = lv, S
+    emb = plan_for(lay.emb, level0, delta, concat_scale)
+    top, bt = [], []
+    for k, (M, bv) in enumerate(zip(lay.top, lay.bias_top)):
+        top.append(plan_for(M, lv, S, delta))
+        lv -= 1
+        S = delta
+        bt.append(plain_residues(prm, bv, S, lv))
+        if k + 1 < len(lay.top):
+            S = S * S / prm.q[lv]
+            lv -= 1
+    return DLRMSchedule(level0=level0, emb=emb, bottom=bottom, bias_bottom=bb, top=top, bias_top=bt,
+                        concat_level=concat_level, concat_scale=concat_scale, out_level=lv)
+
+
+def dlrm_forward(prm: Params, keys: Keys, sch: DLRMSchedule, ct: np.ndarray) -> np.ndarray:
+    """Encrypted forward pass of one packed input ciphertext at sch.level0;
+    returns the logit ciphertext at sch.out_level (slot 0, scale Delta)."""
+    x = ct
+    for plan, b in zip(sch.bottom, sch.bias_bottom):
+        lv = plan.level - 1
+        x = add_plain(prm, lookup(prm, keys, plan, x), b, lv)
+        x = rescale(prm, mul_relin(prm, keys, x, x, lv), lv)
+    e = mod_drop(lookup(prm, keys, sch.emb, ct), sch.concat_level)
+    z = add_ct(prm, e, x, sch.concat_level)
+    for k, (plan, b) in enumerate(zip(sch.top, sch.bias_top)):
+        lv = plan.level - 1
+        z = add_plain(prm, lookup(prm, keys, plan, z), b, lv)
+        if k + 1 < len(sch.top):
+            z = rescale(prm, mul_relin(prm, keys, z, z, lv), lv)
+    return z

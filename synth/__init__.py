@@ -15,7 +15,7 @@ Galois element in ascending order, then the relinearisation key if asked).
 from __future__ import annotations
 
 from dataclasses import dataclass, field
-from typing import Dict, List, Sequence
+from typing import Dict, List, Sequence, Tuple
 
 import numpy as np
 
@@ -133,3 +133,36 @@ def indices(g: np.random.Generator, row_counts: Sequence[int]) -> List[int]:
 def poisson_arrivals(g: np.random.Generator, rate: float, n: int) -> np.ndarray:
     """Arrival times (s) of a Poisson process with the given rate."""
     return np.cumsum(g.exponential(1.0 / rate, size=n))
+
+
+@dataclass
+class SmallDLRMDraws:
+    """Weights of the small DLRM: embedding tables (rows U{2..200} x d,
+    values U[lo, hi]), dense layers (weights and biases N(0, sigma^2))."""
+    table_rows: List[int]
+    tables: List[np.ndarray]
+    bottom: List[Tuple[np.ndarray, np.ndarray]]
+    top: List[Tuple[np.ndarray, np.ndarray]]
+    n_dense: int
+
+
+def small_dlrm_draws(seed: int = 0, n_tables: int = 8, n_dense: int = 13, d: int = 16,
+                     bottom: Sequence[int] = (64, 16), top: Sequence[int] = (32, 1),
+                     rows_lo: int = 2, rows_hi: int = 200, lo: float = -0.05, hi: float = 0.05,
+                     sigma: float = 0.1) -> SmallDLRMDraws:
+    g = rng(seed)
+    rows = [int(r) for r in g.integers(rows_lo, rows_hi + 1, size=n_tables)]
+    tables = [uniform_table(g, r, d, lo, hi) for r in rows]
+    layers_b, prev = [], n_dense
+    for w in bottom:
+        layers_b.append((g.normal(0.0, sigma, (w, prev)), g.normal(0.0, sigma, w)))
+        prev = w
+    layers_t, prev = [], n_tables * d + bottom[-1]
+    for w in top:
+        layers_t.append((g.normal(0.0, sigma, (w, prev)), g.normal(0.0, sigma, w)))
+        prev = w
+    return SmallDLRMDraws(table_rows=rows, tables=tables, bottom=layers_b, top=layers_t, n_dense=n_dense)
+
+
+def dense_features(g: np.random.Generator, n_dense: int) -> np.ndarray:
+    return g.uniform(0.0, 1.0, n_dense)

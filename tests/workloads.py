@@ -74,3 +74,17 @@ def config1(n_queries: int = 2, compressed: bool = True, n1: int = 4, radix: int
 def decrypt_slots(w: Workload, ct: np.ndarray, scale: float, count: int) -> np.ndarray:
     m = O.decrypt(w.prm, w.keys, ct)
     return O.decode(m, scale, w.prm)[:count].real
+
+
+def small_dlrm(seed: int = 0, **kw) -> O.SmallDLRM:
+    """The small DLRM of the batched end-to-end configuration: 8 uncompressed
+    tables of 2-200 rows x 16, 13 dense features, bottom 13-64-16, top
+    144-32-1 (weights from ``synth``)."""
+    d = synth.small_dlrm_draws(seed, **kw)
+    tables = [O.TableSpec(rows=r, d=t.shape[1], E=t) for r, t in zip(d.table_rows, d.tables)]
+    return O.SmallDLRM(tables=tables, bottom=list(d.bottom), top=list(d.top), n_dense=d.n_dense)
+
+
+def dlrm_params_toy() -> O.Params:
+    """N=2^12 with a chain deep enough for the forward pass (L=8, one prime per digit)."""
+    return O.make_params(N=4096, L=8, K=1, alpha=1)
