@@ -120,6 +120,10 @@ def parse():
     ap.add_argument("--group-size", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=16)
     ap.add_argument("--streams", type=int, default=2)
+    ap.add_argument("--dlrm", action="store_true",
+                    help="encrypted small DLRM (8 tables of 2-200 rows, 13 dense features, bottom 13-64-16, "
+                         "top 144-32-1, square activation) on a batch of requests")
+    ap.add_argument("--dlrm-level", type=int, default=8, help="input level of the DLRM pass (7 levels used)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the run, copy a 1 GiB buffer 3 times (reference kernel for HBM counters)")
     return ap.parse_args()
@@ -269,6 +273,75 @@ def serve_bench(args):
     print(json.dumps(res))
 
 
+def dlrm_bench(args):
+    """Batched end-to-end small DLRM: one selector ciphertext per request
+    (dense features and one-hots), the whole forward pass on the GPU per
+    batch, logits decrypted and compared with the fp64 model."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_18150_amd import dlrm, params
+
+    prm = params.n16()
+    d = synth.small_dlrm_draws(0)
+    w = dlrm.DLRMWeights(tables=d.tables, bottom=list(d.bottom), top=list(d.top), n_dense=d.n_dense)
+    t0 = time.time()
+    sess = dlrm.DLRMSession(prm, w, args.dlrm_level,
+                            lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals, relin=True),
+                            n1=args.n1 or 16, radix=args.radix or 8, sign=args.sign or -1)
+    setup_s = time.time() - t0
+    B = args.batch or 128
+    g = synth.rng(3)
+    dense = [synth.dense_features(g, d.n_dense) for _ in range(B)]
+    idx = [synth.indices(g, d.table_rows) for _ in range(B)]
+    sel = sess.encrypt(dense, idx, [synth.enc_draws(g, prm.N) for _ in range(B)])
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        out = sess.forward(sel, stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record(stream)
+    for k in range(args.steps):
+        out = sess.forward(sel, stream)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    ms = ev[0].elapsed_time(ev[-1]) / args.steps
+    logits = sess.decrypt_logits(out)
+    err = float(max(abs(logits[k] - w.cleartext(dense[k], idx[k])[0]) for k in range(B)))
+    res = {"metric": "encrypted DLRM inferences/s", "value": B / (ms / 1e3), "unit": "inferences/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": f"small DLRM: 8 tables of {min(d.table_rows)}-{max(d.table_rows)} rows x 16, 13 dense "
+                                  f"features, bottom 13-64-16, top 144-32-1, square activation; N=2^16, input at level "
+                                  f"{args.dlrm_level}; batch {B} requests per call",
+                      "batch": B, "level": args.dlrm_level},
+           "lookups_per_s": len(d.tables) * B / (ms / 1e3),
+           "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
+           "max_abs_err": err, "setup_s": round(setup_s, 1)}
+    if not args.no_kernel_timing:
+        sess.ctx.helrm_timing_enable(True)
+        for _ in range(max(1, args.steps // 2)):
+            sess.forward(sel, stream)
+        torch.cuda.synchronize()
+        n = max(1, args.steps // 2)
+        table = {}
+        for k in KERNELS:
+            v = sess.ctx.helrm_timing_read(k)
+            if v["launches"]:
+                table[k] = {"ms_per_step": v["ms"] / n, "avg_us": 1e3 * v["ms"] / v["launches"],
+                            "GB/s": v["bytes"] / (v["ms"] * 1e6), "bytes_per_launch": v["bytes"] / v["launches"]}
+        sess.ctx.helrm_timing_enable(False)
+        dom = max(table, key=lambda k: table[k]["ms_per_step"])
+        symbol = dict(KERNEL_SYMBOL)
+        symbol["baby_mac"] = "baby_mac_kernel|baby_mac_shared_kernel"
+        res["roofline"] = {"kernel": symbol[dom], "bound": "hbm", "achieved": table[dom]["GB/s"], "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": table[dom]["GB/s"] / HBM_PEAK_GBS, "traffic": None}
+        res["kernels"] = {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in table.items()}
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -276,6 +349,8 @@ def main():
         sys.exit(2)
     if args.serve:
         return serve_bench(args)
+    if args.dlrm:
+        return dlrm_bench(args)
     import numpy as np
     import torch
 

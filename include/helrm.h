@@ -234,6 +234,32 @@ int helrm_timing_enable(helrm_ctx *ctx, int enable);
 int helrm_timing_read(helrm_ctx *ctx, const char *kernel, double *ms, int64_t *launches, double *bytes,
                       double *ops);
 
+/* Ciphertext-ciphertext product with relinearisation (Appendix A
+ * "Multiplication", "Key-switching"): the tensor product
+ * (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1) followed by a hybrid key switch
+ * of d2 from s^2 to s with the relinearisation key (loaded as Galois element
+ * 0): ModUp(d2), inner product with the key plus P (d0, d1), ModDown.  No
+ * rescale (call helrm_rescale).  a, b, out: device [batch][2][level+1][N] in
+ * evaluation form; a may equal b (square) and out may alias a or b.  Errors:
+ * HELRM_EINVAL (level, NULL buffer, no relinearisation key). */
+int helrm_mul_relin(helrm_ctx *ctx, const uint64_t *a, const uint64_t *b, int level, uint64_t *out, int batch,
+                    void *stream);
+
+/* Plaintext-ciphertext addition (Appendix A "Addition"): out = (c0 + pt, c1)
+ * for every ciphertext of the batch.  ct, out: device [batch][2][level+1][N];
+ * pt: device [level+1][N] residues in evaluation form (the plaintext encoded at
+ * the ciphertext's scale), shared by the batch; out may alias ct.  Errors:
+ * HELRM_EINVAL. */
+int helrm_add_plain(helrm_ctx *ctx, const uint64_t *ct, const uint64_t *pt, int level, uint64_t *out,
+                    int batch, void *stream);
+
+/* Level alignment without rescaling: the same ciphertext modulo Q_level_out
+ * (limbs above q_level_out dropped), so that ciphertexts of different depths
+ * can be added.  in: device [batch][2][level_in+1][N]; out: device
+ * [batch][2][level_out+1][N], distinct from in.  Errors: HELRM_EINVAL. */
+int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *out, int level_out, int batch,
+                   void *stream);
+
 /* Schedule knobs set by the autotuner.  "ks_tile" and "baby_tile" cap how many
  * ciphertexts of a batch one thread serves in the key inner product and the
  * fused baby-step kernel (1, 2 or 4; default 4): larger tiles read each key

@@ -52,7 +52,7 @@ EXPORTS = [
     "helrm_from_signed", "helrm_keyswitch_hoisted", "helrm_rescale", "helrm_plan_create",
     "helrm_plan_destroy", "helrm_plan_rotation_steps", "helrm_ptxt_ct_matvec_diag",
     "helrm_lookup_packed", "helrm_footprint", "helrm_reserve", "helrm_timing_enable", "helrm_timing_read",
-    "helrm_set_tuning",
+    "helrm_set_tuning", "helrm_mul_relin", "helrm_add_plain", "helrm_mod_drop",
 ]
 
 _lib = None
@@ -88,6 +88,9 @@ def lib() -> ctypes.CDLL:
     L.helrm_reserve.argtypes = [_vp, _vp, _c_int, _vp]
     L.helrm_timing_enable.argtypes = [_vp, _c_int]
     L.helrm_set_tuning.argtypes = [_vp, ctypes.c_char_p, _c_int]
+    L.helrm_mul_relin.argtypes = [_vp, _vp, _vp, _c_int, _vp, _c_int, _vp]
+    L.helrm_add_plain.argtypes = [_vp, _vp, _vp, _c_int, _vp, _c_int, _vp]
+    L.helrm_mod_drop.argtypes = [_vp, _vp, _c_int, _vp, _c_int, _c_int, _vp]
     L.helrm_timing_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]
@@ -225,6 +228,15 @@ class Context:
 
     def helrm_reserve(self, plan: "Plan", batch: int, stream=None):
         _check(lib().helrm_reserve(self.h, plan.h, batch, _stream(stream)))
+
+    def helrm_mul_relin(self, a, b, level: int, out, batch: int, stream=None):
+        _check(lib().helrm_mul_relin(self.h, _ptr(a), _ptr(b), level, _ptr(out), batch, _stream(stream)))
+
+    def helrm_add_plain(self, ct, pt, level: int, out, batch: int, stream=None):
+        _check(lib().helrm_add_plain(self.h, _ptr(ct), _ptr(pt), level, _ptr(out), batch, _stream(stream)))
+
+    def helrm_mod_drop(self, d_in, level_in: int, d_out, level_out: int, batch: int, stream=None):
+        _check(lib().helrm_mod_drop(self.h, _ptr(d_in), level_in, _ptr(d_out), level_out, batch, _stream(stream)))
 
     def helrm_set_tuning(self, knob: str, value: int):
         _check(lib().helrm_set_tuning(self.h, knob.encode(), int(value)))

@@ -918,6 +918,79 @@ extern "C" int helrm_rescale(helrm_ctx *c, const uint64_t *in, int level, uint64
   API_GUARD_END
 }
 
+extern "C" int helrm_mul_relin(helrm_ctx *c, const uint64_t *a, const uint64_t *b, int level, uint64_t *out,
+                               int batch, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(level >= 0 && level <= c->L, "level %d out of range", level);
+  CHECK_ARG(batch >= 0, "batch < 0");
+  if (batch == 0) return HELRM_OK;
+  CHECK_ARG(a && b && out, "NULL buffer");
+  auto it = c->keys.find(0u);
+  CHECK_ARG(it != c->keys.end(), "no relinearisation key loaded (galois element 0)");
+  hipStream_t s = as_stream(stream);
+  const size_t N = c->N;
+  const int qn = level + 1, pqn = level + 1 + c->K, beta = c->n_digits(level);
+  KsSizes z = ks_sizes(c, level, batch, 1);
+  const size_t dw = (size_t)batch * 3 * qn * N;
+  size_t bytes = rnd(dw) + rnd(z.coef) + rnd(z.D) + rnd(z.X) + rnd(z.mdP) + rnd(z.mdT);
+  char *base;
+  TRY(ensure_ws(c, s, bytes, &base));
+  Arena ar{base};
+  u64 *d = ar.take(dw), *coef = ar.take(z.coef), *D = ar.take(z.D), *X = ar.take(z.X), *mdP = ar.take(z.mdP),
+      *mdT = ar.take(z.mdT);
+  // 1. tensor product (d0, d1, d2)
+  TRY(launch_tensor(c, a, b, d, level, batch, s));
+  // 2. ModUp of d2, 3. key inner product with the relinearisation key plus
+  //    P (d0, d1), 4. ModDown (P (d0, d1) passes through it as (d0, d1))
+  const int d_bs = beta * pqn;
+  TRY(do_modup(c, level, d + (size_t)2 * qn * N, 3 * qn, D, d_bs, coef, batch, s));
+  KsTerm t;
+  t.digits = D;
+  t.c0 = nullptr;
+  t.key = it->second.d;
+  t.galois = 1;
+  TRY(launch_ks_accumulate(c, level, &t, 1, (size_t)d_bs * N, 0, d, (size_t)3 * qn * N, X, (size_t)2 * pqn * N,
+                           batch, s));
+  TRY(do_moddown(c, level, X, 2 * pqn, out, 2 * qn, mdP, mdT, batch, s));
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_add_plain(helrm_ctx *c, const uint64_t *ct, const uint64_t *pt, int level, uint64_t *out,
+                               int batch, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(level >= 0 && level <= c->L, "level %d out of range", level);
+  CHECK_ARG(batch >= 0, "batch < 0");
+  if (batch == 0) return HELRM_OK;
+  CHECK_ARG(ct && pt && out, "NULL buffer");
+  return launch_add_plain(c, ct, pt, out, level, batch, as_stream(stream));
+  API_GUARD_END
+}
+
+extern "C" int helrm_mod_drop(helrm_ctx *c, const uint64_t *in, int level_in, uint64_t *out, int level_out,
+                              int batch, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(level_in >= 0 && level_in <= c->L, "level_in %d out of range", level_in);
+  CHECK_ARG(level_out >= 0 && level_out <= level_in, "level_out must be in [0, level_in]");
+  CHECK_ARG(batch >= 0, "batch < 0");
+  if (batch == 0) return HELRM_OK;
+  CHECK_ARG(in && out, "NULL buffer");
+  CHECK_ARG(in != out, "in and out must differ");
+  const int qi = level_in + 1, qo = level_out + 1;
+  LimbList cp = ll_make(2 * qo, 2 * qi, 2 * qo);
+  for (int cc = 0; cc < 2; cc++)
+    for (int r = 0; r < qo; r++) {
+      cp.src_off[cc * qo + r] = cc * qi + r;
+      cp.dst_off[cc * qo + r] = cc * qo + r;
+      cp.prime[cc * qo + r] = (unsigned char)r;
+    }
+  return launch_copy_limbs(in, out, cp, batch, c->N, as_stream(stream));
+  API_GUARD_END
+}
+
 extern "C" int helrm_plan_create(helrm_ctx *c, const helrm_plan_desc *d, helrm_plan **out) {
   API_GUARD_BEGIN
   CHECK_ARG(c && d && out, "NULL argument");

@@ -379,7 +379,7 @@ int launch_rescale_spread(helrm_ctx *ctx, const u64 *top, u64 *out, int level, i
 
 struct KsTerm {
   const u64 *digits;  // [beta][level+1+K][N] (batch stride given separately)
-  const u64 *c0;      // [level+1][N]
+  const u64 *c0;      // [level+1][N], or null: no P sigma(c0) term
   const u64 *key;     // [dnum][2][L+1+K][N] Montgomery form
   uint32_t galois;
 };
@@ -394,6 +394,12 @@ inline uint32_t galois_of_step(const helrm_ctx *ctx, long step) {
     if (k & 1) g = g * b & mask;
   return (uint32_t)g;
 }
+
+// (d0, d1, d2) of two ciphertexts at `level` ([batch][2][level+1] -> [batch][3][level+1]).
+int launch_tensor(helrm_ctx *ctx, const u64 *a, const u64 *b, u64 *d, int level, int batch, hipStream_t s);
+// (c0 + pt, c1) with one plaintext [level+1] limbs for every ciphertext of the batch.
+int launch_add_plain(helrm_ctx *ctx, const u64 *ct, const u64 *pt, u64 *out, int level, int batch,
+                     hipStream_t s);
 
 // out (PQ, 2 polys) = [lift_P(base)] + sum_t KeyIP(term t).
 int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_terms,

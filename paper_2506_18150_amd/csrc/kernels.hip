@@ -194,6 +194,49 @@ __global__ __launch_bounds__(TPB) void rescale_spread_kernel(const u64 *top, u64
   out[((size_t)cb * level + i) * N + x] = r;
 }
 
+// ---------------------------------------------------------------- ciphertext products and additions
+
+// (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1) per limb, canonical residues.
+// a, b: [batch][2][qn] limbs; d: [batch][3][qn].  Each product is a REDC of a
+// 128-bit sum (a b 2^-64) followed by a REDC with 2^128 mod q.
+__global__ __launch_bounds__(TPB) void tensor_kernel(const u64 *a, const u64 *b, u64 *d, int qn,
+                                                     const PrimeInfo *pinfo, int N) {
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int r = blockIdx.y % qn, bat = blockIdx.y / qn;
+  const PrimeInfo pi = pinfo[r];
+  const size_t ia = ((size_t)bat * 2 * qn + r) * N + x, off1 = (size_t)qn * N;
+  const u64 a0 = a[ia], a1 = a[ia + off1], b0 = b[ia], b1 = b[ia + off1];
+  auto finish = [&](const Acc &s) {
+    const u64 t = redc_acc(s, pi.q, pi.qn);
+    const u128 p = (u128)t * pi.r2;
+    return redc((u64)p, (u64)(p >> 64), pi.q, pi.qn);
+  };
+  Acc s0, s1, s2;
+  acc_zero(s0);
+  acc_zero(s1);
+  acc_zero(s2);
+  acc_mac(s0, a0, b0);
+  acc_mac(s1, a0, b1);
+  acc_mac(s1, a1, b0);
+  acc_mac(s2, a1, b1);
+  const size_t id = ((size_t)bat * 3 * qn + r) * N + x;
+  d[id] = finish(s0);
+  d[id + off1] = finish(s1);
+  d[id + 2 * off1] = finish(s2);
+}
+
+// out = (c0 + pt, c1); ct, out: [batch][2][qn] limbs; pt: [qn] limbs, shared.
+__global__ __launch_bounds__(TPB) void add_plain_kernel(const u64 *ct, const u64 *pt, u64 *out, int qn,
+                                                        const PrimeInfo *pinfo, int N) {
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int li = blockIdx.y % (2 * qn), bat = blockIdx.y / (2 * qn);
+  const size_t i = ((size_t)bat * 2 * qn + li) * N + x;
+  if (li < qn)
+    out[i] = add_mod(ct[i], pt[(size_t)li * N + x], pinfo[li].q);
+  else
+    out[i] = ct[i];
+}
+
 // ---------------------------------------------------------------- key switching
 
 struct KsArgs {
@@ -275,7 +318,7 @@ __device__ __forceinline__ void ks_acc_body(const KsArgs &T, const LevelGeom &G,
         const u64 *dg = T.digits[t] + (b0 + k) * dig_bs;
 #pragma unroll
         for (int j = 0; j < BETA; j++) in.d[k][j] = dg[((size_t)j * G.pqn + r) * N + src];
-        in.c0[k] = isq ? T.c0[t][(b0 + k) * c0_bs + (size_t)r * N + src] : 0;
+        in.c0[k] = isq && T.c0[t] ? T.c0[t][(b0 + k) * c0_bs + (size_t)r * N + src] : 0;
       }
     }
   };
@@ -881,8 +924,10 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
   // per coefficient of a Q limb: terms * 3 beta words (digit, key b, key a) + terms c0 words
   // + 2 base words + 2 output words; special limbs: no c0 / base words.  Keys count once per
   // launch, the rest once per ciphertext.
+  double nc0 = 0;
+  for (int i = 0; i < n_terms; i++) nc0 += terms[i].c0 ? 1 : 0;
   const double qn = level + 1, K = ctx->K, nt = n_terms, beta = G.beta, B = batch;
-  const double words = qn * (nt * 2 * beta + B * (nt * beta + nt + (base ? 2 : 0) + 2)) +
+  const double words = qn * (nt * 2 * beta + B * (nt * beta + nc0 + (base ? 2 : 0) + 2)) +
                        K * (nt * 2 * beta + B * (nt * beta + 2));
   const int bt = pick_bt(batch, ctx->tune_ks_tile);
   const int ntiles = (batch + bt - 1) / bt;
@@ -1021,6 +1066,25 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
 #undef BABY
   }
   tm.lap(TK_BABY_MAC, 8.0 * ctx->N * words, (2.0 * nrot * beta + 2.0 * npt) * ctx->N * B * (qn + K));
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_tensor(helrm_ctx *ctx, const u64 *a, const u64 *b, u64 *d, int level, int batch, hipStream_t s) {
+  const int qn = level + 1;
+  if (batch == 0) return HELRM_OK;
+  hipLaunchKernelGGL(tensor_kernel, ew_grid(ctx, qn * batch), dim3(TPB), 0, s, a, b, d, qn, ctx->d_pinfo,
+                     ctx->N);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_add_plain(helrm_ctx *ctx, const u64 *ct, const u64 *pt, u64 *out, int level, int batch,
+                     hipStream_t s) {
+  const int qn = level + 1;
+  if (batch == 0) return HELRM_OK;
+  hipLaunchKernelGGL(add_plain_kernel, ew_grid(ctx, 2 * qn * batch), dim3(TPB), 0, s, ct, pt, out, qn,
+                     ctx->d_pinfo, ctx->N);
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
 }

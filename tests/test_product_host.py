@@ -75,3 +75,22 @@ def test_plan_spec_rotation_steps():
     assert spec.rotation_steps()[:15] == list(range(-15, 0))
     assert len(spec.rotation_steps()) == 15 + 14
     assert planner.compress_rule(501, 500) and not planner.compress_rule(500, 500)
+
+
+def test_dlrm_layout_matches_oracle():
+    """The product's slot layout of the small DLRM equals the oracle's."""
+    from paper_2506_18150_amd import dlrm
+    d = synth.small_dlrm_draws(0)
+    w = dlrm.DLRMWeights(tables=d.tables, bottom=list(d.bottom), top=list(d.top), n_dense=d.n_dense)
+    model = O.SmallDLRM(tables=[O.TableSpec(rows=r, d=t.shape[1], E=t) for r, t in zip(d.table_rows, d.tables)],
+                        bottom=list(d.bottom), top=list(d.top), n_dense=d.n_dense)
+    emb, bottom, bb, top, bt = dlrm.layer_matrices(w)
+    lay = O.dlrm_layout(model)
+    assert np.array_equal(emb, lay.emb)
+    for a, b in zip(bottom + bb + top + bt, lay.bottom + lay.bias_bottom + lay.top + lay.bias_top):
+        assert np.array_equal(a, b)
+    g = synth.rng(2)
+    dense = synth.dense_features(g, d.n_dense)
+    idx = synth.indices(g, d.table_rows)
+    assert np.array_equal(w.input_slots(dense, idx), model.input_slots(dense, idx))
+    assert np.allclose(w.cleartext(dense, idx), O.dlrm_cleartext(model, dense, idx), atol=1e-14)

@@ -86,5 +86,6 @@ def small_dlrm(seed: int = 0, **kw) -> O.SmallDLRM:
 
 
 def dlrm_params_toy() -> O.Params:
-    """N=2^12 with a chain deep enough for the forward pass (L=8, one prime per digit)."""
-    return O.make_params(N=4096, L=8, K=1, alpha=1)
+    """N=2^12 with a chain deep enough for the forward pass: L=8, digits of
+    three primes (dnum=3), three special primes."""
+    return O.make_params(N=4096, L=8, K=3, alpha=3)
