@@ -9,6 +9,11 @@ Workloads (seeded synthetic data of the paper's shapes):
       (~3.4e7 rows), 16-dim, base 256 (tables of at most 256 rows stay
       uncompressed), all packed block-diagonally into one selector ciphertext
       per query; batch of 64 queries.
+  w6  same parameters; the lookup shape of the paper's comparison with prior
+      work (Table I): d = 768 rows from 32 digit tables of 16 x 768 (512
+      selector slots), selector at level 1.
+Other modes: --serve (continuous-batching request loop on the w3 tables in
+groups), --dlrm (batched end-to-end small DLRM).
 A step is one helrm_lookup_packed call over one batch of selector ciphertexts
 already resident in HBM; a lookup is one (query, table) embedding row.
 
@@ -40,7 +45,9 @@ KERNEL_SYMBOL = {
     "ntt_inv_blk": "ntt_pass_kernel<4, false, false>", "ntt_inv_col": "ntt_pass_kernel<4, false, true>",
     "conv": "conv_kernel", "ks_acc": "ks_acc_kernel", "baby_mac": "baby_mac_kernel", "sub_mul": "sub_mul_kernel",
 }
-DEFAULTS = {"w2": dict(n1=16, radix=8, sign=-1, batch=1), "w3": dict(n1=64, radix=8, sign=-1, batch=64)}
+DEFAULTS = {"w2": dict(n1=16, radix=8, sign=-1, batch=1, level=23),
+            "w3": dict(n1=64, radix=8, sign=-1, batch=64, level=23),
+            "w6": dict(n1=32, radix=2, sign=-1, batch=1, level=1)}
 PMC_DIR = "profiles"   # *_pmc.json: FETCH_SIZE / WRITE_SIZE records, one per kernel and workload
 
 
@@ -96,8 +103,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="w2", choices=["w2", "w3"])
-    ap.add_argument("--level", type=int, default=23)
+    ap.add_argument("--workload", default="w2", choices=["w2", "w3", "w6"])
+    ap.add_argument("--level", type=int, default=None, help="selector level (default 23; 1 for w6)")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--n1", type=int, default=None)
     ap.add_argument("--radix", type=int, default=None)
@@ -137,6 +144,9 @@ def make_tables(workload: str, synth, planner):
     if workload == "w2":
         parts = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(2)]
         return [planner.Table(rows=65536, d=16, base=256, parts=parts)]
+    if workload == "w6":
+        parts = [synth.uniform_table(g, 16, 768, -0.05, 0.05) for _ in range(32)]
+        return [planner.Table(rows=16 ** 32, d=768, base=16, parts=parts)]
     _, counts = synth.criteo_like_row_counts()
     tables = []
     for k in counts:
@@ -163,6 +173,9 @@ def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int):
     if workload == "w2":
         C = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(2)]
         tables = [O.TableSpec(rows=65536, d=16, base=256, C=C)]
+    elif workload == "w6":
+        C = [synth.uniform_table(g, 16, 768, -0.05, 0.05) for _ in range(32)]
+        tables = [O.TableSpec(rows=16 ** 32, d=768, base=16, C=C)]
     else:
         _, counts = synth.criteo_like_row_counts()
         tables = []
@@ -183,7 +196,7 @@ def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int):
     t0 = time.perf_counter()
     out = O.lookup(prm, keys, plan, ct, pts)
     dt = time.perf_counter() - t0
-    rows = len(tables) * 16
+    rows = sum(t.d for t in tables)
     got = O.decode(O.decrypt(prm, keys, out), prm.delta, prm)[:rows].real
     ref = np.concatenate([t.lookup(i) for t, i in zip(tables, idx)])
     err = float(np.max(np.abs(got - ref)))
@@ -289,7 +302,7 @@ def dlrm_bench(args):
     t0 = time.time()
     sess = dlrm.DLRMSession(prm, w, args.dlrm_level,
                             lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals, relin=True),
-                            n1=args.n1 or 16, radix=args.radix or 8, sign=args.sign or -1)
+                            n1=args.n1 or 32, radix=args.radix or 8, sign=args.sign or -1)
     setup_s = time.time() - t0
     B = args.batch or 128
     g = synth.rng(3)
@@ -344,6 +357,8 @@ def dlrm_bench(args):
 
 def main():
     args = parse()
+    if args.level is None:
+        args.level = DEFAULTS[args.workload]["level"] if not (args.serve or args.dlrm) else 23
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU benchmark: run with --gpus 1 (multi-GPU is not built)"}))
         sys.exit(2)

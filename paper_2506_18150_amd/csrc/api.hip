@@ -462,16 +462,9 @@ int run_matvec(helrm_ctx *ctx, const helrm_plan *p, const u64 *ct, u64 *out, int
     }
     const int ng_ = gi;
     const bool has0 = p->giants[0] == 0;
-    for (size_t t0 = 0; t0 < terms.size(); t0 += HELRM_MAX_TERMS) {
-      const int nt = (int)std::min<size_t>(HELRM_MAX_TERMS, terms.size() - t0);
-      if (t0 != 0) {
-        set_error("more than %d giant steps are not supported", HELRM_MAX_TERMS);
-        return HELRM_EINVAL;
-      }
-      TRY(launch_ks_accumulate(ctx, lv, terms.data() + t0, nt, (size_t)ng_ * d_bs * N,
-                               (size_t)n2 * 2 * qn * N, has0 ? w.xg : nullptr, (size_t)n2 * 2 * qn * N,
-                               w.acc, (size_t)2 * pqn * N, batch, s));
-    }
+    TRY(launch_ks_accumulate(ctx, lv, terms.data(), (int)terms.size(), (size_t)ng_ * d_bs * N,
+                             (size_t)n2 * 2 * qn * N, has0 ? w.xg : nullptr, (size_t)n2 * 2 * qn * N, w.acc,
+                             (size_t)2 * pqn * N, batch, s));
     u64 *dst = no_fold ? out : zbuf;
     TRY(do_moddown(ctx, lv, w.acc, 2 * pqn, dst, 2 * qn, w.mdP, w.mdT, batch, s));
     if (no_fold) return HELRM_OK;

@@ -241,6 +241,7 @@ __global__ __launch_bounds__(TPB) void add_plain_kernel(const u64 *ct, const u64
 
 struct KsArgs {
   int n;
+  int accum;   // add the result to what `out` holds (later chunks of a long term list)
   const u64 *digits[HELRM_MAX_TERMS];
   const u64 *c0[HELRM_MAX_TERMS];
   const u64 *key[HELRM_MAX_TERMS];
@@ -367,6 +368,10 @@ __device__ __forceinline__ void ks_acc_body(const KsArgs &T, const LevelGeom &G,
       Bv = add_mod(Bv, shoup(cs, pi.pmod, pi.pmod_p, pi.q), pi.q);
     }
     u64 *o = out + bat * out_bs;
+    if (T.accum) {
+      Bv = add_mod(Bv, o[(size_t)r * N + x], pi.q);
+      Av = add_mod(Av, o[((size_t)G.pqn + r) * N + x], pi.q);
+    }
     o[(size_t)r * N + x] = Bv;
     o[((size_t)G.pqn + r) * N + x] = Av;
   }
@@ -903,39 +908,41 @@ int pick_bt(int batch, int cap) {
 int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_terms,
                          size_t digits_bstride, size_t c0_bstride, const u64 *base, size_t base_bstride,
                          u64 *out, size_t out_bstride, int batch, hipStream_t s) {
-  if (n_terms > HELRM_MAX_TERMS) {
-    set_error("ks_accumulate: at most %d terms", HELRM_MAX_TERMS);
-    return HELRM_EINVAL;
-  }
-  KsArgs T;
-  T.n = n_terms;
-  for (int i = 0; i < n_terms; i++) {
-    T.digits[i] = terms[i].digits;
-    T.c0[i] = terms[i].c0;
-    T.key[i] = terms[i].key;
-    T.gal[i] = terms[i].galois;
-  }
   LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn};
   if (G.beta > MAXBETA || G.beta < 1) {
     set_error("key switching with %d digits (1 to %d supported)", G.beta, MAXBETA);
     return HELRM_EINVAL;
   }
   if (batch == 0) return HELRM_OK;
-  // per coefficient of a Q limb: terms * 3 beta words (digit, key b, key a) + terms c0 words
-  // + 2 base words + 2 output words; special limbs: no c0 / base words.  Keys count once per
-  // launch, the rest once per ciphertext.
-  double nc0 = 0;
-  for (int i = 0; i < n_terms; i++) nc0 += terms[i].c0 ? 1 : 0;
-  const double qn = level + 1, K = ctx->K, nt = n_terms, beta = G.beta, B = batch;
-  const double words = qn * (nt * 2 * beta + B * (nt * beta + nc0 + (base ? 2 : 0) + 2)) +
-                       K * (nt * 2 * beta + B * (nt * beta + 2));
   const int bt = pick_bt(batch, ctx->tune_ks_tile);
   const int ntiles = (batch + bt - 1) / bt;
   const int grid = (ctx->N / TPB) * G.pqn * ntiles;
-  KTimer tm(ctx, s);
+  // long term lists run as several launches: the first writes `out` (with the
+  // lifted base), the others add to it
+  for (int t0 = 0; t0 == 0 || t0 < n_terms; t0 += HELRM_MAX_TERMS) {
+    const int nt_i = std::min(HELRM_MAX_TERMS, n_terms - t0);
+    KsArgs T;
+    T.n = nt_i;
+    T.accum = t0 > 0;
+    for (int i = 0; i < nt_i; i++) {
+      T.digits[i] = terms[t0 + i].digits;
+      T.c0[i] = terms[t0 + i].c0;
+      T.key[i] = terms[t0 + i].key;
+      T.gal[i] = terms[t0 + i].galois;
+    }
+    const u64 *bse = t0 == 0 ? base : nullptr;
+    // per coefficient of a Q limb: terms * 3 beta words (digit, key b, key a) + the c0 words
+    // + 2 base words + 2 output words (4 when adding to out); special limbs: no c0 / base
+    // words.  Keys count once per launch, the rest once per ciphertext.
+    double nc0 = 0;
+    for (int i = 0; i < nt_i; i++) nc0 += T.c0[i] ? 1 : 0;
+    const double qn = level + 1, K = ctx->K, nt = nt_i, beta = G.beta, B = batch, ow = T.accum ? 4 : 2;
+    const double words = qn * (nt * 2 * beta + B * (nt * beta + nc0 + (bse ? 2 : 0) + ow)) +
+                         K * (nt * 2 * beta + B * (nt * beta + ow));
+    KTimer tm(ctx, s);
 #define KSACC(BT_, BETA_)                                                                              \
   hipLaunchKernelGGL((ks_acc_kernel<BT_, BETA_>), dim3(grid), dim3(TPB), 0, s, T, G, ctx->L, batch,     \
-                     ntiles, digits_bstride, c0_bstride, base, base_bstride, out, out_bstride, ctx->d_pinfo)
+                     ntiles, digits_bstride, c0_bstride, bse, base_bstride, out, out_bstride, ctx->d_pinfo)
 #define KSACC_B(BT_)                      \
   switch (G.beta) {                       \
     case 1: KSACC(BT_, 1); break;         \
@@ -943,15 +950,16 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
     case 3: KSACC(BT_, 3); break;         \
     default: KSACC(BT_, 4); break;        \
   }
-  switch (bt) {
-    case 1: KSACC_B(1); break;
-    case 2: KSACC_B(2); break;
-    default: KSACC_B(4); break;
-  }
+    switch (bt) {
+      case 1: KSACC_B(1); break;
+      case 2: KSACC_B(2); break;
+      default: KSACC_B(4); break;
+    }
 #undef KSACC_B
 #undef KSACC
-  tm.lap(TK_KS_ACC, 8.0 * ctx->N * words, 2.0 * nt * beta * ctx->N * B * (qn + K));
-  HIP_TRY(hipGetLastError());
+    tm.lap(TK_KS_ACC, 8.0 * ctx->N * words, 2.0 * nt * beta * ctx->N * B * (qn + K));
+    HIP_TRY(hipGetLastError());
+  }
   return HELRM_OK;
 }
 

@@ -127,7 +127,25 @@ def criteo_like_row_counts(n_tables: int = 26, lo: float = 4.0, hi: float = 1e7,
 
 
 def indices(g: np.random.Generator, row_counts: Sequence[int]) -> List[int]:
-    return [int(g.integers(0, k)) for k in row_counts]
+    """One uniform index per table; row counts of 2^62 or more (digit-encoded
+    vocabularies such as 16^32) are drawn 62 bits at a time with rejection."""
+    out = []
+    for k in row_counts:
+        k = int(k)
+        if k < 1 << 62:
+            out.append(int(g.integers(0, k)))
+            continue
+        nbits = (k - 1).bit_length()
+        while True:
+            v, got = 0, 0
+            while got < nbits:
+                take = min(62, nbits - got)
+                v |= int(g.integers(0, 1 << take)) << got
+                got += take
+            if v < k:
+                out.append(v)
+                break
+    return out
 
 
 def poisson_arrivals(g: np.random.Generator, rate: float, n: int) -> np.ndarray:

@@ -292,6 +292,23 @@ def test_lookup_multitable_batched_cfg2(ctx2):
     assert_bit_exact(alone[0], glk[3], "batch invariance query 3")
 
 
+def test_lookup_table1_shape_toy(p1):
+    """d=768 rows from 32 base-16 digit tables (512 selector slots, m=1024
+    diagonals, n1=32) on the toy ring at level 1, batch 2."""
+    ctx = context_for(p1)
+    w = W.table1_shape(p1, 1, n_queries=2)
+    load_keys(ctx, w.keys)
+    _check_lookup(ctx, w, gpu_plan(ctx, w.plan), [0, 1])
+
+
+def test_lookup_table1_shape_n16(ctx2):
+    """The same shape at N=2^16, selector at level 1 (the level of the paper's
+    comparison with prior work)."""
+    w = W.table1_shape(O.config2_params(), 1, n_queries=1)
+    load_keys(ctx2, w.keys)
+    _check_lookup(ctx2, w, gpu_plan(ctx2, w.plan), [0])
+
+
 def test_graph_capture_replays(ctx1, w1):
     """The batched lookup captured in a HIP graph: every replay (with eager
     work and synchronisation between replays) equals the eager result."""

@@ -154,3 +154,13 @@ def test_config1_other_schedules_agree_semantically():
         out = O.lookup(w.prm, w.keys, w.plan, w.cts[0])
         got = W.decrypt_slots(w, out, w.prm.delta, 16)
         assert np.max(np.abs(got - w.expected[0])) < 1e-4
+
+
+def test_table1_shape_decrypts_to_row():
+    """Table I shape (d=768, p=16, l=32 digits, 512 selector slots) on the toy
+    ring: the encrypted lookup decrypts to the sum of the 32 digit rows."""
+    w = W.table1_shape(O.config1_params(), 1, n_queries=1)
+    assert w.M.shape == (768, 512) and w.plan.m == 1024
+    out = O.lookup(w.prm, w.keys, w.plan, w.cts[0])
+    got = W.decrypt_slots(w, out, w.prm.delta, 768)
+    assert np.max(np.abs(got - w.expected[0])) < 1e-4

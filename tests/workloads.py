@@ -89,3 +89,13 @@ def dlrm_params_toy() -> O.Params:
     """N=2^12 with a chain deep enough for the forward pass: L=8, digits of
     three primes (dnum=3), three special primes."""
     return O.make_params(N=4096, L=8, K=3, alpha=3)
+
+
+def table1_shape(prm: O.Params, level: int, n_queries: int = 1, d: int = 768, p: int = 16, l: int = 32,
+                 n1: int = 32, radix: int = 2, seed: int = 0) -> Workload:
+    """The lookup shape of the paper's comparison with prior work (Table I):
+    one table of p^l rows stored as l digit tables of p x d (512 selector
+    slots for p=16, l=32), values U[-0.05, 0.05]."""
+    g = synth.rng(seed)
+    t = O.TableSpec(rows=p ** l, d=d, base=p, C=[synth.uniform_table(g, p, d, -0.05, 0.05) for _ in range(l)])
+    return build(prm, [t], level=level, n1=n1, radix=radix, n_queries=n_queries, seed=seed, sign=-1)
