@@ -1033,3 +1033,84 @@ def dlrm_forward(prm: Params, keys: Keys, sch: DLRMSchedule, ct: np.ndarray) -> 
         if k + 1 < len(sch.top):
             z = rescale(prm, mul_relin(prm, keys, z, z, lv), lv)
     return z
+
+
+# ------------------------------------------------------------------ selectors over several ciphertexts (Sec. III-C)
+
+def split_columns(M: np.ndarray, n: int) -> List[np.ndarray]:
+    """Column blocks of at most n columns: block c multiplies ciphertext c,
+    which holds selector slots [c n, (c+1) n)."""
+    return [M[:, c:c + n] for c in range(0, M.shape[1], n)]
+
+
+def split_selector(s: np.ndarray, n: int) -> List[np.ndarray]:
+    return [s[c:c + n] for c in range(0, len(s), n)]
+
+
+def make_multi_plan(prm: Params, M: np.ndarray, level: int, n1: int, radix: int = 2, sign: int = 1) -> List[Plan]:
+    """One plan per column block, all with the same m, n1, n2 and fold (the
+    widest block's span), so their products can be summed before the fold."""
+    blocks = split_columns(M, prm.n)
+    span = max(fold_span(B, prm.n, sign) for B in blocks)
+    plans = []
+    for B in blocks:
+        p = make_plan(prm, B, level, n1, radix, sign)
+        p.span = span
+        p.stages = fold_stages(span, p.m, radix)
+        plans.append(p)
+    return plans
+
+
+def matvec_multi(prm: Params, keys: Keys, plans: List[Plan], cts: List[np.ndarray]) -> np.ndarray:
+    """sum_c M_c s_c for one ciphertext per column block: every block's
+    baby-step products are summed into the same giant-step accumulators
+    X_g = sum_c sum_b pt_{c,g,b} * R_{c,b} over PQ, then ModDown, the giant
+    steps and the fold run once (no rescale)."""
+    p0 = plans[0]
+    lv = p0.level
+    PQ = prm.PQ(lv)
+    X = {}
+    for plan, ct in zip(plans, cts):
+        pts = plan_residues(prm, plan)
+        d = modup(prm, ct[1], lv)
+        for b in plan.baby_steps():
+            if b == 0:
+                R = lift_P(prm, ct, lv)
+            else:
+                gal = galois_for_step(plan.sign * b, prm)
+                R = key_inner_product(prm, d, ct[0], lv, keys.swk[gal], gal)
+            for g in plan.giant_steps():
+                if (g, b) not in pts:
+                    continue
+                acc = X.setdefault(g, np.zeros((2, len(PQ), prm.N), dtype=np.uint64))
+                for c in range(2):
+                    acc[c] = add(acc[c], mul(pts[(g, b)], R[c], PQ), PQ)
+    giants = sorted(X)
+    xs = {g: moddown(prm, X[g], lv) for g in giants}
+    if giants == [0]:
+        z = xs[0]
+    else:
+        acc = np.zeros((2, len(PQ), prm.N), dtype=np.uint64)
+        for g in giants:
+            if g == 0:
+                Y = lift_P(prm, xs[0], lv)
+            else:
+                gal = galois_for_step(p0.sign * p0.n1 * g, prm)
+                Y = key_inner_product(prm, modup(prm, xs[g][1], lv), xs[g][0], lv, keys.swk[gal], gal)
+            for c in range(2):
+                acc[c] = add(acc[c], Y[c], PQ)
+        z = moddown(prm, acc, lv)
+    for s, r in p0.stages:
+        dz = modup(prm, z[1], lv)
+        acc = lift_P(prm, z, lv)
+        for t in range(1, r):
+            gal = galois_for_step(t * s, prm)
+            Y = key_inner_product(prm, dz, z[0], lv, keys.swk[gal], gal)
+            for c in range(2):
+                acc[c] = add(acc[c], Y[c], PQ)
+        z = moddown(prm, acc, lv)
+    return z
+
+
+def lookup_multi(prm: Params, keys: Keys, plans: List[Plan], cts: List[np.ndarray]) -> np.ndarray:
+    return rescale(prm, matvec_multi(prm, keys, plans, cts), plans[0].level)

@@ -164,3 +164,26 @@ def test_table1_shape_decrypts_to_row():
     out = O.lookup(w.prm, w.keys, w.plan, w.cts[0])
     got = W.decrypt_slots(w, out, w.prm.delta, 768)
     assert np.max(np.abs(got - w.expected[0])) < 1e-4
+
+
+def test_multi_ciphertext_selector_decrypts():
+    """A packed selector of 3,000 slots on the toy ring (n = 2048) travels as
+    two ciphertexts; the summed product decrypts to every table's row, and a
+    single-block split reproduces the one-ciphertext product bit for bit."""
+    prm = O.config1_params()
+    g = synth.rng(9)
+    tables = [W.uncompressed_table(g, 1000, 16, -1, 1) for _ in range(3)]
+    w = W.build_multi(prm, tables, level=2, n1=16, radix=4, n_queries=2)
+    assert len(w.plans) == 2 and len(w.cts[0]) == 2
+    assert {(p.m, p.n1, p.n2, p.span) for p in w.plans} == {(64, 16, 4, 2048)}
+    for cts, ref in zip(w.cts, w.expected):
+        out = O.lookup_multi(prm, w.keys, w.plans, cts)
+        m = O.decrypt(prm, w.keys, out)
+        got = O.decode(m, prm.delta, prm)[:48].real
+        assert np.max(np.abs(got - ref)) < 1e-4
+    # one block: the same residues as the single-ciphertext matvec
+    w1 = W.config1(n_queries=1, n1=4, radix=2, sign=-1)
+    plans = O.make_multi_plan(w1.prm, w1.M, w1.level, 4, 2, -1)
+    assert len(plans) == 1
+    assert np.array_equal(O.matvec_multi(w1.prm, w1.keys, plans, [w1.cts[0]]),
+                          O.matvec(w1.prm, w1.keys, w1.plan, w1.cts[0]))

@@ -99,3 +99,36 @@ def table1_shape(prm: O.Params, level: int, n_queries: int = 1, d: int = 768, p:
     g = synth.rng(seed)
     t = O.TableSpec(rows=p ** l, d=d, base=p, C=[synth.uniform_table(g, p, d, -0.05, 0.05) for _ in range(l)])
     return build(prm, [t], level=level, n1=n1, radix=radix, n_queries=n_queries, seed=seed, sign=-1)
+
+
+@dataclass
+class MultiWorkload:
+    prm: O.Params
+    tables: List[O.TableSpec]
+    M: np.ndarray
+    plans: List[O.Plan]
+    keys: O.Keys
+    cts: List[List[np.ndarray]]       # per query: one ciphertext per column block
+    expected: List[np.ndarray]
+    level: int
+
+
+def build_multi(prm: O.Params, tables: List[O.TableSpec], level: int, n1: int, radix: int, n_queries: int,
+                seed: int = 0, sign: int = -1) -> MultiWorkload:
+    """Packed selectors wider than one ciphertext: one ciphertext per block
+    of n slots (Sec. III-C)."""
+    M = O.pack_tables(tables)
+    plans = O.make_multi_plan(prm, M, level, n1, radix, sign)
+    steps = sorted({k for p in plans for k in p.rotation_steps()})
+    gals = [O.galois_for_step(k, prm) for k in steps]
+    keys = O.keygen(prm, synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals))
+    g = synth.rng(seed + 2000)
+    cts, expected = [], []
+    for _ in range(n_queries):
+        idx = synth.indices(g, [t.rows for t in tables])
+        sel = O.pack_selector(tables, idx)
+        cts.append([O.encrypt(prm, keys, O.encode(part, prm.delta, prm), level, synth.enc_draws(g, prm.N))
+                    for part in O.split_selector(sel, prm.n)])
+        expected.append(np.concatenate([t.lookup(i) for t, i in zip(tables, idx)]))
+    return MultiWorkload(prm=prm, tables=tables, M=M, plans=plans, keys=keys, cts=cts, expected=expected,
+                         level=level)
