@@ -12,6 +12,9 @@ Workloads (seeded synthetic data of the paper's shapes):
   w6  same parameters; the lookup shape of the paper's comparison with prior
       work (Table I): d = 768 rows from 32 digit tables of 16 x 768 (512
       selector slots), selector at level 1.
+  w7  the w3 tables with the threshold rule of Table II: tables of at most
+      --threshold rows stay uncompressed, so the packed selector spans several
+      ciphertexts (50,000: 3 ciphertexts; 500,000: 20), selector at level 4.
 Other modes: --serve (continuous-batching request loop on the w3 tables in
 groups), --dlrm (batched end-to-end small DLRM).
 A step is one helrm_lookup_packed call over one batch of selector ciphertexts
@@ -47,7 +50,8 @@ KERNEL_SYMBOL = {
 }
 DEFAULTS = {"w2": dict(n1=16, radix=8, sign=-1, batch=1, level=23),
             "w3": dict(n1=64, radix=8, sign=-1, batch=64, level=23),
-            "w6": dict(n1=32, radix=2, sign=-1, batch=1, level=1)}
+            "w6": dict(n1=32, radix=2, sign=-1, batch=1, level=1),
+            "w7": dict(n1=64, radix=8, sign=-1, batch=1, level=4)}
 PMC_DIR = "profiles"   # *_pmc.json: FETCH_SIZE / WRITE_SIZE records, one per kernel and workload
 
 
@@ -103,7 +107,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="w2", choices=["w2", "w3", "w6"])
+    ap.add_argument("--workload", default="w2", choices=["w2", "w3", "w6", "w7"])
+    ap.add_argument("--threshold", type=int, default=50000,
+                    help="w7: tables of at most this many rows stay uncompressed (selector slots grow)")
     ap.add_argument("--level", type=int, default=None, help="selector level (default 23; 1 for w6)")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--n1", type=int, default=None)
@@ -136,7 +142,7 @@ def parse():
     return ap.parse_args()
 
 
-def make_tables(workload: str, synth, planner):
+def make_tables(workload: str, synth, planner, threshold: int = 256):
     """Seeded synthetic tables.  w2: one 65,536-row table as two base-256
     digit tables.  w3: 26 tables with log-uniform row counts (the first seed
     whose total lies in [3.0e7, 3.8e7])."""
@@ -149,8 +155,9 @@ def make_tables(workload: str, synth, planner):
         return [planner.Table(rows=16 ** 32, d=768, base=16, parts=parts)]
     _, counts = synth.criteo_like_row_counts()
     tables = []
+    limit = threshold if workload == "w7" else 256
     for k in counts:
-        if k <= 256:
+        if k <= limit:
             tables.append(planner.Table(rows=k, d=16, full=synth.uniform_table(g, k, 16, -0.05, 0.05)))
         else:
             nd = planner.n_digits(k, 256)
@@ -375,7 +382,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     prm = params.n16()
-    tables = make_tables(args.workload, synth, planner)
+    tables = make_tables(args.workload, synth, planner, args.threshold)
     M = planner.packed_matrix(tables)
     dflt = DEFAULTS[args.workload]
     B = args.batch or dflt["batch"]
@@ -408,7 +415,9 @@ def main():
     setup_s = time.time() - t0
     qg = synth.rng(1)
     idx = [synth.indices(qg, [t.rows for t in tables]) for _ in range(B)]
-    sel = sess.encrypt(idx, [synth.enc_draws(qg, prm.N) for _ in range(B)])
+    draws = lambda g_, nb: [synth.enc_draws(g_, prm.N) if sess.n_in == 1 else
+                            [synth.enc_draws(g_, prm.N) for _ in range(sess.n_in)] for _ in range(nb)]
+    sel = sess.encrypt(idx, draws(qg, B))
     out = sess.new_output(B)
     stream = torch.cuda.current_stream()
     sess.ctx.helrm_reserve(sess.plan, B, stream)
@@ -461,7 +470,9 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: N=2^16, L=23, dnum=3, K=8; {len(tables)} table(s), packed "
-                               f"{M.shape[0]}x{M.shape[1]}; selector at level {args.level}; n1={n1}, fold radix "
+                               f"{M.shape[0]}x{M.shape[1]}"
+                               + (f" in {sess.n_in} selector ciphertexts" if sess.n_in > 1 else "")
+                               + f"; selector at level {args.level}; n1={n1}, fold radix "
                                f"{radix}, rotation sign {sign} (fold span {spec.span}); batch {B} ciphertext(s) per "
                                f"call" + (", HIP graph replay" if args.graph else ""),
                    "name": args.workload, "level": args.level, "batch": B, "tables": len(tables), "n1": n1,
@@ -481,7 +492,7 @@ def main():
         Bb = args.batched
         bg = synth.rng(2)
         bidx = [synth.indices(bg, [t.rows for t in tables]) for _ in range(Bb)]
-        bsel = sess.encrypt(bidx, [synth.enc_draws(bg, prm.N) for _ in range(Bb)])
+        bsel = sess.encrypt(bidx, draws(bg, Bb))
         bout = sess.new_output(Bb)
         sess.ctx.helrm_reserve(sess.plan, Bb, stream)
         bs = autotune.tuned_schedule(prm.N, prm.L, args.level, M.shape[0], M.shape[1], Bb)
@@ -551,7 +562,7 @@ def main():
         torch.cuda.synchronize()
         res["copy_calibration_bytes"] = 1 << 30
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload != "w7":
         res["cpu_baseline"] = cpu_baseline(args.workload, args.level, n1, radix, sign)
     print(json.dumps(res))
 

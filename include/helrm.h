@@ -234,6 +234,20 @@ int helrm_timing_enable(helrm_ctx *ctx, int enable);
 int helrm_timing_read(helrm_ctx *ctx, const char *kernel, double *ms, int64_t *launches, double *bytes,
                       double *ops);
 
+/* Lookup for a packed selector wider than one ciphertext (Sec. III-C: a
+ * selector of k slots needs ceil(k / n) ciphertexts): ciphertext c carries
+ * slots [c n, (c+1) n) and plans[c] holds the diagonals of the matching column
+ * block of M.  The plans must share level, m, n1, n2, rotation direction, fold
+ * radix and fold span; every block's baby-step products are summed into the
+ * same giant-step accumulators, after which the giant steps, the fold and the
+ * rescale run once, so out = Enc(sum_c M_c s_c) at level-1.  sel: device
+ * [batch][n_in][2][level+1][N]; out: device [batch][2][level][N].  Workspace as
+ * helrm_footprint of plans[0] (plus the digits of every giant step in the
+ * union of the plans').  Errors: HELRM_EINVAL (mismatched plans, missing key),
+ * HELRM_ENOMEM. */
+int helrm_lookup_multi(helrm_ctx *ctx, const helrm_plan *const *plans, int n_in, const uint64_t *sel, int batch,
+                       uint64_t *out, void *stream);
+
 /* Ciphertext-ciphertext product with relinearisation (Appendix A
  * "Multiplication", "Key-switching"): the tensor product
  * (d0, d1, d2) = (a0 b0, a0 b1 + a1 b0, a1 b1) followed by a hybrid key switch

@@ -52,7 +52,7 @@ EXPORTS = [
     "helrm_from_signed", "helrm_keyswitch_hoisted", "helrm_rescale", "helrm_plan_create",
     "helrm_plan_destroy", "helrm_plan_rotation_steps", "helrm_ptxt_ct_matvec_diag",
     "helrm_lookup_packed", "helrm_footprint", "helrm_reserve", "helrm_timing_enable", "helrm_timing_read",
-    "helrm_set_tuning", "helrm_mul_relin", "helrm_add_plain", "helrm_mod_drop",
+    "helrm_set_tuning", "helrm_mul_relin", "helrm_add_plain", "helrm_mod_drop", "helrm_lookup_multi",
 ]
 
 _lib = None
@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
     L.helrm_mul_relin.argtypes = [_vp, _vp, _vp, _c_int, _vp, _c_int, _vp]
     L.helrm_add_plain.argtypes = [_vp, _vp, _vp, _c_int, _vp, _c_int, _vp]
     L.helrm_mod_drop.argtypes = [_vp, _vp, _c_int, _vp, _c_int, _c_int, _vp]
+    L.helrm_lookup_multi.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, _vp, _c_int, _vp, _vp]
     L.helrm_timing_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]
@@ -220,6 +221,10 @@ class Context:
 
     def helrm_lookup_packed(self, plan: "Plan", sel, batch: int, out, stream=None):
         _check(lib().helrm_lookup_packed(self.h, plan.h, _ptr(sel), batch, _ptr(out), _stream(stream)))
+
+    def helrm_lookup_multi(self, plans: Sequence["Plan"], sel, batch: int, out, stream=None):
+        arr = (_vp * len(plans))(*[p.h for p in plans])
+        _check(lib().helrm_lookup_multi(self.h, arr, len(plans), _ptr(sel), batch, _ptr(out), _stream(stream)))
 
     def helrm_footprint(self, plan: "Plan", batch: int) -> int:
         v = ctypes.c_size_t()

@@ -355,12 +355,20 @@ struct MatvecWS {
   u64 *coef, *D, *Dg, *X, *xg, *acc, *zA, *zB, *mdP, *mdT, *top, *V, *mv;
 };
 
-size_t matvec_ws_bytes(const helrm_ctx *ctx, const helrm_plan *p, int batch, bool with_rescale) {
+// Non-zero giant steps of a plan, or of the union of several plans' giants.
+size_t nonzero_giants(const helrm_plan *const *ps, int n_in) {
+  std::vector<int> u;
+  for (int c = 0; c < n_in; c++)
+    for (int g : ps[c]->giants)
+      if (g != 0 && std::find(u.begin(), u.end(), g) == u.end()) u.push_back(g);
+  return u.size();
+}
+
+size_t matvec_ws_bytes(const helrm_ctx *ctx, const helrm_plan *p, int batch, bool with_rescale,
+                       size_t ng_union = 0) {
   const size_t N = ctx->N, lv = p->level, qn = lv + 1, pqn = lv + 1 + ctx->K, beta = ctx->n_digits((int)lv);
   const size_t B = batch, n2 = p->n2;
-  size_t ng = 0;
-  for (int g : p->giants)
-    if (g != 0) ng++;
+  const size_t ng = std::max(ng_union, nonzero_giants(&p, 1));
   size_t tot = 0;
   tot += rnd(B * qn * N);                       // coef
   tot += rnd(B * beta * pqn * N);               // D
@@ -379,12 +387,11 @@ size_t matvec_ws_bytes(const helrm_ctx *ctx, const helrm_plan *p, int batch, boo
   return tot;
 }
 
-MatvecWS carve_matvec(const helrm_ctx *ctx, const helrm_plan *p, int batch, bool with_rescale, char *base) {
+MatvecWS carve_matvec(const helrm_ctx *ctx, const helrm_plan *p, int batch, bool with_rescale, char *base,
+                      size_t ng_union = 0) {
   const size_t N = ctx->N, lv = p->level, qn = lv + 1, pqn = lv + 1 + ctx->K, beta = ctx->n_digits((int)lv);
   const size_t B = batch, n2 = p->n2;
-  size_t ng = 0;
-  for (int g : p->giants)
-    if (g != 0) ng++;
+  const size_t ng = std::max(ng_union, nonzero_giants(&p, 1));
   Arena a{base};
   MatvecWS w;
   w.coef = a.take(B * qn * N);
@@ -406,28 +413,44 @@ MatvecWS carve_matvec(const helrm_ctx *ctx, const helrm_plan *p, int batch, bool
   return w;
 }
 
-int run_matvec(helrm_ctx *ctx, const helrm_plan *p, const u64 *ct, u64 *out, int batch, MatvecWS &w,
-               hipStream_t s) {
+// Matvec of n_in ciphertexts (the column blocks of one selector) with plans
+// that share m, n1, n2 and the fold; ciphertext c of batch element b is at
+// ct + (b * ct_bs + 2 (level+1) c) limbs.  Every block's baby-step products
+// go into the same giant accumulators X_g, then ModDown, giant steps and the
+// fold run once.
+int run_matvec(helrm_ctx *ctx, const helrm_plan *const *ps, int n_in, const u64 *ct, int ct_bs, u64 *out,
+               int batch, MatvecWS &w, hipStream_t s) {
+  const helrm_plan *p = ps[0];
   const int N = ctx->N, lv = p->level, qn = lv + 1, pqn = lv + 1 + ctx->K, beta = ctx->n_digits(lv);
   const int n2 = p->n2;
-  const int ct_bs = 2 * qn, d_bs = beta * pqn;
-  // 1. hoisted ModUp of c1
-  TRY(do_modup(ctx, lv, ct + (size_t)qn * N, ct_bs, w.D, d_bs, w.coef, batch, s));
-  // 2. fused baby steps + plaintext MAC, giant outputs in tiles
+  const int d_bs = beta * pqn;
   const size_t x_bs = (size_t)n2 * 2 * pqn;  // limbs per batch element of X
-  for (int g0 = 0; g0 < n2; g0 += HELRM_MAX_GTILE) {
-    const int ng = std::min(HELRM_MAX_GTILE, n2 - g0);
-    bool any = false;
-    for (int g : p->giants)
-      if (g >= g0 && g < g0 + ng) any = true;
-    if (!any) continue;
-    TRY(launch_baby_mac(ctx, p, w.D, (size_t)d_bs * N, ct, (size_t)ct_bs * N, w.X + (size_t)g0 * 2 * pqn * N,
-                        x_bs * N, g0, ng, batch, s));
+  std::vector<int> giants;
+  for (int c = 0; c < n_in; c++) {
+    const helrm_plan *pc = ps[c];
+    const u64 *ctc = ct + (size_t)c * 2 * qn * N;
+    // 1. hoisted ModUp of c1
+    TRY(do_modup(ctx, lv, ctc + (size_t)qn * N, ct_bs, w.D, d_bs, w.coef, batch, s));
+    // 2. fused baby steps + plaintext MAC, giant outputs in tiles (the first
+    //    block writes every tile a later block may add to)
+    for (int g0 = 0; g0 < n2; g0 += HELRM_MAX_GTILE) {
+      const int ng = std::min(HELRM_MAX_GTILE, n2 - g0);
+      bool any = false;
+      for (int g : pc->giants)
+        if (g >= g0 && g < g0 + ng) any = true;
+      const bool force = c == 0 && n_in > 1;
+      if (!any && !force) continue;
+      TRY(launch_baby_mac(ctx, pc, w.D, (size_t)d_bs * N, ctc, (size_t)ct_bs * N, w.X + (size_t)g0 * 2 * pqn * N,
+                          x_bs * N, g0, ng, batch, s, c > 0, force));
+    }
+    for (int g : pc->giants)
+      if (std::find(giants.begin(), giants.end(), g) == giants.end()) giants.push_back(g);
   }
+  std::sort(giants.begin(), giants.end());
   // 3. x_g = ModDown(X_g) for every g (batch of batch*n2)
   TRY(do_moddown(ctx, lv, w.X, 2 * pqn, w.xg, 2 * qn, w.mdP, w.mdT, batch * n2, s));
   const u64 *z;
-  const bool only0 = p->giants.size() == 1 && p->giants[0] == 0;
+  const bool only0 = giants.size() == 1 && giants[0] == 0;
   const bool no_fold = p->stages.empty();
   u64 *zbuf = w.zA;
   if (only0) {
@@ -447,11 +470,11 @@ int run_matvec(helrm_ctx *ctx, const helrm_plan *p, const u64 *ct, u64 *out, int
     // 4. giant rotations by n1 g of x_g (g >= 1), accumulated in PQ with P x_0
     std::vector<KsTerm> terms;
     int gi = 0;
-    for (int g : p->giants) {
+    for (int g : giants) {
       if (g == 0) continue;
       const u64 *xgp = w.xg + (size_t)g * 2 * qn * N;
       u64 *Dg = w.Dg + (size_t)gi * beta * pqn * N;
-      const int ng_ = (int)(p->giants.size() - (p->giants[0] == 0 ? 1 : 0));
+      const int ng_ = (int)(giants.size() - (giants[0] == 0 ? 1 : 0));
       TRY(do_modup(ctx, lv, xgp + (size_t)qn * N, n2 * 2 * qn, Dg, ng_ * d_bs, w.coef, batch, s));
       KsTerm t;
       t.digits = Dg;
@@ -461,7 +484,7 @@ int run_matvec(helrm_ctx *ctx, const helrm_plan *p, const u64 *ct, u64 *out, int
       gi++;
     }
     const int ng_ = gi;
-    const bool has0 = p->giants[0] == 0;
+    const bool has0 = giants[0] == 0;
     TRY(launch_ks_accumulate(ctx, lv, terms.data(), (int)terms.size(), (size_t)ng_ * d_bs * N,
                              (size_t)n2 * 2 * qn * N, has0 ? w.xg : nullptr, (size_t)n2 * 2 * qn * N, w.acc,
                              (size_t)2 * pqn * N, batch, s));
@@ -1106,7 +1129,7 @@ extern "C" int helrm_ptxt_ct_matvec_diag(helrm_ctx *c, const helrm_plan *p, cons
   char *base;
   TRY(ensure_ws(c, s, matvec_ws_bytes(c, p, batch, false), &base));
   MatvecWS w = carve_matvec(c, p, batch, false, base);
-  return run_matvec(c, p, ct, out, batch, w, s);
+  return run_matvec(c, &p, 1, ct, 2 * (p->level + 1), out, batch, w, s);
   API_GUARD_END
 }
 
@@ -1122,8 +1145,35 @@ extern "C" int helrm_lookup_packed(helrm_ctx *c, const helrm_plan *p, const uint
   char *base;
   TRY(ensure_ws(c, s, matvec_ws_bytes(c, p, batch, true), &base));
   MatvecWS w = carve_matvec(c, p, batch, true, base);
-  TRY(run_matvec(c, p, sel, w.mv, batch, w, s));
+  TRY(run_matvec(c, &p, 1, sel, 2 * (p->level + 1), w.mv, batch, w, s));
   const int lv = p->level;
+  return do_rescale(c, lv, w.mv, 2 * (lv + 1), out, 2 * lv, w.top, w.V, batch, s);
+  API_GUARD_END
+}
+
+extern "C" int helrm_lookup_multi(helrm_ctx *c, const helrm_plan *const *plans, int n_in, const uint64_t *sel,
+                                  int batch, uint64_t *out, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && plans && n_in >= 1, "need at least one plan");
+  const helrm_plan *p = plans[0];
+  for (int i = 0; i < n_in; i++) {
+    const helrm_plan *q = plans[i];
+    CHECK_ARG(q && q->ctx == c, "NULL or foreign plan %d", i);
+    CHECK_ARG(q->level == p->level && q->m == p->m && q->n1 == p->n1 && q->n2 == p->n2 && q->sign == p->sign &&
+                  q->span == p->span && q->radix == p->radix,
+              "plan %d differs from plan 0 in level, m, n1, n2, sign, radix or fold span", i);
+  }
+  CHECK_ARG(p->level >= 1, "lookup needs plans at level >= 1");
+  CHECK_ARG(batch >= 0, "batch < 0");
+  if (batch == 0) return HELRM_OK;
+  CHECK_ARG(sel && out, "NULL buffer");
+  hipStream_t s = as_stream(stream);
+  const size_t ngu = nonzero_giants(plans, n_in);
+  char *base;
+  TRY(ensure_ws(c, s, matvec_ws_bytes(c, p, batch, true, ngu), &base));
+  MatvecWS w = carve_matvec(c, p, batch, true, base, ngu);
+  const int lv = p->level;
+  TRY(run_matvec(c, plans, n_in, sel, n_in * 2 * (lv + 1), w.mv, batch, w, s));
   return do_rescale(c, lv, w.mv, 2 * (lv + 1), out, 2 * lv, w.top, w.V, batch, s);
   API_GUARD_END
 }

@@ -408,6 +408,8 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
 
 // Fused baby steps + plaintext MAC: X_g = sum_b pt_{g,b} (.) R_b for g in
 // [g0, g0+ng).
+// accum: add to what X holds; force: launch (writing zeros) even when no baby
+// step of this plan feeds giants g0..g0+ng-1.
 int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, size_t digits_bstride,
                     const u64 *ct, size_t ct_bstride, u64 *X, size_t x_bstride, int g0, int ng,
-                    int batch, hipStream_t s);
+                    int batch, hipStream_t s, bool accum = false, bool force = false);

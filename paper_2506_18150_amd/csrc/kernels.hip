@@ -424,7 +424,7 @@ template <int GT, int BT, int BETA, class M>
 __device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeom &G, int batch, int x, int r,
                                               int b0, int p, const PrimeInfo &pi, const u64 *digits,
                                               size_t dig_bs, const u64 *ct, size_t ct_bs, const u64 *pt, int ng,
-                                              u64 *X, size_t x_bs) {
+                                              u64 *X, size_t x_bs, int accum) {
   const int N = 1 << G.logn;
   const bool isq = r <= G.level;
   const int nct = min(BT, batch - b0);
@@ -529,8 +529,14 @@ __device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeo
 #pragma unroll
     for (int gi = 0; gi < GT; gi++) {
       if (gi < ng) {
-        o[((size_t)(gi * 2) * G.pqn + r) * N + x] = acc[k][gi][0].finish(pi.q, pi.qn);
-        o[((size_t)(gi * 2 + 1) * G.pqn + r) * N + x] = acc[k][gi][1].finish(pi.q, pi.qn);
+        const size_t i0 = ((size_t)(gi * 2) * G.pqn + r) * N + x, i1 = ((size_t)(gi * 2 + 1) * G.pqn + r) * N + x;
+        u64 v0 = acc[k][gi][0].finish(pi.q, pi.qn), v1 = acc[k][gi][1].finish(pi.q, pi.qn);
+        if (accum) {
+          v0 = add_mod(v0, o[i0], pi.q);
+          v1 = add_mod(v1, o[i1], pi.q);
+        }
+        o[i0] = v0;
+        o[i1] = v1;
       }
     }
   }
@@ -540,7 +546,7 @@ template <int GT, int BT, int BETA>
 __global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G, int L, int batch, int ntiles,
                                                        const u64 *digits, size_t dig_bs, const u64 *ct,
                                                        size_t ct_bs, const u64 *pt, int ng, u64 *X, size_t x_bs,
-                                                       const PrimeInfo *pinfo) {
+                                                       int accum, const PrimeInfo *pinfo) {
   const int N = 1 << G.logn;
   const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles);
   const int x = tm.xb * TPB + threadIdx.x;
@@ -548,10 +554,10 @@ __global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G,
   const PrimeInfo pi = pinfo[p];
   if (pi.q < SPLIT_MAC_LIMIT)
     baby_mac_body<GT, BT, BETA, SplitMac>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs, ct, ct_bs,
-                                          pt, ng, X, x_bs);
+                                          pt, ng, X, x_bs, accum);
   else
     baby_mac_body<GT, BT, BETA, WideMac>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs, ct, ct_bs,
-                                         pt, ng, X, x_bs);
+                                         pt, ng, X, x_bs, accum);
 }
 
 // The same product for launches with several giant outputs and a batch.  A
@@ -592,7 +598,7 @@ __device__ __forceinline__ void baby_shared_body(u64 (*R)[W][2][64], const BabyA
                                                  int batch, int x, int lane, int w, int r, int b0, int p,
                                                  const PrimeInfo &pi, const u64 *digits, size_t dig_bs,
                                                  const u64 *ct, size_t ct_bs, const u64 *pt, int ng, u64 *X,
-                                                 size_t x_bs) {
+                                                 size_t x_bs, int accum) {
   using Pk = typename PackOf<M>::T;
   const int N = 1 << G.logn;
   const int nct = min(W, batch - b0);
@@ -718,8 +724,14 @@ __device__ __forceinline__ void baby_shared_body(u64 (*R)[W][2][64], const BabyA
     for (int gi = 0; gi < GPW; gi++) {
       const int g = gw + gi;
       if (g < ng) {
-        o[((size_t)(g * 2) * G.pqn + r) * N + x] = acc[k][gi][0].finish(pi.q, pi.qn);
-        o[((size_t)(g * 2 + 1) * G.pqn + r) * N + x] = acc[k][gi][1].finish(pi.q, pi.qn);
+        const size_t i0 = ((size_t)(g * 2) * G.pqn + r) * N + x, i1 = ((size_t)(g * 2 + 1) * G.pqn + r) * N + x;
+        u64 v0 = acc[k][gi][0].finish(pi.q, pi.qn), v1 = acc[k][gi][1].finish(pi.q, pi.qn);
+        if (accum) {
+          v0 = add_mod(v0, o[i0], pi.q);
+          v1 = add_mod(v1, o[i1], pi.q);
+        }
+        o[i0] = v0;
+        o[i1] = v1;
       }
     }
   }
@@ -729,7 +741,7 @@ template <int W, int GPW, int BETA>
 __global__ __launch_bounds__(64 * W) void baby_mac_shared_kernel(BabyArgs BA, LevelGeom G, int L, int batch,
                                                                  int ntiles, const u64 *digits, size_t dig_bs,
                                                                  const u64 *ct, size_t ct_bs, const u64 *pt,
-                                                                 int ng, u64 *X, size_t x_bs,
+                                                                 int ng, u64 *X, size_t x_bs, int accum,
                                                                  const PrimeInfo *pinfo) {
   __shared__ u64 R[2][W][2][64];
   const int N = 1 << G.logn;
@@ -740,10 +752,10 @@ __global__ __launch_bounds__(64 * W) void baby_mac_shared_kernel(BabyArgs BA, Le
   const PrimeInfo pi = pinfo[p];
   if (pi.q < SPLIT_MAC_LIMIT)
     baby_shared_body<W, GPW, BETA, SplitMac>(R, BA, G, batch, x, lane, w, tm.r, tm.tile * W, p, pi, digits,
-                                             dig_bs, ct, ct_bs, pt, ng, X, x_bs);
+                                             dig_bs, ct, ct_bs, pt, ng, X, x_bs, accum);
   else
     baby_shared_body<W, GPW, BETA, WideMac>(R, BA, G, batch, x, lane, w, tm.r, tm.tile * W, p, pi, digits,
-                                            dig_bs, ct, ct_bs, pt, ng, X, x_bs);
+                                            dig_bs, ct, ct_bs, pt, ng, X, x_bs, accum);
 }
 
 dim3 ew_grid(const helrm_ctx *ctx, int rows) { return dim3(ctx->N / TPB, rows); }
@@ -965,7 +977,7 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
 
 int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, size_t digits_bstride,
                     const u64 *ct, size_t ct_bstride, u64 *X, size_t x_bstride, int g0, int ng, int batch,
-                    hipStream_t s) {
+                    hipStream_t s, bool accum, bool force) {
   if (ng > HELRM_MAX_GTILE) {
     set_error("baby_mac: at most %d giant outputs per launch", HELRM_MAX_GTILE);
     return HELRM_EINVAL;
@@ -1012,12 +1024,13 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
     set_error("key switching with %d digits (1 to %d supported)", G.beta, MAXBETA);
     return HELRM_EINVAL;
   }
-  if (batch == 0 || ng == 0 || (BA.nrot == 0 && !BA.has0)) return HELRM_OK;
+  if (batch == 0 || ng == 0 || (BA.nrot == 0 && !BA.has0 && !force)) return HELRM_OK;
   // algorithmic words per coefficient: keys and plaintexts once per launch, the rest per ciphertext
   const double nrot = BA.nrot, has0 = BA.has0;
   const double qn = level + 1, K = ctx->K, beta = G.beta, B = batch;
-  const double words = qn * (nrot * 2 * beta + npt + B * (nrot * (beta + 1) + 2 * has0 + 2 * ng)) +
-                       K * (nrot * 2 * beta + npt + B * (nrot * beta + 2 * ng));
+  const double xw = accum ? 4 : 2;   // output words per giant (read as well when accumulating)
+  const double words = qn * (nrot * 2 * beta + npt + B * (nrot * (beta + 1) + 2 * has0 + xw * ng)) +
+                       K * (nrot * 2 * beta + npt + B * (nrot * beta + xw * ng));
   const int gt = ng <= 1 ? 1 : ng <= 2 ? 2 : ng <= 4 ? 4 : 8;
   KTimer tm(ctx, s);
   if (ng >= 2 && batch >= 2 && ctx->tune_baby_share >= 2) {
@@ -1029,7 +1042,7 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
 #define BABYS(W_, GPW_, BETA_)                                                                           \
   hipLaunchKernelGGL((baby_mac_shared_kernel<W_, GPW_, BETA_>), dim3(grid), dim3(64 * W_), 0, s, BA, G,  \
                      ctx->L, batch, ntiles, digits, digits_bstride, ct, ct_bstride, plan->d_pt, ng, X,     \
-                     x_bstride, ctx->d_pinfo)
+                     x_bstride, accum ? 1 : 0, ctx->d_pinfo)
 #define BABYS_B(W_, GPW_)                     \
   switch (G.beta) {                           \
     case 1: BABYS(W_, GPW_, 1); break;        \
@@ -1053,7 +1066,7 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
 #define BABY(GT_, BT_, BETA_)                                                                            \
   hipLaunchKernelGGL((baby_mac_kernel<GT_, BT_, BETA_>), dim3(grid), dim3(TPB), 0, s, BA, G, ctx->L,      \
                      batch, ntiles, digits, digits_bstride, ct, ct_bstride, plan->d_pt, ng, X, x_bstride,  \
-                     ctx->d_pinfo)
+                     accum ? 1 : 0, ctx->d_pinfo)
 #define BABY_B(GT_, BT_)                      \
   switch (G.beta) {                           \
     case 1: BABY(GT_, BT_, 1); break;         \

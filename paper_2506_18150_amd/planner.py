@@ -170,5 +170,22 @@ def make_plan(M: np.ndarray, N: int, level: int, scale: float, n1: int, radix: i
                     rows=M.shape[0], stages=fold_stages(span, m, radix), sign=sign, span=span)
 
 
+def make_multi_plan(M: np.ndarray, N: int, level: int, scale: float, n1: int, radix: int = 2,
+                    sign: int = -1) -> List[PlanSpec]:
+    """A packed matrix wider than the N/2 slots of one ciphertext (Sec. III-C):
+    one plan per block of N/2 columns, all folding over the widest block's
+    span so their products can be summed before the fold."""
+    n = N // 2
+    blocks = [M[:, c:c + n] for c in range(0, M.shape[1], n)]
+    span = max(fold_span(B.shape[0], B.shape[1], n, sign) for B in blocks)
+    specs = []
+    for B in blocks:
+        sp = make_plan(B, N, level, scale, n1, radix, sign)
+        sp.span = span
+        sp.stages = fold_stages(span, sp.m, radix)
+        specs.append(sp)
+    return specs
+
+
 def galois(step: int, N: int) -> int:
     return pow(5, step % (N // 2), 2 * N)

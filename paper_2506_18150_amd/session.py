@@ -28,12 +28,15 @@ class LookupSession:
         self.level = level
         self.ctx = ctx or Context(prm.log_n, prm.q, prm.p, prm.alpha)
         self.M = planner.packed_matrix(self.tables)
-        self.spec = planner.make_plan(self.M, prm.N, level, float(prm.q[level]), n1, radix, sign)
-        self.plan: Plan = self.ctx.helrm_plan_create(level, self.spec.m, self.spec.n1, self.spec.n2,
-                                                     self.spec.radix, self.spec.diag, self.spec.coeffs,
-                                                     self.spec.sign, self.spec.span)
-        steps = self.plan.rotation_steps()
-        assert steps == self.spec.rotation_steps()
+        # a selector wider than one ciphertext travels as n_in ciphertexts,
+        # one plan per column block (Sec. III-C)
+        self.specs = planner.make_multi_plan(self.M, prm.N, level, float(prm.q[level]), n1, radix, sign)
+        self.n_in = len(self.specs)
+        self.plans: List[Plan] = [self.ctx.helrm_plan_create(level, sp.m, sp.n1, sp.n2, sp.radix, sp.diag,
+                                                             sp.coeffs, sp.sign, sp.span) for sp in self.specs]
+        self.spec, self.plan = self.specs[0], self.plans[0]
+        steps = sorted({k for p in self.plans for k in p.rotation_steps()})
+        assert steps == sorted({k for sp in self.specs for k in sp.rotation_steps()})
         self.galois = [planner.galois(s, prm.N) for s in steps]
         self.client = Client(self.ctx, prm)
         self.client.keygen(key_draws_fn(self.galois), self.galois)
@@ -44,19 +47,30 @@ class LookupSession:
 
     def encrypt(self, idx_batch: Sequence[Sequence[int]], enc_draws: Sequence) -> torch.Tensor:
         """Client: digits -> one-hots -> packed selector -> encode at Delta ->
-        encrypt, for each query.  Returns [B][2][level+1][N]."""
+        encrypt, for each query (one draw per selector ciphertext when the
+        selector spans several).  Returns [B][2][level+1][N], or
+        [B][n_in][2][level+1][N] for n_in > 1."""
         cts = []
+        n = self.prm.N // 2
         for idx, ed in zip(idx_batch, enc_draws):
             sel = planner.packed_selector(self.tables, idx)
-            m = encoding.encode(sel, self.prm.delta, self.prm.N)
-            cts.append(self.client.encrypt(m, self.level, ed))
+            eds = ed if isinstance(ed, (list, tuple)) else [ed]
+            parts = []
+            for c, e in zip(range(0, len(sel), n), eds):
+                m = encoding.encode(sel[c:c + n], self.prm.delta, self.prm.N)
+                parts.append(self.client.encrypt(m, self.level, e))
+            assert len(parts) == self.n_in, "one encryption draw per selector ciphertext"
+            cts.append(parts[0] if self.n_in == 1 else torch.stack(parts))
         return torch.stack(cts).contiguous()
 
     def new_output(self, batch: int) -> torch.Tensor:
         return torch.zeros(batch, 2, self.level, self.prm.N, dtype=torch.int64, device="cuda")
 
     def lookup(self, sel: torch.Tensor, out: torch.Tensor, stream=None):
-        self.ctx.helrm_lookup_packed(self.plan, sel, sel.shape[0], out, stream)
+        if self.n_in == 1:
+            self.ctx.helrm_lookup_packed(self.plan, sel, sel.shape[0], out, stream)
+        else:
+            self.ctx.helrm_lookup_multi(self.plans, sel, sel.shape[0], out, stream)
 
     def decrypt_rows(self, out: torch.Tensor) -> np.ndarray:
         m = self.client.decrypt(out)

@@ -309,6 +309,48 @@ def test_lookup_table1_shape_n16(ctx2):
     _check_lookup(ctx2, w, gpu_plan(ctx2, w.plan), [0])
 
 
+def _check_multi(ctx, w, plans_gpu, batch_idx):
+    prm, lv = w.prm, w.level
+    n_in = len(w.plans)
+    sel = np.stack([np.stack(w.cts[i]) for i in batch_idx])
+    B_ = len(batch_idx)
+    say(f"lookup_multi N={prm.N} level={lv} n_in={n_in} batch={B_}")
+    out = empty(B_, 2, lv, prm.N)
+    ctx.helrm_lookup_multi(plans_gpu, to_dev(sel), B_, out)
+    got = to_host(out).reshape(B_, 2, lv, prm.N)
+    for k, qi in enumerate(batch_idx):
+        assert_bit_exact(got[k], O.lookup_multi(prm, w.keys, w.plans, w.cts[qi]), f"multi query {qi}")
+        m = O.decrypt(prm, w.keys, got[k])
+        rows = O.decode(m, prm.delta, prm)[: len(w.expected[qi])].real
+        assert np.max(np.abs(rows - w.expected[qi])) < 1e-4
+    return got
+
+
+def test_lookup_multi_ciphertext_toy(p1):
+    """3,000 selector slots on the toy ring (n = 2048): two ciphertexts per
+    query, batch 3, every result bit-exact; query 2 alone equals its slot."""
+    ctx = context_for(p1)
+    g = synth.rng(9)
+    tables = [W.uncompressed_table(g, 1000, 16, -1, 1) for _ in range(3)]
+    w = W.build_multi(p1, tables, level=2, n1=16, radix=4, n_queries=3)
+    load_keys(ctx, w.keys)
+    plans = [gpu_plan(ctx, p) for p in w.plans]
+    got = _check_multi(ctx, w, plans, [0, 1, 2])
+    alone = _check_multi(ctx, w, plans, [2])
+    assert_bit_exact(alone[0], got[2], "multi batch invariance")
+
+
+def test_lookup_multi_ciphertext_n16(ctx2):
+    """N=2^16: four 10,000-row uncompressed tables (40,000 slots, two
+    ciphertexts), level 1, batch 2."""
+    g = synth.rng(10)
+    tables = [W.uncompressed_table(g, 10000, 16, -0.05, 0.05) for _ in range(4)]
+    w = W.build_multi(O.config2_params(), tables, level=1, n1=16, radix=8, n_queries=2)
+    assert len(w.plans) == 2
+    load_keys(ctx2, w.keys)
+    _check_multi(ctx2, w, [gpu_plan(ctx2, p) for p in w.plans], [0, 1])
+
+
 def test_graph_capture_replays(ctx1, w1):
     """The batched lookup captured in a HIP graph: every replay (with eager
     work and synchronisation between replays) equals the eager result."""

@@ -94,3 +94,21 @@ def test_dlrm_layout_matches_oracle():
     idx = synth.indices(g, d.table_rows)
     assert np.array_equal(w.input_slots(dense, idx), model.input_slots(dense, idx))
     assert np.allclose(w.cleartext(dense, idx), O.dlrm_cleartext(model, dense, idx), atol=1e-14)
+
+
+def test_multi_plan_matches_oracle():
+    """Column blocks of a selector wider than one ciphertext: the product's
+    per-block plans and shared fold equal the oracle's."""
+    prm = O.config1_params()
+    g = synth.rng(9)
+    E = [synth.uniform_table(g, 1000, 16, -1, 1) for _ in range(3)]
+    mine = planner.packed_matrix([planner.Table(rows=1000, d=16, full=e) for e in E])
+    theirs = O.pack_tables([O.TableSpec(rows=1000, d=16, E=e) for e in E])
+    assert np.array_equal(mine, theirs)
+    specs = planner.make_multi_plan(mine, prm.N, 2, float(prm.q[2]), 16, 4, -1)
+    plans = O.make_multi_plan(prm, theirs, 2, 16, 4, -1)
+    assert len(specs) == len(plans) == 2
+    for sp, p in zip(specs, plans):
+        assert (sp.m, sp.n1, sp.n2, sp.span, sp.stages) == (p.m, p.n1, p.n2, p.span, p.stages)
+        assert sp.diag == sorted(gg * p.n1 + b for (gg, b) in p.coeffs)
+        assert sp.rotation_steps() == p.rotation_steps()
