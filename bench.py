@@ -119,6 +119,9 @@ def parse():
     ap.add_argument("--ks-tile", type=int, default=None)
     ap.add_argument("--baby-tile", type=int, default=None)
     ap.add_argument("--baby-share", type=int, default=None)
+    ap.add_argument("--ntt-col-w", type=int, default=None, help="NTT column-pass width (8, 16; 0 = by size)")
+    ap.add_argument("--ntt-blk-w", type=int, default=None, help="NTT block-pass width (4, 8; 0 = by size)")
+    ap.add_argument("--ntt-small-limbs", type=int, default=None)
     ap.add_argument("--autotune", action="store_true", help="measure candidate schedules first")
     ap.add_argument("--autotune-out", default=None, help="write the tuning record to this file")
     ap.add_argument("--graph", action="store_true", help="replay one captured HIP graph per step")
@@ -400,7 +403,8 @@ def main():
     sched = autotune.tuned_schedule(prm.N, prm.L, args.level, M.shape[0], M.shape[1], B)
     if tune_rec is not None:
         b = tune_rec["best"]
-        sched = autotune.Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b["baby_share"])
+        sched = autotune.Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b["baby_share"],
+                                  b["ntt_col_w"], b["ntt_blk_w"])
     if sched is None:
         sched = autotune.Schedule(dflt["n1"], dflt["radix"], dflt["sign"])
     n1 = args.n1 or sched.n1
@@ -412,6 +416,11 @@ def main():
     sess.ctx.helrm_set_tuning("baby_tile", args.baby_tile or sched.baby_tile)
     share = args.baby_share or sched.baby_share
     sess.ctx.helrm_set_tuning("baby_share", share)
+    for knob, v in (("ntt_col_w", args.ntt_col_w if args.ntt_col_w is not None else sched.ntt_col_w),
+                    ("ntt_blk_w", args.ntt_blk_w if args.ntt_blk_w is not None else sched.ntt_blk_w),
+                    ("ntt_small_limbs", args.ntt_small_limbs)):
+        if v is not None:
+            sess.ctx.helrm_set_tuning(knob, v)
     setup_s = time.time() - t0
     qg = synth.rng(1)
     idx = [synth.indices(qg, [t.rows for t in tables]) for _ in range(B)]

@@ -281,8 +281,11 @@ int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *o
  * "baby_share" (1, 2, 4 or 8; default 8) is the number of ciphertexts one
  * workgroup of the fused baby-step kernel serves when a launch has several
  * giant outputs and a batch (each plaintext word is then read once per that
- * many ciphertexts); 1 turns that kernel off.  Results do not depend on the
- * knobs.  Errors: HELRM_EINVAL for an unknown knob or value. */
+ * many ciphertexts); 1 turns that kernel off.  "ntt_col_w" (8 or 16, default
+ * 16) and "ntt_blk_w" (4 or 8, default 4) are the sub-transforms per workgroup
+ * of the NTT's column and block passes; 0 picks the narrow shape for launches
+ * of fewer than "ntt_small_limbs" limbs (default 48).  Results do not depend
+ * on the knobs.  Errors: HELRM_EINVAL for an unknown knob or value. */
 int helrm_set_tuning(helrm_ctx *ctx, const char *knob, int value);
 
 #ifdef __cplusplus

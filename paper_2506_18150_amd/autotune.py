@@ -36,6 +36,8 @@ class Schedule:
     ks_tile: int = 4
     baby_tile: int = 4
     baby_share: int = 8
+    ntt_col_w: int = 16
+    ntt_blk_w: int = 4
 
 
 def candidate_schedules(rows: int, cols: int, n: int, n1s=(4, 8, 16, 32, 64), radices=(4, 8, 16),
@@ -62,7 +64,8 @@ def tuned_schedule(N: int, L: int, level: int, rows: int, cols: int, batch: int,
     if rec is None:
         return None
     b = rec["best"]
-    return Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b.get("baby_share", 8))
+    return Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b.get("baby_share", 8),
+                    b.get("ntt_col_w", 16), b.get("ntt_blk_w", 4))
 
 
 def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
@@ -130,7 +133,34 @@ def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
             if log:
                 log(rec)
         plan.close()
-    best = min(results, key=lambda r: r["ms_per_batch"])
+    best = dict(min(results, key=lambda r: r["ms_per_batch"]))
+    # NTT workgroup shapes for the chosen schedule
+    sc = Schedule(best["n1"], best["radix"], best["sign"])
+    spec = next(sp for s_, sp in specs if (s_.n1, s_.radix, s_.sign) == (sc.n1, sc.radix, sc.sign))
+    plan = ctx.helrm_plan_create(level, spec.m, spec.n1, spec.n2, spec.radix, spec.diag, spec.coeffs, spec.sign,
+                                 spec.span)
+    for knob in ("ks_tile", "baby_tile", "baby_share"):
+        ctx.helrm_set_tuning(knob, best[knob])
+    best_ntt = None
+    for wc, wb in ((16, 4), (16, 8), (8, 4)):
+        ctx.helrm_set_tuning("ntt_col_w", wc)
+        ctx.helrm_set_tuning("ntt_blk_w", wb)
+        for _ in range(warmup):
+            ctx.helrm_lookup_packed(plan, sel, batch, out, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            ctx.helrm_lookup_packed(plan, sel, batch, out, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        if log:
+            log({"ntt_col_w": wc, "ntt_blk_w": wb, "ms_per_batch": ms})
+        if best_ntt is None or ms < best_ntt[2]:
+            best_ntt = (wc, wb, ms)
+    plan.close()
+    best["ntt_col_w"], best["ntt_blk_w"] = best_ntt[0], best_ntt[1]
     ctx.close()
     return {"key": shape_key(prm.N, prm.L, level, rows, cols, batch), "best": best, "results": results,
             "when": time.strftime("%Y-%m-%d %H:%M:%S")}

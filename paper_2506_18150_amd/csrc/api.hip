@@ -1238,6 +1238,15 @@ extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
   if (strcmp(knob, "ks_tile") == 0 || strcmp(knob, "baby_tile") == 0) {
     CHECK_ARG(value == 1 || value == 2 || value == 4, "%s must be 1, 2 or 4", knob);
     (knob[0] == 'k' ? c->tune_ks_tile : c->tune_baby_tile) = value;
+  } else if (strcmp(knob, "ntt_col_w") == 0) {
+    CHECK_ARG(value == 0 || value == 8 || value == 16, "ntt_col_w must be 0, 8 or 16");
+    c->tune_ntt_col_w = value;
+  } else if (strcmp(knob, "ntt_blk_w") == 0) {
+    CHECK_ARG(value == 0 || value == 4 || value == 8, "ntt_blk_w must be 0, 4 or 8");
+    c->tune_ntt_blk_w = value;
+  } else if (strcmp(knob, "ntt_small_limbs") == 0) {
+    CHECK_ARG(value >= 0, "ntt_small_limbs must be >= 0");
+    c->ntt_small_limbs = value;
   } else if (strcmp(knob, "baby_share") == 0) {
     CHECK_ARG(value == 1 || value == 2 || value == 4 || value == 8, "baby_share must be 1, 2, 4 or 8");
     c->tune_baby_share = value;

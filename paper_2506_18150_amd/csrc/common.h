@@ -262,6 +262,9 @@ struct helrm_ctx {
   int tune_ks_tile = 4;      // ciphertexts per thread in ks_acc (1, 2, 4)
   int tune_baby_tile = 4;    // ciphertexts per thread in baby_mac when one giant output (1, 2, 4)
   int tune_baby_share = 8;   // ciphertexts per workgroup in baby_mac with several giant outputs (1 = off, 2, 4, 8)
+  int tune_ntt_col_w = 16;   // NTT column-pass columns per workgroup (8, 16; 0 = by launch size)
+  int tune_ntt_blk_w = 4;    // NTT block-pass blocks per workgroup (4, 8; 0 = by launch size)
+  int ntt_small_limbs = 48;  // launches of fewer limbs take the narrow shapes when a width is 0
   bool timing = false;
   std::mutex tmu;
   std::vector<TimingRec> trecs;

@@ -39,12 +39,12 @@ __device__ __forceinline__ void gs_bfly(u64 &x, u64 &y, const TW &t, u64 q, u64 
 // Workgroup shape of one pass.  The column pass keeps WC consecutive columns
 // per workgroup (WC words per row contiguous in HBM); the block pass keeps WB
 // blocks.  Small workgroups let a launch of a few limbs fill 256 CUs.
-template <int H, bool COLS>
+template <int H, bool COLS, int W_ = (COLS ? 16 : 8)>
 struct Shape {
   static constexpr int E = 1 << H;                    // residues per thread
   static constexpr int R = E * E;                     // sub-transform length
   static constexpr int N = R * R;                     // ring degree
-  static constexpr int W = COLS ? 16 : 8;             // sub-transforms per workgroup
+  static constexpr int W = W_;                        // sub-transforms per workgroup
   static constexpr int T = W * E;                     // threads per workgroup
   static constexpr int WPL = R / W;                   // workgroups per limb
   // column pass: row stride E*W + W keeps the lane groups of a wave on
@@ -185,10 +185,10 @@ __device__ __forceinline__ void inv_phase_a(typename A::V (&x)[1 << H], const A 
 }
 
 // The body of one pass for one arithmetic policy.
-template <int H, bool FWD, bool COLS, class A>
+template <int H, bool FWD, bool COLS, int WS, class A>
 __device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 *in, u64 *out, int part, int bat,
                                           int li, const PrimeInfo &pi, const NttEpi &epi) {
-  using S = Shape<H, COLS>;
+  using S = Shape<H, COLS, WS>;
   constexpr int E = S::E, R = S::R, N = S::N, W = S::W;
   using V = typename A::V;
   const int tid = threadIdx.x;
@@ -286,13 +286,13 @@ __device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 *in, 
 // One pass of the transform.  FWD: column pass first (src -> dst), block pass
 // second (in place, final reduction).  INV: block pass first, column pass
 // second (in place, times N^-1).  Primes below 2^45 take the fp64 path.
-template <int H, bool FWD, bool COLS>
-__global__ __launch_bounds__((Shape<H, COLS>::T)) void ntt_pass_kernel(const u64 *src, u64 *dst, LimbList ll,
-                                                                     const TW *__restrict__ twtab,
-                                                                     const double *__restrict__ twdtab,
-                                                                     const PrimeInfo *__restrict__ pinfo,
-                                                                     const NttEpi epi) {
-  using S = Shape<H, COLS>;
+template <int H, bool FWD, bool COLS, int WS>
+__global__ __launch_bounds__((Shape<H, COLS, WS>::T)) void ntt_pass_kernel(const u64 *src, u64 *dst, LimbList ll,
+                                                                         const TW *__restrict__ twtab,
+                                                                         const double *__restrict__ twdtab,
+                                                                         const PrimeInfo *__restrict__ pinfo,
+                                                                         const NttEpi epi) {
+  using S = Shape<H, COLS, WS>;
   constexpr int N = S::N, WPL = S::WPL;
   __shared__ u64 lds[S::LDS];
   const int limb_lin = blockIdx.x / WPL;
@@ -305,19 +305,21 @@ __global__ __launch_bounds__((Shape<H, COLS>::T)) void ntt_pass_kernel(const u64
   const PrimeInfo pi = pinfo[p];
   if (pi.q < (1ull << 45)) {
     FltA ar{pi.qd, 2.0 * pi.qd, pi.qinv_d, twdtab + (size_t)p * N};
-    pass_body<H, FWD, COLS>(ar, lds, in, out, part, bat, li, pi, epi);
+    pass_body<H, FWD, COLS, WS>(ar, lds, in, out, part, bat, li, pi, epi);
   } else {
     IntA ar{pi.q, 2 * pi.q, twtab + (size_t)p * N};
-    pass_body<H, FWD, COLS>(ar, lds, in, out, part, bat, li, pi, epi);
+    pass_body<H, FWD, COLS, WS>(ar, lds, in, out, part, bat, li, pi, epi);
   }
 }
 
-template <int H>
-int launch_ntt_h(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int batch, bool forward,
-                 hipStream_t s, const NttEpi &epi) {
-  using S = Shape<H, true>;
-  using SC = Shape<H, true>;
-  using SB = Shape<H, false>;
+// Column-pass and block-pass workgroup widths (sub-transforms per workgroup):
+// wider groups make longer contiguous runs in the column pass, narrower ones
+// more workgroups for launches of few limbs.
+template <int H, int WC, int WB>
+int launch_ntt_hw(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int batch, bool forward,
+                  hipStream_t s, const NttEpi &epi) {
+  using SC = Shape<H, true, WC>;
+  using SB = Shape<H, false, WB>;
   LimbList second = ll;
   for (int i = 0; i < ll.n; i++) second.src_off[i] = ll.dst_off[i];
   second.src_bstride = ll.dst_bstride;
@@ -325,25 +327,39 @@ int launch_ntt_h(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, i
   if (gc == 0) return HELRM_OK;
   // per pass and limb: N words read and written, (N/2) log2(R) butterflies
   const double limbs = (double)ll.n * batch;
-  const double bytes = limbs * 16.0 * S::N, ops = limbs * (S::N / 2) * (2 * H);
+  const double bytes = limbs * 16.0 * SC::N, ops = limbs * (SC::N / 2) * (2 * H);
   KTimer tm(ctx, s);
   if (forward) {
-    hipLaunchKernelGGL((ntt_pass_kernel<H, true, true>), dim3(gc), dim3(SC::T), 0, s, src, dst, ll,
+    hipLaunchKernelGGL((ntt_pass_kernel<H, true, true, WC>), dim3(gc), dim3(SC::T), 0, s, src, dst, ll,
                        ctx->d_tw_fwd, ctx->d_twd_fwd, ctx->d_pinfo, NttEpi{});
     tm.lap(TK_NTT_FWD_COL, bytes, ops);
-    hipLaunchKernelGGL((ntt_pass_kernel<H, true, false>), dim3(gb), dim3(SB::T), 0, s, dst, dst,
+    hipLaunchKernelGGL((ntt_pass_kernel<H, true, false, WB>), dim3(gb), dim3(SB::T), 0, s, dst, dst,
                        second, ctx->d_tw_fwd, ctx->d_twd_fwd, ctx->d_pinfo, epi);
     tm.lap(TK_NTT_FWD_BLK, epi.a ? bytes * 1.5 : bytes, ops);
   } else {
-    hipLaunchKernelGGL((ntt_pass_kernel<H, false, false>), dim3(gb), dim3(SB::T), 0, s, src, dst, ll,
+    hipLaunchKernelGGL((ntt_pass_kernel<H, false, false, WB>), dim3(gb), dim3(SB::T), 0, s, src, dst, ll,
                        ctx->d_tw_inv, ctx->d_twd_inv, ctx->d_pinfo, NttEpi{});
     tm.lap(TK_NTT_INV_BLK, bytes, ops);
-    hipLaunchKernelGGL((ntt_pass_kernel<H, false, true>), dim3(gc), dim3(SC::T), 0, s, dst, dst,
+    hipLaunchKernelGGL((ntt_pass_kernel<H, false, true, WC>), dim3(gc), dim3(SC::T), 0, s, dst, dst,
                        second, ctx->d_tw_inv, ctx->d_twd_inv, ctx->d_pinfo, NttEpi{});
     tm.lap(TK_NTT_INV_COL, bytes, ops);
   }
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
+}
+
+template <int H>
+int launch_ntt_h(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int batch, bool forward,
+                 hipStream_t s, const NttEpi &epi) {
+  // widths: the autotuner's choice, or by launch size (launches of few limbs
+  // take the narrow shapes so they spread over more compute units)
+  int wc = ctx->tune_ntt_col_w, wb = ctx->tune_ntt_blk_w;
+  if (wc == 0) wc = (long)ll.n * batch < ctx->ntt_small_limbs ? 8 : 16;
+  if (wb == 0) wb = (long)ll.n * batch < ctx->ntt_small_limbs ? 4 : 8;
+  if (wc == 8 && wb == 4) return launch_ntt_hw<H, 8, 4>(ctx, src, dst, ll, batch, forward, s, epi);
+  if (wc == 8) return launch_ntt_hw<H, 8, 8>(ctx, src, dst, ll, batch, forward, s, epi);
+  if (wb == 4) return launch_ntt_hw<H, 16, 4>(ctx, src, dst, ll, batch, forward, s, epi);
+  return launch_ntt_hw<H, 16, 8>(ctx, src, dst, ll, batch, forward, s, epi);
 }
 
 }  // namespace

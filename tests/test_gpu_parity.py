@@ -67,6 +67,33 @@ def test_ntt_parity(which, p1, p2, ctx1, ctx2):
             assert_bit_exact(got[b], O.intt(x[b], mods, prm), f"intt batch {b}")
 
 
+@pytest.mark.parametrize("which", ["cfg1", "cfg2"])
+@pytest.mark.parametrize("wc,wb", [(8, 4), (8, 8), (16, 8)])
+def test_ntt_parity_other_shapes(which, wc, wb, p1, p2, ctx1, ctx2):
+    """The other workgroup shapes of both NTT passes (the default, 16 columns
+    and 4 blocks, is covered above), forward and inverse, bit-exact."""
+    prm, ctx = (p1, ctx1) if which == "cfg1" else (p2, ctx2)
+    allm = prm.q + prm.p
+    rng = np.random.default_rng(11)
+    pidx, batch = list(range(len(allm))), 2
+    mods = [allm[i] for i in pidx]
+    x = rand_limbs(rng, mods, prm.N, batch)
+    say(f"ntt {which} shape col {wc} blk {wb}")
+    ctx.helrm_set_tuning("ntt_col_w", wc)
+    ctx.helrm_set_tuning("ntt_blk_w", wb)
+    try:
+        d = to_dev(x)
+        ctx.helrm_ntt(d, pidx, batch)
+        got = to_host(d).reshape(x.shape)
+        for b in range(batch):
+            assert_bit_exact(got[b], O.ntt(x[b], mods, prm), f"ntt batch {b}")
+        ctx.helrm_intt(d, pidx, batch)
+        assert_bit_exact(to_host(d).reshape(x.shape), x, "intt(ntt(x))")
+    finally:
+        ctx.helrm_set_tuning("ntt_col_w", 16)
+        ctx.helrm_set_tuning("ntt_blk_w", 4)
+
+
 def test_ntt_edge_values(p2, ctx2):
     say("ntt edge values q-1 / 0")
     prm, ctx = p2, ctx2
