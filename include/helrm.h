@@ -94,10 +94,23 @@ int helrm_get_psi(const helrm_ctx *ctx, int prime_index, uint64_t *psi);
  * slots: 5^r mod 2N); galois 0 denotes the relinearisation key.  `keys`
  * (host or device memory) is [n_keys][dnum][2][L+1+K][N]: for digit j the pair
  * (b_j, a_j) over all L+1+K primes in evaluation form, with
- * b_j = -a_j s + e_j + [P]_{q_i} s' on digit j's primes.  A key loaded again
- * for the same element replaces the old one.  Blocks. */
+ * b_j = -a_j s + e_j + [P]_{q_i} s' on digit j's primes.  `seeds` (host, may
+ * be NULL) gives each key's 64-bit seed when its a_j halves are the seeded
+ * uniform polynomials of helrm_key_uniform; kernels that use every key word
+ * once (one ciphertext per call) then regenerate a_j instead of reading it,
+ * so the caller must pass the seed the a_j were expanded from.  A key loaded
+ * again for the same element replaces the old one.  Blocks. */
 int helrm_load_eval_keys(helrm_ctx *ctx, const uint32_t *galois, int n_keys,
-                         const uint64_t *keys);
+                         const uint64_t *keys, const uint64_t *seeds);
+
+/* The uniform half a_j (digit j) of a switching key with the given seed, over
+ * all L+1+K primes in evaluation form: out is device [L+1+K][N].  Value x on
+ * prime index p is (X mod q_p) 2^-128 mod q_p with X = o_{2c+2} 2^64 + o_{2c+1}
+ * (X = o_{2c+1} when q_p < 2^40), c = x + 2^16 p + 2^24 j, o_n the n-th output
+ * of the SplitMix64 generator
+ * (Steele, Lea and Flood, OOPSLA 2014) seeded with `seed`.  Errors:
+ * HELRM_EINVAL (digit out of range, NULL out). */
+int helrm_key_uniform(helrm_ctx *ctx, uint64_t seed, int digit, uint64_t *out, void *stream);
 
 /* Forward / inverse negacyclic NTT, in place, of `batch` blocks of n_limbs
  * limbs each (block b at d_data + b*n_limbs*N); limb i of every block uses
@@ -285,7 +298,9 @@ int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *o
  * 16) and "ntt_blk_w" (4 or 8, default 4) are the sub-transforms per workgroup
  * of the NTT's column and block passes; 0 picks the narrow shape for launches
  * of fewer than "ntt_small_limbs" limbs (default 48).  Results do not depend
- * on the knobs.  Errors: HELRM_EINVAL for an unknown knob or value. */
+ * on the knobs.  "gen_key_a" (1, default, or 0) lets kernels that use every
+ * key word once regenerate seeded keys' a_j halves instead of reading them.
+ * Errors: HELRM_EINVAL for an unknown knob or value. */
 int helrm_set_tuning(helrm_ctx *ctx, const char *knob, int value);
 
 #ifdef __cplusplus

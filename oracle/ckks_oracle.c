@@ -290,3 +290,35 @@ void or_basis_convert(const u64 *x, int nin, const u64 *qin, u64 *out, int nout,
   free(hat_inv);
   free(hat_out);
 }
+
+/* ------------------------------------------------------------ seeded uniform key polynomials
+ *
+ * The uniform part a_j of a switching key is expanded from the key's 64-bit
+ * seed with SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom
+ * number generators", OOPSLA 2014): output n >= 1 of the generator seeded with
+ * s is mix(s + n * 0x9E3779B97F4A7C15), where mix is the finaliser below.
+ * Value x of digit j on prime index p takes outputs 2c+1 (low word) and 2c+2
+ * (high word), c = x + 2^16 p + 2^24 j, as the 128-bit integer X (for primes
+ * below 2^40 the low word alone, whose residue is within 2^-24 of uniform),
+ * and is a = (X mod q) * 2^-128 mod q, i.e. the Montgomery-form value
+ * (X mod q) * 2^-64 stands for a. */
+
+u64 or_splitmix64(u64 seed, u64 n) {
+  u64 z = seed + n * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+void or_key_uniform(u64 seed, int j, int p, u64 q, int N, u64 *out) {
+  /* 2^-128 mod q */
+  const u64 two64 = (u64)(((u128)1 << 64) % q);
+  const u64 inv128 = or_invmod(or_mulmod(two64, two64, q), q);
+  for (int x = 0; x < N; x++) {
+    const u64 c = (u64)x + ((u64)p << 16) + ((u64)j << 24);
+    const u64 lo = or_splitmix64(seed, 2 * c + 1);
+    const u64 hi = q < (1ULL << 40) ? 0 : or_splitmix64(seed, 2 * c + 2);
+    const u128 X = ((u128)hi << 64) | lo;
+    out[x] = or_mulmod((u64)(X % q), inv128, q);
+  }
+}

@@ -34,6 +34,8 @@ GPU library must take the same ones for bit-exact parity):
   * hybrid key switching with dnum digits of alpha primes and K special
     primes; ModUp uncorrected; ModDown without a rounding offset; hoisted
     rotations apply the automorphism after ModUp; rescale rounds half up;
+    the uniform part of every switching key is expanded from a 64-bit seed
+    with SplitMix64 (a counter-based generator, so a key stores only b_j);
   * hybrid diagonals u_k[j] = M[j mod m][(j+k) mod n] for k < m,
     m = next_pow2(rows), summed over the m-periodic copies by a fold.
 """
@@ -93,6 +95,8 @@ def lib():
             f.argtypes = [u64p, u64p, u64p, ci, ci, u64p]
         L.or_from_signed.argtypes = [i64p, u64p, ci, ci, u64p]
         L.or_basis_convert.argtypes = [u64p, ci, u64p, u64p, ci, u64p, ci]
+        L.or_splitmix64.restype = u64; L.or_splitmix64.argtypes = [u64, u64]
+        L.or_key_uniform.argtypes = [u64, ci, ci, u64, ci, u64p]
         _lib = L
     return _lib
 
@@ -364,16 +368,35 @@ class Keys:
     pk: Tuple[np.ndarray, np.ndarray]  # (b, a) over Q_L
     swk: Dict[int, np.ndarray] = field(default_factory=dict)  # galois -> uint64 [dnum][2][L+1+K][N]
     relin: Optional[np.ndarray] = None
+    seeds: Dict[int, int] = field(default_factory=dict)       # galois (0: relinearisation) -> seed of a_j
+
+
+def splitmix64(seed: int, n: int) -> int:
+    return int(lib().or_splitmix64(int(seed) & (2 ** 64 - 1), int(n) & (2 ** 64 - 1)))
+
+
+def key_uniform(prm: Params, seed: int, j: int) -> np.ndarray:
+    """Uniform polynomial a_j of a switching key over every prime of PQ_L
+    (evaluation form), expanded from the key's seed by the counter-based
+    SplitMix64 generator (ckks_oracle.c, or_key_uniform)."""
+    allm = prm.q + prm.p
+    out = np.empty((len(allm), prm.N), dtype=np.uint64)
+    for p, q in enumerate(allm):
+        row = np.empty(prm.N, dtype=np.uint64)
+        lib().or_key_uniform(int(seed), j, p, int(q), prm.N, _p(row))
+        out[p] = row
+    return out
 
 
 def _switch_key(prm: Params, s_all: np.ndarray, s_from: np.ndarray, draws) -> np.ndarray:
     """Hybrid switching key from s_from to s: for digit j,
     b_j = -a_j s + e_j + [P Qhat_j (Qhat_j^-1 mod Q_j)] s_from over PQ_L.
-    The gadget factor is [P]_{q_i} on the primes of digit j and 0 elsewhere."""
+    The gadget factor is [P]_{q_i} on the primes of digit j and 0 elsewhere;
+    a_j is expanded from the key's seed."""
     allm = prm.q + prm.p
     out = np.zeros((prm.dnum, 2, len(allm), prm.N), dtype=np.uint64)
     for j in range(prm.dnum):
-        a = np.ascontiguousarray(draws.a[j], dtype=np.uint64)
+        a = key_uniform(prm, draws.a_seed, j)
         e = ntt(from_signed(draws.e[j], allm), allm, prm)
         b = add(neg(mul(a, s_all, allm), allm), e, allm)
         for i in prm.digit(j, prm.L):
@@ -397,8 +420,10 @@ def keygen(prm: Params, draws) -> Keys:
     keys = Keys(s=s_all, pk=(pk_b, pk_a))
     for gal, d in draws.swk.items():
         keys.swk[gal] = _switch_key(prm, s_all, automorph_ntt(s_all, gal, prm.N), d)
+        keys.seeds[gal] = d.a_seed
     if draws.relin is not None:
         keys.relin = _switch_key(prm, s_all, mul(s_all, s_all, allm), draws.relin)
+        keys.seeds[0] = draws.relin.a_seed
     return keys
 
 

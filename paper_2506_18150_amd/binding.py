@@ -53,6 +53,7 @@ EXPORTS = [
     "helrm_plan_destroy", "helrm_plan_rotation_steps", "helrm_ptxt_ct_matvec_diag",
     "helrm_lookup_packed", "helrm_footprint", "helrm_reserve", "helrm_timing_enable", "helrm_timing_read",
     "helrm_set_tuning", "helrm_mul_relin", "helrm_add_plain", "helrm_mod_drop", "helrm_lookup_multi",
+    "helrm_key_uniform",
 ]
 
 _lib = None
@@ -70,7 +71,8 @@ def lib() -> ctypes.CDLL:
     L.helrm_create.argtypes = [ctypes.POINTER(helrm_params), ctypes.POINTER(_vp)]
     L.helrm_destroy.argtypes = [_vp]
     L.helrm_get_psi.argtypes = [_vp, _c_int, _u64p]
-    L.helrm_load_eval_keys.argtypes = [_vp, _u32p, _c_int, _vp]
+    L.helrm_load_eval_keys.argtypes = [_vp, _u32p, _c_int, _vp, _u64p]
+    L.helrm_key_uniform.argtypes = [_vp, ctypes.c_uint64, _c_int, _vp, _vp]
     L.helrm_ntt.argtypes = [_vp, _vp, _c_int, _i32p, _c_int, _vp]
     L.helrm_intt.argtypes = [_vp, _vp, _c_int, _i32p, _c_int, _vp]
     L.helrm_automorph.argtypes = [_vp, _vp, _vp, ctypes.c_uint32, _c_int, _c_int, _vp]
@@ -167,9 +169,14 @@ class Context:
         _check(lib().helrm_get_psi(self.h, i, ctypes.byref(v)))
         return int(v.value)
 
-    def helrm_load_eval_keys(self, galois: Sequence[int], keys: torch.Tensor):
+    def helrm_load_eval_keys(self, galois: Sequence[int], keys: torch.Tensor, seeds: Optional[Sequence[int]] = None):
         g = np.ascontiguousarray(np.array(list(galois), dtype=np.uint32))
-        _check(lib().helrm_load_eval_keys(self.h, g.ctypes.data_as(_u32p), len(g), _ptr(keys)))
+        sd = None if seeds is None else np.ascontiguousarray(np.array([int(x) for x in seeds], dtype=np.uint64))
+        _check(lib().helrm_load_eval_keys(self.h, g.ctypes.data_as(_u32p), len(g), _ptr(keys),
+                                          None if sd is None else sd.ctypes.data_as(_u64p)))
+
+    def helrm_key_uniform(self, seed: int, digit: int, out, stream=None):
+        _check(lib().helrm_key_uniform(self.h, int(seed), digit, _ptr(out), _stream(stream)))
 
     def helrm_ntt(self, data: torch.Tensor, prime_index: Sequence[int], batch: int, stream=None):
         a, pa = _i32(prime_index)

@@ -7,7 +7,8 @@ it comes from the caller's seeded draws, so this module only does the
 arithmetic:
   pk = (-a s + e, a) over Q_L;
   switching key s' -> s, digit j: b_j = -a_j s + e_j + [P]_{q_i} s' on the
-  primes q_i of digit j, a_j over all Q and special primes;
+  primes q_i of digit j, a_j over all Q and special primes, expanded on the
+  GPU from the key's seed (helrm_key_uniform);
   rotation by k: s' = sigma_{5^k}(s); relinearisation: s' = s^2;
   encryption at level l: (v pk_b + e0 + m, v pk_a + e1) over q_0..q_l;
   decryption: c0 + c1 s on q_0, centred.
@@ -58,14 +59,14 @@ class Client:
             sg = self._zeros(self.kl, self.N)
             self.ctx.helrm_automorph(self.s_all, sg, g, self.kl, 1)
             key = self._switch_key(sg, draws.swk[g])
-            self.ctx.helrm_load_eval_keys([g], key)
+            self.ctx.helrm_load_eval_keys([g], key, [draws.swk[g].a_seed])
             del key
         if getattr(draws, "relin", None) is not None:
             # relinearisation key (s^2 -> s), loaded as Galois element 0
             s2 = self._zeros(self.kl, self.N)
             self.ctx.helrm_poly_op(HELRM_OP_MUL, self.s_all, self.s_all, s2, allp, 1)
             key = self._switch_key(s2, draws.relin)
-            self.ctx.helrm_load_eval_keys([0], key)
+            self.ctx.helrm_load_eval_keys([0], key, [draws.relin.a_seed])
             del key
         torch.cuda.synchronize()
 
@@ -73,7 +74,8 @@ class Client:
         allp = list(range(self.kl))
         key = self._zeros(self.prm.dnum, 2, self.kl, self.N)
         for j in range(self.prm.dnum):
-            a = device_u64(d.a[j], self.dev)
+            a = self._zeros(self.kl, self.N)
+            self.ctx.helrm_key_uniform(d.a_seed, j, a)
             e = self._signed_ntt(d.e[j], allp)
             t = self._zeros(self.kl, self.N)
             self.ctx.helrm_poly_op(HELRM_OP_MUL, a, self.s_all, t, allp, 1)

@@ -322,14 +322,17 @@ int do_rescale(helrm_ctx *ctx, int level, const u64 *in, int in_bs, u64 *out, in
   return HELRM_OK;
 }
 
-int key_for(helrm_ctx *ctx, long step, const u64 **key, uint32_t *gal) {
-  *gal = galois_of_step(ctx, step);
-  auto it = ctx->keys.find(*gal);
+// Key, Galois element and seed of the rotation by `step` into t.
+int key_for(helrm_ctx *ctx, long step, KsTerm *t) {
+  t->galois = galois_of_step(ctx, step);
+  auto it = ctx->keys.find(t->galois);
   if (it == ctx->keys.end()) {
-    set_error("no evaluation key loaded for rotation %ld (galois %u)", step, *gal);
+    set_error("no evaluation key loaded for rotation %ld (galois %u)", step, t->galois);
     return HELRM_EINVAL;
   }
-  *key = it->second.d;
+  t->key = it->second.d;
+  t->seed = it->second.seed;
+  t->seeded = it->second.seeded;
   return HELRM_OK;
 }
 
@@ -479,7 +482,7 @@ int run_matvec(helrm_ctx *ctx, const helrm_plan *const *ps, int n_in, const u64 
       KsTerm t;
       t.digits = Dg;
       t.c0 = xgp;
-      TRY(key_for(ctx, (long)p->sign * p->n1 * g, &t.key, &t.galois));
+      TRY(key_for(ctx, (long)p->sign * p->n1 * g, &t));
       terms.push_back(t);
       gi++;
     }
@@ -502,7 +505,7 @@ int run_matvec(helrm_ctx *ctx, const helrm_plan *const *ps, int n_in, const u64 
       KsTerm k;
       k.digits = w.D;
       k.c0 = z;
-      TRY(key_for(ctx, (long)t * st, &k.key, &k.galois));
+      TRY(key_for(ctx, (long)t * st, &k));
       terms.push_back(k);
     }
     if ((int)terms.size() > HELRM_MAX_TERMS) {
@@ -737,7 +740,8 @@ extern "C" int helrm_get_psi(const helrm_ctx *c, int i, uint64_t *psi) {
   return HELRM_OK;
 }
 
-extern "C" int helrm_load_eval_keys(helrm_ctx *c, const uint32_t *galois, int n_keys, const uint64_t *keys) {
+extern "C" int helrm_load_eval_keys(helrm_ctx *c, const uint32_t *galois, int n_keys, const uint64_t *keys,
+                                    const uint64_t *seeds) {
   API_GUARD_BEGIN
   CHECK_ARG(c, "NULL context");
   CHECK_ARG(n_keys >= 0, "n_keys < 0");
@@ -759,6 +763,8 @@ extern "C" int helrm_load_eval_keys(helrm_ctx *c, const uint32_t *galois, int n_
       }
       c->keys[galois[k]] = KeyEntry{d};
     }
+    c->keys[galois[k]].seed = seeds ? seeds[k] : 0;
+    c->keys[galois[k]].seeded = seeds != nullptr;
     HIP_TRY(hipMemcpy(d, keys + (size_t)k * words, words * sizeof(u64), hipMemcpyDefault));
     LimbList ll = ll_make((int)kl, (int)kl, (int)kl);
     for (size_t i = 0; i < kl; i++) { ll.src_off[i] = (int)i; ll.dst_off[i] = (int)i; ll.prime[i] = (unsigned char)i; }
@@ -875,7 +881,7 @@ extern "C" int helrm_keyswitch_hoisted(helrm_ctx *c, const uint64_t *ct, int lev
   for (int r = 0; r < n_rot; r++) {
     terms[r].digits = nullptr;
     terms[r].c0 = ct;
-    if (steps[r] % (c->N / 2) != 0) TRY(key_for(c, steps[r], &terms[r].key, &terms[r].galois));
+    if (steps[r] % (c->N / 2) != 0) TRY(key_for(c, steps[r], &terms[r]));
     else terms[r].galois = 1;
   }
   KsSizes z = ks_sizes(c, level, batch, 1);
@@ -934,6 +940,14 @@ extern "C" int helrm_rescale(helrm_ctx *c, const uint64_t *in, int level, uint64
   API_GUARD_END
 }
 
+extern "C" int helrm_key_uniform(helrm_ctx *c, uint64_t seed, int digit, uint64_t *out, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && out, "NULL argument");
+  CHECK_ARG(digit >= 0 && digit < c->dnum, "digit %d out of range", digit);
+  return launch_key_uniform(c, seed, digit, out, as_stream(stream));
+  API_GUARD_END
+}
+
 extern "C" int helrm_mul_relin(helrm_ctx *c, const uint64_t *a, const uint64_t *b, int level, uint64_t *out,
                                int batch, void *stream) {
   API_GUARD_BEGIN
@@ -966,6 +980,8 @@ extern "C" int helrm_mul_relin(helrm_ctx *c, const uint64_t *a, const uint64_t *
   t.c0 = nullptr;
   t.key = it->second.d;
   t.galois = 1;
+  t.seed = it->second.seed;
+  t.seeded = it->second.seeded;
   TRY(launch_ks_accumulate(c, level, &t, 1, (size_t)d_bs * N, 0, d, (size_t)3 * qn * N, X, (size_t)2 * pqn * N,
                            batch, s));
   TRY(do_moddown(c, level, X, 2 * pqn, out, 2 * qn, mdP, mdT, batch, s));
@@ -1247,6 +1263,9 @@ extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
   } else if (strcmp(knob, "ntt_small_limbs") == 0) {
     CHECK_ARG(value >= 0, "ntt_small_limbs must be >= 0");
     c->ntt_small_limbs = value;
+  } else if (strcmp(knob, "gen_key_a") == 0) {
+    CHECK_ARG(value == 0 || value == 1, "gen_key_a must be 0 or 1");
+    c->tune_gen_key_a = value;
   } else if (strcmp(knob, "baby_share") == 0) {
     CHECK_ARG(value == 1 || value == 2 || value == 4 || value == 8, "baby_share must be 1, 2, 4 or 8");
     c->tune_baby_share = value;

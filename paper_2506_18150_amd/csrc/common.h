@@ -172,6 +172,21 @@ __device__ __forceinline__ unsigned galois_src(unsigned j, unsigned g, int logn)
   return __brev((e2 - 1u) >> 1) >> (32 - logn);
 }
 
+// Uniform half a_j of a switching key, regenerated from the key's seed with
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output n of the generator
+// seeded with s is mix(s + n * 0x9E3779B97F4A7C15).  Value x of digit j on
+// prime index p uses X = out_{2c+2} 2^64 + out_{2c+1} (X = out_{2c+1} for
+// primes below 2^40), c = x + 2^16 p + 2^24 j; the key holds a_j = (X mod q)
+// 2^-128 in Montgomery form, which is X 2^-64 mod q = REDC((out_{2c+2} mod q)
+// 2^64 + out_{2c+1}).
+constexpr u64 SM_GAMMA = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ u64 sm_mix(u64 z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // ---------------------------------------------------------------- per-prime device constants
 
 struct PrimeInfo {
@@ -188,6 +203,17 @@ struct PrimeInfo {
 struct TW {
   u64 w, wp;
 };
+
+// Montgomery-form a_j value of a seeded key at (digit j, prime index p,
+// coefficient x).  Primes below 2^40 take X = o_{2c+1} alone (64 bits, so
+// X mod q is within 2^-24 of uniform), the others the 128-bit X.
+__device__ __forceinline__ u64 key_uniform_mont(u64 seed, int j, int p, int x, const PrimeInfo &pi) {
+  const u64 c = (u64)x + ((u64)p << 16) + ((u64)j << 24);
+  const u64 lo = sm_mix(seed + (2 * c + 1) * SM_GAMMA);
+  if (pi.q < SPLIT_MAC_LIMIT) return redc(lo, 0, pi.q, pi.qn);
+  const u64 hi = sm_mix(seed + (2 * c + 2) * SM_GAMMA);
+  return redc(lo, reduce64(hi, pi.q, pi.mu), pi.q, pi.qn);
+}
 
 // A list of limbs for one launch.  Limb i of batch element b lives at
 // base + (b * bstride + off[i]) * N and uses prime prime[i].
@@ -213,7 +239,9 @@ struct ConvTable {
 // ---------------------------------------------------------------- context
 
 struct KeyEntry {
-  u64 *d;   // [dnum][2][L+1+K][N], Montgomery form
+  u64 *d;            // [dnum][2][L+1+K][N], Montgomery form
+  u64 seed = 0;      // seed the a_j halves were expanded from
+  bool seeded = false;
 };
 
 struct Workspace {
@@ -265,6 +293,8 @@ struct helrm_ctx {
   int tune_ntt_col_w = 16;   // NTT column-pass columns per workgroup (8, 16; 0 = by launch size)
   int tune_ntt_blk_w = 4;    // NTT block-pass blocks per workgroup (4, 8; 0 = by launch size)
   int ntt_small_limbs = 48;  // launches of fewer limbs take the narrow shapes when a width is 0
+  int tune_gen_key_a = 1;    // regenerate keys' a_j halves from their seeds: 0 never, 1 where a kernel
+                             // serves one ciphertext per thread and streams keys (default)
   bool timing = false;
   std::mutex tmu;
   std::vector<TimingRec> trecs;
@@ -385,6 +415,8 @@ struct KsTerm {
   const u64 *c0;      // [level+1][N], or null: no P sigma(c0) term
   const u64 *key;     // [dnum][2][L+1+K][N] Montgomery form
   uint32_t galois;
+  u64 seed = 0;       // the key's seed, when its a_j halves may be regenerated
+  bool seeded = false;
 };
 
 // 5^(step mod n) mod 2N by square-and-multiply (2N is a power of two).
@@ -398,6 +430,8 @@ inline uint32_t galois_of_step(const helrm_ctx *ctx, long step) {
   return (uint32_t)g;
 }
 
+// Plain a_j of a seeded key over every prime of PQ_L: out [L+1+K][N].
+int launch_key_uniform(helrm_ctx *ctx, u64 seed, int digit, u64 *out, hipStream_t s);
 // (d0, d1, d2) of two ciphertexts at `level` ([batch][2][level+1] -> [batch][3][level+1]).
 int launch_tensor(helrm_ctx *ctx, const u64 *a, const u64 *b, u64 *d, int level, int batch, hipStream_t s);
 // (c0 + pt, c1) with one plaintext [level+1] limbs for every ciphertext of the batch.

@@ -242,6 +242,7 @@ __global__ __launch_bounds__(TPB) void add_plain_kernel(const u64 *ct, const u64
 struct KsArgs {
   int n;
   int accum;   // add the result to what `out` holds (later chunks of a long term list)
+  u64 seed[HELRM_MAX_TERMS];   // key seeds (used when the a_j halves are regenerated)
   const u64 *digits[HELRM_MAX_TERMS];
   const u64 *c0[HELRM_MAX_TERMS];
   const u64 *key[HELRM_MAX_TERMS];
@@ -290,7 +291,7 @@ struct KsIn {
   u64 kb[BETA], ka[BETA], d[BT][BETA], c0[BT];
 };
 
-template <int BT, int BETA, class M>
+template <int BT, int BETA, class M, bool GEN>
 __device__ __forceinline__ void ks_acc_body(const KsArgs &T, const LevelGeom &G, int batch, int x, int r, int b0,
                                             int p, const PrimeInfo &pi, size_t dig_bs, size_t c0_bs,
                                             const u64 *base, size_t base_bs, u64 *out, size_t out_bs) {
@@ -311,7 +312,7 @@ __device__ __forceinline__ void ks_acc_body(const KsArgs &T, const LevelGeom &G,
 #pragma unroll
     for (int j = 0; j < BETA; j++) {
       in.kb[j] = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
-      in.ka[j] = kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
+      in.ka[j] = GEN ? key_uniform_mont(T.seed[t], j, p, x, pi) : kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
     }
 #pragma unroll
     for (int k = 0; k < BT; k++) {
@@ -377,7 +378,7 @@ __device__ __forceinline__ void ks_acc_body(const KsArgs &T, const LevelGeom &G,
   }
 }
 
-template <int BT, int BETA>
+template <int BT, int BETA, bool GEN>
 __global__ __launch_bounds__(TPB) void ks_acc_kernel(KsArgs T, LevelGeom G, int L, int batch, int ntiles,
                                                      size_t dig_bs, size_t c0_bs, const u64 *base,
                                                      size_t base_bs, u64 *out, size_t out_bs,
@@ -388,11 +389,11 @@ __global__ __launch_bounds__(TPB) void ks_acc_kernel(KsArgs T, LevelGeom G, int 
   const int p = pq_prime_dev(tm.r, G.level, L);
   const PrimeInfo pi = pinfo[p];
   if (pi.q < SPLIT_MAC_LIMIT)
-    ks_acc_body<BT, BETA, SplitMac>(T, G, batch, x, tm.r, tm.tile * BT, p, pi, dig_bs, c0_bs, base, base_bs, out,
-                                    out_bs);
+    ks_acc_body<BT, BETA, SplitMac, GEN>(T, G, batch, x, tm.r, tm.tile * BT, p, pi, dig_bs, c0_bs, base, base_bs,
+                                         out, out_bs);
   else
-    ks_acc_body<BT, BETA, WideMac>(T, G, batch, x, tm.r, tm.tile * BT, p, pi, dig_bs, c0_bs, base, base_bs, out,
-                                   out_bs);
+    ks_acc_body<BT, BETA, WideMac, GEN>(T, G, batch, x, tm.r, tm.tile * BT, p, pi, dig_bs, c0_bs, base, base_bs,
+                                        out, out_bs);
 }
 
 // Rotation steps of one fused baby-step launch, compacted on the host: only
@@ -403,6 +404,7 @@ struct BabyArgs {
   short slot0[HELRM_MAX_GTILE];                    // plaintext of (g0 + gi, b = 0), -1: none
   unsigned gal[HELRM_MAX_BABY];                    // Galois element of each step
   const u64 *key[HELRM_MAX_BABY];                  // its evaluation key
+  u64 seed[HELRM_MAX_BABY];                        // the key's seed (a_j regenerated from it)
   short slot[HELRM_MAX_BABY][HELRM_MAX_GTILE];     // plaintext of (g0 + gi, step), -1: none
 };
 
@@ -420,7 +422,7 @@ struct StepIn {
 // step are issued before the products of the current one.  M is the
 // multiply-accumulate policy (SplitMac on limbs whose prime is below 2^40,
 // WideMac otherwise); BETA is the number of key-switching digits.
-template <int GT, int BT, int BETA, class M>
+template <int GT, int BT, int BETA, class M, bool GEN>
 __device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeom &G, int batch, int x, int r,
                                               int b0, int p, const PrimeInfo &pi, const u64 *digits,
                                               size_t dig_bs, const u64 *ct, size_t ct_bs, const u64 *pt, int ng,
@@ -463,7 +465,7 @@ __device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeo
 #pragma unroll
     for (int j = 0; j < BETA; j++) {
       in.kb[j] = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
-      in.ka[j] = kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
+      in.ka[j] = GEN ? key_uniform_mont(BA.seed[i], j, p, x, pi) : kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
     }
 #pragma unroll
     for (int k = 0; k < BT; k++) {
@@ -542,7 +544,7 @@ __device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeo
   }
 }
 
-template <int GT, int BT, int BETA>
+template <int GT, int BT, int BETA, bool GEN>
 __global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G, int L, int batch, int ntiles,
                                                        const u64 *digits, size_t dig_bs, const u64 *ct,
                                                        size_t ct_bs, const u64 *pt, int ng, u64 *X, size_t x_bs,
@@ -553,11 +555,11 @@ __global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G,
   const int p = pq_prime_dev(tm.r, G.level, L);
   const PrimeInfo pi = pinfo[p];
   if (pi.q < SPLIT_MAC_LIMIT)
-    baby_mac_body<GT, BT, BETA, SplitMac>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs, ct, ct_bs,
-                                          pt, ng, X, x_bs, accum);
+    baby_mac_body<GT, BT, BETA, SplitMac, GEN>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs, ct,
+                                               ct_bs, pt, ng, X, x_bs, accum);
   else
-    baby_mac_body<GT, BT, BETA, WideMac>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs, ct, ct_bs,
-                                         pt, ng, X, x_bs, accum);
+    baby_mac_body<GT, BT, BETA, WideMac, GEN>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs, ct,
+                                              ct_bs, pt, ng, X, x_bs, accum);
 }
 
 // The same product for launches with several giant outputs and a batch.  A
@@ -758,6 +760,14 @@ __global__ __launch_bounds__(64 * W) void baby_mac_shared_kernel(BabyArgs BA, Le
                                             dig_bs, ct, ct_bs, pt, ng, X, x_bs, accum);
 }
 
+// Plain a_j of a seeded key (REDC of the Montgomery-form value) on every prime.
+__global__ __launch_bounds__(TPB) void key_uniform_kernel(u64 seed, int j, u64 *out, const PrimeInfo *pinfo,
+                                                          int N) {
+  const int x = blockIdx.x * TPB + threadIdx.x, p = blockIdx.y;
+  const PrimeInfo pi = pinfo[p];
+  out[(size_t)p * N + x] = redc(key_uniform_mont(seed, j, p, x, pi), 0, pi.q, pi.qn);
+}
+
 dim3 ew_grid(const helrm_ctx *ctx, int rows) { return dim3(ctx->N / TPB, rows); }
 
 }  // namespace
@@ -936,12 +946,18 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
     KsArgs T;
     T.n = nt_i;
     T.accum = t0 > 0;
+    bool seeded = true;
     for (int i = 0; i < nt_i; i++) {
       T.digits[i] = terms[t0 + i].digits;
       T.c0[i] = terms[t0 + i].c0;
       T.key[i] = terms[t0 + i].key;
       T.gal[i] = terms[t0 + i].galois;
+      T.seed[i] = terms[t0 + i].seed;
+      seeded = seeded && terms[t0 + i].seeded;
     }
+    // one ciphertext per thread: every key word is used once, so regenerating
+    // the a_j halves halves the key traffic
+    const bool gen = bt == 1 && seeded && nt_i > 0 && ctx->tune_gen_key_a == 1;
     const u64 *bse = t0 == 0 ? base : nullptr;
     // per coefficient of a Q limb: terms * 3 beta words (digit, key b, key a) + the c0 words
     // + 2 base words + 2 output words (4 when adding to out); special limbs: no c0 / base
@@ -949,23 +965,29 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
     double nc0 = 0;
     for (int i = 0; i < nt_i; i++) nc0 += T.c0[i] ? 1 : 0;
     const double qn = level + 1, K = ctx->K, nt = nt_i, beta = G.beta, B = batch, ow = T.accum ? 4 : 2;
-    const double words = qn * (nt * 2 * beta + B * (nt * beta + nc0 + (bse ? 2 : 0) + ow)) +
-                         K * (nt * 2 * beta + B * (nt * beta + ow));
+    const double kw = gen ? beta : 2 * beta;   // key words per term and coefficient read from memory
+    const double words = qn * (nt * kw + B * (nt * beta + nc0 + (bse ? 2 : 0) + ow)) +
+                         K * (nt * kw + B * (nt * beta + ow));
     KTimer tm(ctx, s);
-#define KSACC(BT_, BETA_)                                                                              \
-  hipLaunchKernelGGL((ks_acc_kernel<BT_, BETA_>), dim3(grid), dim3(TPB), 0, s, T, G, ctx->L, batch,     \
-                     ntiles, digits_bstride, c0_bstride, bse, base_bstride, out, out_bstride, ctx->d_pinfo)
-#define KSACC_B(BT_)                      \
-  switch (G.beta) {                       \
-    case 1: KSACC(BT_, 1); break;         \
-    case 2: KSACC(BT_, 2); break;         \
-    case 3: KSACC(BT_, 3); break;         \
-    default: KSACC(BT_, 4); break;        \
+#define KSACC(BT_, BETA_, GEN_)                                                                        \
+  hipLaunchKernelGGL((ks_acc_kernel<BT_, BETA_, GEN_>), dim3(grid), dim3(TPB), 0, s, T, G, ctx->L,      \
+                     batch, ntiles, digits_bstride, c0_bstride, bse, base_bstride, out, out_bstride,    \
+                     ctx->d_pinfo)
+#define KSACC_B(BT_, GEN_)                      \
+  switch (G.beta) {                             \
+    case 1: KSACC(BT_, 1, GEN_); break;         \
+    case 2: KSACC(BT_, 2, GEN_); break;         \
+    case 3: KSACC(BT_, 3, GEN_); break;         \
+    default: KSACC(BT_, 4, GEN_); break;        \
   }
-    switch (bt) {
-      case 1: KSACC_B(1); break;
-      case 2: KSACC_B(2); break;
-      default: KSACC_B(4); break;
+    if (gen) {
+      KSACC_B(1, true);
+    } else {
+      switch (bt) {
+        case 1: KSACC_B(1, false); break;
+        case 2: KSACC_B(2, false); break;
+        default: KSACC_B(4, false); break;
+      }
     }
 #undef KSACC_B
 #undef KSACC
@@ -985,6 +1007,7 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   BabyArgs BA;
   BA.nrot = 0;
   BA.has0 = 0;
+  bool seeded = true;
   for (int gi = 0; gi < HELRM_MAX_GTILE; gi++) BA.slot0[gi] = -1;
   double npt = 0;
   for (int b : plan->babies) {
@@ -1016,6 +1039,8 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
     const int i = BA.nrot++;
     BA.key[i] = it->second.d;
     BA.gal[i] = (unsigned)g;
+    BA.seed[i] = it->second.seed;
+    seeded = seeded && it->second.seeded;
     for (int gi = 0; gi < HELRM_MAX_GTILE; gi++) BA.slot[i][gi] = sl[gi];
   }
   const int level = plan->level;
@@ -1028,10 +1053,17 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   // algorithmic words per coefficient: keys and plaintexts once per launch, the rest per ciphertext
   const double nrot = BA.nrot, has0 = BA.has0;
   const double qn = level + 1, K = ctx->K, beta = G.beta, B = batch;
-  const double xw = accum ? 4 : 2;   // output words per giant (read as well when accumulating)
-  const double words = qn * (nrot * 2 * beta + npt + B * (nrot * (beta + 1) + 2 * has0 + xw * ng)) +
-                       K * (nrot * 2 * beta + npt + B * (nrot * beta + xw * ng));
   const int gt = ng <= 1 ? 1 : ng <= 2 ? 2 : ng <= 4 ? 4 : 8;
+  const double xw = accum ? 4 : 2;   // output words per giant (read as well when accumulating)
+  // one ciphertext per thread and few giant outputs: the kernel streams keys,
+  // so it regenerates their a_j halves instead of reading them
+  const bool shared_path = ng >= 2 && batch >= 2 && ctx->tune_baby_share >= 2;
+  const int bt_path = shared_path ? 0 : pick_bt(batch, gt >= 4 ? 1 : gt == 2 ? std::min(2, ctx->tune_baby_tile)
+                                                                             : ctx->tune_baby_tile);
+  const bool gen = !shared_path && bt_path == 1 && gt <= 2 && seeded && BA.nrot > 0 && ctx->tune_gen_key_a == 1;
+  const double kw = gen ? beta : 2 * beta;
+  const double words = qn * (nrot * kw + npt + B * (nrot * (beta + 1) + 2 * has0 + xw * ng)) +
+                       K * (nrot * kw + npt + B * (nrot * beta + xw * ng));
   KTimer tm(ctx, s);
   if (ng >= 2 && batch >= 2 && ctx->tune_baby_share >= 2) {
     // several giant outputs and a batch: W ciphertexts per workgroup
@@ -1063,25 +1095,27 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
     const int bt = pick_bt(batch, gt >= 4 ? 1 : gt == 2 ? std::min(2, ctx->tune_baby_tile) : ctx->tune_baby_tile);
     const int ntiles = (batch + bt - 1) / bt;
     const int grid = (ctx->N / TPB) * G.pqn * ntiles;
-#define BABY(GT_, BT_, BETA_)                                                                            \
-  hipLaunchKernelGGL((baby_mac_kernel<GT_, BT_, BETA_>), dim3(grid), dim3(TPB), 0, s, BA, G, ctx->L,      \
-                     batch, ntiles, digits, digits_bstride, ct, ct_bstride, plan->d_pt, ng, X, x_bstride,  \
-                     accum ? 1 : 0, ctx->d_pinfo)
-#define BABY_B(GT_, BT_)                      \
-  switch (G.beta) {                           \
-    case 1: BABY(GT_, BT_, 1); break;         \
-    case 2: BABY(GT_, BT_, 2); break;         \
-    case 3: BABY(GT_, BT_, 3); break;         \
-    default: BABY(GT_, BT_, 4); break;        \
+#define BABY(GT_, BT_, BETA_, GEN_)                                                                      \
+  hipLaunchKernelGGL((baby_mac_kernel<GT_, BT_, BETA_, GEN_>), dim3(grid), dim3(TPB), 0, s, BA, G,        \
+                     ctx->L, batch, ntiles, digits, digits_bstride, ct, ct_bstride, plan->d_pt, ng, X,     \
+                     x_bstride, accum ? 1 : 0, ctx->d_pinfo)
+#define BABY_B(GT_, BT_, GEN_)                      \
+  switch (G.beta) {                                 \
+    case 1: BABY(GT_, BT_, 1, GEN_); break;         \
+    case 2: BABY(GT_, BT_, 2, GEN_); break;         \
+    case 3: BABY(GT_, BT_, 3, GEN_); break;         \
+    default: BABY(GT_, BT_, 4, GEN_); break;        \
   }
-    if (gt == 1) {
-      if (bt == 1) BABY_B(1, 1) else if (bt == 2) BABY_B(1, 2) else BABY_B(1, 4)
+    if (gen) {
+      if (gt == 1) BABY_B(1, 1, true) else BABY_B(2, 1, true)
+    } else if (gt == 1) {
+      if (bt == 1) BABY_B(1, 1, false) else if (bt == 2) BABY_B(1, 2, false) else BABY_B(1, 4, false)
     } else if (gt == 2) {
-      if (bt == 1) BABY_B(2, 1) else BABY_B(2, 2)
+      if (bt == 1) BABY_B(2, 1, false) else BABY_B(2, 2, false)
     } else if (gt == 4) {
-      BABY_B(4, 1);
+      BABY_B(4, 1, false);
     } else {
-      BABY_B(8, 1);
+      BABY_B(8, 1, false);
     }
 #undef BABY_B
 #undef BABY
@@ -1106,6 +1140,14 @@ int launch_add_plain(helrm_ctx *ctx, const u64 *ct, const u64 *pt, u64 *out, int
   if (batch == 0) return HELRM_OK;
   hipLaunchKernelGGL(add_plain_kernel, ew_grid(ctx, 2 * qn * batch), dim3(TPB), 0, s, ct, pt, out, qn,
                      ctx->d_pinfo, ctx->N);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_key_uniform(helrm_ctx *ctx, u64 seed, int digit, u64 *out, hipStream_t s) {
+  const int kl = ctx->L + 1 + ctx->K;
+  hipLaunchKernelGGL(key_uniform_kernel, ew_grid(ctx, kl), dim3(TPB), 0, s, seed, digit, out, ctx->d_pinfo,
+                     ctx->N);
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
 }

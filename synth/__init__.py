@@ -11,6 +11,9 @@ tables and query indices are drawn here too; the method's own client steps
 Generator: numpy ``Generator(PCG64(seed))``.  Draw order for key material is
 fixed by :class:`KeyDraws` (secret, public key, then one switching key per
 Galois element in ascending order, then the relinearisation key if asked).
+The uniform polynomials of switching keys are not drawn here: a switching key
+gets a 64-bit seed, which the oracle and the library each expand with their
+own implementation of the counter-based generator that both follow.
 """
 from __future__ import annotations
 
@@ -53,9 +56,10 @@ def uniform_residues(g: np.random.Generator, moduli: Sequence[int], n: int) -> n
 
 @dataclass
 class SwitchKeyDraws:
-    """Randomness of one switching key: per digit a uniform polynomial over the
-    full extended basis (drawn directly in evaluation form) and an error."""
-    a: np.ndarray          # uint64 [dnum][L+1+K][N]
+    """Randomness of one switching key: the 64-bit seed of its uniform
+    polynomials (each side expands it with the same published counter-based
+    generator, so a key need not store them) and one error per digit."""
+    a_seed: int            # seed of the uniform part a_j of every digit j
     e: np.ndarray          # int64  [dnum][N]
 
 
@@ -72,19 +76,18 @@ def key_draws(seed: int, N: int, q_moduli: Sequence[int], p_moduli: Sequence[int
               dnum: int, galois: Sequence[int], relin: bool = False) -> KeyDraws:
     """All key randomness for one parameter set, in the fixed draw order."""
     g = rng(seed)
-    pq = list(q_moduli) + list(p_moduli)
     s = ternary(g, N)
     pk_a = uniform_residues(g, q_moduli, N)
     pk_e = gaussian(g, N)
     kd = KeyDraws(s=s, pk_a=pk_a, pk_e=pk_e)
     for gal in sorted(set(int(x) for x in galois)):
-        a = np.stack([uniform_residues(g, pq, N) for _ in range(dnum)])
+        seed = int(g.integers(0, 1 << 63))
         e = np.stack([gaussian(g, N) for _ in range(dnum)])
-        kd.swk[gal] = SwitchKeyDraws(a=a, e=e)
+        kd.swk[gal] = SwitchKeyDraws(a_seed=seed, e=e)
     if relin:
-        a = np.stack([uniform_residues(g, pq, N) for _ in range(dnum)])
+        seed = int(g.integers(0, 1 << 63))
         e = np.stack([gaussian(g, N) for _ in range(dnum)])
-        kd.relin = SwitchKeyDraws(a=a, e=e)
+        kd.relin = SwitchKeyDraws(a_seed=seed, e=e)
     return kd
 
 

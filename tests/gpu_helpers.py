@@ -24,7 +24,7 @@ def load_keys(ctx, keys: O.Keys):
     import torch
     from paper_2506_18150_amd import binding as B
     for g, k in sorted(keys.swk.items()):
-        ctx.helrm_load_eval_keys([g], B.device_u64(k))
+        ctx.helrm_load_eval_keys([g], B.device_u64(k), [keys.seeds[g]])
     torch.cuda.synchronize()
 
 

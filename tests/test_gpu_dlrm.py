@@ -19,7 +19,7 @@ def load_all_keys(ctx, keys):
     import torch
     from paper_2506_18150_amd import binding as B
     load_keys(ctx, keys)
-    ctx.helrm_load_eval_keys([0], B.device_u64(keys.relin))
+    ctx.helrm_load_eval_keys([0], B.device_u64(keys.relin), [keys.seeds[0]])
     torch.cuda.synchronize()
 
 

@@ -94,6 +94,18 @@ def test_ntt_parity_other_shapes(which, wc, wb, p1, p2, ctx1, ctx2):
         ctx.helrm_set_tuning("ntt_blk_w", 4)
 
 
+@pytest.mark.parametrize("which", ["cfg1", "cfg2"])
+def test_key_uniform_parity(which, p1, p2, ctx1, ctx2):
+    """Seeded key polynomials expanded on the GPU equal the oracle's expansion."""
+    prm, ctx = (p1, ctx1) if which == "cfg1" else (p2, ctx2)
+    for seed in (0, 0x0123456789ABCDEF, 2 ** 63 - 1):
+        for j in range(prm.dnum):
+            say(f"key_uniform {which} seed={seed} digit={j}")
+            out = empty(len(prm.q) + len(prm.p), prm.N)
+            ctx.helrm_key_uniform(seed, j, out)
+            assert_bit_exact(to_host(out), O.key_uniform(prm, seed, j), f"key_uniform digit {j}")
+
+
 def test_ntt_edge_values(p2, ctx2):
     say("ntt edge values q-1 / 0")
     prm, ctx = p2, ctx2
@@ -269,6 +281,21 @@ def test_lookup_parity_cfg2_full_level(radix, sign, ctx2):
     w = cfg2_workload(23, 16, radix, sign=sign)
     load_keys(ctx2, w.keys)
     _check_lookup(ctx2, w, gpu_plan(ctx2, w.plan), [0])
+
+
+def test_lookup_regenerated_key_halves_cfg2(ctx2):
+    """Batch 1 regenerates the keys' a_j halves from their seeds; with the
+    knob off the kernels read them: both bit-exact against the oracle."""
+    w = cfg2_workload(4, 16, 8, sign=-1)
+    load_keys(ctx2, w.keys)
+    plan = gpu_plan(ctx2, w.plan)
+    try:
+        for gen in (1, 0):
+            say(f"lookup cfg2 level 4 gen_key_a={gen}")
+            ctx2.helrm_set_tuning("gen_key_a", gen)
+            _check_lookup(ctx2, w, plan, [0])
+    finally:
+        ctx2.helrm_set_tuning("gen_key_a", 1)
 
 
 def test_lookup_batched_ragged_cfg2(ctx2):

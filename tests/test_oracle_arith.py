@@ -212,3 +212,38 @@ def test_basis_convert_exact_integer(tiny):
                     us.add(u)
         assert len(us) >= 1
         assert any(all((xv[c] + u * Qin) % qr == int(out[r, c]) for r, qr in enumerate(qout)) for u in us)
+
+
+def test_splitmix64_published_outputs():
+    """The counter-based generator behind seeded key polynomials reproduces
+    the published SplitMix64 outputs (output n of seed s is the n-th draw)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "splitmix64.json")) as f:
+        g = json.load(f)
+    for case in g["outputs"]:
+        for n, v in enumerate(case["values"], start=1):
+            assert O.splitmix64(case["seed"], n) == int(v, 0)
+
+
+def test_key_uniform_definition_and_spread(tiny):
+    """a = (X mod q) 2^-128 mod q with X = out_{2c+2} 2^64 + out_{2c+1}
+    (out_{2c+1} alone below 2^40), c = x + 2^16 p + 2^24 j; values cover
+    [0, q) evenly."""
+    prm = tiny
+    seed = 0x1234_5678_9ABC_DEF0
+    allm = prm.q + prm.p
+    for j in range(prm.dnum):
+        a = O.key_uniform(prm, seed, j)
+        for p, q in enumerate(allm):
+            for x in (0, 1, prm.N - 1):
+                c = x + (p << 16) + (j << 24)
+                hi = O.splitmix64(seed, 2 * c + 2) if q >= 2 ** 40 else 0
+                X = (hi << 64) | O.splitmix64(seed, 2 * c + 1)
+                assert int(a[p, x]) == (X % q) * pow(pow(2, 128, q), -1, q) % q
+    # spread: a larger ring, the fraction of values in each quarter of [0, q)
+    big = O.make_params(N=4096, L=1, K=1, alpha=1)
+    a = O.key_uniform(big, 7, 0)
+    for p, q in enumerate(big.q + big.p):
+        quarters = np.bincount((a[p].astype(object) * 4 // q).astype(np.int64), minlength=4) / big.N
+        assert np.all(np.abs(quarters - 0.25) < 0.03)
