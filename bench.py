@@ -122,6 +122,8 @@ def parse():
     ap.add_argument("--ntt-col-w", type=int, default=None, help="NTT column-pass width (8, 16; 0 = by size)")
     ap.add_argument("--ntt-blk-w", type=int, default=None, help="NTT block-pass width (4, 8; 0 = by size)")
     ap.add_argument("--ntt-small-limbs", type=int, default=None)
+    ap.add_argument("--knob", action="append", default=[], metavar="NAME=VALUE",
+                    help="any other library tuning knob (repeatable), e.g. conv_wgs=0")
     ap.add_argument("--autotune", action="store_true", help="measure candidate schedules first")
     ap.add_argument("--autotune-out", default=None, help="write the tuning record to this file")
     ap.add_argument("--graph", action="store_true", help="replay one captured HIP graph per step")
@@ -421,6 +423,9 @@ def main():
                     ("ntt_small_limbs", args.ntt_small_limbs)):
         if v is not None:
             sess.ctx.helrm_set_tuning(knob, v)
+    for kv in args.knob:
+        name, v = kv.split("=")
+        sess.ctx.helrm_set_tuning(name, int(v))
     setup_s = time.time() - t0
     qg = synth.rng(1)
     idx = [synth.indices(qg, [t.rows for t in tables]) for _ in range(B)]

@@ -300,6 +300,9 @@ int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *o
  * of fewer than "ntt_small_limbs" limbs (default 48).  Results do not depend
  * on the knobs.  "gen_key_a" (1, default, or 0) lets kernels that use every
  * key word once regenerate seeded keys' a_j halves instead of reading them.
+ * "conv_wgs" (>= 0, default 2048): a base conversion launch with fewer
+ * workgroups than this splits its outputs into chunks (at least four outputs
+ * each) until it has that many; 0 never splits.
  * Errors: HELRM_EINVAL for an unknown knob or value. */
 int helrm_set_tuning(helrm_ctx *ctx, const char *knob, int value);
 

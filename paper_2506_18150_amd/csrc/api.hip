@@ -285,6 +285,7 @@ int do_moddown(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *out, int 
   e.out = out;
   e.c = ctx->moddown_pinv[level];
   e.inner = 2;
+  e.n_fin = qn;
   e.a_bs = x_bs;
   e.a_cs = pqn;
   e.out_bs = out_bs;
@@ -313,12 +314,149 @@ int do_rescale(helrm_ctx *ctx, int level, const u64 *in, int in_bs, u64 *out, in
   e.out = out;
   e.c = ctx->rescale_qinv[level];
   e.inner = 2;
+  e.n_fin = level;
   e.a_bs = in_bs;
   e.a_cs = qn;
   e.out_bs = out_bs;
   e.out_cs = level;
   for (int i = 0; i < level; i++) { e.a_off[i] = i; e.out_off[i] = i; }
   TRY(launch_ntt_epi(ctx, V, V, b, 2 * batch, true, s, e));
+  return HELRM_OK;
+}
+
+// A ModDown whose result feeds a ModUp (the next key switch of a fold or
+// giant step), done in coefficient form: NTT^-1 is exact and linear, so
+// (X - NTT(t)) P^-1 in evaluation form and NTT((NTT^-1(X) - t) P^-1) are the
+// same residues, and the ModUp's own NTT^-1 of c1 disappears.
+//   1. NTT^-1 of c0's special limbs and of all of c1's limbs (X -> C);
+//   2. one conversion P -> Q: t0 for c0, z1 = (X1 - t1) P^-1 for c1 (C -> F);
+//   3. the ModUp conversion of z1 to every digit (F -> F);
+//   4. one forward NTT of t0 (finished into z.c0: (X0 - NTT(t0)) P^-1), of z1
+//      (into the digits' own limbs and z.c1) and of the converted limbs.
+// X: [batch] x x_bs limbs, (c0, c1) PQ limbs at 0 and pqn; z: [batch][2][qn]
+// at batch stride z_bs; F: [batch] x f_bs limbs, t0 at 0, z1 at qn, digits
+// ([beta][pqn]) at 2 qn; C: [batch][K + pqn].
+int fused_fits(const helrm_ctx *ctx, int level) {
+  const int qn = level + 1, pqn = level + 1 + ctx->K;
+  return 2 * qn + ctx->n_digits(level) * pqn - qn <= HELRM_MAX_LIMBS && ctx->K + pqn <= HELRM_MAX_LIMBS &&
+         2 * pqn <= HELRM_MAX_LIMBS && qn <= HELRM_MAX_EPI;
+}
+
+int do_moddown_modup(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *z, int z_bs, u64 *F, int f_bs,
+                     u64 *C, int batch, hipStream_t s) {
+  const int K = ctx->K, qn = level + 1, pqn = level + 1 + K, beta = ctx->n_digits(level);
+  const int c_bs = K + pqn;
+  // 1.
+  LimbList a = ll_make(K + pqn, x_bs, c_bs);
+  for (int k = 0; k < K; k++) {
+    a.src_off[k] = qn + k;
+    a.dst_off[k] = k;
+    a.prime[k] = ctx->L + 1 + k;
+  }
+  for (int i = 0; i < pqn; i++) {
+    a.src_off[K + i] = pqn + i;
+    a.dst_off[K + i] = K + i;
+    a.prime[K + i] = ctx->pq_prime(i, level);
+  }
+  TRY(launch_ntt(ctx, X, C, a, batch, false, s));
+  // 2.
+  ConvSpec md[2];
+  for (int c = 0; c < 2; c++) {
+    md[c].t = &ctx->moddown_tabs[level];
+    md[c].src_off0 = c == 0 ? 0 : K + qn;
+    for (int i = 0; i < qn; i++) md[c].dst_off[i] = c * qn + i;
+  }
+  md[1].fin = CONV_FIN_MODDOWN;
+  md[1].fin_off0 = K;
+  TRY(launch_conv(ctx, md, 2, C, c_bs, nullptr, 0, F, f_bs, batch, s));
+  // 3.
+  ConvSpec up[HELRM_MAX_CONV_JOBS];
+  CHECK_ARG(beta <= HELRM_MAX_CONV_JOBS, "modup: at most %d digits", HELRM_MAX_CONV_JOBS);
+  LimbList f = ll_make(0, f_bs, f_bs);
+  NttEpi e;
+  e.a = X;
+  e.out = z;
+  e.c = ctx->moddown_pinv[level];
+  e.inner = 1;
+  e.n_fin = qn;
+  e.a_bs = x_bs;
+  e.out_bs = z_bs;
+  e.dup = z;
+  e.dup_bs = z_bs;
+  for (int i = 0; i < qn; i++) {   // t0 -> z.c0 (finish)
+    f.src_off[f.n] = i;
+    f.dst_off[f.n] = i;
+    f.prime[f.n] = i;
+    e.a_off[i] = i;
+    e.out_off[i] = i;
+    e.dup_off[f.n] = -1;
+    f.n++;
+  }
+  for (int j = 0; j < beta; j++) {
+    const int lo = ctx->digit_lo(j), hi = ctx->digit_hi(j, level);
+    for (int i = lo; i < hi; i++) {   // z1 -> digit j's own limb and z.c1
+      f.src_off[f.n] = qn + i;
+      f.dst_off[f.n] = 2 * qn + j * pqn + i;
+      f.prime[f.n] = i;
+      e.dup_off[f.n] = qn + i;
+      f.n++;
+    }
+  }
+  for (int j = 0; j < beta; j++) {
+    ConvSpec &sp = up[j];
+    sp.t = &ctx->modup_tabs[level][j];
+    const int lo = ctx->digit_lo(j), hi = ctx->digit_hi(j, level);
+    sp.src_off0 = qn + lo;
+    int k = 0;
+    for (int r = 0; r < pqn; r++) {
+      if (r >= lo && r < hi) continue;
+      sp.dst_off[k++] = 2 * qn + j * pqn + r;
+      f.src_off[f.n] = 2 * qn + j * pqn + r;
+      f.dst_off[f.n] = 2 * qn + j * pqn + r;
+      f.prime[f.n] = ctx->pq_prime(r, level);
+      e.dup_off[f.n] = -1;
+      f.n++;
+    }
+  }
+  TRY(launch_conv(ctx, up, beta, F, f_bs, nullptr, 0, F, f_bs, batch, s));
+  // 4.
+  TRY(launch_ntt_epi(ctx, F, F, f, batch, true, s, e));
+  return HELRM_OK;
+}
+
+// A ModDown followed by the rescale by q_level, in coefficient form:
+// NTT^-1 of every limb of X (-> C), one conversion P -> Q_level with both
+// finishes (-> F as [batch][2][level] coefficient limbs), one forward NTT
+// (-> out, [batch][2][level] at batch stride out_bs).
+int do_moddown_rescale(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *out, int out_bs, u64 *F,
+                       u64 *C, int batch, hipStream_t s) {
+  const int K = ctx->K, qn = level + 1, pqn = level + 1 + K;
+  LimbList a = ll_make(2 * pqn, x_bs, 2 * pqn);
+  for (int c = 0; c < 2; c++)
+    for (int i = 0; i < pqn; i++) {
+      a.src_off[c * pqn + i] = c * pqn + i;
+      a.dst_off[c * pqn + i] = c * pqn + i;
+      a.prime[c * pqn + i] = ctx->pq_prime(i, level);
+    }
+  TRY(launch_ntt(ctx, X, C, a, batch, false, s));
+  ConvSpec md[2];
+  for (int c = 0; c < 2; c++) {
+    md[c].t = &ctx->moddown_tabs[level];
+    md[c].src_off0 = c * pqn + qn;
+    md[c].fin = CONV_FIN_RESCALE;
+    md[c].fin_off0 = c * pqn;
+    md[c].qlinv = ctx->rescale_qinv[level];
+    for (int i = 0; i < level; i++) md[c].dst_off[i] = c * level + i;
+  }
+  TRY(launch_conv(ctx, md, 2, C, 2 * pqn, nullptr, 0, F, 2 * level, batch, s));
+  LimbList b = ll_make(2 * level, 2 * level, out_bs);
+  for (int c = 0; c < 2; c++)
+    for (int i = 0; i < level; i++) {
+      b.src_off[c * level + i] = c * level + i;
+      b.dst_off[c * level + i] = c * level + i;
+      b.prime[c * level + i] = i;
+    }
+  TRY(launch_ntt(ctx, F, out, b, batch, true, s));
   return HELRM_OK;
 }
 
@@ -354,8 +492,11 @@ KsSizes ks_sizes(const helrm_ctx *ctx, int level, int batch, int n_pq) {
 
 // ---------------------------------------------------------------- matvec
 
+// F: per batch element [t0: qn][z1: qn][digits: beta][pqn] (do_moddown_modup);
+// the digits of every ModUp of the path live in F at offset 2 qn.
+// C: coefficient-form limbs of a ModDown input ([2][pqn] per element).
 struct MatvecWS {
-  u64 *coef, *D, *Dg, *X, *xg, *acc, *zA, *zB, *mdP, *mdT, *top, *V, *mv;
+  u64 *coef, *F, *C, *Dg, *X, *xg, *acc, *zA, *zB, *mdP, *mdT, *top, *V, *mv;
 };
 
 // Non-zero giant steps of a plan, or of the union of several plans' giants.
@@ -374,7 +515,8 @@ size_t matvec_ws_bytes(const helrm_ctx *ctx, const helrm_plan *p, int batch, boo
   const size_t ng = std::max(ng_union, nonzero_giants(&p, 1));
   size_t tot = 0;
   tot += rnd(B * qn * N);                       // coef
-  tot += rnd(B * beta * pqn * N);               // D
+  tot += rnd(B * (2 * qn + beta * pqn) * N);    // F
+  tot += rnd(B * 2 * pqn * N);                  // C
   tot += rnd(B * std::max<size_t>(ng, 1) * beta * pqn * N);  // Dg
   tot += rnd(B * n2 * 2 * pqn * N);             // X
   tot += rnd(B * n2 * 2 * qn * N);              // xg
@@ -398,7 +540,8 @@ MatvecWS carve_matvec(const helrm_ctx *ctx, const helrm_plan *p, int batch, bool
   Arena a{base};
   MatvecWS w;
   w.coef = a.take(B * qn * N);
-  w.D = a.take(B * beta * pqn * N);
+  w.F = a.take(B * (2 * qn + beta * pqn) * N);
+  w.C = a.take(B * 2 * pqn * N);
   w.Dg = a.take(B * std::max<size_t>(ng, 1) * beta * pqn * N);
   w.X = a.take(B * n2 * 2 * pqn * N);
   w.xg = a.take(B * n2 * 2 * qn * N);
@@ -420,20 +563,26 @@ MatvecWS carve_matvec(const helrm_ctx *ctx, const helrm_plan *p, int batch, bool
 // that share m, n1, n2 and the fold; ciphertext c of batch element b is at
 // ct + (b * ct_bs + 2 (level+1) c) limbs.  Every block's baby-step products
 // go into the same giant accumulators X_g, then ModDown, giant steps and the
-// fold run once.
+// fold run once.  The result (level `level`) goes to out; with rs_out, the
+// rescaled result (level - 1, [batch][2][level]) goes to rs_out.  A ModDown
+// that feeds a ModUp or the rescale runs fused with it in coefficient form
+// (knob fuse_ks).
 int run_matvec(helrm_ctx *ctx, const helrm_plan *const *ps, int n_in, const u64 *ct, int ct_bs, u64 *out,
-               int batch, MatvecWS &w, hipStream_t s) {
+               u64 *rs_out, int batch, MatvecWS &w, hipStream_t s) {
   const helrm_plan *p = ps[0];
   const int N = ctx->N, lv = p->level, qn = lv + 1, pqn = lv + 1 + ctx->K, beta = ctx->n_digits(lv);
   const int n2 = p->n2;
-  const int d_bs = beta * pqn;
+  const int d_bs = beta * pqn;               // Dg: [giant][beta][pqn] per element
+  const int f_bs = 2 * qn + beta * pqn;      // F
+  u64 *const D = w.F + (size_t)2 * qn * N;   // digits in F
   const size_t x_bs = (size_t)n2 * 2 * pqn;  // limbs per batch element of X
+  const bool fuse = ctx->tune_fuse_ks && fused_fits(ctx, lv);
   std::vector<int> giants;
   for (int c = 0; c < n_in; c++) {
     const helrm_plan *pc = ps[c];
     const u64 *ctc = ct + (size_t)c * 2 * qn * N;
     // 1. hoisted ModUp of c1
-    TRY(do_modup(ctx, lv, ctc + (size_t)qn * N, ct_bs, w.D, d_bs, w.coef, batch, s));
+    TRY(do_modup(ctx, lv, ctc + (size_t)qn * N, ct_bs, D, f_bs, w.coef, batch, s));
     // 2. fused baby steps + plaintext MAC, giant outputs in tiles (the first
     //    block writes every tile a later block may add to)
     for (int g0 = 0; g0 < n2; g0 += HELRM_MAX_GTILE) {
@@ -443,67 +592,92 @@ int run_matvec(helrm_ctx *ctx, const helrm_plan *const *ps, int n_in, const u64 
         if (g >= g0 && g < g0 + ng) any = true;
       const bool force = c == 0 && n_in > 1;
       if (!any && !force) continue;
-      TRY(launch_baby_mac(ctx, pc, w.D, (size_t)d_bs * N, ctc, (size_t)ct_bs * N, w.X + (size_t)g0 * 2 * pqn * N,
+      TRY(launch_baby_mac(ctx, pc, D, (size_t)f_bs * N, ctc, (size_t)ct_bs * N, w.X + (size_t)g0 * 2 * pqn * N,
                           x_bs * N, g0, ng, batch, s, c > 0, force));
     }
     for (int g : pc->giants)
       if (std::find(giants.begin(), giants.end(), g) == giants.end()) giants.push_back(g);
   }
   std::sort(giants.begin(), giants.end());
-  // 3. x_g = ModDown(X_g) for every g (batch of batch*n2)
-  TRY(do_moddown(ctx, lv, w.X, 2 * pqn, w.xg, 2 * qn, w.mdP, w.mdT, batch * n2, s));
-  const u64 *z;
   const bool only0 = giants.size() == 1 && giants[0] == 0;
   const bool no_fold = p->stages.empty();
-  u64 *zbuf = w.zA;
-  if (only0) {
+  bool z_digits = false;   // D holds the ModUp of the current z's c1
+  const u64 *z = nullptr;
+  if (only0 && fuse) {
+    // 3. x_0 = ModDown(X_0), fused with what follows it
     if (no_fold) {
-      // copy x_0 to out
-      LimbList cp = ll_make(2 * qn, n2 * 2 * qn, 2 * qn);
-      for (int i = 0; i < 2 * qn; i++) { cp.src_off[i] = i; cp.dst_off[i] = i; cp.prime[i] = 0; }
-      TRY(launch_copy_limbs(w.xg, out, cp, batch, N, s));
-      return HELRM_OK;
+      if (rs_out) {
+        TRY(do_moddown_rescale(ctx, lv, w.X, (int)x_bs, rs_out, 2 * lv, w.F, w.C, batch, s));
+        return HELRM_OK;
+      }
+      return do_moddown(ctx, lv, w.X, (int)x_bs, out, 2 * qn, w.mdP, w.mdT, batch, s);
     }
-    // x_0 is element 0 of every n2-group of xg
-    LimbList cp = ll_make(2 * qn, n2 * 2 * qn, 2 * qn);
-    for (int i = 0; i < 2 * qn; i++) { cp.src_off[i] = i; cp.dst_off[i] = i; cp.prime[i] = 0; }
-    TRY(launch_copy_limbs(w.xg, zbuf, cp, batch, N, s));
-    z = zbuf;
+    TRY(do_moddown_modup(ctx, lv, w.X, (int)x_bs, w.zA, 2 * qn, w.F, f_bs, w.C, batch, s));
+    z = w.zA;
+    z_digits = true;
   } else {
-    // 4. giant rotations by n1 g of x_g (g >= 1), accumulated in PQ with P x_0
-    std::vector<KsTerm> terms;
-    int gi = 0;
-    for (int g : giants) {
-      if (g == 0) continue;
-      const u64 *xgp = w.xg + (size_t)g * 2 * qn * N;
-      u64 *Dg = w.Dg + (size_t)gi * beta * pqn * N;
-      const int ng_ = (int)(giants.size() - (giants[0] == 0 ? 1 : 0));
-      TRY(do_modup(ctx, lv, xgp + (size_t)qn * N, n2 * 2 * qn, Dg, ng_ * d_bs, w.coef, batch, s));
-      KsTerm t;
-      t.digits = Dg;
-      t.c0 = xgp;
-      TRY(key_for(ctx, (long)p->sign * p->n1 * g, &t));
-      terms.push_back(t);
-      gi++;
+    // 3. x_g = ModDown(X_g) for every g (batch of batch*n2)
+    TRY(do_moddown(ctx, lv, w.X, 2 * pqn, w.xg, 2 * qn, w.mdP, w.mdT, batch * n2, s));
+    u64 *zbuf = w.zA;
+    if (only0) {
+      if (no_fold) {
+        // copy x_0 to out
+        LimbList cp = ll_make(2 * qn, n2 * 2 * qn, 2 * qn);
+        for (int i = 0; i < 2 * qn; i++) { cp.src_off[i] = i; cp.dst_off[i] = i; cp.prime[i] = 0; }
+        TRY(launch_copy_limbs(w.xg, out, cp, batch, N, s));
+      } else if (n2 == 1) {
+        // x_0 is element 0 of every n2-group of xg; with one giant step xg
+        // already has the layout of z
+        z = w.xg;
+      } else {
+        LimbList cp = ll_make(2 * qn, n2 * 2 * qn, 2 * qn);
+        for (int i = 0; i < 2 * qn; i++) { cp.src_off[i] = i; cp.dst_off[i] = i; cp.prime[i] = 0; }
+        TRY(launch_copy_limbs(w.xg, zbuf, cp, batch, N, s));
+        z = zbuf;
+      }
+    } else {
+      // 4. giant rotations by n1 g of x_g (g >= 1), accumulated in PQ with P x_0
+      std::vector<KsTerm> terms;
+      int gi = 0;
+      for (int g : giants) {
+        if (g == 0) continue;
+        const u64 *xgp = w.xg + (size_t)g * 2 * qn * N;
+        u64 *Dg = w.Dg + (size_t)gi * beta * pqn * N;
+        const int ng_ = (int)(giants.size() - (giants[0] == 0 ? 1 : 0));
+        TRY(do_modup(ctx, lv, xgp + (size_t)qn * N, n2 * 2 * qn, Dg, ng_ * d_bs, w.coef, batch, s));
+        KsTerm t;
+        t.digits = Dg;
+        t.c0 = xgp;
+        TRY(key_for(ctx, (long)p->sign * p->n1 * g, &t));
+        terms.push_back(t);
+        gi++;
+      }
+      const int ng_ = gi;
+      const bool has0 = giants[0] == 0;
+      TRY(launch_ks_accumulate(ctx, lv, terms.data(), (int)terms.size(), (size_t)ng_ * d_bs * N,
+                               (size_t)n2 * 2 * qn * N, has0 ? w.xg : nullptr, (size_t)n2 * 2 * qn * N, w.acc,
+                               (size_t)2 * pqn * N, batch, s));
+      if (no_fold && fuse && rs_out) {
+        TRY(do_moddown_rescale(ctx, lv, w.acc, 2 * pqn, rs_out, 2 * lv, w.F, w.C, batch, s));
+        return HELRM_OK;
+      }
+      if (!no_fold && fuse) {
+        TRY(do_moddown_modup(ctx, lv, w.acc, 2 * pqn, zbuf, 2 * qn, w.F, f_bs, w.C, batch, s));
+        z_digits = true;
+      } else {
+        TRY(do_moddown(ctx, lv, w.acc, 2 * pqn, no_fold ? out : zbuf, 2 * qn, w.mdP, w.mdT, batch, s));
+      }
+      z = zbuf;
     }
-    const int ng_ = gi;
-    const bool has0 = giants[0] == 0;
-    TRY(launch_ks_accumulate(ctx, lv, terms.data(), (int)terms.size(), (size_t)ng_ * d_bs * N,
-                             (size_t)n2 * 2 * qn * N, has0 ? w.xg : nullptr, (size_t)n2 * 2 * qn * N, w.acc,
-                             (size_t)2 * pqn * N, batch, s));
-    u64 *dst = no_fold ? out : zbuf;
-    TRY(do_moddown(ctx, lv, w.acc, 2 * pqn, dst, 2 * qn, w.mdP, w.mdT, batch, s));
-    if (no_fold) return HELRM_OK;
-    z = zbuf;
   }
   // 5. fold stages
   for (size_t si = 0; si < p->stages.size(); si++) {
     const int st = p->stages[si].first, r = p->stages[si].second;
-    TRY(do_modup(ctx, lv, z + (size_t)qn * N, 2 * qn, w.D, d_bs, w.coef, batch, s));
+    if (!z_digits) TRY(do_modup(ctx, lv, z + (size_t)qn * N, 2 * qn, D, f_bs, w.coef, batch, s));
     std::vector<KsTerm> terms;
     for (int t = 1; t < r; t++) {
       KsTerm k;
-      k.digits = w.D;
+      k.digits = D;
       k.c0 = z;
       TRY(key_for(ctx, (long)t * st, &k));
       terms.push_back(k);
@@ -512,13 +686,24 @@ int run_matvec(helrm_ctx *ctx, const helrm_plan *const *ps, int n_in, const u64 
       set_error("fold radix above %d is not supported", HELRM_MAX_TERMS + 1);
       return HELRM_EINVAL;
     }
-    TRY(launch_ks_accumulate(ctx, lv, terms.data(), (int)terms.size(), (size_t)d_bs * N, (size_t)2 * qn * N,
+    TRY(launch_ks_accumulate(ctx, lv, terms.data(), (int)terms.size(), (size_t)f_bs * N, (size_t)2 * qn * N,
                              z, (size_t)2 * qn * N, w.acc, (size_t)2 * pqn * N, batch, s));
     const bool last = si + 1 == p->stages.size();
+    if (last && fuse && rs_out) {
+      TRY(do_moddown_rescale(ctx, lv, w.acc, 2 * pqn, rs_out, 2 * lv, w.F, w.C, batch, s));
+      return HELRM_OK;
+    }
     u64 *dst = last ? out : (z == w.zA ? w.zB : w.zA);
-    TRY(do_moddown(ctx, lv, w.acc, 2 * pqn, dst, 2 * qn, w.mdP, w.mdT, batch, s));
+    if (!last && fuse) {
+      TRY(do_moddown_modup(ctx, lv, w.acc, 2 * pqn, dst, 2 * qn, w.F, f_bs, w.C, batch, s));
+      z_digits = true;
+    } else {
+      TRY(do_moddown(ctx, lv, w.acc, 2 * pqn, dst, 2 * qn, w.mdP, w.mdT, batch, s));
+      z_digits = false;
+    }
     z = dst;
   }
+  if (rs_out) TRY(do_rescale(ctx, lv, out, 2 * qn, rs_out, 2 * lv, w.top, w.V, batch, s));
   return HELRM_OK;
 }
 
@@ -1145,7 +1330,7 @@ extern "C" int helrm_ptxt_ct_matvec_diag(helrm_ctx *c, const helrm_plan *p, cons
   char *base;
   TRY(ensure_ws(c, s, matvec_ws_bytes(c, p, batch, false), &base));
   MatvecWS w = carve_matvec(c, p, batch, false, base);
-  return run_matvec(c, &p, 1, ct, 2 * (p->level + 1), out, batch, w, s);
+  return run_matvec(c, &p, 1, ct, 2 * (p->level + 1), out, nullptr, batch, w, s);
   API_GUARD_END
 }
 
@@ -1161,9 +1346,7 @@ extern "C" int helrm_lookup_packed(helrm_ctx *c, const helrm_plan *p, const uint
   char *base;
   TRY(ensure_ws(c, s, matvec_ws_bytes(c, p, batch, true), &base));
   MatvecWS w = carve_matvec(c, p, batch, true, base);
-  TRY(run_matvec(c, &p, 1, sel, 2 * (p->level + 1), w.mv, batch, w, s));
-  const int lv = p->level;
-  return do_rescale(c, lv, w.mv, 2 * (lv + 1), out, 2 * lv, w.top, w.V, batch, s);
+  return run_matvec(c, &p, 1, sel, 2 * (p->level + 1), w.mv, out, batch, w, s);
   API_GUARD_END
 }
 
@@ -1189,8 +1372,7 @@ extern "C" int helrm_lookup_multi(helrm_ctx *c, const helrm_plan *const *plans, 
   TRY(ensure_ws(c, s, matvec_ws_bytes(c, p, batch, true, ngu), &base));
   MatvecWS w = carve_matvec(c, p, batch, true, base, ngu);
   const int lv = p->level;
-  TRY(run_matvec(c, plans, n_in, sel, n_in * 2 * (lv + 1), w.mv, batch, w, s));
-  return do_rescale(c, lv, w.mv, 2 * (lv + 1), out, 2 * lv, w.top, w.V, batch, s);
+  return run_matvec(c, plans, n_in, sel, n_in * 2 * (lv + 1), w.mv, out, batch, w, s);
   API_GUARD_END
 }
 
@@ -1266,6 +1448,12 @@ extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
   } else if (strcmp(knob, "gen_key_a") == 0) {
     CHECK_ARG(value == 0 || value == 1, "gen_key_a must be 0 or 1");
     c->tune_gen_key_a = value;
+  } else if (strcmp(knob, "fuse_ks") == 0) {
+    CHECK_ARG(value == 0 || value == 1, "fuse_ks must be 0 or 1");
+    c->tune_fuse_ks = value;
+  } else if (strcmp(knob, "conv_wgs") == 0) {
+    CHECK_ARG(value >= 0, "conv_wgs must be >= 0");
+    c->tune_conv_wgs = value;
   } else if (strcmp(knob, "baby_share") == 0) {
     CHECK_ARG(value == 1 || value == 2 || value == 4 || value == 8, "baby_share must be 1, 2, 4 or 8");
     c->tune_baby_share = value;

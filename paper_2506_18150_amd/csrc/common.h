@@ -196,7 +196,7 @@ struct PrimeInfo {
   u64 ninv, ninv_p;    // N^-1 mod q with its Shoup companion
   u64 pmod, pmod_p;    // [P]_q with Shoup companion (P = product of special primes)
   u64 pinv, pinv_p;    // [P^-1]_q (Q primes only)
-  double qd, qinv_d;   // q and 1/q as doubles (fp64 NTT path, q < 2^45)
+  double qd, qinv_d;   // q and 1/q as doubles (fp64 NTT path, q < 2^41)
   double ninv_d;       // N^-1 mod q as a double
 };
 
@@ -223,7 +223,7 @@ struct LimbList {
   int dst_bstride;   // in limbs
   int src_off[HELRM_MAX_LIMBS];
   int dst_off[HELRM_MAX_LIMBS];
-  unsigned char prime[HELRM_MAX_LIMBS];
+  int prime[HELRM_MAX_LIMBS];        // int, not byte: a uniform index reads it with a scalar load
 };
 
 // Fast base conversion for one (level, digit) or the ModDown of one level.
@@ -293,6 +293,8 @@ struct helrm_ctx {
   int tune_ntt_col_w = 16;   // NTT column-pass columns per workgroup (8, 16; 0 = by launch size)
   int tune_ntt_blk_w = 4;    // NTT block-pass blocks per workgroup (4, 8; 0 = by launch size)
   int ntt_small_limbs = 48;  // launches of fewer limbs take the narrow shapes when a width is 0
+  int tune_fuse_ks = 1;       // ModDown fused with the ModUp or rescale that follows it (0 = off)
+  int tune_conv_wgs = 2048;  // base conversion: split outputs into chunks until a launch has this many workgroups (0 = off)
   int tune_gen_key_a = 1;    // regenerate keys' a_j halves from their seeds: 0 never, 1 where a kernel
                              // serves one ciphertext per thread and streams keys (default)
   bool timing = false;
@@ -355,18 +357,24 @@ struct KTimer {
 
 #define HELRM_MAX_EPI 64
 
-// Fused finish of a forward NTT: instead of storing y = NTT(x), store
-// out = (a - y) * c[i] for list entry i.  The transform's batch index splits
-// into (outer, inner) = (bat / inner, bat % inner); a and out limbs live at
-// outer * bs + inner * cs + off[i].
+// Fused finish of a forward NTT: for list entries i < n_fin, instead of
+// storing y = NTT(x), store out = (a - y) * c[i].  The transform's batch index
+// splits into (outer, inner) = (bat / inner, bat % inner); a and out limbs
+// live at outer * bs + inner * cs + off[i].  Entries i >= n_fin store y as
+// usual and, where dup_off[i] >= 0, also at limb dup_off[i] of dup (batch
+// stride dup_bs limbs).
 struct NttEpi {
   const u64 *a = nullptr;
   u64 *out = nullptr;
   const TW *c = nullptr;
   int inner = 1;
+  int n_fin = 0;
   int a_bs = 0, a_cs = 0, out_bs = 0, out_cs = 0;
   int a_off[HELRM_MAX_EPI] = {};
   int out_off[HELRM_MAX_EPI] = {};
+  u64 *dup = nullptr;
+  int dup_bs = 0;
+  int dup_off[HELRM_MAX_LIMBS];
 };
 
 // NTT of the limbs in `ll` (src -> dst, may be in place).
@@ -389,13 +397,23 @@ int launch_copy_limbs(const u64 *src, u64 *dst, const LimbList &ll, int batch, i
 // One fast base conversion (coefficient form) of a launch: inputs are the
 // consecutive limbs src_off0.. of src, outputs go to dst_off[r]; ncopy limbs
 // are copied unchanged from copy_src (evaluation-form own limbs of a digit).
+// Finish of a P -> Q_l conversion done in coefficient form (ConvSpec::fin).
+enum { CONV_FIN_NONE = 0, CONV_FIN_MODDOWN = 1, CONV_FIN_RESCALE = 2 };
+
 struct ConvSpec {
   const ConvTable *t;
   int src_off0;
   int dst_off[HELRM_MAX_PRIMES];
-  int ncopy;
+  int ncopy = 0;
   int copy_src_off[16];
   int copy_dst_off[16];
+  // CONV_FIN_MODDOWN: out_r = (A_r - conv_r) P^-1 mod q_r with A_r limb
+  // fin_off0 + r of the source.  CONV_FIN_RESCALE: the same for every output,
+  // then the rescale by the last output prime q_l; writes l outputs (qlinv:
+  // q_l^-1 mod q_r, r < l).
+  int fin = CONV_FIN_NONE;
+  int fin_off0 = 0;
+  const TW *qlinv = nullptr;
 };
 int launch_conv(helrm_ctx *ctx, const ConvSpec *specs, int nspecs, const u64 *src, int src_bstride,
                 const u64 *copy_src, int copy_bstride, u64 *dst, int dst_bstride, int batch, hipStream_t s);

@@ -124,6 +124,9 @@ struct ConvJob {
   int ncopy;
   int copy_src_off[16];
   int copy_dst_off[16];
+  int fin;            // CONV_FIN_* (ConvSpec)
+  int fin_off0;       // A_r is limb fin_off0 + r of src
+  const TW *qlinv;    // CONV_FIN_RESCALE: q_l^-1 mod q_r for r < l
 };
 
 struct ConvJobs {
@@ -135,40 +138,90 @@ struct ConvJobs {
 constexpr int CONV_TPB = 256;
 
 // y_i = x_i (Qin/q_i)^-1 mod q_i;  out_r = sum_i y_i [Qin/q_i]_r mod r.
-// One thread per coefficient computes every output, so each input residue
-// is read once; the [NIN][nout] constant matrix is staged in LDS and read as
-// broadcasts.  Grid: (N/CONV_TPB, 1, batch * njobs).
+// A thread owns one coefficient and one chunk of the outputs (J.nchunks
+// chunks per job; the copies are dealt round-robin over the chunks).  Small
+// launches (batch 1: a few hundred coefficient blocks) split the outputs so
+// every SIMD holds several waves; each chunk re-reads the NIN inputs, which
+// the neighbouring workgroups of the same coefficient block (consecutive
+// block indices) find in L2.  The [NIN][nout] constant matrix is staged in
+// LDS and read as broadcasts.  Grid: (N/CONV_TPB * nchunks, 1, batch * njobs).
+//
+// With a finish (ModDown in coefficient form, the conversion being P -> Q_l)
+// output r becomes z_r = (A_r - out_r) P^-1 mod q_r, A_r the coefficient-form
+// Q limb of the input; with the rescale as well, every chunk also forms the
+// top output z_l and writes (z_r - [t - h]_{q_r}) q_l^-1 for r < l, where
+// t = (z_l + h) mod q_l and h = floor(q_l / 2) (rounding division by q_l).
 template <int NIN>
 __global__ __launch_bounds__(CONV_TPB) void conv_kernel(const ConvJobs J, const u64 *src, int src_bstride,
                                                         const u64 *copy_src, int copy_bstride, u64 *dst,
                                                         int dst_bstride, const PrimeInfo *pinfo, int N) {
   __shared__ u64 cm[NIN * HELRM_MAX_PRIMES];
-  __shared__ u64 oq[HELRM_MAX_PRIMES], oqn[HELRM_MAX_PRIMES];
-  const int x = blockIdx.x * CONV_TPB + threadIdx.x;
+  __shared__ u64 oq[HELRM_MAX_PRIMES], oqn[HELRM_MAX_PRIMES], opi[HELRM_MAX_PRIMES], opp[HELRM_MAX_PRIMES],
+      omu[HELRM_MAX_PRIMES];
+  const int chunk = blockIdx.x % J.nchunks;
+  const int x = (blockIdx.x / J.nchunks) * CONV_TPB + threadIdx.x;
   const int job = blockIdx.z % J.njobs, bat = blockIdx.z / J.njobs;
   const ConvJob &jb = J.j[job];
   const int nout = jb.t.nout;
+  const int fin = jb.fin;
+  const int nw = fin == CONV_FIN_RESCALE ? nout - 1 : nout;   // outputs written
+  const int per = (nw + J.nchunks - 1) / J.nchunks;
+  const int r0 = chunk * per, r1 = min(nw, r0 + per);
   for (int k = threadIdx.x; k < NIN * nout; k += CONV_TPB) cm[k] = jb.t.hat_mont[k];
   for (int k = threadIdx.x; k < nout; k += CONV_TPB) {
-    oq[k] = pinfo[jb.t.out_prime[k]].q;
-    oqn[k] = pinfo[jb.t.out_prime[k]].qn;
+    const PrimeInfo &po = pinfo[jb.t.out_prime[k]];
+    oq[k] = po.q;
+    oqn[k] = po.qn;
+    opi[k] = po.pinv;
+    opp[k] = po.pinv_p;
+    omu[k] = po.mu;
   }
   u64 y[NIN];
+  if (r0 < r1) {
 #pragma unroll
-  for (int i = 0; i < NIN; i++) {
-    const u64 q = pinfo[jb.t.in_prime[i]].q;
-    const u64 v = src[limb_ptr(bat, src_bstride, jb.src_off0 + i, N) + x];
-    y[i] = shoup(v, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, q);
+    for (int i = 0; i < NIN; i++) {
+      const u64 q = pinfo[jb.t.in_prime[i]].q;
+      const u64 v = src[limb_ptr(bat, src_bstride, jb.src_off0 + i, N) + x];
+      y[i] = shoup(v, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, q);
+    }
   }
   __syncthreads();
-  for (int r = 0; r < nout; r++) {
+  // converted (and finished) output r
+  auto outv = [&](int r) -> u64 {
     Acc a;
     acc_zero(a);
 #pragma unroll
     for (int i = 0; i < NIN; i++) acc_mac(a, y[i], cm[i * nout + r]);
-    dst[limb_ptr(bat, dst_bstride, jb.dst_off[r], N) + x] = redc_acc(a, oq[r], oqn[r]);
+    u64 v = redc_acc(a, oq[r], oqn[r]);
+    if (fin != CONV_FIN_NONE) {
+      const u64 A = src[limb_ptr(bat, src_bstride, jb.fin_off0 + r, N) + x];
+      v = shoup(sub_mod(A, v, oq[r]), opi[r], opp[r], oq[r]);
+    }
+    return v;
+  };
+  if (fin == CONV_FIN_RESCALE) {
+    if (r0 < r1) {
+      const int top = nout - 1;
+      const u64 ql = oq[top], h = ql >> 1;
+      u64 t = outv(top) + h;
+      t = t >= ql ? t - ql : t;
+      for (int r = r0; r < r1; r++) {
+        const u64 q = oq[r];
+        u64 sp;
+        if (t >= h) {
+          sp = reduce64(t - h, q, omu[r]);
+        } else {
+          sp = reduce64(h - t, q, omu[r]);
+          sp = sp == 0 ? 0 : q - sp;
+        }
+        const TW c = jb.qlinv[r];
+        dst[limb_ptr(bat, dst_bstride, jb.dst_off[r], N) + x] = shoup(sub_mod(outv(r), sp, q), c.w, c.wp, q);
+      }
+    }
+  } else {
+    for (int r = r0; r < r1; r++) dst[limb_ptr(bat, dst_bstride, jb.dst_off[r], N) + x] = outv(r);
   }
-  for (int c = 0; c < jb.ncopy; c++)
+  for (int c = chunk; c < jb.ncopy; c += J.nchunks)
     dst[limb_ptr(bat, dst_bstride, jb.copy_dst_off[c], N) + x] =
         copy_src[limb_ptr(bat, copy_bstride, jb.copy_src_off[c], N) + x];
 }
@@ -865,10 +918,23 @@ int launch_conv(helrm_ctx *ctx, const ConvSpec *specs, int nspecs, const u64 *sr
         jb.copy_src_off[c] = sp.copy_src_off[c];
         jb.copy_dst_off[c] = sp.copy_dst_off[c];
       }
-      words += sp.t->nin + sp.t->nout + 2.0 * sp.ncopy;
+      jb.fin = sp.fin;
+      jb.fin_off0 = sp.fin_off0;
+      jb.qlinv = sp.qlinv;
+      const int nw = sp.fin == CONV_FIN_RESCALE ? sp.t->nout - 1 : sp.t->nout;
+      words += sp.t->nin + nw + 2.0 * sp.ncopy + (sp.fin != CONV_FIN_NONE ? sp.t->nout : 0);
       macs += (double)sp.t->nin * sp.t->nout;
     }
-    dim3 grid(ctx->N / CONV_TPB, 1, batch * J.njobs);
+    // output chunks: enough workgroups for several waves per SIMD, at least
+    // four outputs per chunk
+    int minout = HELRM_MAX_PRIMES;
+    for (int k = 0; k < J.njobs; k++)
+      minout = std::min(minout, J.j[k].t.nout - (J.j[k].fin == CONV_FIN_RESCALE ? 1 : 0));
+    const long base = (long)(ctx->N / CONV_TPB) * batch * J.njobs;
+    if (ctx->tune_conv_wgs > 0 && base < ctx->tune_conv_wgs)
+      J.nchunks = (int)std::max(1L, std::min((long)std::max(1, minout / 4),
+                                             (ctx->tune_conv_wgs + base - 1) / base));
+    dim3 grid(ctx->N / CONV_TPB * J.nchunks, 1, batch * J.njobs);
     KTimer tm(ctx, s);
 #define CONV(NIN_)                                                                                    \
   hipLaunchKernelGGL((conv_kernel<NIN_>), grid, dim3(CONV_TPB), 0, s, J, src, src_bstride, copy_src,  \

@@ -13,10 +13,11 @@
 // the residues through LDS (swizzled against bank conflicts) and the thread
 // runs the other H stages.  Global loads and stores are coalesced: in the
 // column pass consecutive lanes own consecutive columns, in the block pass
-// consecutive lanes own consecutive elements.  Butterflies are Harvey's lazy
-// ones (values in [0,4q) forward, [0,2q) inverse) with Shoup twiddle
-// products for 60-bit primes and exact fp64 products for primes below 2^45;
-// only the last pass reduces to [0,q).
+// consecutive lanes own consecutive elements.  Primes of 41 bits and more
+// take Harvey's lazy integer butterflies with Shoup twiddle products; smaller
+// primes take signed fp64 butterflies with exact products and no reductions
+// inside a pass (the policies below state the bounds).  Only the last pass
+// reduces to [0,q); between the passes the lazy values go through HBM.
 #include "common.h"
 
 namespace {
@@ -68,24 +69,39 @@ __device__ __forceinline__ int col_idx(int w, int r) {
 
 // ---------------------------------------------------------------- arithmetic policies
 //
-// IntA: residues as uint64 with Shoup twiddle products (any prime < 2^61).
-// FltA: residues as fp64 for primes below 2^45, where every lazy value
-// (< 4q < 2^47) and every twiddle is an exact double.  a*w mod q is computed
-// exactly: h = fl(a w) and l = fma(a, w, -h) give a w = h + l exactly; the
-// quotient estimate qq = floor(h * (1/q)) is off by at most one, so
-// r = fma(-qq, q, h) + l (both steps exact) lies in (-q, 2q) and one
-// correction brings it to [0, 2q).  fp64 FMA runs at full rate on gfx950,
-// four times the rate of the 32-bit integer multiplies the Shoup product needs.
+// IntA: residues as uint64 with Shoup twiddle products (any prime < 2^61):
+// Harvey's lazy butterflies, values in [0, 4q) forward and [0, 2q) inverse.
+//
+// FltA: residues as signed fp64 for primes below 2^41 (FLT_LIMIT).  The
+// product a*w mod q is formed exactly: h = fl(a w) and l = fma(a, w, -h) give
+// a w = h + l; qq = floor(h / q) (through the rounded reciprocal) is within
+// one of floor(a w / q) while |a w / q| < 2^49; then fma(-qq, q, h) is the
+// exact integer a w - qq q - l (its magnitude is below 2^53) and adding l
+// gives r = a w - qq q exactly, with r in (-q, 2q).  No butterfly reduces or
+// compares: a forward (Cooley-Tukey) stage adds at most 2q to the largest
+// magnitude (x +- r), so 16 stages from [0, q) stay below 33q < 2^47; an
+// inverse (Gentleman-Sande) stage at most doubles it (x + y), so each pass
+// of 8 stages stays below 2^8 q < 2^49 and the first inverse pass ends with
+// one floor reduction to [0, q].  The last step maps to [0, q) with
+// r = v - q floor(v / q) (the quotient is exact for |v| < 2^50: its error is
+// below 2^-44 < 1/q, except at exact multiples, where r may come out as q)
+// and one conditional subtraction.  The intermediate between the two passes
+// is stored as raw fp64 bits; fp64 FMA runs at the full VALU rate on gfx950.
+
+constexpr u64 FLT_LIMIT = 1ull << 41;
 
 struct IntA {
   using V = u64;
+  using T = TW;
   u64 q, q2;
   const TW *tw;
   __device__ __forceinline__ V load(u64 x) const { return x; }
   __device__ __forceinline__ u64 bits(V v) const { return v; }
   __device__ __forceinline__ V unbits(u64 b) const { return b; }
-  __device__ __forceinline__ void ct(V &x, V &y, int idx) const { ct_bfly(x, y, tw[idx], q, q2); }
-  __device__ __forceinline__ void gs(V &x, V &y, int idx) const { gs_bfly(x, y, tw[idx], q, q2); }
+  // value stored between the passes (lazy)
+  __device__ __forceinline__ u64 mid(V v, bool) const { return v; }
+  __device__ __forceinline__ void ct(V &x, V &y, const T &t) const { ct_bfly(x, y, t, q, q2); }
+  __device__ __forceinline__ void gs(V &x, V &y, const T &t) const { gs_bfly(x, y, t, q, q2); }
   // [0, 4q) -> [0, q)
   __device__ __forceinline__ u64 canon(V v) const {
     v = v >= q2 ? v - q2 : v;
@@ -96,98 +112,110 @@ struct IntA {
 
 struct FltA {
   using V = double;
-  double q, q2, qinv;
+  using T = double;
+  double q, qinv;
   const double *tw;
-  __device__ __forceinline__ V load(u64 x) const { return (double)x; }
+  // 0 <= x < 2^52: x in the mantissa of 2^52, minus 2^52
+  __device__ __forceinline__ V load(u64 x) const {
+    return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 4503599627370496.0;
+  }
   __device__ __forceinline__ u64 bits(V v) const { return (u64)__double_as_longlong(v); }
   __device__ __forceinline__ V unbits(u64 b) const { return __longlong_as_double((long long)b); }
-  // a * w mod q in [0, 2q) for 0 <= a < 4q, 0 <= w < q
+  // a w - qq q in (-q, 2q) for |a w / q| < 2^49
   __device__ __forceinline__ double mm(double a, double w) const {
 #pragma clang fp contract(off)
     const double h = a * w;
     const double l = __fma_rn(a, w, -h);
     const double qq = floor(h * qinv);
-    double r = __fma_rn(-qq, q, h) + l;
-    return r < 0.0 ? r + q : r;
+    return __fma_rn(-qq, q, h) + l;
   }
-  __device__ __forceinline__ void ct(V &x, V &y, int idx) const {
+  // |v| < 2^50 -> [0, q]
+  __device__ __forceinline__ double reduce(double v) const {
 #pragma clang fp contract(off)
-    const double X = x >= q2 ? x - q2 : x;
-    const double T = mm(y, tw[idx]);
-    x = X + T;
-    y = (X - T) + q2;
+    return __fma_rn(-floor(v * qinv), q, v);
   }
-  __device__ __forceinline__ void gs(V &x, V &y, int idx) const {
+  __device__ __forceinline__ u64 mid(V v, bool fwd) const { return bits(fwd ? v : reduce(v)); }
+  __device__ __forceinline__ void ct(V &x, V &y, T t) const {
 #pragma clang fp contract(off)
-    double S = x + y;
-    S = S >= q2 ? S - q2 : S;
-    const double D = (x - y) + q2;
+    const double r = mm(y, t);
+    const double X = x;
+    x = X + r;
+    y = X - r;
+  }
+  __device__ __forceinline__ void gs(V &x, V &y, T t) const {
+#pragma clang fp contract(off)
+    const double S = x + y;
+    const double D = x - y;
     x = S;
-    y = mm(D, tw[idx]);
+    y = mm(D, t);
   }
+  // [0, q) as an integer: r + 2^52 has r in its low mantissa bits
   __device__ __forceinline__ u64 canon(V v) const {
-    v = v >= q2 ? v - q2 : v;
-    v = v >= q ? v - q : v;
-    return (u64)v;
+#pragma clang fp contract(off)
+    double r = reduce(v);
+    r = r >= q ? r - q : r;
+    return (u64)__double_as_longlong(r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
   }
-  __device__ __forceinline__ u64 scale(V v, const PrimeInfo &pi) const {
-    double r = mm(v, pi.ninv_d);
-    return (u64)(r >= q ? r - q : r);
-  }
+  __device__ __forceinline__ u64 scale(V v, const PrimeInfo &pi) const { return canon(mm(v, pi.ninv_d)); }
 };
 
-// Forward stages on x[] in the "A" layout (element u + E k): global stage
-// multiplier m = E/(2h), twiddle index m f + k/(2h).
+// Twiddles of one register phase.  Stage h (pairs k, k+h) uses m = E/(2h)
+// consecutive table entries; in the "A" layout (element u + E k of the
+// sub-transform) they start at m f, in the "B" layout (element E u + k) at
+// m (E f + u).  Entry j = k/(2h) is read when the stage runs.
+template <class A>
+struct TwSrc {
+  const typename A::T *tw;
+  int base;   // f ("A" layout) or E f + u ("B" layout)
+  __device__ __forceinline__ typename A::T operator()(int m, int j) const { return tw[m * base + j]; }
+};
+
+// H forward (Cooley-Tukey) stages on the E registers, h = E/2 .. 1.
 template <int H, class A>
-__device__ __forceinline__ void fwd_phase_a(typename A::V (&x)[1 << H], const A &ar, int f) {
+__device__ __forceinline__ void fwd_phase(typename A::V (&x)[1 << H], const A &ar, const TwSrc<A> &t) {
   constexpr int E = 1 << H;
 #pragma unroll
   for (int h = E / 2; h >= 1; h >>= 1) {
 #pragma unroll
     for (int k = 0; k < E; k++)
-      if ((k & h) == 0) ar.ct(x[k], x[k + h], (E / (2 * h)) * f + k / (2 * h));
+      if ((k & h) == 0) ar.ct(x[k], x[k + h], t(E / (2 * h), k / (2 * h)));
   }
 }
 
-// Forward stages in the "B" layout (element E u + k): m = R/(2h), twiddle
-// index m f + u E/(2h) + k/(2h).
+// H inverse (Gentleman-Sande) stages, h = 1 .. E/2.
 template <int H, class A>
-__device__ __forceinline__ void fwd_phase_b(typename A::V (&x)[1 << H], const A &ar, int f, int u) {
-  constexpr int E = 1 << H, R = E * E;
-#pragma unroll
-  for (int h = E / 2; h >= 1; h >>= 1) {
-#pragma unroll
-    for (int k = 0; k < E; k++)
-      if ((k & h) == 0) ar.ct(x[k], x[k + h], (R / (2 * h)) * f + u * (E / (2 * h)) + k / (2 * h));
-  }
-}
-
-template <int H, class A>
-__device__ __forceinline__ void inv_phase_b(typename A::V (&x)[1 << H], const A &ar, int f, int u) {
-  constexpr int E = 1 << H, R = E * E;
-#pragma unroll
-  for (int h = 1; h <= E / 2; h <<= 1) {
-#pragma unroll
-    for (int k = 0; k < E; k++)
-      if ((k & h) == 0) ar.gs(x[k], x[k + h], (R / (2 * h)) * f + u * (E / (2 * h)) + k / (2 * h));
-  }
-}
-
-template <int H, class A>
-__device__ __forceinline__ void inv_phase_a(typename A::V (&x)[1 << H], const A &ar, int f) {
+__device__ __forceinline__ void inv_phase(typename A::V (&x)[1 << H], const A &ar, const TwSrc<A> &t) {
   constexpr int E = 1 << H;
 #pragma unroll
   for (int h = 1; h <= E / 2; h <<= 1) {
 #pragma unroll
     for (int k = 0; k < E; k++)
-      if ((k & h) == 0) ar.gs(x[k], x[k + h], (E / (2 * h)) * f + k / (2 * h));
+      if ((k & h) == 0) ar.gs(x[k], x[k + h], t(E / (2 * h), k / (2 * h)));
   }
 }
 
-// The body of one pass for one arithmetic policy.
+// Global index (within the limb) of register k of this thread for the pass's
+// input; the data words are loaded before the prime is known.
+template <int H, bool FWD, bool COLS, int WS>
+__device__ __forceinline__ int in_index(int part, int k) {
+  using S = Shape<H, COLS, WS>;
+  constexpr int E = S::E, R = S::R, W = S::W;
+  const int tid = threadIdx.x;
+  if (COLS) {
+    const int w = tid % W, u = tid / W;
+    const int c = part * W + w;
+    return FWD ? c + R * (u + E * k) : c + R * (E * u + k);
+  }
+  const int u = tid % E, w = tid / E;
+  return R * (part * W + w) + u + E * k;
+}
+
+// The body of one pass for one arithmetic policy; raw[] holds the thread's
+// input words (canonical residues for a first pass, the lazy intermediate
+// for a second pass).
 template <int H, bool FWD, bool COLS, int WS, class A>
-__device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 *in, u64 *out, int part, int bat,
-                                          int li, const PrimeInfo &pi, const NttEpi &epi) {
+__device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 (&raw)[1 << H], u64 *out, int part,
+                                          int bat, int li, const PrimeInfo &pi, const NttEpi &epi) {
   using S = Shape<H, COLS, WS>;
   constexpr int E = S::E, R = S::R, N = S::N, W = S::W;
   using V = typename A::V;
@@ -198,29 +226,31 @@ __device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 *in, 
     const int c = part * W + w;
     if (FWD) {
       // first forward pass: stages m = 1 .. R/2 on column c
+      const TwSrc<A> t1{ar.tw, 1}, t2{ar.tw, E + u};
 #pragma unroll
-      for (int k = 0; k < E; k++) x[k] = ar.load(in[c + R * (u + E * k)]);
-      fwd_phase_a<H>(x, ar, 1);
+      for (int k = 0; k < E; k++) x[k] = ar.load(raw[k]);
+      fwd_phase<H>(x, ar, t1);
 #pragma unroll
       for (int k = 0; k < E; k++) lds[col_idx<H, W>(w, u + E * k)] = ar.bits(x[k]);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[col_idx<H, W>(w, E * u + k)]);
-      fwd_phase_b<H>(x, ar, 1, u);
-      // lazy values in [0, 4q) go to memory as integers
+      fwd_phase<H>(x, ar, t2);
+      // lazy values go to memory (integers below 4q, or fp64 bits)
 #pragma unroll
-      for (int k = 0; k < E; k++) out[c + R * (E * u + k)] = (u64)x[k];
+      for (int k = 0; k < E; k++) out[c + R * (E * u + k)] = ar.mid(x[k], true);
     } else {
       // last inverse pass: stages m = R/2 .. 1 on column c, then N^-1
+      const TwSrc<A> t1{ar.tw, E + u}, t2{ar.tw, 1};
 #pragma unroll
-      for (int k = 0; k < E; k++) x[k] = ar.load(in[c + R * (E * u + k)]);
-      inv_phase_b<H>(x, ar, 1, u);
+      for (int k = 0; k < E; k++) x[k] = ar.unbits(raw[k]);
+      inv_phase<H>(x, ar, t1);
 #pragma unroll
       for (int k = 0; k < E; k++) lds[col_idx<H, W>(w, E * u + k)] = ar.bits(x[k]);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[col_idx<H, W>(w, u + E * k)]);
-      inv_phase_a<H>(x, ar, 1);
+      inv_phase<H>(x, ar, t2);
 #pragma unroll
       for (int k = 0; k < E; k++) out[c + R * (u + E * k)] = ar.scale(x[k], pi);
     }
@@ -228,24 +258,25 @@ __device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 *in, 
     const int u = tid % E, w = tid / E;
     const int b = part * W + w;
     const int f = R + b;
-    const u64 *ib = in + (size_t)R * b;
     u64 *ob = out + (size_t)R * b;
-#pragma unroll
-    for (int k = 0; k < E; k++) x[k] = ar.load(ib[u + E * k]);
     if (FWD) {
-      fwd_phase_a<H>(x, ar, f);
+      // second forward pass (reads the lazy intermediate)
+      const TwSrc<A> t1{ar.tw, f}, t2{ar.tw, E * f + u};
+#pragma unroll
+      for (int k = 0; k < E; k++) x[k] = ar.unbits(raw[k]);
+      fwd_phase<H>(x, ar, t1);
 #pragma unroll
       for (int k = 0; k < E; k++) lds[blk_idx<H>(w, u + E * k)] = ar.bits(x[k]);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[blk_idx<H>(w, E * u + k)]);
-      fwd_phase_b<H>(x, ar, f, u);
+      fwd_phase<H>(x, ar, t2);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < E; k++) lds[blk_idx<H>(w, E * u + k)] = ar.bits(x[k]);
       __syncthreads();
       const u64 q = pi.q;
-      if (epi.a) {
+      if (epi.a && li < epi.n_fin) {
         // fused finish: out = (a - NTT(x)) * c  (ModDown: c = P^-1, rescale: c = q_l^-1)
         const int bo = bat / epi.inner, bi = bat % epi.inner;
         const u64 *ea = epi.a + ((size_t)bo * epi.a_bs + (size_t)bi * epi.a_cs + epi.a_off[li]) * (size_t)N +
@@ -258,34 +289,46 @@ __device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 *in, 
           const u64 v = ar.canon(ar.unbits(lds[blk_idx<H>(w, u + E * k)]));
           eo[u + E * k] = shoup(sub_mod(ea[u + E * k], v, q), c.w, c.wp, q);
         }
+      } else if (epi.dup && epi.dup_off[li] >= 0) {
+        u64 *db = epi.dup + ((size_t)bat * epi.dup_bs + epi.dup_off[li]) * (size_t)N + (size_t)R * b;
+#pragma unroll
+        for (int k = 0; k < E; k++) {
+          const u64 v = ar.canon(ar.unbits(lds[blk_idx<H>(w, u + E * k)]));
+          ob[u + E * k] = v;
+          db[u + E * k] = v;
+        }
       } else {
 #pragma unroll
         for (int k = 0; k < E; k++) ob[u + E * k] = ar.canon(ar.unbits(lds[blk_idx<H>(w, u + E * k)]));
       }
     } else {
+      // first inverse pass (reads canonical residues)
+      const TwSrc<A> t1{ar.tw, E * f + u}, t2{ar.tw, f};
+#pragma unroll
+      for (int k = 0; k < E; k++) x[k] = ar.load(raw[k]);
 #pragma unroll
       for (int k = 0; k < E; k++) lds[blk_idx<H>(w, u + E * k)] = ar.bits(x[k]);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[blk_idx<H>(w, E * u + k)]);
-      inv_phase_b<H>(x, ar, f, u);
+      inv_phase<H>(x, ar, t1);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < E; k++) lds[blk_idx<H>(w, E * u + k)] = ar.bits(x[k]);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[blk_idx<H>(w, u + E * k)]);
-      inv_phase_a<H>(x, ar, f);
-      // values in [0, 2q) go to memory as integers
+      inv_phase<H>(x, ar, t2);
+      // values go to memory (integers below 2q, or fp64 bits in [0, q])
 #pragma unroll
-      for (int k = 0; k < E; k++) ob[u + E * k] = (u64)x[k];
+      for (int k = 0; k < E; k++) ob[u + E * k] = ar.mid(x[k], false);
     }
   }
 }
 
 // One pass of the transform.  FWD: column pass first (src -> dst), block pass
 // second (in place, final reduction).  INV: block pass first, column pass
-// second (in place, times N^-1).  Primes below 2^45 take the fp64 path.
+// second (in place, times N^-1).  Primes below 2^41 take the fp64 path.
 template <int H, bool FWD, bool COLS, int WS>
 __global__ __launch_bounds__((Shape<H, COLS, WS>::T)) void ntt_pass_kernel(const u64 *src, u64 *dst, LimbList ll,
                                                                          const TW *__restrict__ twtab,
@@ -293,7 +336,7 @@ __global__ __launch_bounds__((Shape<H, COLS, WS>::T)) void ntt_pass_kernel(const
                                                                          const PrimeInfo *__restrict__ pinfo,
                                                                          const NttEpi epi) {
   using S = Shape<H, COLS, WS>;
-  constexpr int N = S::N, WPL = S::WPL;
+  constexpr int E = S::E, N = S::N, WPL = S::WPL;
   __shared__ u64 lds[S::LDS];
   const int limb_lin = blockIdx.x / WPL;
   const int part = blockIdx.x % WPL;
@@ -301,14 +344,18 @@ __global__ __launch_bounds__((Shape<H, COLS, WS>::T)) void ntt_pass_kernel(const
   const int li = limb_lin - bat * ll.n;
   const u64 *in = src + ((size_t)bat * ll.src_bstride + ll.src_off[li]) * (size_t)N;
   u64 *out = dst + ((size_t)bat * ll.dst_bstride + ll.dst_off[li]) * (size_t)N;
+  // the data loads go out first, the prime's constants and twiddles follow
+  u64 raw[E];
+#pragma unroll
+  for (int k = 0; k < E; k++) raw[k] = in[in_index<H, FWD, COLS, WS>(part, k)];
   const int p = ll.prime[li];
   const PrimeInfo pi = pinfo[p];
-  if (pi.q < (1ull << 45)) {
-    FltA ar{pi.qd, 2.0 * pi.qd, pi.qinv_d, twdtab + (size_t)p * N};
-    pass_body<H, FWD, COLS, WS>(ar, lds, in, out, part, bat, li, pi, epi);
+  if (pi.q < FLT_LIMIT) {
+    FltA ar{pi.qd, pi.qinv_d, twdtab + (size_t)p * N};
+    pass_body<H, FWD, COLS, WS>(ar, lds, raw, out, part, bat, li, pi, epi);
   } else {
     IntA ar{pi.q, 2 * pi.q, twtab + (size_t)p * N};
-    pass_body<H, FWD, COLS, WS>(ar, lds, in, out, part, bat, li, pi, epi);
+    pass_body<H, FWD, COLS, WS>(ar, lds, raw, out, part, bat, li, pi, epi);
   }
 }
 
@@ -335,7 +382,7 @@ int launch_ntt_hw(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, 
     tm.lap(TK_NTT_FWD_COL, bytes, ops);
     hipLaunchKernelGGL((ntt_pass_kernel<H, true, false, WB>), dim3(gb), dim3(SB::T), 0, s, dst, dst,
                        second, ctx->d_tw_fwd, ctx->d_twd_fwd, ctx->d_pinfo, epi);
-    tm.lap(TK_NTT_FWD_BLK, epi.a ? bytes * 1.5 : bytes, ops);
+    tm.lap(TK_NTT_FWD_BLK, bytes + (double)epi.n_fin * batch * 8.0 * SC::N, ops);
   } else {
     hipLaunchKernelGGL((ntt_pass_kernel<H, false, false, WB>), dim3(gb), dim3(SB::T), 0, s, src, dst, ll,
                        ctx->d_tw_inv, ctx->d_twd_inv, ctx->d_pinfo, NttEpi{});
@@ -371,8 +418,8 @@ int launch_ntt(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int
 
 int launch_ntt_epi(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int batch, bool forward,
                    hipStream_t s, const NttEpi &epi) {
-  if (epi.a && (!forward || ll.n > HELRM_MAX_EPI)) {
-    set_error("NTT epilogue: forward transforms of at most %d limbs only", HELRM_MAX_EPI);
+  if ((epi.a || epi.dup) && (!forward || epi.n_fin > HELRM_MAX_EPI || epi.n_fin > ll.n)) {
+    set_error("NTT epilogue: forward transforms, finish on at most %d limbs", HELRM_MAX_EPI);
     return HELRM_EINVAL;
   }
   if (ctx->logn == 16) return launch_ntt_h<4>(ctx, src, dst, ll, batch, forward, s, epi);

@@ -283,6 +283,26 @@ def test_lookup_parity_cfg2_full_level(radix, sign, ctx2):
     _check_lookup(ctx2, w, gpu_plan(ctx2, w.plan), [0])
 
 
+@pytest.mark.parametrize("fuse", [1, 0])
+def test_lookup_fused_boundaries(fuse, p1, ctx2):
+    """A ModDown feeding a ModUp or the rescale runs fused with it in
+    coefficient form (fuse_ks=1) or in the plain order (fuse_ks=0): both
+    bit-exact, with giant steps and fold stages (toy ring n1=2, radix 2), with
+    the fold alone (n1=16) and at N=2^16 with giant steps (level 4, sign -1)."""
+    cases = [(p1, W.config1(n_queries=1, n1=2, radix=2)), (p1, W.config1(n_queries=1, n1=16, radix=4)),
+             (None, cfg2_workload(4, 4, 2, sign=-1))]
+    for prm, w in cases:
+        ctx = ctx2 if prm is None else context_for(prm)
+        load_keys(ctx, w.keys)
+        plan = gpu_plan(ctx, w.plan)
+        try:
+            say(f"lookup fuse_ks={fuse} N={w.prm.N} level={w.level} n1={w.plan.n1}")
+            ctx.helrm_set_tuning("fuse_ks", fuse)
+            _check_lookup(ctx, w, plan, [0])
+        finally:
+            ctx.helrm_set_tuning("fuse_ks", 1)
+
+
 def test_lookup_regenerated_key_halves_cfg2(ctx2):
     """Batch 1 regenerates the keys' a_j halves from their seeds; with the
     knob off the kernels read them: both bit-exact against the oracle."""
