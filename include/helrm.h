@@ -298,9 +298,15 @@ int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *o
  * 16) and "ntt_blk_w" (4 or 8, default 4) are the sub-transforms per workgroup
  * of the NTT's column and block passes; 0 picks the narrow shape for launches
  * of fewer than "ntt_small_limbs" limbs (default 48).  Results do not depend
- * on the knobs.  "gen_key_a" (1, default, or 0) lets kernels that use every
- * key word once regenerate seeded keys' a_j halves instead of reading them.
- * "conv_wgs" (>= 0, default 2048): a base conversion launch with fewer
+ * on the knobs.  "gen_key_a" lets kernels that use every key word once
+ * regenerate seeded keys' a_j halves instead of reading them: 0 never, 1
+ * (default) on primes below 2^40 (one generator output per word), 2 on every
+ * prime.
+ * "limb_xcd" (0, default, or 1): the key-switching kernels deal coefficient
+ * blocks over all 8 XCDs, or give each XCD whole limbs (a limb's rotated words
+ * are then re-read from one L2: less HBM traffic, less even load).  "fuse_ks" (1, default, or 0): a
+ * ModDown feeding a ModUp or the rescale runs fused with it in coefficient
+ * form.  "conv_wgs" (>= 0, default 2048): a base conversion launch with fewer
  * workgroups than this splits its outputs into chunks (at least four outputs
  * each) until it has that many; 0 never splits.
  * Errors: HELRM_EINVAL for an unknown knob or value. */

@@ -1446,8 +1446,11 @@ extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
     CHECK_ARG(value >= 0, "ntt_small_limbs must be >= 0");
     c->ntt_small_limbs = value;
   } else if (strcmp(knob, "gen_key_a") == 0) {
-    CHECK_ARG(value == 0 || value == 1, "gen_key_a must be 0 or 1");
+    CHECK_ARG(value >= 0 && value <= 2, "gen_key_a must be 0, 1 or 2");
     c->tune_gen_key_a = value;
+  } else if (strcmp(knob, "limb_xcd") == 0) {
+    CHECK_ARG(value == 0 || value == 1, "limb_xcd must be 0 or 1");
+    c->tune_limb_xcd = value;
   } else if (strcmp(knob, "fuse_ks") == 0) {
     CHECK_ARG(value == 0 || value == 1, "fuse_ks must be 0 or 1");
     c->tune_fuse_ks = value;

@@ -149,6 +149,65 @@ struct SplitMac {
 
 constexpr u64 SPLIT_MAC_LIMIT = 1ull << 40;   // SplitMac needs every residue below this
 
+// Sum of at most 16 products of residues below 2^60 in 30-bit halves:
+// x = x0 + 2^30 x1, y = y0 + 2^30 y1, so x y = x0 y0 + 2^30 (x0 y1 + x1 y0)
+// + 2^60 x1 y1.  Each half-product is one 32x32->64 multiply-add and below
+// 2^60, so the four 64-bit partial sums cannot overflow for 16 terms; the
+// exact sum (the same value a 128-bit accumulator holds) is rebuilt once.
+// Operands are packed as lo | hi << 32.
+__device__ __forceinline__ u64 split30(u64 v) { return (v & 0x3FFFFFFFull) | ((v >> 30) << 32); }
+
+struct Sum30 {
+  u64 s00, s01, s10, s11;
+  __device__ __forceinline__ void zero() { s00 = s01 = s10 = s11 = 0; }
+  __device__ __forceinline__ void mac(u64 x, u64 y) {   // both split30-packed
+    const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32), y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32);
+    s00 += (u64)x0 * y0;
+    s01 += (u64)x0 * y1;
+    s10 += (u64)x1 * y0;
+    s11 += (u64)x1 * y1;
+  }
+  __device__ __forceinline__ Acc value() const {
+    const u128 v = (u128)s00 + ((u128)s01 << 30) + ((u128)s10 << 30) + ((u128)s11 << 60);
+    return Acc{(u64)v, (u64)(v >> 64)};
+  }
+};
+
+// Wide30Mac: WideMac's result for residues below 2^60 at four 32-bit
+// multiply-adds per product: products go into a Sum30, which is folded into
+// the 128-bit total every 16 products (and at the end).  Twelve registers per
+// accumulator, so kernels use it where a thread holds few accumulators.
+struct Wide30Mac {
+  using Op = u64;   // split30-packed
+  Sum30 s;
+  Acc a;
+  int n;
+  static __device__ __forceinline__ Op prep(u64 v) { return split30(v); }
+  __device__ __forceinline__ void zero() {
+    s.zero();
+    acc_zero(a);
+    n = 0;
+  }
+  __device__ __forceinline__ void fold() {
+    const Acc v = s.value();
+    a.lo += v.lo;
+    a.hi += v.hi + (a.lo < v.lo ? 1 : 0);
+    s.zero();
+    n = 0;
+  }
+  __device__ __forceinline__ void mac(Op x, Op y) {
+    s.mac(x, y);
+    if (++n == 16) fold();
+  }
+  __device__ __forceinline__ u64 finish(u64 q, u64 qn) const {
+    const Acc v = s.value();
+    Acc t = a;
+    t.lo += v.lo;
+    t.hi += v.hi + (t.lo < v.lo ? 1 : 0);
+    return redc_acc(t, q, qn);
+  }
+};
+
 __device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) {
   u64 s = a + b;
   return s >= q ? s - q : s;
@@ -293,10 +352,12 @@ struct helrm_ctx {
   int tune_ntt_col_w = 16;   // NTT column-pass columns per workgroup (8, 16; 0 = by launch size)
   int tune_ntt_blk_w = 4;    // NTT block-pass blocks per workgroup (4, 8; 0 = by launch size)
   int ntt_small_limbs = 48;  // launches of fewer limbs take the narrow shapes when a width is 0
+  int tune_limb_xcd = 0;      // key-switching kernels: whole limbs per XCD (1) or blocks dealt over the XCDs (0)
   int tune_fuse_ks = 1;       // ModDown fused with the ModUp or rescale that follows it (0 = off)
   int tune_conv_wgs = 2048;  // base conversion: split outputs into chunks until a launch has this many workgroups (0 = off)
-  int tune_gen_key_a = 1;    // regenerate keys' a_j halves from their seeds: 0 never, 1 where a kernel
-                             // serves one ciphertext per thread and streams keys (default)
+  int tune_gen_key_a = 1;    // regenerate keys' a_j halves from their seeds where a kernel serves one
+                             // ciphertext per thread and streams keys: 0 never, 1 on primes below
+                             // 2^40 (default), 2 on every prime
   bool timing = false;
   std::mutex tmu;
   std::vector<TimingRec> trecs;

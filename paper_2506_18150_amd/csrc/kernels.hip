@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -137,8 +138,9 @@ struct ConvJobs {
 
 constexpr int CONV_TPB = 256;
 
-// y_i = x_i (Qin/q_i)^-1 mod q_i;  out_r = sum_i y_i [Qin/q_i]_r mod r.
-// A thread owns one coefficient and one chunk of the outputs (J.nchunks
+// y_i = x_i (Qin/q_i)^-1 mod q_i;  out_r = sum_i y_i [Qin/q_i]_r mod r, the
+// sum of NIN <= 16 products formed in 30-bit halves (Sum30) and finished by
+// one REDC (the constants are in Montgomery form).  A thread owns one coefficient and one chunk of the outputs (J.nchunks
 // chunks per job; the copies are dealt round-robin over the chunks).  Small
 // launches (batch 1: a few hundred coefficient blocks) split the outputs so
 // every SIMD holds several waves; each chunk re-reads the NIN inputs, which
@@ -167,7 +169,7 @@ __global__ __launch_bounds__(CONV_TPB) void conv_kernel(const ConvJobs J, const 
   const int nw = fin == CONV_FIN_RESCALE ? nout - 1 : nout;   // outputs written
   const int per = (nw + J.nchunks - 1) / J.nchunks;
   const int r0 = chunk * per, r1 = min(nw, r0 + per);
-  for (int k = threadIdx.x; k < NIN * nout; k += CONV_TPB) cm[k] = jb.t.hat_mont[k];
+  for (int k = threadIdx.x; k < NIN * nout; k += CONV_TPB) cm[k] = split30(jb.t.hat_mont[k]);
   for (int k = threadIdx.x; k < nout; k += CONV_TPB) {
     const PrimeInfo &po = pinfo[jb.t.out_prime[k]];
     oq[k] = po.q;
@@ -182,17 +184,17 @@ __global__ __launch_bounds__(CONV_TPB) void conv_kernel(const ConvJobs J, const 
     for (int i = 0; i < NIN; i++) {
       const u64 q = pinfo[jb.t.in_prime[i]].q;
       const u64 v = src[limb_ptr(bat, src_bstride, jb.src_off0 + i, N) + x];
-      y[i] = shoup(v, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, q);
+      y[i] = split30(shoup(v, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, q));
     }
   }
   __syncthreads();
   // converted (and finished) output r
   auto outv = [&](int r) -> u64 {
-    Acc a;
-    acc_zero(a);
+    Sum30 a;
+    a.zero();
 #pragma unroll
-    for (int i = 0; i < NIN; i++) acc_mac(a, y[i], cm[i * nout + r]);
-    u64 v = redc_acc(a, oq[r], oqn[r]);
+    for (int i = 0; i < NIN; i++) a.mac(y[i], cm[i * nout + r]);
+    u64 v = redc_acc(a.value(), oq[r], oqn[r]);
     if (fin != CONV_FIN_NONE) {
       const u64 A = src[limb_ptr(bat, src_bstride, jb.fin_off0 + r, N) + x];
       v = shoup(sub_mod(A, v, oq[r]), opi[r], opp[r], oq[r]);
@@ -304,34 +306,56 @@ struct KsArgs {
 
 struct LevelGeom {
   int level, beta, pqn, keyl, logn;
+  int limb_xcd;   // tile_map: whole limbs per XCD (1) or blocks dealt over the XCDs (0)
+  int gen_wide;   // kernels that regenerate key halves do so on primes >= 2^40 too (1)
 };
 
 __device__ __forceinline__ int pq_prime_dev(int r, int level, int L) {
   return r <= level ? r : L + 1 + (r - level - 1);
 }
 
-// Workgroup order for kernels whose operands (keys, plaintexts) are shared by
-// every ciphertext of a batch: a group is one (256-coefficient block, limb)
-// pair and a tile is BT ciphertexts of the batch.  Workgroup L runs on XCD
-// L mod 8 (round-robin dispatch); the mapping sends all tiles of a group to
-// the same XCD back to back, so the group's key and plaintext words come from
-// HBM once and from that XCD's L2 afterwards.
+// Workgroup order of the key-switching kernels.  A group is one block of
+// coefficients of one limb (nx blocks per limb, nr limbs), a tile is one
+// slice of the batch; workgroup L runs on XCD L mod 8 (round-robin dispatch)
+// and each XCD starts its workgroups in order.  With limb_xcd, limb r of the
+// first 8 floor(nr/8) limbs is served by XCD r mod 8 alone, group by group,
+// the tiles of a group back to back: the rotations of a limb gather its
+// digit and c0 words from the blocks the Galois map sends them to (a
+// 64-aligned block of slots maps onto another one), so after the first
+// rotation they come from that XCD's L2, and the key and plaintext words of a
+// group serve every tile from L2 as well.  The other nr mod 8 limbs (and
+// every limb without limb_xcd) are dealt over the XCDs group by group.
 struct TileMap {
   int xb, r, tile;
 };
 
-__device__ __forceinline__ TileMap tile_map(int L, int nx, int ntiles) {
+__device__ __forceinline__ TileMap tile_map(int L, int nx, int ntiles, int nr, int limb_xcd) {
   const int xcd = L & 7, k = L >> 3;
-  const int tile = k % ntiles;
-  const int grp = (k / ntiles) * 8 + xcd;
+  const int nr8 = limb_xcd ? (nr & ~7) : 0;
+  const int first = (nr8 >> 3) * nx * ntiles;   // workgroups per XCD on whole limbs
   TileMap m;
-  m.xb = grp % nx;
-  m.r = grp / nx;
-  m.tile = tile;
+  if (k < first) {
+    const int g = k / ntiles;
+    m.tile = k % ntiles;
+    m.xb = g % nx;
+    m.r = (g / nx) * 8 + xcd;
+  } else {
+    const int k2 = k - first;
+    const int grp = (k2 / ntiles) * 8 + xcd;
+    m.tile = k2 % ntiles;
+    m.xb = grp % nx;
+    m.r = nr8 + grp / nx;
+  }
   return m;
 }
 
 constexpr int MAXBETA = 4;   // digits per key switch handled in registers
+
+// Multiply-accumulate policy of limbs with primes of 40 bits and more: the
+// four-multiply Wide30Mac where a thread holds at most two accumulator pairs,
+// the four-register WideMac otherwise.
+template <int TILES>
+using WideOf = typename std::conditional<(TILES <= 2), Wide30Mac, WideMac>::type;
 
 // out = (B, A) over PQ:  B = sum_t sum_j sigma_t(d_{t,j}) b_{t,j}
 //                          + P (sum_t sigma_t(c0_t) + base_c0),
@@ -437,16 +461,19 @@ __global__ __launch_bounds__(TPB) void ks_acc_kernel(KsArgs T, LevelGeom G, int 
                                                      size_t base_bs, u64 *out, size_t out_bs,
                                                      const PrimeInfo *pinfo) {
   const int N = 1 << G.logn;
-  const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles);
+  const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles, G.pqn, G.limb_xcd);
   const int x = tm.xb * TPB + threadIdx.x;
   const int p = pq_prime_dev(tm.r, G.level, L);
   const PrimeInfo pi = pinfo[p];
   if (pi.q < SPLIT_MAC_LIMIT)
     ks_acc_body<BT, BETA, SplitMac, GEN>(T, G, batch, x, tm.r, tm.tile * BT, p, pi, dig_bs, c0_bs, base, base_bs,
                                          out, out_bs);
+  else if (GEN && G.gen_wide)
+    ks_acc_body<BT, BETA, WideOf<BT>, GEN>(T, G, batch, x, tm.r, tm.tile * BT, p, pi, dig_bs, c0_bs, base,
+                                           base_bs, out, out_bs);
   else
-    ks_acc_body<BT, BETA, WideMac, GEN>(T, G, batch, x, tm.r, tm.tile * BT, p, pi, dig_bs, c0_bs, base, base_bs,
-                                        out, out_bs);
+    ks_acc_body<BT, BETA, WideOf<BT>, false>(T, G, batch, x, tm.r, tm.tile * BT, p, pi, dig_bs, c0_bs, base,
+                                             base_bs, out, out_bs);
 }
 
 // Rotation steps of one fused baby-step launch, compacted on the host: only
@@ -603,16 +630,19 @@ __global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G,
                                                        size_t ct_bs, const u64 *pt, int ng, u64 *X, size_t x_bs,
                                                        int accum, const PrimeInfo *pinfo) {
   const int N = 1 << G.logn;
-  const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles);
+  const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles, G.pqn, G.limb_xcd);
   const int x = tm.xb * TPB + threadIdx.x;
   const int p = pq_prime_dev(tm.r, G.level, L);
   const PrimeInfo pi = pinfo[p];
   if (pi.q < SPLIT_MAC_LIMIT)
     baby_mac_body<GT, BT, BETA, SplitMac, GEN>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs, ct,
                                                ct_bs, pt, ng, X, x_bs, accum);
+  else if (GEN && G.gen_wide)
+    baby_mac_body<GT, BT, BETA, WideOf<GT * BT>, GEN>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs,
+                                                      ct, ct_bs, pt, ng, X, x_bs, accum);
   else
-    baby_mac_body<GT, BT, BETA, WideMac, GEN>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs, ct,
-                                              ct_bs, pt, ng, X, x_bs, accum);
+    baby_mac_body<GT, BT, BETA, WideOf<GT * BT>, false>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits,
+                                                        dig_bs, ct, ct_bs, pt, ng, X, x_bs, accum);
 }
 
 // The same product for launches with several giant outputs and a batch.  A
@@ -800,7 +830,7 @@ __global__ __launch_bounds__(64 * W) void baby_mac_shared_kernel(BabyArgs BA, Le
                                                                  const PrimeInfo *pinfo) {
   __shared__ u64 R[2][W][2][64];
   const int N = 1 << G.logn;
-  const TileMap tm = tile_map(blockIdx.x, N / 64, ntiles);
+  const TileMap tm = tile_map(blockIdx.x, N / 64, ntiles, G.pqn, G.limb_xcd);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int x = tm.xb * 64 + lane;
   const int p = pq_prime_dev(tm.r, G.level, L);
@@ -993,10 +1023,23 @@ int pick_bt(int batch, int cap) {
   return bt;
 }
 
+// Key words per coefficient of one rotation read from memory, summed over
+// the PQ limbs of `level`: 2 beta (both halves), or beta where the kernel
+// regenerates the a_j halves (primes below 2^40, or every prime with gen_wide).
+double key_limb_words(const helrm_ctx *ctx, int level, bool gen, int gen_wide, double beta) {
+  double w = 0;
+  for (int r = 0; r < level + 1 + ctx->K; r++) {
+    const bool small = ctx->primes[ctx->pq_prime(r, level)] < SPLIT_MAC_LIMIT;
+    w += gen && (small || gen_wide) ? beta : 2 * beta;
+  }
+  return w;
+}
+
 int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_terms,
                          size_t digits_bstride, size_t c0_bstride, const u64 *base, size_t base_bstride,
                          u64 *out, size_t out_bstride, int batch, hipStream_t s) {
-  LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn};
+  LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn, ctx->tune_limb_xcd,
+               ctx->tune_gen_key_a == 2 ? 1 : 0};
   if (G.beta > MAXBETA || G.beta < 1) {
     set_error("key switching with %d digits (1 to %d supported)", G.beta, MAXBETA);
     return HELRM_EINVAL;
@@ -1022,8 +1065,9 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
       seeded = seeded && terms[t0 + i].seeded;
     }
     // one ciphertext per thread: every key word is used once, so regenerating
-    // the a_j halves halves the key traffic
-    const bool gen = bt == 1 && seeded && nt_i > 0 && ctx->tune_gen_key_a == 1;
+    // the a_j halves halves the key traffic (on primes below 2^40, where the
+    // generator is cheap, unless gen_key_a = 2)
+    const bool gen = bt == 1 && seeded && nt_i > 0 && ctx->tune_gen_key_a >= 1;
     const u64 *bse = t0 == 0 ? base : nullptr;
     // per coefficient of a Q limb: terms * 3 beta words (digit, key b, key a) + the c0 words
     // + 2 base words + 2 output words (4 when adding to out); special limbs: no c0 / base
@@ -1031,9 +1075,9 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
     double nc0 = 0;
     for (int i = 0; i < nt_i; i++) nc0 += T.c0[i] ? 1 : 0;
     const double qn = level + 1, K = ctx->K, nt = nt_i, beta = G.beta, B = batch, ow = T.accum ? 4 : 2;
-    const double kw = gen ? beta : 2 * beta;   // key words per term and coefficient read from memory
-    const double words = qn * (nt * kw + B * (nt * beta + nc0 + (bse ? 2 : 0) + ow)) +
-                         K * (nt * kw + B * (nt * beta + ow));
+    // key words per term and coefficient read from memory, summed over the limbs
+    const double kl = key_limb_words(ctx, level, gen, G.gen_wide, beta);
+    const double words = nt * kl + qn * B * (nt * beta + nc0 + (bse ? 2 : 0) + ow) + K * B * (nt * beta + ow);
     KTimer tm(ctx, s);
 #define KSACC(BT_, BETA_, GEN_)                                                                        \
   hipLaunchKernelGGL((ks_acc_kernel<BT_, BETA_, GEN_>), dim3(grid), dim3(TPB), 0, s, T, G, ctx->L,      \
@@ -1110,7 +1154,8 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
     for (int gi = 0; gi < HELRM_MAX_GTILE; gi++) BA.slot[i][gi] = sl[gi];
   }
   const int level = plan->level;
-  LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn};
+  LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn, ctx->tune_limb_xcd,
+               ctx->tune_gen_key_a == 2 ? 1 : 0};
   if (G.beta > MAXBETA || G.beta < 1) {
     set_error("key switching with %d digits (1 to %d supported)", G.beta, MAXBETA);
     return HELRM_EINVAL;
@@ -1126,10 +1171,10 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   const bool shared_path = ng >= 2 && batch >= 2 && ctx->tune_baby_share >= 2;
   const int bt_path = shared_path ? 0 : pick_bt(batch, gt >= 4 ? 1 : gt == 2 ? std::min(2, ctx->tune_baby_tile)
                                                                              : ctx->tune_baby_tile);
-  const bool gen = !shared_path && bt_path == 1 && gt <= 2 && seeded && BA.nrot > 0 && ctx->tune_gen_key_a == 1;
-  const double kw = gen ? beta : 2 * beta;
-  const double words = qn * (nrot * kw + npt + B * (nrot * (beta + 1) + 2 * has0 + xw * ng)) +
-                       K * (nrot * kw + npt + B * (nrot * beta + xw * ng));
+  const bool gen = !shared_path && bt_path == 1 && gt <= 2 && seeded && BA.nrot > 0 && ctx->tune_gen_key_a >= 1;
+  const double kl = key_limb_words(ctx, level, gen, G.gen_wide, beta);
+  const double words = nrot * kl + (qn + K) * npt + qn * B * (nrot * (beta + 1) + 2 * has0 + xw * ng) +
+                       K * B * (nrot * beta + xw * ng);
   KTimer tm(ctx, s);
   if (ng >= 2 && batch >= 2 && ctx->tune_baby_share >= 2) {
     // several giant outputs and a batch: W ciphertexts per workgroup

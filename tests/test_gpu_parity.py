@@ -304,13 +304,14 @@ def test_lookup_fused_boundaries(fuse, p1, ctx2):
 
 
 def test_lookup_regenerated_key_halves_cfg2(ctx2):
-    """Batch 1 regenerates the keys' a_j halves from their seeds; with the
-    knob off the kernels read them: both bit-exact against the oracle."""
+    """Batch 1 regenerates the keys' a_j halves from their seeds (on the
+    40-bit primes, or on every prime); with the knob off the kernels read
+    them: all bit-exact against the oracle."""
     w = cfg2_workload(4, 16, 8, sign=-1)
     load_keys(ctx2, w.keys)
     plan = gpu_plan(ctx2, w.plan)
     try:
-        for gen in (1, 0):
+        for gen in (1, 2, 0):
             say(f"lookup cfg2 level 4 gen_key_a={gen}")
             ctx2.helrm_set_tuning("gen_key_a", gen)
             _check_lookup(ctx2, w, plan, [0])
