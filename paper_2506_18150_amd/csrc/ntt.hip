@@ -108,6 +108,10 @@ struct IntA {
     return v >= q ? v - q : v;
   }
   __device__ __forceinline__ u64 scale(V v, const PrimeInfo &pi) const { return shoup(v, pi.ninv, pi.ninv_p, q); }
+  // fused finish: (a - y) c mod q for the transform output y, a in [0, q)
+  __device__ __forceinline__ u64 finish(V v, u64 a, const TW &c) const {
+    return shoup(sub_mod(a, canon(v), q), c.w, c.wp, q);
+  }
 };
 
 struct FltA {
@@ -157,6 +161,11 @@ struct FltA {
     return (u64)__double_as_longlong(r + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
   }
   __device__ __forceinline__ u64 scale(V v, const PrimeInfo &pi) const { return canon(mm(v, pi.ninv_d)); }
+  // fused finish: (a - y) c mod q for the lazy transform output y (|a - y| < 34 q)
+  __device__ __forceinline__ u64 finish(V v, u64 a, const TW &c) const {
+#pragma clang fp contract(off)
+    return canon(mm(load(a) - v, (double)c.w));
+  }
 };
 
 // Twiddles of one register phase.  Stage h (pairs k, k+h) uses m = E/(2h)
@@ -275,7 +284,6 @@ __device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 (&raw
 #pragma unroll
       for (int k = 0; k < E; k++) lds[blk_idx<H>(w, E * u + k)] = ar.bits(x[k]);
       __syncthreads();
-      const u64 q = pi.q;
       if (epi.a && li < epi.n_fin) {
         // fused finish: out = (a - NTT(x)) * c  (ModDown: c = P^-1, rescale: c = q_l^-1)
         const int bo = bat / epi.inner, bi = bat % epi.inner;
@@ -285,10 +293,7 @@ __device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 (&raw
                   (size_t)R * b;
         const TW c = epi.c[li];
 #pragma unroll
-        for (int k = 0; k < E; k++) {
-          const u64 v = ar.canon(ar.unbits(lds[blk_idx<H>(w, u + E * k)]));
-          eo[u + E * k] = shoup(sub_mod(ea[u + E * k], v, q), c.w, c.wp, q);
-        }
+        for (int k = 0; k < E; k++) eo[u + E * k] = ar.finish(ar.unbits(lds[blk_idx<H>(w, u + E * k)]), ea[u + E * k], c);
       } else if (epi.dup && epi.dup_off[li] >= 0) {
         u64 *db = epi.dup + ((size_t)bat * epi.dup_bs + epi.dup_off[li]) * (size_t)N + (size_t)R * b;
 #pragma unroll
