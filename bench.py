@@ -367,6 +367,27 @@ def dlrm_bench(args):
     print(json.dumps(res))
 
 
+def hbm_copy_rate(gib: int = 2, reps: int = 5) -> dict:
+    """Achievable HBM rate of a plain streaming copy on this GPU (a device-to-
+    device tensor copy, read + write), as context for the 8 TB/s peak."""
+    import torch
+    a = torch.ones(gib << 27, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    moved = 2 * a.numel() * 8
+    del a, b
+    return {"GB/s": moved / (ms * 1e6), "bytes_per_copy": moved, "frac_of_peak": moved / (ms * 1e6) / HBM_PEAK_GBS,
+            "what": "device-to-device tensor copy, bytes read + written"}
+
+
 def main():
     args = parse()
     if args.level is None:
@@ -567,6 +588,7 @@ def main():
         limb_ntts = (kt["ntt_fwd_col"]["ops"] + kt["ntt_inv_blk"]["ops"]) / ((prm.N // 2) * 8) / args.steps
         res["ntts_per_s"] = limb_ntts * (1e3 / ms_per_step)
         res["kernels"] = {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in table.items()}
+        res["hbm_copy"] = hbm_copy_rate()
 
     if args.calibrate_copy:
         a = torch.zeros(1 << 27, dtype=torch.int64, device="cuda")
