@@ -514,10 +514,10 @@ size_t matvec_ws_bytes(const helrm_ctx *ctx, const helrm_plan *p, int batch, boo
   const size_t B = batch, n2 = p->n2;
   const size_t ng = std::max(ng_union, nonzero_giants(&p, 1));
   size_t tot = 0;
-  tot += rnd(B * qn * N);                       // coef
+  tot += rnd(B * n2 * qn * N);                  // coef (one ModUp of every giant's x_g)
   tot += rnd(B * (2 * qn + beta * pqn) * N);    // F
   tot += rnd(B * 2 * pqn * N);                  // C
-  tot += rnd(B * std::max<size_t>(ng, 1) * beta * pqn * N);  // Dg
+  tot += rnd(B * (ng > 0 ? n2 : 1) * beta * pqn * N);  // Dg
   tot += rnd(B * n2 * 2 * pqn * N);             // X
   tot += rnd(B * n2 * 2 * qn * N);              // xg
   tot += rnd(B * 2 * pqn * N);                  // acc
@@ -539,10 +539,10 @@ MatvecWS carve_matvec(const helrm_ctx *ctx, const helrm_plan *p, int batch, bool
   const size_t ng = std::max(ng_union, nonzero_giants(&p, 1));
   Arena a{base};
   MatvecWS w;
-  w.coef = a.take(B * qn * N);
+  w.coef = a.take(B * n2 * qn * N);
   w.F = a.take(B * (2 * qn + beta * pqn) * N);
   w.C = a.take(B * 2 * pqn * N);
-  w.Dg = a.take(B * std::max<size_t>(ng, 1) * beta * pqn * N);
+  w.Dg = a.take(B * (ng > 0 ? n2 : 1) * beta * pqn * N);
   w.X = a.take(B * n2 * 2 * pqn * N);
   w.xg = a.take(B * n2 * 2 * qn * N);
   w.acc = a.take(B * 2 * pqn * N);
@@ -636,25 +636,22 @@ int run_matvec(helrm_ctx *ctx, const helrm_plan *const *ps, int n_in, const u64 
         z = zbuf;
       }
     } else {
-      // 4. giant rotations by n1 g of x_g (g >= 1), accumulated in PQ with P x_0
+      // 4. giant rotations by n1 g of x_g (g >= 1), accumulated in PQ with P
+      //    x_0: one ModUp covers every x_g of the batch (batch * n2
+      //    ciphertexts, x_0's digits unused), so its launches do not repeat
+      //    per giant step
+      TRY(do_modup(ctx, lv, w.xg + (size_t)qn * N, 2 * qn, w.Dg, d_bs, w.coef, batch * n2, s));
       std::vector<KsTerm> terms;
-      int gi = 0;
       for (int g : giants) {
         if (g == 0) continue;
-        const u64 *xgp = w.xg + (size_t)g * 2 * qn * N;
-        u64 *Dg = w.Dg + (size_t)gi * beta * pqn * N;
-        const int ng_ = (int)(giants.size() - (giants[0] == 0 ? 1 : 0));
-        TRY(do_modup(ctx, lv, xgp + (size_t)qn * N, n2 * 2 * qn, Dg, ng_ * d_bs, w.coef, batch, s));
         KsTerm t;
-        t.digits = Dg;
-        t.c0 = xgp;
+        t.digits = w.Dg + (size_t)g * d_bs * N;
+        t.c0 = w.xg + (size_t)g * 2 * qn * N;
         TRY(key_for(ctx, (long)p->sign * p->n1 * g, &t));
         terms.push_back(t);
-        gi++;
       }
-      const int ng_ = gi;
       const bool has0 = giants[0] == 0;
-      TRY(launch_ks_accumulate(ctx, lv, terms.data(), (int)terms.size(), (size_t)ng_ * d_bs * N,
+      TRY(launch_ks_accumulate(ctx, lv, terms.data(), (int)terms.size(), (size_t)n2 * d_bs * N,
                                (size_t)n2 * 2 * qn * N, has0 ? w.xg : nullptr, (size_t)n2 * 2 * qn * N, w.acc,
                                (size_t)2 * pqn * N, batch, s));
       if (no_fold && fuse && rs_out) {
