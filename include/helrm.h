@@ -66,7 +66,8 @@ typedef struct helrm_plan helrm_plan;
 
 /* RNS-CKKS parameters.  q[0..L] are the ciphertext primes (q_0 is never
  * dropped), p[0..K-1] the special primes of hybrid key switching; every
- * prime is < 2^61 and = 1 mod 2N.  Key-switching digit j holds the Q primes
+ * prime is < 2^60 (the lazy integer arithmetic keeps 16 q below 2^64) and
+ * = 1 mod 2N.  Key-switching digit j holds the Q primes
  * j*alpha .. j*alpha+alpha-1 (dnum = ceil((L+1)/alpha) digits). */
 typedef struct {
   int log_n;            /* N = 2^log_n; 12 or 16 */

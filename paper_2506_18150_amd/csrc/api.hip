@@ -749,8 +749,8 @@ extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
   const u64 twoN = 2ull * c->N;
   for (int i = 0; i < c->nprimes; i++) {
     const u64 q = c->primes[i];
-    if (q < 3 || q >= (1ull << 61) || q % twoN != 1) {
-      set_error("prime %d (%llu) must be < 2^61 and = 1 mod 2N", i, (unsigned long long)q);
+    if (q < 3 || q >= (1ull << 60) || q % twoN != 1) {
+      set_error("prime %d (%llu) must be < 2^60 and = 1 mod 2N", i, (unsigned long long)q);
       delete c;
       return HELRM_EINVAL;
     }

@@ -22,19 +22,34 @@
 
 namespace {
 
-__device__ __forceinline__ void ct_bfly(u64 &x, u64 &y, const TW &t, u64 q, u64 q2) {
-  u64 X = x >= q2 ? x - q2 : x;
-  u64 T = shoup_lazy(y, t.w, t.wp, q);
-  x = X + T;
-  y = X - T + q2;
+// Shoup product with a three-term quotient: for y = y1 2^32 + y0 and
+// w' = p1 2^32 + p0, floor(y w' / 2^64) is y1 p1 + hi(y1 p0) + hi(y0 p1)
+// plus 0, 1 or 2 (the dropped low terms are below 3 2^64), so
+// y w - qh q lies in [0, 4q) for any 64-bit y (Shoup: [0, 2q) with the exact
+// quotient).
+__device__ __forceinline__ u64 shoup_lazy4(u64 y, u64 w, u64 wp, u64 q) {
+  const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32), p0 = (uint32_t)wp, p1 = (uint32_t)(wp >> 32);
+  const u64 qh = (u64)y1 * p1 + __umulhi(y1, p0) + __umulhi(y0, p1);
+  return y * w - qh * q;
 }
 
-__device__ __forceinline__ void gs_bfly(u64 &x, u64 &y, const TW &t, u64 q, u64 q2) {
+// Integer butterflies on lazy values in [0, 8q) (q < 2^60, so 16 q < 2^64).
+// Forward: X = x mod 4q in [0, 4q), T in [0, 4q): X + T and X - T + 4q stay
+// in [0, 8q).  Inverse: x + y reduced once by 8q, and (x - y + 8q) w.
+__device__ __forceinline__ void ct_bfly(u64 &x, u64 &y, const TW &t, u64 q, u64 q4) {
+  const u64 X = x >= q4 ? x - q4 : x;
+  const u64 T = shoup_lazy4(y, t.w, t.wp, q);
+  x = X + T;
+  y = X - T + q4;
+}
+
+__device__ __forceinline__ void gs_bfly(u64 &x, u64 &y, const TW &t, u64 q, u64 q4) {
+  const u64 q8 = 2 * q4;
   u64 S = x + y;
-  S = S >= q2 ? S - q2 : S;
-  u64 D = x - y + q2;
+  S = S >= q8 ? S - q8 : S;
+  const u64 D = x - y + q8;
   x = S;
-  y = shoup_lazy(D, t.w, t.wp, q);
+  y = shoup_lazy4(D, t.w, t.wp, q);
 }
 
 // Workgroup shape of one pass.  The column pass keeps WC consecutive columns
@@ -69,8 +84,9 @@ __device__ __forceinline__ int col_idx(int w, int r) {
 
 // ---------------------------------------------------------------- arithmetic policies
 //
-// IntA: residues as uint64 with Shoup twiddle products (any prime < 2^61):
-// Harvey's lazy butterflies, values in [0, 4q) forward and [0, 2q) inverse.
+// IntA: residues as uint64 with Shoup twiddle products (primes below 2^60):
+// lazy butterflies in the manner of Harvey on values in [0, 8q), with a
+// three-term Shoup quotient (two 32-bit multiplies fewer per butterfly).
 //
 // FltA: residues as signed fp64 for primes below 2^41 (FLT_LIMIT).  The
 // product a*w mod q is formed exactly: h = fl(a w) and l = fma(a, w, -h) give
@@ -93,17 +109,19 @@ constexpr u64 FLT_LIMIT = 1ull << 41;
 struct IntA {
   using V = u64;
   using T = TW;
-  u64 q, q2;
+  u64 q, q4;
   const TW *tw;
   __device__ __forceinline__ V load(u64 x) const { return x; }
   __device__ __forceinline__ u64 bits(V v) const { return v; }
   __device__ __forceinline__ V unbits(u64 b) const { return b; }
   // value stored between the passes (lazy)
   __device__ __forceinline__ u64 mid(V v, bool) const { return v; }
-  __device__ __forceinline__ void ct(V &x, V &y, const T &t) const { ct_bfly(x, y, t, q, q2); }
-  __device__ __forceinline__ void gs(V &x, V &y, const T &t) const { gs_bfly(x, y, t, q, q2); }
-  // [0, 4q) -> [0, q)
+  __device__ __forceinline__ void ct(V &x, V &y, const T &t) const { ct_bfly(x, y, t, q, q4); }
+  __device__ __forceinline__ void gs(V &x, V &y, const T &t) const { gs_bfly(x, y, t, q, q4); }
+  // [0, 8q) -> [0, q)
   __device__ __forceinline__ u64 canon(V v) const {
+    v = v >= q4 ? v - q4 : v;
+    const u64 q2 = q4 >> 1;
     v = v >= q2 ? v - q2 : v;
     return v >= q ? v - q : v;
   }
@@ -245,7 +263,7 @@ __device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 (&raw
 #pragma unroll
       for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[col_idx<H, W>(w, E * u + k)]);
       fwd_phase<H>(x, ar, t2);
-      // lazy values go to memory (integers below 4q, or fp64 bits)
+      // lazy values go to memory (integers below 8q, or fp64 bits)
 #pragma unroll
       for (int k = 0; k < E; k++) out[c + R * (E * u + k)] = ar.mid(x[k], true);
     } else {
@@ -324,7 +342,7 @@ __device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 (&raw
 #pragma unroll
       for (int k = 0; k < E; k++) x[k] = ar.unbits(lds[blk_idx<H>(w, u + E * k)]);
       inv_phase<H>(x, ar, t2);
-      // values go to memory (integers below 2q, or fp64 bits in [0, q])
+      // values go to memory (integers below 8q, or fp64 bits in [0, q])
 #pragma unroll
       for (int k = 0; k < E; k++) ob[u + E * k] = ar.mid(x[k], false);
     }
@@ -359,7 +377,7 @@ __global__ __launch_bounds__((Shape<H, COLS, WS>::T)) void ntt_pass_kernel(const
     FltA ar{pi.qd, pi.qinv_d, twdtab + (size_t)p * N};
     pass_body<H, FWD, COLS, WS>(ar, lds, raw, out, part, bat, li, pi, epi);
   } else {
-    IntA ar{pi.q, 2 * pi.q, twtab + (size_t)p * N};
+    IntA ar{pi.q, 4 * pi.q, twtab + (size_t)p * N};
     pass_body<H, FWD, COLS, WS>(ar, lds, raw, out, part, bat, li, pi, epi);
   }
 }
