@@ -346,6 +346,7 @@ int do_moddown_modup(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *z, 
                      u64 *C, int batch, hipStream_t s) {
   const int K = ctx->K, qn = level + 1, pqn = level + 1 + K, beta = ctx->n_digits(level);
   const int c_bs = K + pqn;
+  CHECK_ARG(beta <= HELRM_MAX_CONV_JOBS, "modup: at most %d digits", HELRM_MAX_CONV_JOBS);
   // 1.
   LimbList a = ll_make(K + pqn, x_bs, c_bs);
   for (int k = 0; k < K; k++) {
@@ -371,7 +372,6 @@ int do_moddown_modup(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *z, 
   TRY(launch_conv(ctx, md, 2, C, c_bs, nullptr, 0, F, f_bs, batch, s));
   // 3.
   ConvSpec up[HELRM_MAX_CONV_JOBS];
-  CHECK_ARG(beta <= HELRM_MAX_CONV_JOBS, "modup: at most %d digits", HELRM_MAX_CONV_JOBS);
   LimbList f = ll_make(0, f_bs, f_bs);
   NttEpi e;
   e.a = X;

@@ -132,6 +132,29 @@ def test_automorph_parity(p1, p2, ctx1, ctx2):
                 assert_bit_exact(got[b], O.automorph_ntt(x[b], g, prm.N), "automorph")
 
 
+def test_tuning_knobs_validate(p1):
+    """Every schedule knob accepts its documented values and rejects the
+    others (and unknown names) with HELRM_EINVAL, leaving the context usable."""
+    from paper_2506_18150_amd import binding as B
+    ctx = context_for(p1)
+    good = {"ks_tile": [1, 2, 4], "baby_tile": [1, 2, 4], "baby_share": [1, 2, 4, 8], "ntt_col_w": [0, 8, 16],
+            "ntt_blk_w": [0, 4, 8], "ntt_small_limbs": [0, 48], "gen_key_a": [0, 1, 2], "limb_xcd": [0, 1],
+            "fuse_ks": [0, 1], "conv_wgs": [0, 2048]}
+    bad = {"ks_tile": [0, 3, 8], "baby_tile": [0, 3], "baby_share": [0, 3, 16], "ntt_col_w": [4, 32],
+           "ntt_blk_w": [2, 16], "ntt_small_limbs": [-1], "gen_key_a": [-1, 3], "limb_xcd": [2],
+           "fuse_ks": [2], "conv_wgs": [-1]}
+    for knob, vals in good.items():
+        for v in vals:
+            ctx.helrm_set_tuning(knob, v)
+    for knob, vals in bad.items():
+        for v in vals:
+            with pytest.raises(B.HelrmError):
+                ctx.helrm_set_tuning(knob, v)
+    with pytest.raises(B.HelrmError):
+        ctx.helrm_set_tuning("no_such_knob", 1)
+    assert ctx.helrm_get_psi(0) > 1
+
+
 def test_elementwise_parity(p2, ctx2):
     prm, ctx = p2, ctx2
     from paper_2506_18150_amd import binding as B
