@@ -99,8 +99,11 @@ int helrm_get_psi(const helrm_ctx *ctx, int prime_index, uint64_t *psi);
  * be NULL) gives each key's 64-bit seed when its a_j halves are the seeded
  * uniform polynomials of helrm_key_uniform; kernels that use every key word
  * once (one ciphertext per call) then regenerate a_j instead of reading it,
- * so the caller must pass the seed the a_j were expanded from.  A key loaded
- * again for the same element replaces the old one.  Blocks. */
+ * so the caller must pass the seed the a_j were expanded from.  The library
+ * holds each key in Montgomery form plus a second copy of the b_j halves on
+ * the primes below 2^40 as 40-bit words (5 bytes), which the kernels stream;
+ * a key takes dnum (L+1+K) N (16 + 5) bytes.  A key loaded again for the same
+ * element replaces the old one.  Blocks. */
 int helrm_load_eval_keys(helrm_ctx *ctx, const uint32_t *galois, int n_keys,
                          const uint64_t *keys, const uint64_t *seeds);
 

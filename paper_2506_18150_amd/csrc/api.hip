@@ -929,7 +929,8 @@ extern "C" int helrm_load_eval_keys(helrm_ctx *c, const uint32_t *galois, int n_
   CHECK_ARG(n_keys >= 0, "n_keys < 0");
   CHECK_ARG(n_keys == 0 || (galois && keys), "NULL galois or keys");
   const size_t N = c->N, kl = c->L + 1 + c->K;
-  const size_t words = (size_t)c->dnum * 2 * kl * N;
+  const size_t words = key_words(c->dnum, (int)kl, (int)N);
+  const size_t bytes = key_bytes(c->dnum, (int)kl, (int)N);
   for (int k = 0; k < n_keys; k++)
     CHECK_ARG(galois[k] == 0 || (galois[k] & 1u) && galois[k] < 2u * c->N, "bad galois element %u", galois[k]);
   for (int k = 0; k < n_keys; k++) {
@@ -938,9 +939,9 @@ extern "C" int helrm_load_eval_keys(helrm_ctx *c, const uint32_t *galois, int n_
     if (it != c->keys.end()) {
       d = it->second.d;
     } else {
-      if (hipMalloc(&d, words * sizeof(u64)) != hipSuccess) {
+      if (hipMalloc(&d, bytes) != hipSuccess) {
         (void)hipGetLastError();
-        set_error("key allocation (%zu bytes) failed", words * sizeof(u64));
+        set_error("key allocation (%zu bytes) failed", bytes);
         return HELRM_ENOMEM;
       }
       c->keys[galois[k]] = KeyEntry{d};
@@ -951,6 +952,7 @@ extern "C" int helrm_load_eval_keys(helrm_ctx *c, const uint32_t *galois, int n_
     LimbList ll = ll_make((int)kl, (int)kl, (int)kl);
     for (size_t i = 0; i < kl; i++) { ll.src_off[i] = (int)i; ll.dst_off[i] = (int)i; ll.prime[i] = (unsigned char)i; }
     TRY(launch_to_mont(c, d, ll, c->dnum * 2, 0));
+    TRY(launch_pack_key(c, d, 0));
   }
   HIP_TRY(hipDeviceSynchronize());
   return HELRM_OK;

@@ -297,6 +297,21 @@ struct ConvTable {
 
 // ---------------------------------------------------------------- context
 
+// A switching key's allocation: [dnum][2][L+1+K][N] Montgomery-form words,
+// then the b halves again as 40-bit words (primes below 2^40), in a plane of
+// low 32 bits [dnum][L+1+K][N] and a plane of high 8 bits of the same shape,
+// so the kernels stream 5 bytes per b word instead of 8 on those limbs.
+__host__ __device__ inline size_t key_words(int dnum, int keyl, int N) { return (size_t)dnum * 2 * keyl * N; }
+__host__ __device__ inline size_t key_bytes(int dnum, int keyl, int N) {
+  return key_words(dnum, keyl, N) * 8 + (((size_t)dnum * keyl * N * 5 + 7) & ~(size_t)7);
+}
+__device__ __forceinline__ u64 key_b40(const u64 *key, int dnum, int keyl, int N, int j, int p, int x) {
+  const uint32_t *lo = (const uint32_t *)(key + key_words(dnum, keyl, N));
+  const uint8_t *hi = (const uint8_t *)(lo + (size_t)dnum * keyl * N);
+  const size_t i = ((size_t)j * keyl + p) * N + x;
+  return (u64)lo[i] | ((u64)hi[i] << 32);
+}
+
 struct KeyEntry {
   u64 *d;            // [dnum][2][L+1+K][N], Montgomery form
   u64 seed = 0;      // seed the a_j halves were expanded from
@@ -453,6 +468,8 @@ int launch_mul_scalar(helrm_ctx *ctx, const u64 *a, const u64 *scal, u64 *out, c
 int launch_from_signed(helrm_ctx *ctx, const int64_t *in, u64 *out, const LimbList &ll, int batch,
                        hipStream_t s);
 int launch_to_mont(helrm_ctx *ctx, u64 *data, const LimbList &ll, int batch, hipStream_t s);
+// Fill a key's 40-bit planes of the b halves from its Montgomery-form words.
+int launch_pack_key(helrm_ctx *ctx, u64 *key, hipStream_t s);
 int launch_copy_limbs(const u64 *src, u64 *dst, const LimbList &ll, int batch, int N, hipStream_t s);
 
 // One fast base conversion (coefficient form) of a launch: inputs are the

@@ -306,6 +306,7 @@ struct KsArgs {
 
 struct LevelGeom {
   int level, beta, pqn, keyl, logn;
+  int keyd;       // digits of a stored key (dnum), for the 40-bit planes of its b halves
   int limb_xcd;   // tile_map: whole limbs per XCD (1) or blocks dealt over the XCDs (0)
   int gen_wide;   // kernels that regenerate key halves do so on primes >= 2^40 too (1)
 };
@@ -373,6 +374,7 @@ __device__ __forceinline__ void ks_acc_body(const KsArgs &T, const LevelGeom &G,
                                             int p, const PrimeInfo &pi, size_t dig_bs, size_t c0_bs,
                                             const u64 *base, size_t base_bs, u64 *out, size_t out_bs) {
   const int N = 1 << G.logn;
+  constexpr bool NARROW = std::is_same<M, SplitMac>::value;   // prime below 2^40: b halves from the 40-bit planes
   const bool isq = r <= G.level;
   const int nct = min(BT, batch - b0);
   M ab[BT], aa[BT];
@@ -388,7 +390,7 @@ __device__ __forceinline__ void ks_acc_body(const KsArgs &T, const LevelGeom &G,
     const u64 *kk = T.key[t];
 #pragma unroll
     for (int j = 0; j < BETA; j++) {
-      in.kb[j] = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
+      in.kb[j] = NARROW ? key_b40(kk, G.keyd, G.keyl, N, j, p, x) : kk[((size_t)(2 * j) * G.keyl + p) * N + x];
       in.ka[j] = GEN ? key_uniform_mont(T.seed[t], j, p, x, pi) : kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
     }
 #pragma unroll
@@ -508,6 +510,7 @@ __device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeo
                                               size_t dig_bs, const u64 *ct, size_t ct_bs, const u64 *pt, int ng,
                                               u64 *X, size_t x_bs, int accum) {
   const int N = 1 << G.logn;
+  constexpr bool NARROW = std::is_same<M, SplitMac>::value;   // prime below 2^40: b halves from the 40-bit planes
   const bool isq = r <= G.level;
   const int nct = min(BT, batch - b0);
   M acc[BT][GT][2];
@@ -544,7 +547,7 @@ __device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeo
     const u64 *kk = BA.key[i];
 #pragma unroll
     for (int j = 0; j < BETA; j++) {
-      in.kb[j] = kk[((size_t)(2 * j) * G.keyl + p) * N + x];
+      in.kb[j] = NARROW ? key_b40(kk, G.keyd, G.keyl, N, j, p, x) : kk[((size_t)(2 * j) * G.keyl + p) * N + x];
       in.ka[j] = GEN ? key_uniform_mont(BA.seed[i], j, p, x, pi) : kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x];
     }
 #pragma unroll
@@ -895,6 +898,24 @@ int launch_from_signed(helrm_ctx *ctx, const int64_t *in, u64 *out, const LimbLi
   return HELRM_OK;
 }
 
+__global__ __launch_bounds__(TPB) void pack_key_kernel(const u64 *key, uint32_t *lo, uint8_t *hi, int keyl, int N) {
+  const int x = blockIdx.x * TPB + threadIdx.x;
+  const int j = blockIdx.y / keyl, p = blockIdx.y % keyl;
+  const u64 v = key[((size_t)(2 * j) * keyl + p) * N + x];
+  const size_t i = ((size_t)j * keyl + p) * N + x;
+  lo[i] = (uint32_t)v;
+  hi[i] = (uint8_t)(v >> 32);
+}
+
+int launch_pack_key(helrm_ctx *ctx, u64 *key, hipStream_t s) {
+  const int keyl = ctx->L + 1 + ctx->K;
+  uint32_t *lo = (uint32_t *)(key + key_words(ctx->dnum, keyl, ctx->N));
+  uint8_t *hi = (uint8_t *)(lo + (size_t)ctx->dnum * keyl * ctx->N);
+  hipLaunchKernelGGL(pack_key_kernel, ew_grid(ctx, ctx->dnum * keyl), dim3(TPB), 0, s, key, lo, hi, keyl, ctx->N);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
 int launch_to_mont(helrm_ctx *ctx, u64 *data, const LimbList &ll, int batch, hipStream_t s) {
   if (ll.n * batch == 0) return HELRM_OK;
   hipLaunchKernelGGL(to_mont_kernel, ew_grid(ctx, ll.n * batch), dim3(TPB), 0, s, data, ll, ctx->d_pinfo,
@@ -1024,13 +1045,16 @@ int pick_bt(int batch, int cap) {
 }
 
 // Key words per coefficient of one rotation read from memory, summed over
-// the PQ limbs of `level`: 2 beta (both halves), or beta where the kernel
-// regenerates the a_j halves (primes below 2^40, or every prime with gen_wide).
-double key_limb_words(const helrm_ctx *ctx, int level, bool gen, int gen_wide, double beta) {
+// the PQ limbs of `level`: 2 beta (both halves), less beta where the kernel
+// regenerates the a_j halves (primes below 2^40, or every prime with
+// gen_wide), the b halves counted at 5/8 where read from their 40-bit planes.
+double key_limb_words(const helrm_ctx *ctx, int level, bool gen, int gen_wide, double beta, bool packed) {
+  // b halves: 5 bytes per word on primes below 2^40 where the kernel reads
+  // their 40-bit planes (packed)
   double w = 0;
   for (int r = 0; r < level + 1 + ctx->K; r++) {
     const bool small = ctx->primes[ctx->pq_prime(r, level)] < SPLIT_MAC_LIMIT;
-    w += gen && (small || gen_wide) ? beta : 2 * beta;
+    w += (small && packed ? beta * 5.0 / 8.0 : beta) + (gen && (small || gen_wide) ? 0.0 : beta);
   }
   return w;
 }
@@ -1038,7 +1062,7 @@ double key_limb_words(const helrm_ctx *ctx, int level, bool gen, int gen_wide, d
 int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_terms,
                          size_t digits_bstride, size_t c0_bstride, const u64 *base, size_t base_bstride,
                          u64 *out, size_t out_bstride, int batch, hipStream_t s) {
-  LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn, ctx->tune_limb_xcd,
+  LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn, ctx->dnum, ctx->tune_limb_xcd,
                ctx->tune_gen_key_a == 2 ? 1 : 0};
   if (G.beta > MAXBETA || G.beta < 1) {
     set_error("key switching with %d digits (1 to %d supported)", G.beta, MAXBETA);
@@ -1076,7 +1100,7 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
     for (int i = 0; i < nt_i; i++) nc0 += T.c0[i] ? 1 : 0;
     const double qn = level + 1, K = ctx->K, nt = nt_i, beta = G.beta, B = batch, ow = T.accum ? 4 : 2;
     // key words per term and coefficient read from memory, summed over the limbs
-    const double kl = key_limb_words(ctx, level, gen, G.gen_wide, beta);
+    const double kl = key_limb_words(ctx, level, gen, G.gen_wide, beta, true);
     const double words = nt * kl + qn * B * (nt * beta + nc0 + (bse ? 2 : 0) + ow) + K * B * (nt * beta + ow);
     KTimer tm(ctx, s);
 #define KSACC(BT_, BETA_, GEN_)                                                                        \
@@ -1154,7 +1178,7 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
     for (int gi = 0; gi < HELRM_MAX_GTILE; gi++) BA.slot[i][gi] = sl[gi];
   }
   const int level = plan->level;
-  LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn, ctx->tune_limb_xcd,
+  LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn, ctx->dnum, ctx->tune_limb_xcd,
                ctx->tune_gen_key_a == 2 ? 1 : 0};
   if (G.beta > MAXBETA || G.beta < 1) {
     set_error("key switching with %d digits (1 to %d supported)", G.beta, MAXBETA);
@@ -1172,7 +1196,7 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   const int bt_path = shared_path ? 0 : pick_bt(batch, gt >= 4 ? 1 : gt == 2 ? std::min(2, ctx->tune_baby_tile)
                                                                              : ctx->tune_baby_tile);
   const bool gen = !shared_path && bt_path == 1 && gt <= 2 && seeded && BA.nrot > 0 && ctx->tune_gen_key_a >= 1;
-  const double kl = key_limb_words(ctx, level, gen, G.gen_wide, beta);
+  const double kl = key_limb_words(ctx, level, gen, G.gen_wide, beta, !shared_path);
   const double words = nrot * kl + (qn + K) * npt + qn * B * (nrot * (beta + 1) + 2 * has0 + xw * ng) +
                        K * B * (nrot * beta + xw * ng);
   KTimer tm(ctx, s);

@@ -110,7 +110,8 @@ class GroupedDeployment:
         self.client = Client(self.ctx, prm)
         self.client.keygen(key_draws_fn(self.galois), self.galois)
         kl = prm.L + 1 + prm.K
-        self.key_bytes = len(self.galois) * prm.dnum * 2 * kl * prm.N * 8
+        # per key: Montgomery-form words plus the 40-bit planes of the b halves
+        self.key_bytes = len(self.galois) * prm.dnum * kl * prm.N * (16 + 5)
         self.plan_bytes = sum(len(sp.diag) * (level + 1 + prm.K) * prm.N * 8 for sp in self.specs)
 
     def group_of(self, table: int) -> int:
