@@ -303,8 +303,8 @@ int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *o
  * of the NTT's column and block passes; 0 picks the narrow shape for launches
  * of fewer than "ntt_small_limbs" limbs (default 48).  Results do not depend
  * on the knobs.  "gen_key_a" lets kernels that use every key word once
- * regenerate seeded keys' a_j halves instead of reading them: 0 never, 1
- * (default) on primes below 2^40 (one generator output per word), 2 on every
+ * regenerate seeded keys' a_j halves instead of reading them: 0 never, 1 on
+ * primes below 2^40 (one generator output per word), 2 (default) on every
  * prime.
  * "limb_xcd" (0, default, or 1): the key-switching kernels deal coefficient
  * blocks over all 8 XCDs, or give each XCD whole limbs (a limb's rotated words
