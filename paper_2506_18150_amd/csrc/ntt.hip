@@ -26,30 +26,19 @@ namespace {
 // w' = p1 2^32 + p0, floor(y w' / 2^64) is y1 p1 + hi(y1 p0) + hi(y0 p1)
 // plus 0, 1 or 2 (the dropped low terms are below 3 2^64), so
 // y w - qh q lies in [0, 4q) for any 64-bit y (Shoup: [0, 2q) with the exact
-// quotient).
-__device__ __forceinline__ u64 shoup_lazy4(u64 y, u64 w, u64 wp, u64 q) {
+// quotient).  NEG forms it as y w + qh (2^64 - q) mod 2^64 (nq = 2^64 - q):
+// both products go through the 32-bit multiply-adds into one sum with no
+// borrow chain; fewer instructions, more live registers.
+template <bool NEG>
+__device__ __forceinline__ u64 shoup_lazy4(u64 y, u64 w, u64 wp, u64 q, u64 nq) {
   const uint32_t y0 = (uint32_t)y, y1 = (uint32_t)(y >> 32), p0 = (uint32_t)wp, p1 = (uint32_t)(wp >> 32);
   const u64 qh = (u64)y1 * p1 + __umulhi(y1, p0) + __umulhi(y0, p1);
-  return y * w - qh * q;
-}
-
-// Integer butterflies on lazy values in [0, 8q) (q < 2^60, so 16 q < 2^64).
-// Forward: X = x mod 4q in [0, 4q), T in [0, 4q): X + T and X - T + 4q stay
-// in [0, 8q).  Inverse: x + y reduced once by 8q, and (x - y + 8q) w.
-__device__ __forceinline__ void ct_bfly(u64 &x, u64 &y, const TW &t, u64 q, u64 q4) {
-  const u64 X = x >= q4 ? x - q4 : x;
-  const u64 T = shoup_lazy4(y, t.w, t.wp, q);
-  x = X + T;
-  y = X - T + q4;
-}
-
-__device__ __forceinline__ void gs_bfly(u64 &x, u64 &y, const TW &t, u64 q, u64 q4) {
-  const u64 q8 = 2 * q4;
-  u64 S = x + y;
-  S = S >= q8 ? S - q8 : S;
-  const u64 D = x - y + q8;
-  x = S;
-  y = shoup_lazy4(D, t.w, t.wp, q);
+  if (!NEG) return y * w - qh * q;
+  const uint32_t h0 = (uint32_t)qh, h1 = (uint32_t)(qh >> 32);
+  const uint32_t w0 = (uint32_t)w, w1 = (uint32_t)(w >> 32), n0 = (uint32_t)nq, n1 = (uint32_t)(nq >> 32);
+  const u64 lo = (u64)y0 * w0 + (u64)h0 * n0;
+  const uint32_t hi = (uint32_t)(lo >> 32) + y0 * w1 + y1 * w0 + h0 * n1 + h1 * n0;
+  return ((u64)hi << 32) | (uint32_t)lo;
 }
 
 // Workgroup shape of one pass.  The column pass keeps WC consecutive columns
@@ -105,19 +94,37 @@ __device__ __forceinline__ int col_idx(int w, int r) {
 // is stored as raw fp64 bits; fp64 FMA runs at the full VALU rate on gfx950.
 
 constexpr u64 FLT_LIMIT = 1ull << 41;
+constexpr long NTT_ORDER_MAX_LIMBS = 128;   // column passes of launches of up to this many limbs reorder them
 
+// Integer butterflies on lazy values in [0, 8q) (q < 2^60, so 16 q < 2^64).
+// Forward: X = x mod 4q in [0, 4q), T in [0, 4q): X + T and X - T + 4q stay
+// in [0, 8q).  Inverse: x + y reduced once by 8q, and (x - y + 8q) w.  With
+// NEG a multiple of q is subtracted by adding its negation mod 2^64.
+template <bool NEG>
 struct IntA {
   using V = u64;
   using T = TW;
-  u64 q, q4;
+  u64 q, q4, nq, nq4;   // nq = 2^64 - q, nq4 = 2^64 - 4q
   const TW *tw;
   __device__ __forceinline__ V load(u64 x) const { return x; }
   __device__ __forceinline__ u64 bits(V v) const { return v; }
   __device__ __forceinline__ V unbits(u64 b) const { return b; }
   // value stored between the passes (lazy)
   __device__ __forceinline__ u64 mid(V v, bool) const { return v; }
-  __device__ __forceinline__ void ct(V &x, V &y, const T &t) const { ct_bfly(x, y, t, q, q4); }
-  __device__ __forceinline__ void gs(V &x, V &y, const T &t) const { gs_bfly(x, y, t, q, q4); }
+  __device__ __forceinline__ void ct(V &x, V &y, const T &t) const {
+    const u64 X = x >= q4 ? (NEG ? x + nq4 : x - q4) : x;
+    const u64 T = shoup_lazy4<NEG>(y, t.w, t.wp, q, nq);
+    x = X + T;
+    y = X - T + q4;
+  }
+  __device__ __forceinline__ void gs(V &x, V &y, const T &t) const {
+    const u64 q8 = 2 * q4;
+    u64 S = x + y;
+    S = S >= q8 ? (NEG ? S + 2 * nq4 : S - q8) : S;
+    const u64 D = x - y + q8;
+    x = S;
+    y = shoup_lazy4<NEG>(D, t.w, t.wp, q, nq);
+  }
   // [0, 8q) -> [0, q)
   __device__ __forceinline__ u64 canon(V v) const {
     v = v >= q4 ? v - q4 : v;
@@ -377,9 +384,32 @@ __global__ __launch_bounds__((Shape<H, COLS, WS>::T)) void ntt_pass_kernel(const
     FltA ar{pi.qd, pi.qinv_d, twdtab + (size_t)p * N};
     pass_body<H, FWD, COLS, WS>(ar, lds, raw, out, part, bat, li, pi, epi);
   } else {
-    IntA ar{pi.q, 4 * pi.q, twtab + (size_t)p * N};
+    // the forward block pass (the one with the fused epilogues) keeps the
+    // borrow-chain form: the other holds more registers there and loses a
+    // wave per SIMD
+    IntA<!(FWD && !COLS)> ar{pi.q, 4 * pi.q, 0 - pi.q, 0 - 4 * pi.q, twtab + (size_t)p * N};
     pass_body<H, FWD, COLS, WS>(ar, lds, raw, out, part, bat, li, pi, epi);
   }
+}
+
+// The same limbs with those of primes of 41 bits and more first.  Their
+// workgroups take the integer butterflies, several times the instructions of
+// the fp64 ones; dispatched first they start early and the shorter fp64
+// workgroups fill in behind them.  Each entry keeps its own offsets, so the
+// order changes nothing in the result (a fused epilogue, which is indexed by
+// position, is never given a reordered list).
+LimbList int_first(const helrm_ctx *ctx, const LimbList &ll) {
+  LimbList o = ll;
+  int k = 0;
+  for (int pass = 0; pass < 2; pass++)
+    for (int i = 0; i < ll.n; i++)
+      if ((ctx->primes[ll.prime[i]] >= FLT_LIMIT) == (pass == 0)) {
+        o.src_off[k] = ll.src_off[i];
+        o.dst_off[k] = ll.dst_off[i];
+        o.prime[k] = ll.prime[i];
+        k++;
+      }
+  return o;
 }
 
 // Column-pass and block-pass workgroup widths (sub-transforms per workgroup):
@@ -395,23 +425,27 @@ int launch_ntt_hw(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, 
   second.src_bstride = ll.dst_bstride;
   const int gc = ll.n * batch * SC::WPL, gb = ll.n * batch * SB::WPL;
   if (gc == 0) return HELRM_OK;
+  // integer limbs first where measured faster: the inverse block pass, and
+  // the column passes of launches that fill the chip about once
+  const bool few = (long)ll.n * batch <= NTT_ORDER_MAX_LIMBS;
   // per pass and limb: N words read and written, (N/2) log2(R) butterflies
   const double limbs = (double)ll.n * batch;
   const double bytes = limbs * 16.0 * SC::N, ops = limbs * (SC::N / 2) * (2 * H);
   KTimer tm(ctx, s);
   if (forward) {
-    hipLaunchKernelGGL((ntt_pass_kernel<H, true, true, WC>), dim3(gc), dim3(SC::T), 0, s, src, dst, ll,
-                       ctx->d_tw_fwd, ctx->d_twd_fwd, ctx->d_pinfo, NttEpi{});
+    hipLaunchKernelGGL((ntt_pass_kernel<H, true, true, WC>), dim3(gc), dim3(SC::T), 0, s, src, dst,
+                       few ? int_first(ctx, ll) : ll, ctx->d_tw_fwd, ctx->d_twd_fwd, ctx->d_pinfo, NttEpi{});
     tm.lap(TK_NTT_FWD_COL, bytes, ops);
     hipLaunchKernelGGL((ntt_pass_kernel<H, true, false, WB>), dim3(gb), dim3(SB::T), 0, s, dst, dst,
                        second, ctx->d_tw_fwd, ctx->d_twd_fwd, ctx->d_pinfo, epi);
     tm.lap(TK_NTT_FWD_BLK, bytes + (double)epi.n_fin * batch * 8.0 * SC::N, ops);
   } else {
-    hipLaunchKernelGGL((ntt_pass_kernel<H, false, false, WB>), dim3(gb), dim3(SB::T), 0, s, src, dst, ll,
-                       ctx->d_tw_inv, ctx->d_twd_inv, ctx->d_pinfo, NttEpi{});
+    hipLaunchKernelGGL((ntt_pass_kernel<H, false, false, WB>), dim3(gb), dim3(SB::T), 0, s, src, dst,
+                       int_first(ctx, ll), ctx->d_tw_inv, ctx->d_twd_inv, ctx->d_pinfo, NttEpi{});
     tm.lap(TK_NTT_INV_BLK, bytes, ops);
     hipLaunchKernelGGL((ntt_pass_kernel<H, false, true, WC>), dim3(gc), dim3(SC::T), 0, s, dst, dst,
-                       second, ctx->d_tw_inv, ctx->d_twd_inv, ctx->d_pinfo, NttEpi{});
+                       few ? int_first(ctx, second) : second, ctx->d_tw_inv, ctx->d_twd_inv, ctx->d_pinfo,
+                       NttEpi{});
     tm.lap(TK_NTT_INV_COL, bytes, ops);
   }
   HIP_TRY(hipGetLastError());
