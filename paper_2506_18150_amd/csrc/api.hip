@@ -1260,7 +1260,8 @@ extern "C" int helrm_plan_create(helrm_ctx *c, const helrm_plan_desc *d, helrm_p
     helrm_plan_destroy(p);
     return code;
   };
-  if (hipMalloc(&p->d_pt, (size_t)d->n_diag * pqn * N * sizeof(u64)) != hipSuccess ||
+  p->pt_words = (size_t)d->n_diag * pqn * N;
+  if (hipMalloc(&p->d_pt, pt_bytes(p->pt_words)) != hipSuccess ||
       hipMalloc(&p->d_slot, p->slot.size() * sizeof(int)) != hipSuccess ||
       hipMalloc(&dcoef, (size_t)d->n_diag * N * sizeof(int64_t)) != hipSuccess) {
     (void)hipGetLastError();
@@ -1278,6 +1279,7 @@ extern "C" int helrm_plan_create(helrm_ctx *c, const helrm_plan_desc *d, helrm_p
   if ((rc = launch_from_signed(c, dcoef, p->d_pt, ll, d->n_diag, 0)) != HELRM_OK) return fail(rc);
   if ((rc = launch_ntt(c, p->d_pt, p->d_pt, ll, d->n_diag, true, 0)) != HELRM_OK) return fail(rc);
   if ((rc = launch_to_mont(c, p->d_pt, ll, d->n_diag, 0)) != HELRM_OK) return fail(rc);
+  if ((rc = launch_pack_pt(p->d_pt, p->pt_words, 0)) != HELRM_OK) return fail(rc);
   if (hipDeviceSynchronize() != hipSuccess) {
     set_error("plan preparation failed on the device");
     return fail(HELRM_EHIP);

@@ -312,6 +312,17 @@ __device__ __forceinline__ u64 key_b40(const u64 *key, int dnum, int keyl, int N
   return (u64)lo[i] | ((u64)hi[i] << 32);
 }
 
+// Plaintext diagonals of a plan: [n_diag][L_pq][N] words in Montgomery form,
+// then the same words as 40-bit values (a u32 low plane, then a u8 high
+// plane), which the per-thread baby-step kernel reads on the limbs of primes
+// below 2^40: 5 bytes a word instead of 8.
+__host__ __device__ inline size_t pt_bytes(size_t words) { return words * 8 + ((words * 5 + 7) & ~(size_t)7); }
+__device__ __forceinline__ u64 pt_b40(const u64 *pt, size_t words, size_t i) {
+  const uint32_t *lo = (const uint32_t *)(pt + words);
+  const uint8_t *hi = (const uint8_t *)(lo + words);
+  return (u64)lo[i] | ((u64)hi[i] << 32);
+}
+
 struct KeyEntry {
   u64 *d;            // [dnum][2][L+1+K][N], Montgomery form
   u64 seed = 0;      // seed the a_j halves were expanded from
@@ -398,7 +409,8 @@ struct helrm_plan {
   std::vector<int> babies;               // b values present (ascending)
   std::vector<int> giants;               // g values present (ascending)
   std::vector<int> slot;                 // [n2][n1]: stored diagonal index or -1
-  u64 *d_pt = nullptr;                   // [n_diag][L_pq][N], Montgomery form
+  u64 *d_pt = nullptr;                   // [n_diag][L_pq][N], Montgomery form, then its 40-bit planes
+  size_t pt_words = 0;                   // n_diag * L_pq * N
   int *d_slot = nullptr;                 // device copy of slot
   size_t pt_limb_stride;                 // limbs per stored diagonal (= level+1+K)
 };
@@ -469,6 +481,7 @@ int launch_from_signed(helrm_ctx *ctx, const int64_t *in, u64 *out, const LimbLi
                        hipStream_t s);
 int launch_to_mont(helrm_ctx *ctx, u64 *data, const LimbList &ll, int batch, hipStream_t s);
 // Fill a key's 40-bit planes of the b halves from its Montgomery-form words.
+int launch_pack_pt(u64 *pt, size_t words, hipStream_t s);
 int launch_pack_key(helrm_ctx *ctx, u64 *key, hipStream_t s);
 int launch_copy_limbs(const u64 *src, u64 *dst, const LimbList &ll, int batch, int N, hipStream_t s);
 

@@ -507,10 +507,15 @@ struct StepIn {
 template <int GT, int BT, int BETA, class M, bool GEN>
 __device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeom &G, int batch, int x, int r,
                                               int b0, int p, const PrimeInfo &pi, const u64 *digits,
-                                              size_t dig_bs, const u64 *ct, size_t ct_bs, const u64 *pt, int ng,
-                                              u64 *X, size_t x_bs, int accum) {
+                                              size_t dig_bs, const u64 *ct, size_t ct_bs, const u64 *pt,
+                                              size_t pt_words, int ng, u64 *X, size_t x_bs, int accum) {
   const int N = 1 << G.logn;
-  constexpr bool NARROW = std::is_same<M, SplitMac>::value;   // prime below 2^40: b halves from the 40-bit planes
+  // prime below 2^40: key b halves and plaintexts from their 40-bit planes
+  constexpr bool NARROW = std::is_same<M, SplitMac>::value;
+  auto ptw = [&](int s) -> u64 {
+    const size_t i = ((size_t)s * G.pqn + r) * N + x;
+    return NARROW ? pt_b40(pt, pt_words, i) : pt[i];
+  };
   const bool isq = r <= G.level;
   const int nct = min(BT, batch - b0);
   M acc[BT][GT][2];
@@ -526,7 +531,7 @@ __device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeo
 #pragma unroll
     for (int gi = 0; gi < GT; gi++) {
       const int s = gi < ng ? BA.slot0[gi] : -1;
-      w[gi] = M::prep(s >= 0 ? pt[((size_t)s * G.pqn + r) * N + x] : 0);
+      w[gi] = M::prep(s >= 0 ? ptw(s) : 0);
     }
 #pragma unroll
     for (int k = 0; k < BT; k++) {
@@ -562,7 +567,7 @@ __device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeo
 #pragma unroll
     for (int gi = 0; gi < GT; gi++) {
       const int s = gi < ng ? BA.slot[i][gi] : -1;
-      in.w[gi] = s >= 0 ? pt[((size_t)s * G.pqn + r) * N + x] : 0;
+      in.w[gi] = s >= 0 ? ptw(s) : 0;
     }
   };
   auto step = [&](const StepIn<GT, BT, BETA> &in) {
@@ -627,11 +632,12 @@ __device__ __forceinline__ void baby_mac_body(const BabyArgs &BA, const LevelGeo
   }
 }
 
+// One ciphertext and one giant output per thread: five waves per SIMD (at
+// most 96 registers, a few of them spilled) measured faster than four.
 template <int GT, int BT, int BETA, bool GEN>
-__global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G, int L, int batch, int ntiles,
-                                                       const u64 *digits, size_t dig_bs, const u64 *ct,
-                                                       size_t ct_bs, const u64 *pt, int ng, u64 *X, size_t x_bs,
-                                                       int accum, const PrimeInfo *pinfo) {
+__global__ __launch_bounds__(TPB, (GT * BT == 1 ? 5 : 1)) void baby_mac_kernel(
+    BabyArgs BA, LevelGeom G, int L, int batch, int ntiles, const u64 *digits, size_t dig_bs, const u64 *ct,
+    size_t ct_bs, const u64 *pt, size_t pt_words, int ng, u64 *X, size_t x_bs, int accum, const PrimeInfo *pinfo) {
   const int N = 1 << G.logn;
   const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles, G.pqn, G.limb_xcd);
   const int x = tm.xb * TPB + threadIdx.x;
@@ -639,13 +645,13 @@ __global__ __launch_bounds__(TPB) void baby_mac_kernel(BabyArgs BA, LevelGeom G,
   const PrimeInfo pi = pinfo[p];
   if (pi.q < SPLIT_MAC_LIMIT)
     baby_mac_body<GT, BT, BETA, SplitMac, GEN>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs, ct,
-                                               ct_bs, pt, ng, X, x_bs, accum);
+                                               ct_bs, pt, pt_words, ng, X, x_bs, accum);
   else if (GEN && G.gen_wide)
     baby_mac_body<GT, BT, BETA, WideOf<GT * BT>, GEN>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits, dig_bs,
-                                                      ct, ct_bs, pt, ng, X, x_bs, accum);
+                                                      ct, ct_bs, pt, pt_words, ng, X, x_bs, accum);
   else
     baby_mac_body<GT, BT, BETA, WideOf<GT * BT>, false>(BA, G, batch, x, tm.r, tm.tile * BT, p, pi, digits,
-                                                        dig_bs, ct, ct_bs, pt, ng, X, x_bs, accum);
+                                                        dig_bs, ct, ct_bs, pt, pt_words, ng, X, x_bs, accum);
 }
 
 // The same product for launches with several giant outputs and a batch.  A
@@ -912,6 +918,23 @@ int launch_pack_key(helrm_ctx *ctx, u64 *key, hipStream_t s) {
   uint32_t *lo = (uint32_t *)(key + key_words(ctx->dnum, keyl, ctx->N));
   uint8_t *hi = (uint8_t *)(lo + (size_t)ctx->dnum * keyl * ctx->N);
   hipLaunchKernelGGL(pack_key_kernel, ew_grid(ctx, ctx->dnum * keyl), dim3(TPB), 0, s, key, lo, hi, keyl, ctx->N);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+__global__ __launch_bounds__(TPB) void pack40_kernel(const u64 *in, uint32_t *lo, uint8_t *hi, size_t n) {
+  const size_t i = (size_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  const u64 v = in[i];
+  lo[i] = (uint32_t)v;
+  hi[i] = (uint8_t)(v >> 32);
+}
+
+int launch_pack_pt(u64 *pt, size_t words, hipStream_t s) {
+  if (words == 0) return HELRM_OK;
+  uint32_t *lo = (uint32_t *)(pt + words);
+  uint8_t *hi = (uint8_t *)(lo + words);
+  hipLaunchKernelGGL(pack40_kernel, dim3((unsigned)((words + TPB - 1) / TPB)), dim3(TPB), 0, s, pt, lo, hi, words);
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
 }
@@ -1197,7 +1220,11 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
                                                                              : ctx->tune_baby_tile);
   const bool gen = !shared_path && bt_path == 1 && gt <= 2 && seeded && BA.nrot > 0 && ctx->tune_gen_key_a >= 1;
   const double kl = key_limb_words(ctx, level, gen, G.gen_wide, beta, !shared_path);
-  const double words = nrot * kl + (qn + K) * npt + qn * B * (nrot * (beta + 1) + 2 * has0 + xw * ng) +
+  // plaintext words per coefficient: 5 bytes on the 40-bit limbs of the per-thread kernel
+  double pl = 0;
+  for (int r = 0; r < level + 1 + ctx->K; r++)
+    pl += !shared_path && ctx->primes[ctx->pq_prime(r, level)] < SPLIT_MAC_LIMIT ? 5.0 / 8.0 : 1.0;
+  const double words = nrot * kl + pl * npt + qn * B * (nrot * (beta + 1) + 2 * has0 + xw * ng) +
                        K * B * (nrot * beta + xw * ng);
   KTimer tm(ctx, s);
   if (ng >= 2 && batch >= 2 && ctx->tune_baby_share >= 2) {
@@ -1232,8 +1259,8 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
     const int grid = (ctx->N / TPB) * G.pqn * ntiles;
 #define BABY(GT_, BT_, BETA_, GEN_)                                                                      \
   hipLaunchKernelGGL((baby_mac_kernel<GT_, BT_, BETA_, GEN_>), dim3(grid), dim3(TPB), 0, s, BA, G,        \
-                     ctx->L, batch, ntiles, digits, digits_bstride, ct, ct_bstride, plan->d_pt, ng, X,     \
-                     x_bstride, accum ? 1 : 0, ctx->d_pinfo)
+                     ctx->L, batch, ntiles, digits, digits_bstride, ct, ct_bstride, plan->d_pt,            \
+                     plan->pt_words, ng, X, x_bstride, accum ? 1 : 0, ctx->d_pinfo)
 #define BABY_B(GT_, BT_, GEN_)                      \
   switch (G.beta) {                                 \
     case 1: BABY(GT_, BT_, 1, GEN_); break;         \

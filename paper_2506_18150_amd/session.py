@@ -112,7 +112,7 @@ class GroupedDeployment:
         kl = prm.L + 1 + prm.K
         # per key: Montgomery-form words plus the 40-bit planes of the b halves
         self.key_bytes = len(self.galois) * prm.dnum * kl * prm.N * (16 + 5)
-        self.plan_bytes = sum(len(sp.diag) * (level + 1 + prm.K) * prm.N * 8 for sp in self.specs)
+        self.plan_bytes = sum(len(sp.diag) * (level + 1 + prm.K) * prm.N * (8 + 5) for sp in self.specs)
 
     def group_of(self, table: int) -> int:
         for g, grp in enumerate(self.groups):
