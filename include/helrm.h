@@ -202,7 +202,10 @@ typedef struct {
 } helrm_plan_desc;
 
 /* Reduce the plan's coefficients over the extended basis at its level, take
- * them to evaluation form on the device and keep them resident.  Blocks. */
+ * them to evaluation form on the device and keep them resident, each word
+ * also as a 40-bit value (the per-ciphertext baby-step kernel streams the
+ * limbs of primes below 2^40 in 5 bytes): n_diag (level+1+K) N (8 + 5)
+ * bytes.  Blocks. */
 int helrm_plan_create(helrm_ctx *ctx, const helrm_plan_desc *desc, helrm_plan **out);
 int helrm_plan_destroy(helrm_plan *plan);
 
