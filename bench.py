@@ -231,7 +231,7 @@ def serve_bench(args):
 
     import synth
     from paper_2506_18150_amd import params, planner
-    from paper_2506_18150_amd.serving import GpuExecutor, RealClock, Request, Server
+    from paper_2506_18150_amd.serving import GpuExecutor, RealClock, Request, Server, Unit
     from paper_2506_18150_amd.session import GroupedDeployment
 
     prm = params.n16()
@@ -252,6 +252,15 @@ def serve_bench(args):
     setup_s = time.time() - t0
     total = torch.cuda.get_device_properties(0).total_memory
     static = dep.key_bytes + dep.plan_bytes
+    # warm-up: every group at every batch size the served mode can form, so
+    # that no first launch of a kernel falls inside a measured span
+    wx = GpuExecutor(dep.ctx, dep.plans, args.level, prm.N, n_streams=1, max_batch=args.max_batch,
+                     static_bytes=static)
+    for g in range(len(dep.groups)):
+        for b in range(1, args.max_batch + 1):
+            wx.launch(0, g, [Unit(None, g, pool[g][k % len(pool[g])], 0.0) for k in range(b)])
+    torch.cuda.synchronize()
+    del wx
     out = {"rates": []}
     rg = synth.rng(12)
     for rate in [float(x) for x in args.rates.split(",")]:
