@@ -393,7 +393,7 @@ __global__ __launch_bounds__((Shape<H, COLS, WS>::T)) void ntt_pass_kernel(const
 }
 
 // The same limbs with those of primes of 41 bits and more first.  Their
-// workgroups take the integer butterflies, several times the instructions of
+// workgroups take the integer butterflies, about 2.5 times the instructions of
 // the fp64 ones; dispatched first they start early and the shorter fp64
 // workgroups fill in behind them.  Each entry keeps its own offsets, so the
 // order changes nothing in the result (a fused epilogue, which is indexed by
