@@ -360,7 +360,10 @@ int do_moddown_modup(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *z, 
     a.prime[K + i] = ctx->pq_prime(i, level);
   }
   TRY(launch_ntt(ctx, X, C, a, batch, false, s));
-  // 2.
+  // 2.  With digits of K limbs each, the ModDown of c1 runs in front of each
+  // digit's ModUp conversion (step 3) and only t0's conversion is a job here
+  bool fuse = ctx->tune_fuse_conv && beta + 1 <= HELRM_MAX_CONV_JOBS && ctx->moddown_tabs[level].nin == K;
+  for (int j = 0; j < beta; j++) fuse = fuse && ctx->digit_hi(j, level) - ctx->digit_lo(j) == K;
   ConvSpec md[2];
   for (int c = 0; c < 2; c++) {
     md[c].t = &ctx->moddown_tabs[level];
@@ -369,7 +372,6 @@ int do_moddown_modup(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *z, 
   }
   md[1].fin = CONV_FIN_MODDOWN;
   md[1].fin_off0 = K;
-  TRY(launch_conv(ctx, md, 2, C, c_bs, nullptr, 0, F, f_bs, batch, s));
   // 3.
   ConvSpec up[HELRM_MAX_CONV_JOBS];
   LimbList f = ll_make(0, f_bs, f_bs);
@@ -403,10 +405,17 @@ int do_moddown_modup(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *z, 
     }
   }
   for (int j = 0; j < beta; j++) {
-    ConvSpec &sp = up[j];
+    ConvSpec &sp = up[fuse ? j + 1 : j];
     sp.t = &ctx->modup_tabs[level][j];
     const int lo = ctx->digit_lo(j), hi = ctx->digit_hi(j, level);
     sp.src_off0 = qn + lo;
+    if (fuse) {   // inputs z1 on the digit's limbs, formed from C and written to F
+      sp.pre = &ctx->moddown_tabs[level];
+      sp.pre_src0 = K + qn;
+      sp.pre_a0 = K + lo;
+      sp.pre_col0 = lo;
+      sp.pre_dst0 = qn + lo;
+    }
     int k = 0;
     for (int r = 0; r < pqn; r++) {
       if (r >= lo && r < hi) continue;
@@ -418,7 +427,13 @@ int do_moddown_modup(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *z, 
       f.n++;
     }
   }
-  TRY(launch_conv(ctx, up, beta, F, f_bs, nullptr, 0, F, f_bs, batch, s));
+  if (fuse) {
+    up[0] = md[0];
+    TRY(launch_conv(ctx, up, beta + 1, C, c_bs, nullptr, 0, F, f_bs, batch, s));
+  } else {
+    TRY(launch_conv(ctx, md, 2, C, c_bs, nullptr, 0, F, f_bs, batch, s));
+    TRY(launch_conv(ctx, up, beta, F, f_bs, nullptr, 0, F, f_bs, batch, s));
+  }
   // 4.
   TRY(launch_ntt_epi(ctx, F, F, f, batch, true, s, e));
   return HELRM_OK;
@@ -1443,6 +1458,9 @@ extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
   } else if (strcmp(knob, "ntt_blk_w") == 0) {
     CHECK_ARG(value == 0 || value == 4 || value == 8, "ntt_blk_w must be 0, 4 or 8");
     c->tune_ntt_blk_w = value;
+  } else if (strcmp(knob, "fuse_conv") == 0) {
+    CHECK_ARG(value == 0 || value == 1, "fuse_conv must be 0 or 1");
+    c->tune_fuse_conv = value;
   } else if (strcmp(knob, "ntt_small_limbs") == 0) {
     CHECK_ARG(value >= 0, "ntt_small_limbs must be >= 0");
     c->ntt_small_limbs = value;

@@ -380,6 +380,7 @@ struct helrm_ctx {
   int ntt_small_limbs = 48;  // launches of fewer limbs take the narrow shapes when a width is 0
   int tune_limb_xcd = 0;      // key-switching kernels: whole limbs per XCD (1) or blocks dealt over the XCDs (0)
   int tune_fuse_ks = 1;       // ModDown fused with the ModUp or rescale that follows it (0 = off)
+  int tune_fuse_conv = 1;   // fused boundary: c1's ModDown inside the ModUp conversions (digits of K limbs)
   int tune_conv_wgs = 1536;  // base conversion: split outputs into chunks until a launch has this many workgroups (0 = off)
   int tune_gen_key_a = 2;    // regenerate keys' a_j halves from their seeds where a kernel serves one
                              // ciphertext per thread and streams keys: 0 never, 1 on primes below
@@ -505,6 +506,14 @@ struct ConvSpec {
   int fin = CONV_FIN_NONE;
   int fin_off0 = 0;
   const TW *qlinv = nullptr;
+  // A ModDown in front (fused boundary, pre = table of the ModDown P -> Q_l,
+  // whose number of special primes equals this job's input count): input i
+  // is not read but formed as z_i = (A_i - conv_{c_i}) P^-1 mod q_i, conv
+  // the conversion of the special limbs pre_src0 + k of the source to Q limb
+  // c_i = pre_col0 + i, A_i the coefficient-form Q limb pre_a0 + i of the
+  // source; z_i is also written to limb pre_dst0 + i of the destination.
+  const ConvTable *pre = nullptr;
+  int pre_src0 = 0, pre_a0 = 0, pre_col0 = 0, pre_dst0 = 0;
 };
 int launch_conv(helrm_ctx *ctx, const ConvSpec *specs, int nspecs, const u64 *src, int src_bstride,
                 const u64 *copy_src, int copy_bstride, u64 *dst, int dst_bstride, int batch, hipStream_t s);

@@ -128,6 +128,12 @@ struct ConvJob {
   int fin;            // CONV_FIN_* (ConvSpec)
   int fin_off0;       // A_r is limb fin_off0 + r of src
   const TW *qlinv;    // CONV_FIN_RESCALE: q_l^-1 mod q_r for r < l
+  // ModDown in front (ConvSpec::pre): special primes pre_prime0 + k, their
+  // (P/p_k)^-1 mod p_k and the [K][pre_ncol] Montgomery-form [P/p_k]_q matrix
+  int pre;            // 0: inputs read from src
+  int pre_src0, pre_a0, pre_col0, pre_dst0, pre_ncol, pre_prime0;
+  const TW *pre_hat_inv;
+  const u64 *pre_hat_mont;
 };
 
 struct ConvJobs {
@@ -153,11 +159,17 @@ constexpr int CONV_TPB = 256;
 // Q limb of the input; with the rescale as well, every chunk also forms the
 // top output z_l and writes (z_r - [t - h]_{q_r}) q_l^-1 for r < l, where
 // t = (z_l + h) mod q_l and h = floor(q_l / 2) (rounding division by q_l).
-template <int NIN>
+// With a ModDown in front (a ModUp digit of a fused boundary; PRE kernels)
+// the thread forms the digit's inputs z_i from the special limbs in the same
+// way and writes them; the ModDown's own launch and the re-read of z are
+// saved.  Such launches are not split into output chunks (each chunk would
+// form z again).
+template <int NIN, bool PRE>
 __global__ __launch_bounds__(CONV_TPB) void conv_kernel(const ConvJobs J, const u64 *src, int src_bstride,
                                                         const u64 *copy_src, int copy_bstride, u64 *dst,
                                                         int dst_bstride, const PrimeInfo *pinfo, int N) {
   __shared__ u64 cm[NIN * HELRM_MAX_PRIMES];
+  __shared__ u64 cpre[PRE ? NIN * NIN : 1];
   __shared__ u64 oq[HELRM_MAX_PRIMES], oqn[HELRM_MAX_PRIMES], opi[HELRM_MAX_PRIMES], opp[HELRM_MAX_PRIMES],
       omu[HELRM_MAX_PRIMES];
   const int chunk = blockIdx.x % J.nchunks;
@@ -170,6 +182,9 @@ __global__ __launch_bounds__(CONV_TPB) void conv_kernel(const ConvJobs J, const 
   const int per = (nw + J.nchunks - 1) / J.nchunks;
   const int r0 = chunk * per, r1 = min(nw, r0 + per);
   for (int k = threadIdx.x; k < NIN * nout; k += CONV_TPB) cm[k] = split30(jb.t.hat_mont[k]);
+  if (PRE && jb.pre)
+    for (int k = threadIdx.x; k < NIN * NIN; k += CONV_TPB)
+      cpre[k] = split30(jb.pre_hat_mont[(k / NIN) * jb.pre_ncol + jb.pre_col0 + k % NIN]);
   for (int k = threadIdx.x; k < nout; k += CONV_TPB) {
     const PrimeInfo &po = pinfo[jb.t.out_prime[k]];
     oq[k] = po.q;
@@ -179,15 +194,39 @@ __global__ __launch_bounds__(CONV_TPB) void conv_kernel(const ConvJobs J, const 
     omu[k] = po.mu;
   }
   u64 y[NIN];
-  if (r0 < r1) {
+  if (PRE && jb.pre) {
+    // the special limbs, (P/p_k)^-1 applied
+    u64 yp[NIN];
+#pragma unroll
+    for (int k = 0; k < NIN; k++) {
+      const u64 q = pinfo[jb.pre_prime0 + k].q;
+      const u64 v = src[limb_ptr(bat, src_bstride, jb.pre_src0 + k, N) + x];
+      yp[k] = split30(shoup(v, jb.pre_hat_inv[k].w, jb.pre_hat_inv[k].wp, q));
+    }
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < NIN; i++) {
-      const u64 q = pinfo[jb.t.in_prime[i]].q;
-      const u64 v = src[limb_ptr(bat, src_bstride, jb.src_off0 + i, N) + x];
-      y[i] = split30(shoup(v, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, q));
+      const PrimeInfo &pq = pinfo[jb.t.in_prime[i]];
+      Sum30 a;
+      a.zero();
+#pragma unroll
+      for (int k = 0; k < NIN; k++) a.mac(yp[k], cpre[k * NIN + i]);
+      const u64 A = src[limb_ptr(bat, src_bstride, jb.pre_a0 + i, N) + x];
+      const u64 z = shoup(sub_mod(A, redc_acc(a.value(), pq.q, pq.qn), pq.q), pq.pinv, pq.pinv_p, pq.q);
+      if (chunk == 0) dst[limb_ptr(bat, dst_bstride, jb.pre_dst0 + i, N) + x] = z;
+      y[i] = split30(shoup(z, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, pq.q));
     }
+  } else {
+    if (r0 < r1) {
+#pragma unroll
+      for (int i = 0; i < NIN; i++) {
+        const u64 q = pinfo[jb.t.in_prime[i]].q;
+        const u64 v = src[limb_ptr(bat, src_bstride, jb.src_off0 + i, N) + x];
+        y[i] = split30(shoup(v, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, q));
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   // converted (and finished) output r
   auto outv = [&](int r) -> u64 {
     Sum30 a;
@@ -995,9 +1034,31 @@ int launch_conv(helrm_ctx *ctx, const ConvSpec *specs, int nspecs, const u64 *sr
       jb.fin = sp.fin;
       jb.fin_off0 = sp.fin_off0;
       jb.qlinv = sp.qlinv;
+      jb.pre = sp.pre ? 1 : 0;
+      if (sp.pre) {
+        if (sp.pre->nin != nin || sp.pre_col0 + nin > sp.pre->nout) {
+          set_error("conv: a fused ModDown needs as many special primes as inputs");
+          return HELRM_EINVAL;
+        }
+        jb.pre_src0 = sp.pre_src0;
+        jb.pre_a0 = sp.pre_a0;
+        jb.pre_col0 = sp.pre_col0;
+        jb.pre_dst0 = sp.pre_dst0;
+        jb.pre_ncol = sp.pre->nout;
+        jb.pre_prime0 = sp.pre->in_prime[0];
+        for (int k = 1; k < nin; k++)
+          if (sp.pre->in_prime[k] != jb.pre_prime0 + k) {
+            set_error("conv: a fused ModDown needs consecutive special primes");
+            return HELRM_EINVAL;
+          }
+        jb.pre_hat_inv = sp.pre->hat_inv;
+        jb.pre_hat_mont = sp.pre->hat_mont;
+      }
       const int nw = sp.fin == CONV_FIN_RESCALE ? sp.t->nout - 1 : sp.t->nout;
-      words += sp.t->nin + nw + 2.0 * sp.ncopy + (sp.fin != CONV_FIN_NONE ? sp.t->nout : 0);
-      macs += (double)sp.t->nin * sp.t->nout;
+      // with a ModDown in front: K special and nin A limbs read, nin z limbs written
+      words += (sp.pre ? 3.0 * sp.t->nin : sp.t->nin) + nw + 2.0 * sp.ncopy +
+               (sp.fin != CONV_FIN_NONE ? sp.t->nout : 0);
+      macs += (double)sp.t->nin * (sp.t->nout + (sp.pre ? sp.t->nin : 0));
     }
     // output chunks: enough workgroups for several waves per SIMD, at least
     // four outputs per chunk
@@ -1005,14 +1066,20 @@ int launch_conv(helrm_ctx *ctx, const ConvSpec *specs, int nspecs, const u64 *sr
     for (int k = 0; k < J.njobs; k++)
       minout = std::min(minout, J.j[k].t.nout - (J.j[k].fin == CONV_FIN_RESCALE ? 1 : 0));
     const long base = (long)(ctx->N / CONV_TPB) * batch * J.njobs;
-    if (ctx->tune_conv_wgs > 0 && base < ctx->tune_conv_wgs)
+    bool pre = false;
+    for (int k = 0; k < J.njobs; k++) pre = pre || J.j[k].pre;
+    if (!pre && ctx->tune_conv_wgs > 0 && base < ctx->tune_conv_wgs)
       J.nchunks = (int)std::max(1L, std::min((long)std::max(1, minout / 4),
                                              (ctx->tune_conv_wgs + base - 1) / base));
     dim3 grid(ctx->N / CONV_TPB * J.nchunks, 1, batch * J.njobs);
     KTimer tm(ctx, s);
-#define CONV(NIN_)                                                                                    \
-  hipLaunchKernelGGL((conv_kernel<NIN_>), grid, dim3(CONV_TPB), 0, s, J, src, src_bstride, copy_src,  \
-                     copy_bstride, dst, dst_bstride, ctx->d_pinfo, ctx->N)
+#define CONV(NIN_)                                                                                     \
+  if (pre)                                                                                             \
+    hipLaunchKernelGGL((conv_kernel<NIN_, true>), grid, dim3(CONV_TPB), 0, s, J, src, src_bstride,      \
+                       copy_src, copy_bstride, dst, dst_bstride, ctx->d_pinfo, ctx->N);                \
+  else                                                                                                 \
+    hipLaunchKernelGGL((conv_kernel<NIN_, false>), grid, dim3(CONV_TPB), 0, s, J, src, src_bstride,     \
+                       copy_src, copy_bstride, dst, dst_bstride, ctx->d_pinfo, ctx->N)
     switch (nin) {
       case 1: CONV(1); break;
       case 2: CONV(2); break;

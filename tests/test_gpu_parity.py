@@ -139,10 +139,10 @@ def test_tuning_knobs_validate(p1):
     ctx = context_for(p1)
     good = {"ks_tile": [1, 2, 4], "baby_tile": [1, 2, 4], "baby_share": [1, 2, 4, 8], "ntt_col_w": [0, 8, 16],
             "ntt_blk_w": [0, 4, 8], "ntt_small_limbs": [0, 48], "gen_key_a": [0, 1, 2], "limb_xcd": [0, 1],
-            "fuse_ks": [0, 1], "conv_wgs": [0, 2048]}
+            "fuse_ks": [0, 1], "fuse_conv": [0, 1], "conv_wgs": [0, 2048]}
     bad = {"ks_tile": [0, 3, 8], "baby_tile": [0, 3], "baby_share": [0, 3, 16], "ntt_col_w": [4, 32],
            "ntt_blk_w": [2, 16], "ntt_small_limbs": [-1], "gen_key_a": [-1, 3], "limb_xcd": [2],
-           "fuse_ks": [2], "conv_wgs": [-1]}
+           "fuse_ks": [2], "fuse_conv": [2, -1], "conv_wgs": [-1]}
     for knob, vals in good.items():
         for v in vals:
             ctx.helrm_set_tuning(knob, v)
@@ -311,7 +311,9 @@ def test_lookup_fused_boundaries(fuse, p1, ctx2):
     """A ModDown feeding a ModUp or the rescale runs fused with it in
     coefficient form (fuse_ks=1) or in the plain order (fuse_ks=0): both
     bit-exact, with giant steps and fold stages (toy ring n1=2, radix 2), with
-    the fold alone (n1=16) and at N=2^16 with giant steps (level 4, sign -1)."""
+    the fold alone (n1=16) and at N=2^16 with giant steps (level 4, sign -1).
+    Fused, the toy ring's digits have K limbs, so c1's ModDown also runs inside
+    the ModUp conversions (fuse_conv=1) or as a conversion of its own (0)."""
     cases = [(p1, W.config1(n_queries=1, n1=2, radix=2)), (p1, W.config1(n_queries=1, n1=16, radix=4)),
              (None, cfg2_workload(4, 4, 2, sign=-1))]
     for prm, w in cases:
@@ -319,11 +321,14 @@ def test_lookup_fused_boundaries(fuse, p1, ctx2):
         load_keys(ctx, w.keys)
         plan = gpu_plan(ctx, w.plan)
         try:
-            say(f"lookup fuse_ks={fuse} N={w.prm.N} level={w.level} n1={w.plan.n1}")
-            ctx.helrm_set_tuning("fuse_ks", fuse)
-            _check_lookup(ctx, w, plan, [0])
+            for fc in ((1, 0) if fuse else (1,)):
+                say(f"lookup fuse_ks={fuse} fuse_conv={fc} N={w.prm.N} level={w.level} n1={w.plan.n1}")
+                ctx.helrm_set_tuning("fuse_ks", fuse)
+                ctx.helrm_set_tuning("fuse_conv", fc)
+                _check_lookup(ctx, w, plan, [0])
         finally:
             ctx.helrm_set_tuning("fuse_ks", 1)
+            ctx.helrm_set_tuning("fuse_conv", 1)
 
 
 def test_lookup_regenerated_key_halves_cfg2(ctx2):
