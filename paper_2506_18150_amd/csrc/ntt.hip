@@ -205,8 +205,8 @@ struct TwSrc {
 };
 
 // H forward (Cooley-Tukey) stages on the E registers, h = E/2 .. 1.
-template <int H, class A>
-__device__ __forceinline__ void fwd_phase(typename A::V (&x)[1 << H], const A &ar, const TwSrc<A> &t) {
+template <int H, class A, class TS>
+__device__ __forceinline__ void fwd_phase(typename A::V (&x)[1 << H], const A &ar, const TS &t) {
   constexpr int E = 1 << H;
 #pragma unroll
   for (int h = E / 2; h >= 1; h >>= 1) {
@@ -246,10 +246,11 @@ __device__ __forceinline__ int in_index(int part, int k) {
 
 // The body of one pass for one arithmetic policy; raw[] holds the thread's
 // input words (canonical residues for a first pass, the lazy intermediate
-// for a second pass).
-template <int H, bool FWD, bool COLS, int WS, class A>
-__device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 (&raw)[1 << H], u64 *out, int part,
-                                          int bat, int li, const PrimeInfo &pi, const NttEpi &epi) {
+// for a second pass).  ar1 runs the first register phase of the forward
+// block pass (the same arithmetic in another form), ar everything else.
+template <int H, bool FWD, bool COLS, int WS, class A, class A1>
+__device__ __forceinline__ void pass_body(const A &ar, const A1 &ar1, u64 *lds, const u64 (&raw)[1 << H], u64 *out,
+                                          int part, int bat, int li, const PrimeInfo &pi, const NttEpi &epi) {
   using S = Shape<H, COLS, WS>;
   constexpr int E = S::E, R = S::R, N = S::N, W = S::W;
   using V = typename A::V;
@@ -298,7 +299,7 @@ __device__ __forceinline__ void pass_body(const A &ar, u64 *lds, const u64 (&raw
       const TwSrc<A> t1{ar.tw, f}, t2{ar.tw, E * f + u};
 #pragma unroll
       for (int k = 0; k < E; k++) x[k] = ar.unbits(raw[k]);
-      fwd_phase<H>(x, ar, t1);
+      fwd_phase<H>(x, ar1, t1);
 #pragma unroll
       for (int k = 0; k < E; k++) lds[blk_idx<H>(w, u + E * k)] = ar.bits(x[k]);
       __syncthreads();
@@ -382,13 +383,14 @@ __global__ __launch_bounds__((Shape<H, COLS, WS>::T)) void ntt_pass_kernel(const
   const PrimeInfo pi = pinfo[p];
   if (pi.q < FLT_LIMIT) {
     FltA ar{pi.qd, pi.qinv_d, twdtab + (size_t)p * N};
-    pass_body<H, FWD, COLS, WS>(ar, lds, raw, out, part, bat, li, pi, epi);
+    pass_body<H, FWD, COLS, WS>(ar, ar, lds, raw, out, part, bat, li, pi, epi);
   } else {
-    // the forward block pass (the one with the fused epilogues) keeps the
-    // borrow-chain form: the other holds more registers there and loses a
-    // wave per SIMD
+    // the second phase of the forward block pass (the one with the fused
+    // epilogues) keeps the borrow-chain form: the other holds more registers
+    // there and loses a wave per SIMD
     IntA<!(FWD && !COLS)> ar{pi.q, 4 * pi.q, 0 - pi.q, 0 - 4 * pi.q, twtab + (size_t)p * N};
-    pass_body<H, FWD, COLS, WS>(ar, lds, raw, out, part, bat, li, pi, epi);
+    IntA<true> ar1{pi.q, 4 * pi.q, 0 - pi.q, 0 - 4 * pi.q, twtab + (size_t)p * N};
+    pass_body<H, FWD, COLS, WS>(ar, ar1, lds, raw, out, part, bat, li, pi, epi);
   }
 }
 
