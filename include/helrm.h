@@ -313,9 +313,9 @@ int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *o
  * blocks over all 8 XCDs, or give each XCD whole limbs (a limb's rotated words
  * are then re-read from one L2: less HBM traffic, less even load).  "fuse_ks" (1, default, or 0): a
  * ModDown feeding a ModUp or the rescale runs fused with it in coefficient
- * form.  "fuse_conv" (1, default, or 0): in such a fused boundary with digits
- * of K limbs each, c1's ModDown runs inside the ModUp conversions (one
- * conversion launch instead of two).  "conv_wgs" (>= 0, default 1536): a base conversion launch with fewer
+ * form.  "fuse_conv" (1, default, or 0): in such a fused boundary c1's
+ * ModDown runs inside the ModUp conversions (one conversion launch instead
+ * of two).  "conv_wgs" (>= 0, default 1536): a base conversion launch with fewer
  * workgroups than this splits its outputs into chunks (at least four outputs
  * each) until it has that many; 0 never splits.
  * Errors: HELRM_EINVAL for an unknown knob or value. */

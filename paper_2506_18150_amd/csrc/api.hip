@@ -360,10 +360,10 @@ int do_moddown_modup(helrm_ctx *ctx, int level, const u64 *X, int x_bs, u64 *z, 
     a.prime[K + i] = ctx->pq_prime(i, level);
   }
   TRY(launch_ntt(ctx, X, C, a, batch, false, s));
-  // 2.  With digits of K limbs each, the ModDown of c1 runs in front of each
-  // digit's ModUp conversion (step 3) and only t0's conversion is a job here
+  // 2.  With digits of at most K limbs, the ModDown of c1 runs in front of
+  // each digit's ModUp conversion (step 3), in one launch with t0's conversion
   bool fuse = ctx->tune_fuse_conv && beta + 1 <= HELRM_MAX_CONV_JOBS && ctx->moddown_tabs[level].nin == K;
-  for (int j = 0; j < beta; j++) fuse = fuse && ctx->digit_hi(j, level) - ctx->digit_lo(j) == K;
+  for (int j = 0; j < beta; j++) fuse = fuse && ctx->digit_hi(j, level) - ctx->digit_lo(j) <= K;
   ConvSpec md[2];
   for (int c = 0; c < 2; c++) {
     md[c].t = &ctx->moddown_tabs[level];

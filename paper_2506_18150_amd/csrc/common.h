@@ -380,7 +380,7 @@ struct helrm_ctx {
   int ntt_small_limbs = 48;  // launches of fewer limbs take the narrow shapes when a width is 0
   int tune_limb_xcd = 0;      // key-switching kernels: whole limbs per XCD (1) or blocks dealt over the XCDs (0)
   int tune_fuse_ks = 1;       // ModDown fused with the ModUp or rescale that follows it (0 = off)
-  int tune_fuse_conv = 1;   // fused boundary: c1's ModDown inside the ModUp conversions (digits of K limbs)
+  int tune_fuse_conv = 1;   // fused boundary: c1's ModDown inside the ModUp conversions
   int tune_conv_wgs = 1536;  // base conversion: split outputs into chunks until a launch has this many workgroups (0 = off)
   int tune_gen_key_a = 2;    // regenerate keys' a_j halves from their seeds where a kernel serves one
                              // ciphertext per thread and streams keys: 0 never, 1 on primes below

@@ -181,10 +181,13 @@ __global__ __launch_bounds__(CONV_TPB) void conv_kernel(const ConvJobs J, const 
   const int nw = fin == CONV_FIN_RESCALE ? nout - 1 : nout;   // outputs written
   const int per = (nw + J.nchunks - 1) / J.nchunks;
   const int r0 = chunk * per, r1 = min(nw, r0 + per);
-  for (int k = threadIdx.x; k < NIN * nout; k += CONV_TPB) cm[k] = split30(jb.t.hat_mont[k]);
+  // inputs of this job: a PRE launch may mix jobs of NIN and fewer inputs
+  // (the missing ones enter as zero), the others have NIN each
+  const int nin = PRE ? jb.t.nin : NIN;
+  for (int k = threadIdx.x; k < nin * nout; k += CONV_TPB) cm[k] = split30(jb.t.hat_mont[k]);
   if (PRE && jb.pre)
     for (int k = threadIdx.x; k < NIN * NIN; k += CONV_TPB)
-      cpre[k] = split30(jb.pre_hat_mont[(k / NIN) * jb.pre_ncol + jb.pre_col0 + k % NIN]);
+      cpre[k] = k % NIN < nin ? split30(jb.pre_hat_mont[(k / NIN) * jb.pre_ncol + jb.pre_col0 + k % NIN]) : 0;
   for (int k = threadIdx.x; k < nout; k += CONV_TPB) {
     const PrimeInfo &po = pinfo[jb.t.out_prime[k]];
     oq[k] = po.q;
@@ -206,23 +209,29 @@ __global__ __launch_bounds__(CONV_TPB) void conv_kernel(const ConvJobs J, const 
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NIN; i++) {
-      const PrimeInfo &pq = pinfo[jb.t.in_prime[i]];
-      Sum30 a;
-      a.zero();
+      y[i] = 0;
+      if (i < nin) {
+        const PrimeInfo &pq = pinfo[jb.t.in_prime[i]];
+        Sum30 a;
+        a.zero();
 #pragma unroll
-      for (int k = 0; k < NIN; k++) a.mac(yp[k], cpre[k * NIN + i]);
-      const u64 A = src[limb_ptr(bat, src_bstride, jb.pre_a0 + i, N) + x];
-      const u64 z = shoup(sub_mod(A, redc_acc(a.value(), pq.q, pq.qn), pq.q), pq.pinv, pq.pinv_p, pq.q);
-      if (chunk == 0) dst[limb_ptr(bat, dst_bstride, jb.pre_dst0 + i, N) + x] = z;
-      y[i] = split30(shoup(z, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, pq.q));
+        for (int k = 0; k < NIN; k++) a.mac(yp[k], cpre[k * NIN + i]);
+        const u64 A = src[limb_ptr(bat, src_bstride, jb.pre_a0 + i, N) + x];
+        const u64 z = shoup(sub_mod(A, redc_acc(a.value(), pq.q, pq.qn), pq.q), pq.pinv, pq.pinv_p, pq.q);
+        if (chunk == 0) dst[limb_ptr(bat, dst_bstride, jb.pre_dst0 + i, N) + x] = z;
+        y[i] = split30(shoup(z, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, pq.q));
+      }
     }
   } else {
     if (r0 < r1) {
 #pragma unroll
       for (int i = 0; i < NIN; i++) {
-        const u64 q = pinfo[jb.t.in_prime[i]].q;
-        const u64 v = src[limb_ptr(bat, src_bstride, jb.src_off0 + i, N) + x];
-        y[i] = split30(shoup(v, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, q));
+        y[i] = 0;
+        if (i < nin) {
+          const u64 q = pinfo[jb.t.in_prime[i]].q;
+          const u64 v = src[limb_ptr(bat, src_bstride, jb.src_off0 + i, N) + x];
+          y[i] = split30(shoup(v, jb.t.hat_inv[i].w, jb.t.hat_inv[i].wp, q));
+        }
       }
     }
     __syncthreads();
@@ -1009,12 +1018,19 @@ int launch_conv(helrm_ctx *ctx, const ConvSpec *specs, int nspecs, const u64 *sr
     return HELRM_EINVAL;
   }
   if (batch == 0 || nspecs == 0) return HELRM_OK;
-  // jobs of one launch share the input count; split by it
+  // jobs of one launch share the input count; split by it, except that a list
+  // with a fused ModDown runs as one launch of the largest count
+  bool any_pre = false;
+  for (int k = 0; k < nspecs; k++) any_pre = any_pre || specs[k].pre;
   int done = 0;
   while (done < nspecs) {
-    const int nin = specs[done].t->nin;
+    int nin = specs[done].t->nin;
     int end = done;
-    while (end < nspecs && specs[end].t->nin == nin) end++;
+    if (any_pre) {
+      for (end = done; end < nspecs; end++) nin = std::max(nin, specs[end].t->nin);
+    } else {
+      while (end < nspecs && specs[end].t->nin == nin) end++;
+    }
     ConvJobs J;
     memset(&J, 0, sizeof J);
     J.njobs = end - done;
@@ -1036,7 +1052,7 @@ int launch_conv(helrm_ctx *ctx, const ConvSpec *specs, int nspecs, const u64 *sr
       jb.qlinv = sp.qlinv;
       jb.pre = sp.pre ? 1 : 0;
       if (sp.pre) {
-        if (sp.pre->nin != nin || sp.pre_col0 + nin > sp.pre->nout) {
+        if (sp.pre->nin != nin || sp.pre_col0 + sp.t->nin > sp.pre->nout) {
           set_error("conv: a fused ModDown needs as many special primes as inputs");
           return HELRM_EINVAL;
         }

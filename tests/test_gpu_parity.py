@@ -312,8 +312,9 @@ def test_lookup_fused_boundaries(fuse, p1, ctx2):
     coefficient form (fuse_ks=1) or in the plain order (fuse_ks=0): both
     bit-exact, with giant steps and fold stages (toy ring n1=2, radix 2), with
     the fold alone (n1=16) and at N=2^16 with giant steps (level 4, sign -1).
-    Fused, the toy ring's digits have K limbs, so c1's ModDown also runs inside
-    the ModUp conversions (fuse_conv=1) or as a conversion of its own (0)."""
+    Fused, c1's ModDown also runs inside the ModUp conversions (fuse_conv=1;
+    digits of K limbs on the toy ring, one digit of 5 < K limbs at level 4) or
+    as a conversion of its own (0)."""
     cases = [(p1, W.config1(n_queries=1, n1=2, radix=2)), (p1, W.config1(n_queries=1, n1=16, radix=4)),
              (None, cfg2_workload(4, 4, 2, sign=-1))]
     for prm, w in cases:
