@@ -81,9 +81,16 @@ typedef struct {
 /* Message of the last failing call on this thread ("" if none). */
 const char *helrm_last_error(void);
 
-/* Build a context on the current HIP device: per-prime roots psi (from the
- * smallest quadratic non-residue x: psi = x^((q-1)/2N)), twiddle tables and
- * the constants of base conversion, ModDown and rescale.  Blocks. */
+/* Build a context on the current HIP device for the ring R_Q = Z_Q[X]/(X^N+1)
+ * with Q = q_0 ... q_L held in residue form (Appendix A "CKKS operations";
+ * Sec. II-A "CKKS": ciphertexts are integer polynomials with large
+ * coefficients, manipulated with modular arithmetic) and the special primes P
+ * of key switching (Appendix A "Key-switching"): per-prime roots psi (from
+ * the smallest quadratic non-residue x: psi = x^((q-1)/2N)), twiddle tables
+ * and the constants of base conversion, ModDown and rescale.  params and its
+ * arrays are read during the call only.  Errors: HELRM_EINVAL (log_n not 12
+ * or 16, L/K/alpha out of range, a prime not = 1 mod 2N or not below 2^60, a
+ * repeated prime, more than 16 digits), HELRM_ENOMEM, HELRM_EHIP.  Blocks. */
 int helrm_create(const helrm_params *params, helrm_ctx **out);
 int helrm_destroy(helrm_ctx *ctx);
 
@@ -108,27 +115,38 @@ int helrm_load_eval_keys(helrm_ctx *ctx, const uint32_t *galois, int n_keys,
                          const uint64_t *keys, const uint64_t *seeds);
 
 /* The uniform half a_j (digit j) of a switching key with the given seed, over
- * all L+1+K primes in evaluation form: out is device [L+1+K][N].  Value x on
- * prime index p is (X mod q_p) 2^-128 mod q_p with X = o_{2c+2} 2^64 + o_{2c+1}
- * (X = o_{2c+1} when q_p < 2^40), c = x + 2^16 p + 2^24 j, o_n the n-th output
- * of the SplitMix64 generator
- * (Steele, Lea and Flood, OOPSLA 2014) seeded with `seed`.  Errors:
- * HELRM_EINVAL (digit out of range, NULL out). */
+ * all L+1+K primes in evaluation form: out is device [L+1+K][N].  The paper
+ * asks only for a uniformly random public polynomial (Appendix A
+ * "Encryption", "Key-switching"); this library expands it from a 64-bit seed
+ * so that kernels can regenerate it instead of reading it.  Value x on prime
+ * index p (counter c = x + 2^16 p + 2^24 j, o_n the n-th output of the
+ * SplitMix64 generator of Steele, Lea and Flood, OOPSLA 2014, seeded with
+ * `seed`) is (X mod q_p) 2^-128 mod q_p, where X = o_{2c+2} 2^64 + o_{2c+1}
+ * when q_p >= 2^40 (within 2^-68 of uniform), and when q_p < 2^40 X is the
+ * first of o_{2c+1}, o_{2^32+4c+1}, o_{2^32+4c+2}, o_{2^32+4c+3} below
+ * 2^64 - (2^64 mod q_p) (rejection sampling: uniform but for a 2^-96 tail).
+ * Errors: HELRM_EINVAL (digit out of range, NULL out). */
 int helrm_key_uniform(helrm_ctx *ctx, uint64_t seed, int digit, uint64_t *out, void *stream);
 
 /* Forward / inverse negacyclic NTT, in place, of `batch` blocks of n_limbs
  * limbs each (block b at d_data + b*n_limbs*N); limb i of every block uses
  * prime prime_index[i] (host array).  Forward maps coefficients to evaluation
- * form as defined above; inverse is its exact inverse (includes N^-1). */
+ * form as defined above; inverse is its exact inverse (includes N^-1).  The
+ * paper's polynomial products in R_Q (Appendix A "Multiplication"; Sec. II-A
+ * "CKKS") become slot-wise products in this form, which every other call
+ * works in.  Errors: HELRM_EINVAL (NULL buffer, prime index out of range,
+ * negative size). */
 int helrm_ntt(helrm_ctx *ctx, uint64_t *d_data, int n_limbs, const int32_t *prime_index,
               int batch, void *stream);
 int helrm_intt(helrm_ctx *ctx, uint64_t *d_data, int n_limbs, const int32_t *prime_index,
                int batch, void *stream);
 
 /* Automorphism X -> X^galois in evaluation form (a permutation of each limb):
- * d_out[j] = d_in[j'] with 2 brv(j')+1 = galois (2 brv(j)+1) mod 2N.
- * galois must be odd.  d_in and d_out must not overlap.  Layout
- * [batch][n_limbs][N]. */
+ * d_out[j] = d_in[j'] with 2 brv(j')+1 = galois (2 brv(j)+1) mod 2N.  With
+ * galois = 5^k mod 2N it is the slot rotation by k of Appendix A "Rotation"
+ * before its key switch (the result decrypts under sigma(s)).  galois must
+ * be odd.  d_in and d_out must not overlap.  Layout [batch][n_limbs][N].
+ * Errors: HELRM_EINVAL (even or out-of-range galois, NULL or equal buffers). */
 int helrm_automorph(helrm_ctx *ctx, const uint64_t *d_in, uint64_t *d_out, uint32_t galois,
                     int n_limbs, int batch, void *stream);
 
@@ -236,8 +254,42 @@ int helrm_lookup_packed(helrm_ctx *ctx, const helrm_plan *plan, const uint64_t *
 int helrm_footprint(const helrm_ctx *ctx, const helrm_plan *plan, int batch, size_t *bytes);
 
 /* Grow the workspace of `stream` to serve helrm_lookup_packed(plan, batch)
- * without further allocation (call before capturing a graph). */
+ * without further allocation (call before capturing a graph).  A call that
+ * needs a larger workspace while its stream is being captured fails with
+ * HELRM_ESTATE instead of allocating; a workspace that a capture has used is
+ * kept (not freed) when a later eager call outgrows it, so graphs captured on
+ * it stay valid until helrm_destroy. */
 int helrm_reserve(helrm_ctx *ctx, const helrm_plan *plan, int batch, void *stream);
+
+/* helrm_footprint / helrm_reserve for helrm_lookup_multi: the workspace of
+ * one call with these plans (the same checks as helrm_lookup_multi), which
+ * also holds the ModUp digits of every giant step in the union of the plans'.
+ * Errors: HELRM_EINVAL (mismatched plans), HELRM_ENOMEM. */
+int helrm_footprint_multi(const helrm_ctx *ctx, const helrm_plan *const *plans, int n_in, int batch,
+                          size_t *bytes);
+int helrm_reserve_multi(helrm_ctx *ctx, const helrm_plan *const *plans, int n_in, int batch, void *stream);
+
+/* A batch of lookups captured once as a HIP graph and replayed (the batched
+ * form of the Sec. IV-B pipeline: every ciphertext of the batch goes through
+ * the same plan, so the whole launch sequence of helrm_lookup_packed, or of
+ * helrm_lookup_multi when n_in > 1, is fixed and replays as one graph launch).
+ * helrm_batch_graph_create records lookup(plans, d_sel, batch, d_out) on a
+ * stream of its own (nothing runs), with a workspace the graph owns
+ * (helrm_footprint_multi bytes, allocated here).  d_sel
+ * ([batch][n_in][2][level+1][N]) and d_out ([batch][2][level][N]) are bound
+ * to the graph: the caller writes the next selectors into d_sel and calls
+ * helrm_batch_graph_replay, which enqueues the recorded launches on `stream`
+ * and returns.  d_sel, d_out, the plans and the context's keys must stay
+ * valid until helrm_batch_graph_destroy (which waits for the device).
+ * Replays on different streams must not overlap (they share the workspace).
+ * Errors: HELRM_EINVAL (mismatched plans, batch < 1, NULL buffer, missing
+ * key), HELRM_ESTATE (kernel timing enabled while capturing), HELRM_ENOMEM,
+ * HELRM_EHIP. */
+typedef struct helrm_graph helrm_graph;
+int helrm_batch_graph_create(helrm_ctx *ctx, const helrm_plan *const *plans, int n_in, const uint64_t *d_sel,
+                             int batch, uint64_t *d_out, helrm_graph **out);
+int helrm_batch_graph_replay(helrm_graph *graph, void *stream);
+int helrm_batch_graph_destroy(helrm_graph *graph);
 
 /* Kernel timing for measurement.  While enabled, every launch of the timed
  * kernel classes records a pair of HIP events on its stream (enabling or

@@ -297,11 +297,18 @@ void or_basis_convert(const u64 *x, int nin, const u64 *qin, u64 *out, int nout,
  * seed with SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom
  * number generators", OOPSLA 2014): output n >= 1 of the generator seeded with
  * s is mix(s + n * 0x9E3779B97F4A7C15), where mix is the finaliser below.
- * Value x of digit j on prime index p takes outputs 2c+1 (low word) and 2c+2
- * (high word), c = x + 2^16 p + 2^24 j, as the 128-bit integer X (for primes
- * below 2^40 the low word alone, whose residue is within 2^-24 of uniform),
- * and is a = (X mod q) * 2^-128 mod q, i.e. the Montgomery-form value
- * (X mod q) * 2^-64 stands for a. */
+ * Value x of digit j on prime index p is drawn from counter c = x + 2^16 p +
+ * 2^24 j.  On a prime of 40 bits or more it is the 128-bit integer
+ * X = out_{2c+2} 2^64 + out_{2c+1}, whose residue mod q is within q / 2^128
+ * < 2^-68 of uniform.  On a prime below 2^40 it is one 64-bit output taken by
+ * rejection: candidate 0 is out_{2c+1}, candidate t = 1, 2, 3 is
+ * out_{2^32 + 4c + t} (a range no other counter reaches); the first candidate
+ * below lambda = 2^64 - (2^64 mod q), the largest multiple of q not above
+ * 2^64, is X (candidate 3 if none is), so X mod q is uniform on [0, q) up to
+ * the chance 2^-96 that all four are rejected.  The key value is
+ * a = (X mod q) * 2^-128 mod q: a fixed bijection of X mod q, so exactly as
+ * uniform, chosen so that its Montgomery-form value (X mod q) * 2^-64 is one
+ * reduction of X. */
 
 u64 or_splitmix64(u64 seed, u64 n) {
   u64 z = seed + n * 0x9E3779B97F4A7C15ULL;
@@ -310,15 +317,25 @@ u64 or_splitmix64(u64 seed, u64 n) {
   return z ^ (z >> 31);
 }
 
+/* The 64-bit sample of counter c on a prime below 2^40 (rejection, above). */
+u64 or_key_uniform_sample40(u64 seed, u64 c, u64 q) {
+  const u64 lambda = (u64)0 - (u64)(((u128)1 << 64) % q);   /* 2^64 - (2^64 mod q) */
+  u64 X = or_splitmix64(seed, 2 * c + 1);
+  for (u64 t = 1; t <= 3 && X >= lambda; t++) X = or_splitmix64(seed, ((u64)1 << 32) + 4 * c + t);
+  return X;
+}
+
 void or_key_uniform(u64 seed, int j, int p, u64 q, int N, u64 *out) {
   /* 2^-128 mod q */
   const u64 two64 = (u64)(((u128)1 << 64) % q);
   const u64 inv128 = or_invmod(or_mulmod(two64, two64, q), q);
   for (int x = 0; x < N; x++) {
     const u64 c = (u64)x + ((u64)p << 16) + ((u64)j << 24);
-    const u64 lo = or_splitmix64(seed, 2 * c + 1);
-    const u64 hi = q < (1ULL << 40) ? 0 : or_splitmix64(seed, 2 * c + 2);
-    const u128 X = ((u128)hi << 64) | lo;
+    u128 X;
+    if (q < ((u64)1 << 40))
+      X = or_key_uniform_sample40(seed, c, q);
+    else
+      X = ((u128)or_splitmix64(seed, 2 * c + 2) << 64) | or_splitmix64(seed, 2 * c + 1);
     out[x] = or_mulmod((u64)(X % q), inv128, q);
   }
 }

@@ -97,6 +97,8 @@ def lib():
         L.or_basis_convert.argtypes = [u64p, ci, u64p, u64p, ci, u64p, ci]
         L.or_splitmix64.restype = u64; L.or_splitmix64.argtypes = [u64, u64]
         L.or_key_uniform.argtypes = [u64, ci, ci, u64, ci, u64p]
+        L.or_key_uniform_sample40.restype = u64
+        L.or_key_uniform_sample40.argtypes = [u64, u64, u64]
         _lib = L
     return _lib
 
@@ -375,10 +377,18 @@ def splitmix64(seed: int, n: int) -> int:
     return int(lib().or_splitmix64(int(seed) & (2 ** 64 - 1), int(n) & (2 ** 64 - 1)))
 
 
+def key_uniform_sample40(seed: int, c: int, q: int) -> int:
+    """The 64-bit sample X of counter c on a prime q below 2^40: SplitMix64
+    outputs tried in order (2c+1, then 2^32 + 4c + t for t = 1..3), the first
+    below 2^64 - (2^64 mod q) taken (ckks_oracle.c, or_key_uniform_sample40)."""
+    return int(lib().or_key_uniform_sample40(int(seed) & (2 ** 64 - 1), int(c), int(q)))
+
+
 def key_uniform(prm: Params, seed: int, j: int) -> np.ndarray:
     """Uniform polynomial a_j of a switching key over every prime of PQ_L
     (evaluation form), expanded from the key's seed by the counter-based
-    SplitMix64 generator (ckks_oracle.c, or_key_uniform)."""
+    SplitMix64 generator (ckks_oracle.c, or_key_uniform): a 128-bit sample on
+    primes of 40 bits or more, a rejection-sampled 64-bit one below."""
     allm = prm.q + prm.p
     out = np.empty((len(allm), prm.N), dtype=np.uint64)
     for p, q in enumerate(allm):

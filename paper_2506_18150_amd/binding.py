@@ -53,7 +53,8 @@ EXPORTS = [
     "helrm_plan_destroy", "helrm_plan_rotation_steps", "helrm_ptxt_ct_matvec_diag",
     "helrm_lookup_packed", "helrm_footprint", "helrm_reserve", "helrm_timing_enable", "helrm_timing_read",
     "helrm_set_tuning", "helrm_mul_relin", "helrm_add_plain", "helrm_mod_drop", "helrm_lookup_multi",
-    "helrm_key_uniform",
+    "helrm_key_uniform", "helrm_footprint_multi", "helrm_reserve_multi", "helrm_batch_graph_create",
+    "helrm_batch_graph_replay", "helrm_batch_graph_destroy",
 ]
 
 _lib = None
@@ -94,6 +95,11 @@ def lib() -> ctypes.CDLL:
     L.helrm_add_plain.argtypes = [_vp, _vp, _vp, _c_int, _vp, _c_int, _vp]
     L.helrm_mod_drop.argtypes = [_vp, _vp, _c_int, _vp, _c_int, _c_int, _vp]
     L.helrm_lookup_multi.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, _vp, _c_int, _vp, _vp]
+    L.helrm_footprint_multi.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, _c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.helrm_reserve_multi.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, _c_int, _vp]
+    L.helrm_batch_graph_create.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, _vp, _c_int, _vp, ctypes.POINTER(_vp)]
+    L.helrm_batch_graph_replay.argtypes = [_vp, _vp]
+    L.helrm_batch_graph_destroy.argtypes = [_vp]
     L.helrm_timing_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]
@@ -241,6 +247,25 @@ class Context:
     def helrm_reserve(self, plan: "Plan", batch: int, stream=None):
         _check(lib().helrm_reserve(self.h, plan.h, batch, _stream(stream)))
 
+    def helrm_footprint_multi(self, plans: Sequence["Plan"], batch: int) -> int:
+        arr = (_vp * len(plans))(*[p.h for p in plans])
+        v = ctypes.c_size_t()
+        _check(lib().helrm_footprint_multi(self.h, arr, len(plans), batch, ctypes.byref(v)))
+        return int(v.value)
+
+    def helrm_reserve_multi(self, plans: Sequence["Plan"], batch: int, stream=None):
+        arr = (_vp * len(plans))(*[p.h for p in plans])
+        _check(lib().helrm_reserve_multi(self.h, arr, len(plans), batch, _stream(stream)))
+
+    def helrm_batch_graph_create(self, plans: Sequence["Plan"], sel, batch: int, out) -> "Graph":
+        """sel and out stay bound to the graph: keep the tensors alive and
+        write the next selectors into sel before each replay."""
+        arr = (_vp * len(plans))(*[p.h for p in plans])
+        h = ctypes.c_void_p()
+        _check(lib().helrm_batch_graph_create(self.h, arr, len(plans), _ptr(sel), batch, _ptr(out),
+                                              ctypes.byref(h)))
+        return Graph(self, h, list(plans), sel, out)
+
     def helrm_mul_relin(self, a, b, level: int, out, batch: int, stream=None):
         _check(lib().helrm_mul_relin(self.h, _ptr(a), _ptr(b), level, _ptr(out), batch, _stream(stream)))
 
@@ -278,6 +303,31 @@ class Plan:
     def close(self):
         if getattr(self, "h", None):
             _check(lib().helrm_plan_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """An helrm_graph handle; holds references to the plans and the bound
+    selector / output tensors so they outlive it."""
+
+    def __init__(self, ctx: Context, h, plans, sel, out):
+        self.ctx, self.h, self.plans, self.sel, self.out = ctx, h, plans, sel, out
+
+    def helrm_batch_graph_replay(self, stream=None):
+        _check(lib().helrm_batch_graph_replay(self.h, _stream(stream)))
+
+    def replay(self, stream=None):
+        self.helrm_batch_graph_replay(stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().helrm_batch_graph_destroy(self.h))
             self.h = None
 
     def __del__(self):

@@ -177,15 +177,35 @@ struct Arena {
   }
 };
 
+// The workspace of stream s, grown to at least `bytes`.  Growing is refused
+// while s is being captured (the graph would record an allocation); a
+// workspace a capture has used is never freed when it is outgrown, only
+// retired until helrm_destroy, so graphs captured on it stay valid.
 int ensure_ws(helrm_ctx *ctx, hipStream_t s, size_t bytes, char **out) {
   std::lock_guard<std::mutex> lk(ctx->ws_mu);
   Workspace &w = ctx->ws[s];
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    cs = hipStreamCaptureStatusNone;
+  }
+  const bool capturing = cs != hipStreamCaptureStatusNone;
   if (w.bytes < bytes) {
+    if (capturing) {
+      set_error("the stream's workspace holds %zu bytes and this call needs %zu: reserve it before capturing "
+                "(helrm_reserve / helrm_reserve_multi)", w.bytes, bytes);
+      return HELRM_ESTATE;
+    }
     if (w.ptr) {
-      HIP_TRY(hipStreamSynchronize(s));
-      HIP_TRY(hipFree(w.ptr));
+      if (w.captured) {
+        ctx->ws_retired.push_back(w.ptr);
+      } else {
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipFree(w.ptr));
+      }
       w.ptr = nullptr;
       w.bytes = 0;
+      w.captured = false;
     }
     void *p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -196,6 +216,7 @@ int ensure_ws(helrm_ctx *ctx, hipStream_t s, size_t bytes, char **out) {
     w.ptr = p;
     w.bytes = bytes;
   }
+  if (capturing) w.captured = true;
   *out = (char *)w.ptr;
   return HELRM_OK;
 }
@@ -742,6 +763,8 @@ int check_primes(const helrm_ctx *ctx, int n_limbs, const int32_t *prime_index) 
 
 // ================================================================ C ABI
 
+static int check_multi_plans(const helrm_ctx *c, const helrm_plan *const *plans, int n_in);
+
 extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
   API_GUARD_BEGIN
   CHECK_ARG(prm && out, "NULL argument");
@@ -824,6 +847,7 @@ extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
     pi.qd = (double)q;
     pi.qinv_d = 1.0 / (double)q;
     pi.ninv_d = (double)pi.ninv;
+    pi.lam = (u64)0 - (u64)(((u128)1 << 64) % q);
     c->h_pinfo.push_back(pi);
   }
   std::vector<double> twdf(twf.size()), twdi(twi.size());
@@ -919,6 +943,7 @@ extern "C" int helrm_destroy(helrm_ctx *c) {
   for (auto &kv : c->keys) (void)hipFree(kv.second.d);
   for (auto &kv : c->ws)
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+  for (void *p : c->ws_retired) (void)hipFree(p);
   if (c->d_pinfo) (void)hipFree(c->d_pinfo);
   if (c->d_tw_fwd) (void)hipFree(c->d_tw_fwd);
   if (c->d_tw_inv) (void)hipFree(c->d_tw_inv);
@@ -1369,15 +1394,8 @@ extern "C" int helrm_lookup_packed(helrm_ctx *c, const helrm_plan *p, const uint
 extern "C" int helrm_lookup_multi(helrm_ctx *c, const helrm_plan *const *plans, int n_in, const uint64_t *sel,
                                   int batch, uint64_t *out, void *stream) {
   API_GUARD_BEGIN
-  CHECK_ARG(c && plans && n_in >= 1, "need at least one plan");
+  TRY(check_multi_plans(c, plans, n_in));
   const helrm_plan *p = plans[0];
-  for (int i = 0; i < n_in; i++) {
-    const helrm_plan *q = plans[i];
-    CHECK_ARG(q && q->ctx == c, "NULL or foreign plan %d", i);
-    CHECK_ARG(q->level == p->level && q->m == p->m && q->n1 == p->n1 && q->n2 == p->n2 && q->sign == p->sign &&
-                  q->span == p->span && q->radix == p->radix,
-              "plan %d differs from plan 0 in level, m, n1, n2, sign, radix or fold span", i);
-  }
   CHECK_ARG(p->level >= 1, "lookup needs plans at level >= 1");
   CHECK_ARG(batch >= 0, "batch < 0");
   if (batch == 0) return HELRM_OK;
@@ -1405,6 +1423,134 @@ extern "C" int helrm_reserve(helrm_ctx *c, const helrm_plan *p, int batch, void 
   CHECK_ARG(c && p && batch >= 0, "bad argument");
   char *base;
   return ensure_ws(c, as_stream(stream), matvec_ws_bytes(c, p, batch, true), &base);
+  API_GUARD_END
+}
+
+// Plans of one multi-ciphertext lookup: same context, level, m, n1, n2,
+// direction, fold radix and span.
+static int check_multi_plans(const helrm_ctx *c, const helrm_plan *const *plans, int n_in) {
+  CHECK_ARG(c && plans && n_in >= 1, "need at least one plan");
+  const helrm_plan *p = plans[0];
+  for (int i = 0; i < n_in; i++) {
+    const helrm_plan *q = plans[i];
+    CHECK_ARG(q && q->ctx == c, "NULL or foreign plan %d", i);
+    CHECK_ARG(q->level == p->level && q->m == p->m && q->n1 == p->n1 && q->n2 == p->n2 && q->sign == p->sign &&
+                  q->span == p->span && q->radix == p->radix,
+              "plan %d differs from plan 0 in level, m, n1, n2, sign, radix or fold span", i);
+  }
+  return HELRM_OK;
+}
+
+extern "C" int helrm_footprint_multi(const helrm_ctx *c, const helrm_plan *const *plans, int n_in, int batch,
+                                     size_t *bytes) {
+  API_GUARD_BEGIN
+  TRY(check_multi_plans(c, plans, n_in));
+  CHECK_ARG(bytes && batch >= 0, "bad argument");
+  *bytes = matvec_ws_bytes(c, plans[0], batch, true, nonzero_giants(plans, n_in));
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_reserve_multi(helrm_ctx *c, const helrm_plan *const *plans, int n_in, int batch,
+                                   void *stream) {
+  API_GUARD_BEGIN
+  TRY(check_multi_plans(c, plans, n_in));
+  CHECK_ARG(batch >= 0, "batch < 0");
+  char *base;
+  return ensure_ws(c, as_stream(stream), matvec_ws_bytes(c, plans[0], batch, true, nonzero_giants(plans, n_in)),
+                   &base);
+  API_GUARD_END
+}
+
+// ---------------------------------------------------------------- captured batch graphs
+
+struct helrm_graph {
+  helrm_ctx *ctx = nullptr;
+  void *ws = nullptr;             // the graph's own workspace
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int helrm_batch_graph_destroy(helrm_graph *g) {
+  API_GUARD_BEGIN
+  if (!g) return HELRM_OK;
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->ws) (void)hipFree(g->ws);
+  delete g;
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_batch_graph_create(helrm_ctx *c, const helrm_plan *const *plans, int n_in,
+                                        const uint64_t *sel, int batch, uint64_t *out, helrm_graph **res) {
+  API_GUARD_BEGIN
+  CHECK_ARG(res, "NULL result pointer");
+  *res = nullptr;
+  TRY(check_multi_plans(c, plans, n_in));
+  const helrm_plan *p = plans[0];
+  CHECK_ARG(p->level >= 1, "lookup needs plans at level >= 1");
+  CHECK_ARG(batch >= 1, "batch must be >= 1");
+  CHECK_ARG(sel && out, "NULL buffer");
+  CHECK_ARG(!c->timing, "kernel timing is enabled: disable it before capturing a graph");
+  const size_t ngu = nonzero_giants(plans, n_in);
+  const size_t bytes = matvec_ws_bytes(c, p, batch, true, ngu);
+  helrm_graph *g = new helrm_graph();
+  g->ctx = c;
+  if (hipMalloc(&g->ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete g;
+    set_error("graph workspace allocation of %zu bytes failed", bytes);
+    return HELRM_ENOMEM;
+  }
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    helrm_batch_graph_destroy(g);
+    set_error("stream creation for the capture failed");
+    return HELRM_EHIP;
+  }
+  MatvecWS w = carve_matvec(c, p, batch, true, (char *)g->ws, ngu);
+  int rc = HELRM_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipStreamBeginCapture failed");
+    rc = HELRM_EHIP;
+  } else {
+    const int lv = p->level;
+    rc = run_matvec(c, plans, n_in, sel, n_in * 2 * (lv + 1), w.mv, out, batch, w, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (rc == HELRM_OK && e != hipSuccess) {
+      set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e));
+      rc = HELRM_EHIP;
+    }
+    g->graph = graph;
+    if (rc == HELRM_OK) {
+      const hipError_t ei = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+        rc = HELRM_EHIP;
+      }
+    }
+    (void)hipGetLastError();
+  }
+  (void)hipStreamDestroy(cs);
+  if (rc != HELRM_OK) {
+    helrm_batch_graph_destroy(g);
+    return rc;
+  }
+  *res = g;
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_batch_graph_replay(helrm_graph *g, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(g && g->exec, "NULL or empty graph");
+  HIP_TRY(hipGraphLaunch(g->exec, as_stream(stream)));
+  return HELRM_OK;
   API_GUARD_END
 }
 

@@ -234,10 +234,13 @@ __device__ __forceinline__ unsigned galois_src(unsigned j, unsigned g, int logn)
 // Uniform half a_j of a switching key, regenerated from the key's seed with
 // SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output n of the generator
 // seeded with s is mix(s + n * 0x9E3779B97F4A7C15).  Value x of digit j on
-// prime index p uses X = out_{2c+2} 2^64 + out_{2c+1} (X = out_{2c+1} for
-// primes below 2^40), c = x + 2^16 p + 2^24 j; the key holds a_j = (X mod q)
-// 2^-128 in Montgomery form, which is X 2^-64 mod q = REDC((out_{2c+2} mod q)
-// 2^64 + out_{2c+1}).
+// prime index p draws from counter c = x + 2^16 p + 2^24 j: on primes of 40
+// bits or more X = out_{2c+2} 2^64 + out_{2c+1} (within 2^-68 of uniform mod
+// q); below 2^40 X is the first of out_{2c+1}, out_{2^32+4c+t} (t = 1..3)
+// below 2^64 - (2^64 mod q) (rejection: X mod q exactly uniform but for a
+// 2^-96 tail).  The key holds a_j = (X mod q) 2^-128, whose Montgomery form
+// is X 2^-64 mod q = REDC((out_{2c+2} mod q) 2^64 + out_{2c+1}), or REDC(X)
+// for the 64-bit X.
 constexpr u64 SM_GAMMA = 0x9E3779B97F4A7C15ull;
 
 __device__ __forceinline__ u64 sm_mix(u64 z) {
@@ -257,6 +260,7 @@ struct PrimeInfo {
   u64 pinv, pinv_p;    // [P^-1]_q (Q primes only)
   double qd, qinv_d;   // q and 1/q as doubles (fp64 NTT path, q < 2^41)
   double ninv_d;       // N^-1 mod q as a double
+  u64 lam;             // 2^64 - (2^64 mod q): 64-bit key samples at or above it are rejected
 };
 
 struct TW {
@@ -264,12 +268,21 @@ struct TW {
 };
 
 // Montgomery-form a_j value of a seeded key at (digit j, prime index p,
-// coefficient x).  Primes below 2^40 take X = o_{2c+1} alone (64 bits, so
-// X mod q is within 2^-24 of uniform), the others the 128-bit X.
+// coefficient x).  A rejected first candidate (probability below 2^-24 per
+// word) sends the lane through the retry loop.
 __device__ __forceinline__ u64 key_uniform_mont(u64 seed, int j, int p, int x, const PrimeInfo &pi) {
   const u64 c = (u64)x + ((u64)p << 16) + ((u64)j << 24);
-  const u64 lo = sm_mix(seed + (2 * c + 1) * SM_GAMMA);
-  if (pi.q < SPLIT_MAC_LIMIT) return redc(lo, 0, pi.q, pi.qn);
+  u64 lo = sm_mix(seed + (2 * c + 1) * SM_GAMMA);
+  if (pi.q < SPLIT_MAC_LIMIT) {
+    if (lo >= pi.lam) {
+#pragma unroll 1
+      for (u64 t = 1; t <= 3; t++) {
+        lo = sm_mix(seed + ((1ull << 32) + 4 * c + t) * SM_GAMMA);
+        if (lo < pi.lam) break;
+      }
+    }
+    return redc(lo, 0, pi.q, pi.qn);
+  }
   const u64 hi = sm_mix(seed + (2 * c + 2) * SM_GAMMA);
   return redc(lo, reduce64(hi, pi.q, pi.mu), pi.q, pi.qn);
 }
@@ -332,6 +345,7 @@ struct KeyEntry {
 struct Workspace {
   void *ptr = nullptr;
   size_t bytes = 0;
+  bool captured = false;   // a stream capture has used this allocation
 };
 
 // Kernel classes that can be timed with HIP events (helrm_timing_*).
@@ -372,6 +386,7 @@ struct helrm_ctx {
   std::map<uint32_t, KeyEntry> keys;
   std::mutex ws_mu;
   std::map<hipStream_t, Workspace> ws;
+  std::vector<void *> ws_retired;   // outgrown workspaces a captured graph may still use (freed at destroy)
   int tune_ks_tile = 4;      // ciphertexts per thread in ks_acc (1, 2, 4)
   int tune_baby_tile = 4;    // ciphertexts per thread in baby_mac when one giant output (1, 2, 4)
   int tune_baby_share = 8;   // ciphertexts per workgroup in baby_mac with several giant outputs (1 = off, 2, 4, 8)

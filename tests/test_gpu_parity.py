@@ -96,9 +96,11 @@ def test_ntt_parity_other_shapes(which, wc, wb, p1, p2, ctx1, ctx2):
 
 @pytest.mark.parametrize("which", ["cfg1", "cfg2"])
 def test_key_uniform_parity(which, p1, p2, ctx1, ctx2):
-    """Seeded key polynomials expanded on the GPU equal the oracle's expansion."""
+    """Seeded key polynomials expanded on the GPU equal the oracle's expansion,
+    including a seed whose 64-bit sample on a prime below 2^40 is rejected and
+    redrawn (541 on the toy ring, 1208 at N=2^16)."""
     prm, ctx = (p1, ctx1) if which == "cfg1" else (p2, ctx2)
-    for seed in (0, 0x0123456789ABCDEF, 2 ** 63 - 1):
+    for seed in (0, 0x0123456789ABCDEF, 2 ** 63 - 1, 541 if which == "cfg1" else 1208):
         for j in range(prm.dnum):
             say(f"key_uniform {which} seed={seed} digit={j}")
             out = empty(len(prm.q) + len(prm.p), prm.N)
@@ -484,3 +486,97 @@ def test_graph_capture_replays(ctx1, w1):
         assert_bit_exact(to_host(out), want, f"graph replay {rep}")
         ctx1.helrm_lookup_packed(plan, cts, B_, eager)   # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_batch_graph_abi_replays(ctx1, w1):
+    """helrm_batch_graph_create / _replay / _destroy: the batched lookup
+    recorded once and replayed four times, with new selectors written into
+    the bound input and eager work in between; every replay bit-exact against
+    the oracle (and the eager call)."""
+    import torch
+    plan = gpu_plan(ctx1, w1.plan)
+    B_ = 3
+    order = [[0, 1, 2], [2, 0, 1], [1, 1, 0], [0, 1, 2]]
+    sel = to_dev(np.stack(w1.cts[:B_]))
+    out = empty(B_, 2, w1.level, w1.prm.N)
+    say("batch graph create (C ABI), batch 3")
+    g = ctx1.helrm_batch_graph_create([plan], sel, B_, out)
+    want = {i: O.lookup(w1.prm, w1.keys, w1.plan, w1.cts[i]) for i in range(3)}
+    eager = empty(B_, 2, w1.level, w1.prm.N)
+    s = torch.cuda.Stream()
+    for rep, idx in enumerate(order):
+        sel.copy_(to_dev(np.stack([w1.cts[i] for i in idx])))
+        out.zero_()
+        g.replay(s if rep % 2 else None)
+        torch.cuda.synchronize()
+        got = to_host(out).reshape(B_, 2, w1.level, w1.prm.N)
+        for k, i in enumerate(idx):
+            assert_bit_exact(got[k], want[i], f"replay {rep} slot {k}")
+        ctx1.helrm_lookup_packed(plan, sel, B_, eager)   # eager work between replays
+        torch.cuda.synchronize()
+        assert_bit_exact(to_host(eager).reshape(got.shape), got, f"eager after replay {rep}")
+    g.close()
+
+
+def test_batch_graph_abi_multi_ciphertext(p1):
+    """The graph of a multi-ciphertext lookup (two selector ciphertexts per
+    query, batch 2) replays bit-exact against the oracle."""
+    import torch
+    ctx = context_for(p1)
+    g9 = synth.rng(9)
+    tables = [W.uncompressed_table(g9, 1000, 16, -1, 1) for _ in range(3)]
+    w = W.build_multi(p1, tables, level=2, n1=16, radix=4, n_queries=2)
+    load_keys(ctx, w.keys)
+    plans = [gpu_plan(ctx, p) for p in w.plans]
+    sel = to_dev(np.stack([np.stack(c) for c in w.cts]))
+    out = empty(2, 2, w.level, p1.N)
+    assert ctx.helrm_footprint_multi(plans, 2) >= ctx.helrm_footprint(plans[0], 2)
+    g = ctx.helrm_batch_graph_create(plans, sel, 2, out)
+    for rep in range(2):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        got = to_host(out).reshape(2, 2, w.level, p1.N)
+        for k in range(2):
+            assert_bit_exact(got[k], O.lookup_multi(p1, w.keys, w.plans, w.cts[k]), f"multi replay {rep} q{k}")
+    g.close()
+
+
+def test_capture_guard_and_outgrown_workspace(ctx1, w1):
+    """A lookup captured (torch graph) on a stream whose workspace was not
+    reserved for it fails with HELRM_ESTATE instead of allocating; a graph
+    captured on a reserved workspace still replays bit-exact after an eager
+    call on the same stream outgrew that workspace (the old one is kept)."""
+    import torch
+    from paper_2506_18150_amd import binding as B
+    plan = gpu_plan(ctx1, w1.plan)
+    cts = to_dev(np.stack(w1.cts[:3]))
+    want = [O.lookup(w1.prm, w1.keys, w1.plan, w1.cts[i]) for i in range(3)]
+    s = torch.cuda.Stream()
+    out = empty(1, 2, w1.level, w1.prm.N)
+    say("capture without reserve -> HELRM_ESTATE")
+    g0 = torch.cuda.CUDAGraph()
+    with pytest.raises(B.HelrmError) as ei:
+        with torch.cuda.graph(g0, stream=s):
+            out.zero_()
+            ctx1.helrm_lookup_packed(plan, cts[:1].contiguous(), 1, out, s)
+    assert ei.value.code == -4
+    torch.cuda.synchronize()
+    say("capture on a reserved workspace, then outgrow it eagerly")
+    s2 = torch.cuda.Stream()
+    ctx1.helrm_reserve(plan, 1, s2)
+    one = cts[:1].contiguous()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s2):
+        ctx1.helrm_lookup_packed(plan, one, 1, out, s2)
+    big = empty(3, 2, w1.level, w1.prm.N)
+    with torch.cuda.stream(s2):
+        ctx1.helrm_lookup_packed(plan, cts, 3, big, s2)   # needs a larger workspace on s2
+    torch.cuda.synchronize()
+    for k in range(3):
+        assert_bit_exact(to_host(big)[k], want[k], f"eager batch 3 query {k}")
+    for rep in range(3):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert_bit_exact(to_host(out)[0], want[0], f"replay {rep} after the workspace grew")

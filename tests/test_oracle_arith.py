@@ -227,9 +227,10 @@ def test_splitmix64_published_outputs():
 
 
 def test_key_uniform_definition_and_spread(tiny):
-    """a = (X mod q) 2^-128 mod q with X = out_{2c+2} 2^64 + out_{2c+1}
-    (out_{2c+1} alone below 2^40), c = x + 2^16 p + 2^24 j; values cover
-    [0, q) evenly."""
+    """a = (X mod q) 2^-128 mod q, c = x + 2^16 p + 2^24 j, with
+    X = out_{2c+2} 2^64 + out_{2c+1} on primes of 40 bits or more and, below
+    2^40, the first of out_{2c+1}, out_{2^32+4c+t} (t = 1..3) below
+    2^64 - (2^64 mod q); values cover [0, q) evenly."""
     prm = tiny
     seed = 0x1234_5678_9ABC_DEF0
     allm = prm.q + prm.p
@@ -238,8 +239,11 @@ def test_key_uniform_definition_and_spread(tiny):
         for p, q in enumerate(allm):
             for x in (0, 1, prm.N - 1):
                 c = x + (p << 16) + (j << 24)
-                hi = O.splitmix64(seed, 2 * c + 2) if q >= 2 ** 40 else 0
-                X = (hi << 64) | O.splitmix64(seed, 2 * c + 1)
+                if q >= 2 ** 40:
+                    X = (O.splitmix64(seed, 2 * c + 2) << 64) | O.splitmix64(seed, 2 * c + 1)
+                else:
+                    X = O.splitmix64(seed, 2 * c + 1)
+                    assert X < 2 ** 64 - 2 ** 64 % q   # no rejection at these coefficients
                 assert int(a[p, x]) == (X % q) * pow(pow(2, 128, q), -1, q) % q
     # spread: a larger ring, the fraction of values in each quarter of [0, q)
     big = O.make_params(N=4096, L=1, K=1, alpha=1)
@@ -247,3 +251,36 @@ def test_key_uniform_definition_and_spread(tiny):
     for p, q in enumerate(big.q + big.p):
         quarters = np.bincount((a[p].astype(object) * 4 // q).astype(np.int64), minlength=4) / big.N
         assert np.all(np.abs(quarters - 0.25) < 0.03)
+
+
+# (ring, seed, digit, prime index, coefficient) where the first 64-bit
+# candidate of a prime below 2^40 lies in the rejected range [2^64 - (2^64 mod
+# q), 2^64); found by scanning seeds
+REJECTION_CASES = [("cfg1", 541, 3, 2, 892), ("cfg2", 1208, 0, 22, 7462)]
+
+
+@pytest.mark.parametrize("case", REJECTION_CASES)
+def test_key_uniform_rejection(case):
+    """Below 2^40 a candidate X >= 2^64 - (2^64 mod q) would make the small
+    residues one count more likely than the others (2^64 is not a multiple
+    of q); the sampler rejects it and takes the next candidate of its own
+    counter range, so every accepted X lies in a whole number of periods of q
+    (X mod q exactly uniform)."""
+    ring, seed, j, p, x = case
+    prm = O.config1_params() if ring == "cfg1" else O.config2_params()
+    q = (prm.q + prm.p)[p]
+    assert q < 2 ** 40
+    lam = 2 ** 64 - 2 ** 64 % q
+    assert lam % q == 0
+    c = x + (p << 16) + (j << 24)
+    first = O.splitmix64(seed, 2 * c + 1)
+    assert first >= lam, "the case must exercise the rejection"
+    second = O.splitmix64(seed, 2 ** 32 + 4 * c + 1)
+    assert second < lam
+    assert O.key_uniform_sample40(seed, c, q) == second
+    a = O.key_uniform(prm, seed, j)
+    assert int(a[p, x]) == (second % q) * pow(pow(2, 128, q), -1, q) % q
+    # neighbours draw no rejection: their first candidate is kept
+    for xx in (x - 1, x + 1):
+        cc = xx + (p << 16) + (j << 24)
+        assert O.key_uniform_sample40(seed, cc, q) == O.splitmix64(seed, 2 * cc + 1)
