@@ -58,19 +58,21 @@ class Client:
         for g in sorted(set(int(x) for x in galois)):
             sg = self._zeros(self.kl, self.N)
             self.ctx.helrm_automorph(self.s_all, sg, g, self.kl, 1)
-            key = self._switch_key(sg, draws.swk[g])
+            key = self.switch_key(sg, draws.swk[g])
             self.ctx.helrm_load_eval_keys([g], key, [draws.swk[g].a_seed])
             del key
         if getattr(draws, "relin", None) is not None:
             # relinearisation key (s^2 -> s), loaded as Galois element 0
             s2 = self._zeros(self.kl, self.N)
             self.ctx.helrm_poly_op(HELRM_OP_MUL, self.s_all, self.s_all, s2, allp, 1)
-            key = self._switch_key(s2, draws.relin)
+            key = self.switch_key(s2, draws.relin)
             self.ctx.helrm_load_eval_keys([0], key, [draws.relin.a_seed])
             del key
         torch.cuda.synchronize()
 
-    def _switch_key(self, s_from: torch.Tensor, d) -> torch.Tensor:
+    def switch_key(self, s_from: torch.Tensor, d) -> torch.Tensor:
+        """Switching key from s_from (evaluation form over every prime) to
+        the secret: [dnum][2][L+1+K][N] as helrm_load_eval_keys takes it."""
         allp = list(range(self.kl))
         key = self._zeros(self.prm.dnum, 2, self.kl, self.N)
         for j in range(self.prm.dnum):
