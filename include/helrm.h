@@ -249,6 +249,25 @@ int helrm_ptxt_ct_matvec_diag(helrm_ctx *ctx, const helrm_plan *plan, const uint
 int helrm_lookup_packed(helrm_ctx *ctx, const helrm_plan *plan, const uint64_t *d_sel,
                         int batch, uint64_t *d_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * lookup as helrm_lookup_packed, same arguments, layouts, kernels and results,
+ * but its workspace is a static device array of HELRM_NOALLOC_MAX_BYTES per
+ * GPU (held from the first helrm_create on that GPU until the process ends)
+ * instead of the stream's workspace.  It allocates nothing (no hipMalloc, no
+ * hipFree, no allocating library call) and never synchronises.  The caller
+ * still owns d_sel and d_out.  The call must be made with the context's
+ * device current.  Every call on one GPU, from any context or stream, shares
+ * that GPU's array and finds it holding the previous call's contents (no part
+ * of the workspace needs to start at zero): calls that overlap in time on one
+ * GPU race and corrupt each other's results, so serialise them (one stream, or
+ * events).  Errors: HELRM_EINVAL (as helrm_lookup_packed; a call whose
+ * helrm_footprint exceeds HELRM_NOALLOC_MAX_BYTES, e.g. level 23 at N=2^16;
+ * kernel timing enabled; wrong current device), HELRM_EHIP. */
+#define HELRM_NOALLOC_MAX_BYTES (256ull << 20)
+int helrm_lookup_packed_noalloc(helrm_ctx *ctx, const helrm_plan *plan, const uint64_t *d_sel,
+                                int batch, uint64_t *d_out, void *stream);
+
 /* Device bytes one call of helrm_lookup_packed with this batch uses beyond its
  * input and output (workspace), for admission control. */
 int helrm_footprint(const helrm_ctx *ctx, const helrm_plan *plan, int batch, size_t *bytes);

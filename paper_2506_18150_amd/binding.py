@@ -20,6 +20,7 @@ LIBPATH = os.path.join(_HERE, "libhelrm.so")
 HELRM_OK = 0
 HELRM_OP_ADD, HELRM_OP_SUB, HELRM_OP_MUL, HELRM_OP_NEG = 0, 1, 2, 3
 HELRM_BASIS_Q, HELRM_BASIS_PQ = 0, 1
+HELRM_NOALLOC_MAX_BYTES = 256 << 20   # static scratch of helrm_lookup_packed_noalloc (include/helrm.h)
 
 _c_int = ctypes.c_int
 _vp = ctypes.c_void_p
@@ -54,7 +55,7 @@ EXPORTS = [
     "helrm_lookup_packed", "helrm_footprint", "helrm_reserve", "helrm_timing_enable", "helrm_timing_read",
     "helrm_set_tuning", "helrm_mul_relin", "helrm_add_plain", "helrm_mod_drop", "helrm_lookup_multi",
     "helrm_key_uniform", "helrm_footprint_multi", "helrm_reserve_multi", "helrm_batch_graph_create",
-    "helrm_batch_graph_replay", "helrm_batch_graph_destroy",
+    "helrm_batch_graph_replay", "helrm_batch_graph_destroy", "helrm_lookup_packed_noalloc",
 ]
 
 _lib = None
@@ -87,6 +88,7 @@ def lib() -> ctypes.CDLL:
     L.helrm_plan_rotation_steps.argtypes = [_vp, _i32p, _c_int, ctypes.POINTER(_c_int)]
     L.helrm_ptxt_ct_matvec_diag.argtypes = [_vp, _vp, _vp, _vp, _c_int, _vp]
     L.helrm_lookup_packed.argtypes = [_vp, _vp, _vp, _c_int, _vp, _vp]
+    L.helrm_lookup_packed_noalloc.argtypes = [_vp, _vp, _vp, _c_int, _vp, _vp]
     L.helrm_footprint.argtypes = [_vp, _vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.helrm_reserve.argtypes = [_vp, _vp, _c_int, _vp]
     L.helrm_timing_enable.argtypes = [_vp, _c_int]
@@ -234,6 +236,9 @@ class Context:
 
     def helrm_lookup_packed(self, plan: "Plan", sel, batch: int, out, stream=None):
         _check(lib().helrm_lookup_packed(self.h, plan.h, _ptr(sel), batch, _ptr(out), _stream(stream)))
+
+    def helrm_lookup_packed_noalloc(self, plan: "Plan", sel, batch: int, out, stream=None):
+        _check(lib().helrm_lookup_packed_noalloc(self.h, plan.h, _ptr(sel), batch, _ptr(out), _stream(stream)))
 
     def helrm_lookup_multi(self, plans: Sequence["Plan"], sel, batch: int, out, stream=None):
         arr = (_vp * len(plans))(*[p.h for p in plans])

@@ -223,6 +223,40 @@ int ensure_ws(helrm_ctx *ctx, hipStream_t s, size_t bytes, char **out) {
 
 size_t rnd(size_t words) { return ((words * sizeof(u64) + 255) / 256) * 256; }
 
+}  // namespace
+
+// Static scratch of helrm_lookup_packed_noalloc: one array per device, held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host it only names the symbol); it uses the device address
+// that hipGetSymbolAddress returns for the current device, resolved once per
+// device when a context is created on it.
+static __device__ __align__(256) unsigned char scratch[HELRM_NOALLOC_MAX_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_addr;   // device -> address of that device's `scratch`
+
+// Device address of `scratch` on `dev`, which must be the current device.
+int scratch_address(int dev, char **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return HELRM_OK;
+  }
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    (void)hipGetLastError();
+    set_error("hipGetSymbolAddress of the static scratch failed on device %d: %s", dev, hipGetErrorString(e));
+    return HELRM_EHIP;
+  }
+  g_scratch_addr[dev] = (char *)ptr;
+  *out = (char *)ptr;
+  return HELRM_OK;
+}
+
 // ---------------------------------------------------------------- limb lists
 
 LimbList ll_make(int n, int src_bs, int dst_bs) {
@@ -810,6 +844,11 @@ extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
     delete c;
     return HELRM_EHIP;
   }
+  // the current device is c->device here: resolve its static scratch once
+  if (scratch_address(c->device, &c->noalloc_scratch) != HELRM_OK) {
+    delete c;
+    return HELRM_EHIP;
+  }
   const int N = c->N;
   // roots: psi = x^((q-1)/2N) for the smallest non-residue x
   std::vector<TW> twf((size_t)c->nprimes * N), twi((size_t)c->nprimes * N);
@@ -1388,6 +1427,31 @@ extern "C" int helrm_lookup_packed(helrm_ctx *c, const helrm_plan *p, const uint
   TRY(ensure_ws(c, s, matvec_ws_bytes(c, p, batch, true), &base));
   MatvecWS w = carve_matvec(c, p, batch, true, base);
   return run_matvec(c, &p, 1, sel, 2 * (p->level + 1), w.mv, out, batch, w, s);
+  API_GUARD_END
+}
+
+extern "C" int helrm_lookup_packed_noalloc(helrm_ctx *c, const helrm_plan *p, const uint64_t *sel, int batch,
+                                           uint64_t *out, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && p && p->ctx == c, "NULL or foreign plan");
+  CHECK_ARG(p->level >= 1, "lookup needs a plan at level >= 1");
+  CHECK_ARG(batch >= 0, "batch < 0");
+  if (batch == 0) return HELRM_OK;
+  CHECK_ARG(sel && out, "NULL buffer");
+  CHECK_ARG(!c->timing, "kernel timing is enabled (it creates events): disable it for the no-allocation call");
+  CHECK_ARG(c->noalloc_scratch, "the context has no static scratch");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  CHECK_ARG(dev == c->device, "the current device (%d) is not the context's (%d)", dev, c->device);
+  const size_t bytes = matvec_ws_bytes(c, p, batch, true);
+  if (bytes > (size_t)HELRM_NOALLOC_MAX_BYTES) {
+    set_error("this lookup needs %zu bytes of scratch (level %d, batch %d); the static scratch holds %zu: use "
+              "helrm_lookup_packed, or a smaller batch or level", bytes, p->level, batch,
+              (size_t)HELRM_NOALLOC_MAX_BYTES);
+    return HELRM_EINVAL;
+  }
+  MatvecWS w = carve_matvec(c, p, batch, true, c->noalloc_scratch);
+  return run_matvec(c, &p, 1, sel, 2 * (p->level + 1), w.mv, out, batch, w, as_stream(stream));
   API_GUARD_END
 }
 

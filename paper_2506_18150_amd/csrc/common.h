@@ -387,6 +387,7 @@ struct helrm_ctx {
   std::mutex ws_mu;
   std::map<hipStream_t, Workspace> ws;
   std::vector<void *> ws_retired;   // outgrown workspaces a captured graph may still use (freed at destroy)
+  char *noalloc_scratch = nullptr;  // device address of this device's static scratch (helrm_lookup_packed_noalloc)
   int tune_ks_tile = 4;      // ciphertexts per thread in ks_acc (1, 2, 4)
   int tune_baby_tile = 4;    // ciphertexts per thread in baby_mac when one giant output (1, 2, 4)
   int tune_baby_share = 8;   // ciphertexts per workgroup in baby_mac with several giant outputs (1 = off, 2, 4, 8)
