@@ -129,6 +129,8 @@ def parse():
     ap.add_argument("--graph", action="store_true", help="replay one captured HIP graph per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="w2 only: skip the level sweep, the batched w3 leg and the served leg")
     ap.add_argument("--batched", type=int, default=8,
                     help="also time this batch size on the same plan and keys (0 to skip)")
     ap.add_argument("--serve", action="store_true",
@@ -171,9 +173,10 @@ def make_tables(workload: str, synth, planner, threshold: int = 256):
     return tables
 
 
-def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int):
+def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int, threads=(0,)):
     """The CPU oracle on one selector ciphertext of the same workload (keys,
-    plan encoding and encryption untimed)."""
+    plan encoding and encryption untimed), once per entry of `threads` (0 =
+    every host thread OpenMP sees)."""
     import numpy as np
 
     import synth
@@ -205,28 +208,197 @@ def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int):
     ct = O.encrypt(prm, keys, O.encode(O.pack_selector(tables, idx), prm.delta, prm), level,
                    synth.enc_draws(qg, prm.N))
     pts = O.plan_residues(prm, plan)
-    t0 = time.perf_counter()
-    out = O.lookup(prm, keys, plan, ct, pts)
-    dt = time.perf_counter() - t0
     rows = sum(t.d for t in tables)
-    got = O.decode(O.decrypt(prm, keys, out), prm.delta, prm)[:rows].real
     ref = np.concatenate([t.lookup(i) for t, i in zip(tables, idx)])
-    err = float(np.max(np.abs(got - ref)))
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": len(tables) / dt, "unit": "lookups/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 selector ciphertext ({len(tables)} lookups) of the same workload (level {level}, "
-                      f"n1={n1}, radix {radix}, sign {sign}); {dt:.2f} s; decrypted max error {err:.1e}; "
-                      f"keygen/encoding untimed"}
+    from threadpoolctl import threadpool_limits
+    res = []
+    all_cores = O.max_threads()
+    for nt in threads:
+        nt = all_cores if nt == 0 else nt
+        O.set_threads(nt)
+        with threadpool_limits(limits=nt):
+            t0 = time.perf_counter()
+            out = O.lookup(prm, keys, plan, ct, pts)
+            dt = time.perf_counter() - t0
+        got = O.decode(O.decrypt(prm, keys, out), prm.delta, prm)[:rows].real
+        err = float(np.max(np.abs(got - ref)))
+        res.append({"value": len(tables) / dt, "unit": "lookups/s", "cores": nt, "kind": "oracle",
+                    "sample": f"1 selector ciphertext ({len(tables)} lookups) of the same workload (level {level}, "
+                              f"n1={n1}, radix {radix}, sign {sign}) on {nt} thread(s); {dt:.2f} s; decrypted max "
+                              f"error {err:.1e}; keygen/encoding untimed"})
+    O.set_threads(all_cores)
+    return res
 
 
-def serve_bench(args):
+def sect8d_bytes(prm, level: int, spec, batch: int) -> dict:
+    """Algorithmic HBM bytes per step of the two key-switching kernel classes,
+    counted per unit as the scope table does (limb = 8 N bytes; at level l
+    with pqn = l + 1 + K limbs and b' digits): a hoisted rotation reads its key
+    (2 b' pqn limbs, once per batch) and its ciphertext's digits (b' pqn
+    limbs); a plaintext diagonal is pqn limbs, read once per batch; each giant
+    output or key-switch result is 2 pqn limbs written per ciphertext.  The
+    fused baby-step kernel never writes R_b, so no per-rotation output is
+    counted there.  Every word counts 8 bytes, including the halves the kernels
+    regenerate from seeds or stream as 40-bit words."""
+    limb = 8 * prm.N
+    pqn = level + 1 + prm.K
+    beta = -(-(level + 1) // prm.alpha)
+    key = 2 * beta * pqn * limb
+    dig = beta * pqn * limb
+    out = 2 * pqn * limb
+    babies = sorted({k % spec.n1 for k in spec.diag})
+    giants = sorted({k // spec.n1 for k in spec.diag})
+    nrot = sum(1 for b in babies if b)
+    baby = nrot * (key + batch * dig) + len(spec.diag) * pqn * limb + batch * len(giants) * out
+    ks = 0
+    ng = sum(1 for g in giants if g)
+    if ng:
+        ks += ng * (key + batch * dig) + batch * out
+    for _, r in spec.stages:
+        ks += (r - 1) * (key + batch * dig) + batch * out
+    return {"baby_mac": float(baby), "ks_acc": float(ks)}
+
+
+def alu_peaks(ctx, prm) -> dict:
+    """ALU ceilings measured by the library's calibration kernels on this GPU:
+    butterflies/s of the NTT arithmetic on a 60-bit prime (integer Shoup
+    butterflies) and on a 40-bit prime (fp64 exact products), and 32x32->64
+    integer multiply-adds per second."""
+    from paper_2506_18150_amd.binding import HELRM_CAL_BUTTERFLY, HELRM_CAL_FMA_F64, HELRM_CAL_MAD_U64
+    q_wide = 0                                  # q_0: 60 bits
+    q_small = 1                                 # q_1: 40 bits
+    return {"butterfly_60bit_per_s": ctx.helrm_calibrate_alu(HELRM_CAL_BUTTERFLY, q_wide),
+            "butterfly_40bit_per_s": ctx.helrm_calibrate_alu(HELRM_CAL_BUTTERFLY, q_small),
+            "mad_u64_u32_per_s": ctx.helrm_calibrate_alu(HELRM_CAL_MAD_U64),
+            "fma_f64_per_s": ctx.helrm_calibrate_alu(HELRM_CAL_FMA_F64)}
+
+
+def level_sweep(prm, tables, levels, n1: int, radix: int, sign: int, key_fn, steps: int) -> dict:
+    """Lookups/s at batch 1 (plain path) with the selector at other levels."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_18150_amd.session import LookupSession
+    res = {}
+    for lv in levels:
+        sess = LookupSession(prm, tables, lv, n1, radix, key_fn, sign=sign)
+        qg = synth.rng(1)
+        idx = [synth.indices(qg, [t.rows for t in tables])]
+        sel = sess.encrypt(idx, [synth.enc_draws(qg, prm.N)])
+        out = sess.new_output(1)
+        stream = torch.cuda.current_stream()
+        sess.ctx.helrm_reserve(sess.plan, 1, stream)
+        for _ in range(3):
+            sess.lookup(sel, out, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            sess.lookup(sel, out, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        err = float(np.max(np.abs(sess.decrypt_rows(out)[0] - sess.cleartext(idx[0]))))
+        res[str(lv)] = {"lookups_per_s": len(tables) / (ms / 1e3), "ms_per_lookup": ms, "max_abs_err": err}
+        del sel, out
+        sess.ctx.close()
+    return res
+
+
+def w3_batched(prm, batch: int, steps: int) -> dict:
+    """The batching workload (26 tables in one selector ciphertext per query,
+    level 23): batch `batch` replayed from a graph captured by the C ABI
+    (helrm_batch_graph_create) against the plain path (one ciphertext per
+    call, eager launches) with the same plan and keys."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2506_18150_amd import autotune, planner
+    from paper_2506_18150_amd.session import LookupSession
+    tables = make_tables("w3", synth, planner)
+    M = planner.packed_matrix(tables)
+    dflt = DEFAULTS["w3"]
+    sc = autotune.tuned_schedule(prm.N, prm.L, 23, M.shape[0], M.shape[1], batch) or \
+        autotune.Schedule(dflt["n1"], dflt["radix"], dflt["sign"])
+    key_fn = lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals)
+    t0 = time.time()
+    sess = LookupSession(prm, tables, 23, sc.n1, sc.radix, key_fn, sign=sc.sign)
+    setup_s = time.time() - t0
+    qg = synth.rng(5)
+    idx = [synth.indices(qg, [t.rows for t in tables]) for _ in range(batch)]
+    sel = sess.encrypt(idx, [synth.enc_draws(qg, prm.N) for _ in range(batch)])
+    stream = torch.cuda.current_stream()
+    # plain: one ciphertext per call, default knobs, eager launches
+    out1 = sess.new_output(1)
+    sel1 = sel[:1].contiguous()
+    sess.ctx.helrm_reserve(sess.plan, 1, stream)
+    for _ in range(2):
+        sess.lookup(sel1, out1, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_plain = max(3, steps)
+    e0.record(stream)
+    for _ in range(n_plain):
+        sess.lookup(sel1, out1, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / n_plain
+    # batched: the tuned knobs for this batch, one captured graph per call
+    for k in ("ks_tile", "baby_tile", "baby_share", "ntt_col_w", "ntt_blk_w", "baby_mfma"):
+        sess.ctx.helrm_set_tuning(k, getattr(sc, k))
+    out = sess.new_output(batch)
+    g = sess.ctx.helrm_batch_graph_create([sess.plan], sel, batch, out)
+    g.replay(stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(stream)
+    for k in range(steps):
+        g.replay(stream)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    ms = ev[0].elapsed_time(ev[-1]) / steps
+    rows = sess.decrypt_rows(out)
+    err = max(float(np.max(np.abs(rows[b] - sess.cleartext(idx[b])))) for b in range(batch))
+    rows1 = sess.decrypt_rows(out1)
+    err1 = float(np.max(np.abs(rows1[0] - sess.cleartext(idx[0]))))
+    g.close()
+    spec = sess.spec
+    n_hoisted = sum(1 for b in sorted({k % spec.n1 for k in spec.diag}) if b)
+    n_full = sum(1 for g_ in sorted({k // spec.n1 for k in spec.diag}) if g_) + sum(r - 1 for _, r in spec.stages)
+    lk = len(tables)
+    res = {
+        "workload": f"w3: 26 tables (~3.4e7 rows) packed {M.shape[0]}x{M.shape[1]} in one selector ciphertext per "
+                    f"query, level 23, m={spec.m}, n1={spec.n1}, n2={spec.n2}, fold radix {spec.radix}, sign "
+                    f"{spec.sign}",
+        "batch": batch,
+        "batched": {"lookups_per_s": batch * lk / (ms / 1e3), "ms_per_call": ms,
+                    "p50_ms": float(np.percentile(per, 50)), "p99_ms": float(np.percentile(per, 99)),
+                    "graph": "helrm_batch_graph_create/replay", "steps": steps,
+                    "knobs": {k: getattr(sc, k) for k in ("ks_tile", "baby_tile", "baby_share", "ntt_col_w",
+                                                          "ntt_blk_w", "baby_mfma")},
+                    "key_switches_per_s": {"hoisted": n_hoisted * batch / (ms / 1e3),
+                                           "full": n_full * batch / (ms / 1e3)},
+                    "max_abs_err": err},
+        "plain": {"lookups_per_s": lk / (plain_ms / 1e3), "ms_per_call": plain_ms, "steps": n_plain,
+                  "max_abs_err": err1},
+        "setup_s": round(setup_s, 2),
+    }
+    res["batched_vs_plain"] = res["batched"]["lookups_per_s"] / res["plain"]["lookups_per_s"]
+    del sel, out, out1, sel1
+    sess.ctx.close()
+    torch.cuda.synchronize()
+    return res
+
+
+def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int = 16, radix: int = 8,
+                sign: int = -1, streams: int = 2, max_batch: int = 16, seed: int = 12) -> dict:
     """The request loop on the 26-table set: tables in fixed groups of
-    --group-size, one selector ciphertext per touched group, Poisson arrivals,
+    group_size, one selector ciphertext per touched group, Poisson arrivals,
     each request touching r ~ U{1..26} distinct tables.  Selector ciphertexts
     wait in pinned host memory (a pool per group, encrypted before the run:
     cost is data-oblivious) and are copied in and out by the loop.  Compared
     with the plain per-request path: one stream, one ciphertext per call."""
-    import numpy as np
     import torch
 
     import synth
@@ -237,9 +409,8 @@ def serve_bench(args):
     prm = params.n16()
     tables = make_tables("w3", synth, planner)
     t0 = time.time()
-    dep = GroupedDeployment(prm, tables, args.group_size, args.level, args.n1 or 16, args.radix or 8,
-                            lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals),
-                            sign=args.sign or -1)
+    dep = GroupedDeployment(prm, tables, group_size, level, n1, radix,
+                            lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals), sign=sign)
     eg = synth.rng(11)
     pool = []
     for g, grp in enumerate(dep.groups):
@@ -254,29 +425,28 @@ def serve_bench(args):
     static = dep.key_bytes + dep.plan_bytes
     # warm-up: every group at every batch size the served mode can form, so
     # that no first launch of a kernel falls inside a measured span
-    wx = GpuExecutor(dep.ctx, dep.plans, args.level, prm.N, n_streams=1, max_batch=args.max_batch,
-                     static_bytes=static)
+    wx = GpuExecutor(dep.ctx, dep.plans, level, prm.N, n_streams=1, max_batch=max_batch, static_bytes=static)
     for g in range(len(dep.groups)):
-        for b in range(1, args.max_batch + 1):
+        for b in range(1, max_batch + 1):
             wx.launch(0, g, [Unit(None, g, pool[g][k % len(pool[g])], 0.0) for k in range(b)])
     torch.cuda.synchronize()
     del wx
     out = {"rates": []}
-    rg = synth.rng(12)
-    for rate in [float(x) for x in args.rates.split(",")]:
-        arr = synth.poisson_arrivals(rg, rate, args.requests)
+    rg = synth.rng(seed)
+    for rate in rates:
+        arr = synth.poisson_arrivals(rg, rate, requests)
         specs = []
-        for i in range(args.requests):
+        for i in range(requests):
             r = int(rg.integers(1, len(tables) + 1))
             ts = rg.choice(len(tables), size=r, replace=False)
             groups = sorted({dep.group_of(int(t)) for t in ts})
             specs.append((float(arr[i]), r, [(g, pool[g][int(rg.integers(0, len(pool[g])))]) for g in groups]))
         row = {"rate": rate}
-        for mode, streams, mb in (("served", args.streams, args.max_batch), ("plain", 1, 1)):
-            ex = GpuExecutor(dep.ctx, dep.plans, args.level, prm.N, n_streams=streams, max_batch=mb,
-                             static_bytes=static)
+        for mode, ns, mb, mix in (("served", streams, max_batch, False), ("served_mixed", streams, max_batch, True),
+                                  ("plain", 1, 1, False)):
+            ex = GpuExecutor(dep.ctx, dep.plans, level, prm.N, n_streams=ns, max_batch=mb, static_bytes=static)
             srv = Server(ex, RealClock(), len(dep.groups), hbm_budget=int(total * 0.9), max_batch=mb,
-                         admit_timeout=30.0)
+                         admit_timeout=30.0, mix_groups=mix)
             reqs = [Request(rid=i, arrival=a, units=u) for i, (a, _, u) in enumerate(specs)]
             rep = srv.run(reqs)
             looked = sum(specs[r.rid][1] for r in srv.completed)
@@ -284,7 +454,25 @@ def serve_bench(args):
             row[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in rep.items()}
             del ex, srv
             torch.cuda.synchronize()
+        for mode in ("served", "served_mixed"):
+            row[mode + "_vs_plain"] = (row[mode]["lookups_per_s"] / row["plain"]["lookups_per_s"]
+                                       if row["plain"]["lookups_per_s"] else None)
         out["rates"].append(row)
+    out.update(setup_s=round(setup_s, 1), groups=len(dep.groups), level=level, group_size=group_size,
+               requests=requests, resident_bytes={"keys": dep.key_bytes, "plans": dep.plan_bytes},
+               what=(f"w5: 26 tables (w3 set) in {len(dep.groups)} groups of {group_size}, selectors at level "
+                     f"{level}, Poisson arrivals, {requests} requests per rate, r ~ U{{1..26}} tables per request; "
+                     f"served: {streams} streams, batches of up to {max_batch} units of one group; served_mixed: the "
+                     f"same with units of any groups in one launch (helrm_lookup_batch); plain: 1 stream, 1 "
+                     f"ciphertext per call; latency = arrival to result on the host"))
+    dep.ctx.close()
+    return out
+
+
+def serve_bench(args):
+    """--serve: the request loop at several arrival rates (one JSON line)."""
+    out = serving_run(args.level, [float(x) for x in args.rates.split(",")], args.requests, args.group_size,
+                      args.n1 or 16, args.radix or 8, args.sign or -1, args.streams, args.max_batch)
     best = max(out["rates"], key=lambda r: r["served"]["lookups_per_s"])
     res = {
         "metric": "served encrypted lookups/s",
@@ -294,15 +482,11 @@ def serve_bench(args):
         "higher_is_better": True,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"w5: 26 tables (w3 set) in {len(dep.groups)} groups of {args.group_size}, "
-                               f"selectors at level {args.level}, Poisson arrivals, {args.requests} requests per "
-                               f"rate, r ~ U{{1..26}} tables per request; served: {args.streams} streams, batches "
-                               f"of up to {args.max_batch}; plain: 1 stream, 1 ciphertext per call",
-                   "level": args.level, "group_size": args.group_size},
+        "config": {"workload": out["what"], "level": args.level, "group_size": args.group_size},
         "latency_ms": {"p50": best["served"]["p50_ms"], "p99": best["served"]["p99_ms"]},
         "serving": out,
-        "setup_s": round(setup_s, 1),
-        "resident_bytes": {"keys": dep.key_bytes, "plans": dep.plan_bytes},
+        "setup_s": out["setup_s"],
+        "resident_bytes": out["resident_bytes"],
     }
     print(json.dumps(res))
 
@@ -436,7 +620,7 @@ def main():
     if tune_rec is not None:
         b = tune_rec["best"]
         sched = autotune.Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b["baby_share"],
-                                  b["ntt_col_w"], b["ntt_blk_w"])
+                                  b["ntt_col_w"], b["ntt_blk_w"], b.get("baby_mfma", 8))
     if sched is None:
         sched = autotune.Schedule(dflt["n1"], dflt["radix"], dflt["sign"])
     n1 = args.n1 or sched.n1
@@ -448,6 +632,7 @@ def main():
     sess.ctx.helrm_set_tuning("baby_tile", args.baby_tile or sched.baby_tile)
     share = args.baby_share or sched.baby_share
     sess.ctx.helrm_set_tuning("baby_share", share)
+    sess.ctx.helrm_set_tuning("baby_mfma", sched.baby_mfma)
     for knob, v in (("ntt_col_w", args.ntt_col_w if args.ntt_col_w is not None else sched.ntt_col_w),
                     ("ntt_blk_w", args.ntt_blk_w if args.ntt_blk_w is not None else sched.ntt_blk_w),
                     ("ntt_small_limbs", args.ntt_small_limbs)):
@@ -522,7 +707,7 @@ def main():
                    "name": args.workload, "level": args.level, "batch": B, "tables": len(tables), "n1": n1,
                    "radix": radix, "sign": sign, "fold_span": spec.span, "graph": args.graph,
                    "ks_tile": args.ks_tile or sched.ks_tile, "baby_tile": args.baby_tile or sched.baby_tile,
-                   "baby_share": share},
+                   "baby_share": share, "baby_mfma": sched.baby_mfma},
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
         "key_switches_per_s": {"hoisted": n_hoisted * cts_per_s, "full": n_full * cts_per_s,
                                "per_ciphertext": {"hoisted": n_hoisted, "full": n_full}},
@@ -541,7 +726,8 @@ def main():
         sess.ctx.helrm_reserve(sess.plan, Bb, stream)
         bs = autotune.tuned_schedule(prm.N, prm.L, args.level, M.shape[0], M.shape[1], Bb)
         if bs is not None and (bs.n1, bs.radix, bs.sign) == (n1, radix, sign):
-            for knob, v in (("ks_tile", bs.ks_tile), ("baby_tile", bs.baby_tile), ("baby_share", bs.baby_share)):
+            for knob, v in (("ks_tile", bs.ks_tile), ("baby_tile", bs.baby_tile), ("baby_share", bs.baby_share),
+                            ("baby_mfma", bs.baby_mfma)):
                 sess.ctx.helrm_set_tuning(knob, v)
         for _ in range(2):
             sess.lookup(bsel, bout, stream)
@@ -557,7 +743,7 @@ def main():
         brows = sess.decrypt_rows(bout)
         berr = max(float(np.max(np.abs(brows[b] - sess.cleartext(bidx[b])))) for b in range(Bb))
         for knob, v in (("ks_tile", args.ks_tile or sched.ks_tile), ("baby_tile", args.baby_tile or sched.baby_tile),
-                        ("baby_share", share)):
+                        ("baby_share", share), ("baby_mfma", sched.baby_mfma)):
             sess.ctx.helrm_set_tuning(knob, v)
         res["batched"] = {"batch": Bb, "steps": nb, "ms_per_step": bms,
                           "lookups_per_s": Bb * len(tables) / (bms / 1e3), "max_abs_err": berr,
@@ -579,21 +765,58 @@ def main():
                         "avg_us": 1e3 * v["ms"] / v["launches"], "GB/s": v["bytes"] / (v["ms"] * 1e6),
                         "Gmodmul/s": v["ops"] / (v["ms"] * 1e6), "bytes_per_launch": v["bytes"] / v["launches"]}
         dom = max(table, key=lambda k: table[k]["ms_per_step"])
-        d = table[dom]
         symbol = dict(KERNEL_SYMBOL)
         if B >= 2 and spec.n2 >= 2 and share >= 2:
             symbol["baby_mac"] = "baby_mac_shared_kernel"
         pmc_cfg = dict(workload=args.workload, level=args.level, radix=radix, n1=n1, batch=B, sign=sign)
-        res["roofline"] = {"kernel": symbol[dom], "bound": "hbm", "achieved": d["GB/s"],
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": d["GB/s"] / HBM_PEAK_GBS,
-                           "traffic": measured_traffic(symbol[dom], pmc_cfg),
-                           "avg_us": d["avg_us"], "algorithmic_bytes_per_launch": d["bytes_per_launch"]}
-        ks = table.get("ks_acc")
-        if ks:
-            res["roofline_keyswitch"] = {"kernel": KERNEL_SYMBOL["ks_acc"], "bound": "hbm",
-                                         "achieved": ks["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                         "frac": ks["GB/s"] / HBM_PEAK_GBS, "avg_us": ks["avg_us"],
-                                         "traffic": measured_traffic(symbol["ks_acc"], pmc_cfg)}
+        alg = sect8d_bytes(prm, args.level, spec, B) if sess.n_in == 1 else {}
+
+        def hbm_entry(k):
+            d = table[k]
+            traffic = measured_traffic(symbol[k], pmc_cfg)
+            ent = {"kernel": symbol[k], "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                   "avg_us": d["avg_us"], "launches_per_step": d["launches_per_step"]}
+            if k in alg:
+                ach = alg[k] / (d["ms_per_step"] * 1e6)
+                ent.update(achieved=ach, frac=ach / HBM_PEAK_GBS,
+                           algorithmic_bytes_per_launch=alg[k] / d["launches_per_step"])
+            else:
+                ent.update(achieved=d["GB/s"], frac=d["GB/s"] / HBM_PEAK_GBS,
+                           algorithmic_bytes_per_launch=d["bytes_per_launch"])
+            ent["moved_bytes_per_launch"] = d["bytes_per_launch"]
+            ent["moved_GBps"] = d["GB/s"]
+            ent["traffic"] = traffic
+            ent["traffic_frac"] = (traffic / (d["avg_us"] * 1e3) / HBM_PEAK_GBS) if traffic else None
+            return ent
+
+        res["roofline"] = hbm_entry(dom) if dom in ("baby_mac", "ks_acc") else {
+            "kernel": symbol[dom], "bound": "alu", "note": "see roofline_ntt / roofline_conv"}
+        if "ks_acc" in table:
+            res["roofline_keyswitch"] = hbm_entry("ks_acc")
+        peaks = alu_peaks(sess.ctx, prm)
+        # butterflies of the lookup's transforms: 60-bit limbs take the integer
+        # policy, 40-bit limbs the fp64 one; the launches cover the PQ basis
+        # (q_0 and the K special primes wide, q_1..q_l small)
+        f_wide = (1 + prm.K) / (args.level + 1 + prm.K)
+        bfly_peak = 1.0 / (f_wide / peaks["butterfly_60bit_per_s"] + (1 - f_wide) / peaks["butterfly_40bit_per_s"])
+        ntt_cls = [k for k in ("ntt_fwd_col", "ntt_fwd_blk", "ntt_inv_blk", "ntt_inv_col") if k in kt]
+        ntt_ops = sum(kt[k]["ops"] for k in ntt_cls)
+        ntt_ms = sum(kt[k]["ms"] for k in ntt_cls)
+        if ntt_ms > 0:
+            ach = ntt_ops / (ntt_ms * 1e-3)
+            res["roofline_ntt"] = {"kernel": "ntt_pass_kernel", "bound": "alu", "unit": "Gbutterfly/s",
+                                   "achieved": ach / 1e9, "peak": bfly_peak / 1e9, "frac": ach / bfly_peak,
+                                   "peak_from": "helrm_calibrate_alu butterflies on a 60-bit and a 40-bit prime, "
+                                                f"weighted {f_wide:.3f} / {1 - f_wide:.3f} by the PQ basis",
+                                   "ms_per_step": ntt_ms / args.steps}
+        if "conv" in kt and kt["conv"]["ms"] > 0:
+            ach = kt["conv"]["ops"] / (kt["conv"]["ms"] * 1e-3)
+            pk = peaks["mad_u64_u32_per_s"] / 4
+            res["roofline_conv"] = {"kernel": "conv_kernel", "bound": "alu", "unit": "Gmodmul/s",
+                                    "achieved": ach / 1e9, "peak": pk / 1e9, "frac": ach / pk,
+                                    "peak_from": "helrm_calibrate_alu 32x32->64 multiply-adds / 4 per product "
+                                                 "(30-bit halves)", "ms_per_step": kt["conv"]["ms"] / args.steps}
+        res["alu_calibration"] = peaks
         limb_ntts = (kt["ntt_fwd_col"]["ops"] + kt["ntt_inv_blk"]["ops"]) / ((prm.N // 2) * 8) / args.steps
         res["ntts_per_s"] = limb_ntts * (1e3 / ms_per_step)
         res["kernels"] = {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in table.items()}
@@ -607,8 +830,25 @@ def main():
         torch.cuda.synchronize()
         res["copy_calibration_bytes"] = 1 << 30
 
+    default_run = args.workload == "w2" and not args.no_extras
+    if default_run:
+        sess.ctx.close()
+        del sel, out
+        torch.cuda.synchronize()
+        res["level_sweep"] = level_sweep(prm, tables, [4, 1], n1, radix, sign, key_fn, max(10, args.steps))
+        res["level_sweep"]["23"] = {"lookups_per_s": value, "ms_per_lookup": ms_per_step, "max_abs_err": err}
+        res["batched_w3"] = w3_batched(prm, 64, 3)
+        srv = serving_run(23, [100.0], 240)
+        row = srv["rates"][0]
+        keep = ("lookups_per_s", "p50_ms", "p99_ms", "mean_batch", "completed", "rejected", "span_s")
+        res["served"] = {"rate_per_s": row["rate"], "requests": srv["requests"],
+                         **{m: {k: row[m].get(k) for k in keep} for m in ("served", "served_mixed", "plain")},
+                         "served_vs_plain": row["served_vs_plain"],
+                         "served_mixed_vs_plain": row["served_mixed_vs_plain"], "what": srv["what"]}
     if not args.no_cpu_baseline and args.workload != "w7":
-        res["cpu_baseline"] = cpu_baseline(args.workload, args.level, n1, radix, sign)
+        cb = cpu_baseline(args.workload, args.level, n1, radix, sign, threads=(0, 1))
+        res["cpu_baseline"] = cb[0]
+        res["cpu_baseline_single_thread"] = cb[1]
     print(json.dumps(res))
 
 

@@ -288,6 +288,27 @@ int helrm_footprint_multi(const helrm_ctx *ctx, const helrm_plan *const *plans, 
                           size_t *bytes);
 int helrm_reserve_multi(helrm_ctx *ctx, const helrm_plan *const *plans, int n_in, int batch, void *stream);
 
+/* A batch of lookups over uneven packings: element b of the batch goes
+ * through plans[b] (the encrypted packed lookup of Sec. IV-B, each element with
+ * its own block-diagonal packing, e.g. its own subset of tables).  The plans
+ * share the context, the level, n1 and the rotation direction, and either all
+ * or none have giant steps beyond g = 0; their diagonals, giant steps and fold
+ * spans may differ.  The steps that do not depend on the plan (ModUp,
+ * the ModDown boundaries, the rescale) run once over the whole batch; the
+ * baby-step MAC and the key-switch accumulations run once per distinct plan.
+ * Results are the same residues as helrm_lookup_packed with each element's
+ * plan.  d_sel [batch][2][level+1][N] -> d_out [batch][2][level][N], both
+ * caller-owned; plans is a host array of batch plan pointers, read during the
+ * call.  Errors: HELRM_EINVAL (NULL or foreign plan, plans that differ in
+ * level, n1, direction or in having giant steps), HELRM_ENOMEM,
+ * HELRM_ESTATE (the stream's workspace would grow during capture). */
+int helrm_lookup_batch(helrm_ctx *ctx, const helrm_plan *const *plans, const uint64_t *d_sel, int batch,
+                       uint64_t *d_out, void *stream);
+/* Workspace of one helrm_lookup_batch call with these plans, and its
+ * reservation on `stream` (as helrm_footprint / helrm_reserve). */
+int helrm_footprint_batch(const helrm_ctx *ctx, const helrm_plan *const *plans, int batch, size_t *bytes);
+int helrm_reserve_batch(helrm_ctx *ctx, const helrm_plan *const *plans, int batch, void *stream);
+
 /* A batch of lookups captured once as a HIP graph and replayed (the batched
  * form of the Sec. IV-B pipeline: every ciphertext of the batch goes through
  * the same plan, so the whole launch sequence of helrm_lookup_packed, or of
@@ -307,8 +328,28 @@ int helrm_reserve_multi(helrm_ctx *ctx, const helrm_plan *const *plans, int n_in
 typedef struct helrm_graph helrm_graph;
 int helrm_batch_graph_create(helrm_ctx *ctx, const helrm_plan *const *plans, int n_in, const uint64_t *d_sel,
                              int batch, uint64_t *d_out, helrm_graph **out);
+/* The same for a batch over uneven packings (plans[b] for element b, as
+ * helrm_lookup_batch): one captured launch sequence, replayed with
+ * helrm_batch_graph_replay. */
+int helrm_batch_graph_create_mixed(helrm_ctx *ctx, const helrm_plan *const *plans, const uint64_t *d_sel,
+                                   int batch, uint64_t *d_out, helrm_graph **graph);
 int helrm_batch_graph_replay(helrm_graph *graph, void *stream);
 int helrm_batch_graph_destroy(helrm_graph *graph);
+
+/* ALU ceilings for the rooflines of the integer-bound kernels (measurement
+ * only, not part of any lookup).  kind HELRM_CAL_BUTTERFLY: butterflies per
+ * second of the NTT's arithmetic on prime `prime_index` (the policy its
+ * transforms use: fp64 exact products below 2^41, Shoup products above),
+ * every thread repeating radix-16 butterfly phases on registers with no
+ * memory traffic; HELRM_CAL_MAD_U64: 32x32->64 integer multiply-adds per
+ * second (per lane), the instruction every modular product of the library
+ * is built from; HELRM_CAL_FMA_F64: fp64 FMAs per second (per lane).  Runs
+ * on `stream` after one warm-up launch, allocates a small buffer, blocks.
+ * Errors: HELRM_EINVAL (unknown kind, prime index out of range), HELRM_EHIP. */
+#define HELRM_CAL_BUTTERFLY 0
+#define HELRM_CAL_MAD_U64 1
+#define HELRM_CAL_FMA_F64 2
+int helrm_calibrate_alu(helrm_ctx *ctx, int kind, int prime_index, void *stream, double *per_s);
 
 /* Kernel timing for measurement.  While enabled, every launch of the timed
  * kernel classes records a pair of HIP events on its stream (enabling or

@@ -15,12 +15,20 @@
  *
  * Arrays of residues are laid out [limb][N] (limb-major, N contiguous words).
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 typedef uint64_t u64;
 typedef unsigned __int128 u128;
+
+/* ------------------------------------------------------------ threads */
+
+/* Thread count of the OpenMP loops below (the benchmark times the oracle
+ * with one thread and with every host core). */
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------ scalars */
 

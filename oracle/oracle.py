@@ -96,11 +96,23 @@ def lib():
         L.or_from_signed.argtypes = [i64p, u64p, ci, ci, u64p]
         L.or_basis_convert.argtypes = [u64p, ci, u64p, u64p, ci, u64p, ci]
         L.or_splitmix64.restype = u64; L.or_splitmix64.argtypes = [u64, u64]
+        L.or_set_threads.argtypes = [ci]
+        L.or_max_threads.restype = ci; L.or_max_threads.argtypes = []
         L.or_key_uniform.argtypes = [u64, ci, ci, u64, ci, u64p]
         L.or_key_uniform_sample40.restype = u64
         L.or_key_uniform_sample40.argtypes = [u64, u64, u64]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the C loops (OpenMP)."""
+    lib().or_set_threads(int(n))
+
+
+def max_threads() -> int:
+    """Threads the next C loop may use."""
+    return int(lib().or_max_threads())
 
 
 def _p(a: np.ndarray):

@@ -38,6 +38,22 @@ class Schedule:
     baby_share: int = 8
     ntt_col_w: int = 16
     ntt_blk_w: int = 4
+    baby_mfma: int = 8
+
+
+def library_revision() -> str:
+    """sha256 over the library's sources (HIP files, device header, C header):
+    a tuning record measured on other code says so."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(here, "csrc", "*"))) + [
+        os.path.join(os.path.dirname(here), "include", "helrm.h")]
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def candidate_schedules(rows: int, cols: int, n: int, n1s=(4, 8, 16, 32, 64), radices=(4, 8, 16),
@@ -65,7 +81,7 @@ def tuned_schedule(N: int, L: int, level: int, rows: int, cols: int, batch: int,
         return None
     b = rec["best"]
     return Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b.get("baby_share", 8),
-                    b.get("ntt_col_w", 16), b.get("ntt_blk_w", 4))
+                    b.get("ntt_col_w", 16), b.get("ntt_blk_w", 4), b.get("baby_mfma", 8))
 
 
 def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
@@ -107,15 +123,18 @@ def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
                                      spec.sign, spec.span)
         ctx.helrm_reserve(plan, batch, stream)
         if batch == 1:
-            knobs = [(4, 4, 8)]
+            knobs = [(4, 4, 8, 0)]
         elif spec.n2 == 1:   # one giant output: the per-thread baby-step tile matters
-            knobs = [(a, b, 8) for a in tiles for b in tiles]
-        else:                # several giant outputs: the workgroup-shared kernel's width matters
-            knobs = [(a, 4, c) for a in tiles for c in shares]
-        for kt, bt, sh in knobs:
+            knobs = [(a, b, 8, 0) for a in tiles for b in tiles]
+        else:                # several giant outputs: the workgroup-shared kernel's width, or the matrix cores
+            knobs = [(a, 4, c, 0) for a in tiles for c in shares]
+            if batch >= 8:
+                knobs += [(a, 4, 8, 8) for a in tiles]
+        for kt, bt, sh, mf in knobs:
             ctx.helrm_set_tuning("ks_tile", kt)
             ctx.helrm_set_tuning("baby_tile", bt)
             ctx.helrm_set_tuning("baby_share", sh)
+            ctx.helrm_set_tuning("baby_mfma", mf)
             for _ in range(warmup):
                 ctx.helrm_lookup_packed(plan, sel, batch, out, stream)
             torch.cuda.synchronize()
@@ -127,8 +146,8 @@ def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
             rec = {"n1": sc.n1, "radix": sc.radix, "sign": sc.sign, "span": spec.span, "ks_tile": kt,
-                   "baby_tile": bt, "baby_share": sh, "ms_per_batch": ms, "lookups_per_s": batch * len(tables) / (ms / 1e3),
-                   "keys": len(spec.rotation_steps())}
+                   "baby_tile": bt, "baby_share": sh, "baby_mfma": mf, "ms_per_batch": ms,
+                   "lookups_per_s": batch * len(tables) / (ms / 1e3), "keys": len(spec.rotation_steps())}
             results.append(rec)
             if log:
                 log(rec)
@@ -139,7 +158,7 @@ def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
     spec = next(sp for s_, sp in specs if (s_.n1, s_.radix, s_.sign) == (sc.n1, sc.radix, sc.sign))
     plan = ctx.helrm_plan_create(level, spec.m, spec.n1, spec.n2, spec.radix, spec.diag, spec.coeffs, spec.sign,
                                  spec.span)
-    for knob in ("ks_tile", "baby_tile", "baby_share"):
+    for knob in ("ks_tile", "baby_tile", "baby_share", "baby_mfma"):
         ctx.helrm_set_tuning(knob, best[knob])
     best_ntt = None
     for wc, wb in ((16, 4), (16, 8), (8, 4)):
@@ -163,7 +182,7 @@ def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
     best["ntt_col_w"], best["ntt_blk_w"] = best_ntt[0], best_ntt[1]
     ctx.close()
     return {"key": shape_key(prm.N, prm.L, level, rows, cols, batch), "best": best, "results": results,
-            "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+            "when": time.strftime("%Y-%m-%d %H:%M:%S"), "revision": library_revision()}
 
 
 def record(result: Dict, path: str = TUNED_PATH) -> None:
@@ -172,7 +191,7 @@ def record(result: Dict, path: str = TUNED_PATH) -> None:
             db = json.load(f)
     except OSError:
         db = {}
-    db[result["key"]] = {"best": result["best"], "when": result["when"],
+    db[result["key"]] = {"best": result["best"], "when": result["when"], "revision": result.get("revision"),
                          "candidates": len(result["results"])}
     tmp = path + ".tmp"
     with open(tmp, "w") as f:

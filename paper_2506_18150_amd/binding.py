@@ -20,6 +20,7 @@ LIBPATH = os.path.join(_HERE, "libhelrm.so")
 HELRM_OK = 0
 HELRM_OP_ADD, HELRM_OP_SUB, HELRM_OP_MUL, HELRM_OP_NEG = 0, 1, 2, 3
 HELRM_BASIS_Q, HELRM_BASIS_PQ = 0, 1
+HELRM_CAL_BUTTERFLY, HELRM_CAL_MAD_U64, HELRM_CAL_FMA_F64 = 0, 1, 2
 HELRM_NOALLOC_MAX_BYTES = 256 << 20   # static scratch of helrm_lookup_packed_noalloc (include/helrm.h)
 
 _c_int = ctypes.c_int
@@ -56,6 +57,8 @@ EXPORTS = [
     "helrm_set_tuning", "helrm_mul_relin", "helrm_add_plain", "helrm_mod_drop", "helrm_lookup_multi",
     "helrm_key_uniform", "helrm_footprint_multi", "helrm_reserve_multi", "helrm_batch_graph_create",
     "helrm_batch_graph_replay", "helrm_batch_graph_destroy", "helrm_lookup_packed_noalloc",
+    "helrm_calibrate_alu", "helrm_lookup_batch", "helrm_footprint_batch", "helrm_reserve_batch",
+    "helrm_batch_graph_create_mixed",
 ]
 
 _lib = None
@@ -89,6 +92,7 @@ def lib() -> ctypes.CDLL:
     L.helrm_ptxt_ct_matvec_diag.argtypes = [_vp, _vp, _vp, _vp, _c_int, _vp]
     L.helrm_lookup_packed.argtypes = [_vp, _vp, _vp, _c_int, _vp, _vp]
     L.helrm_lookup_packed_noalloc.argtypes = [_vp, _vp, _vp, _c_int, _vp, _vp]
+    L.helrm_calibrate_alu.argtypes = [_vp, _c_int, _c_int, _vp, ctypes.POINTER(ctypes.c_double)]
     L.helrm_footprint.argtypes = [_vp, _vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.helrm_reserve.argtypes = [_vp, _vp, _c_int, _vp]
     L.helrm_timing_enable.argtypes = [_vp, _c_int]
@@ -101,6 +105,10 @@ def lib() -> ctypes.CDLL:
     L.helrm_reserve_multi.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, _c_int, _vp]
     L.helrm_batch_graph_create.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, _vp, _c_int, _vp, ctypes.POINTER(_vp)]
     L.helrm_batch_graph_replay.argtypes = [_vp, _vp]
+    L.helrm_lookup_batch.argtypes = [_vp, ctypes.POINTER(_vp), _vp, _c_int, _vp, _vp]
+    L.helrm_footprint_batch.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.helrm_reserve_batch.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, _vp]
+    L.helrm_batch_graph_create_mixed.argtypes = [_vp, ctypes.POINTER(_vp), _vp, _c_int, _vp, ctypes.POINTER(_vp)]
     L.helrm_batch_graph_destroy.argtypes = [_vp]
     L.helrm_timing_read.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -237,6 +245,11 @@ class Context:
     def helrm_lookup_packed(self, plan: "Plan", sel, batch: int, out, stream=None):
         _check(lib().helrm_lookup_packed(self.h, plan.h, _ptr(sel), batch, _ptr(out), _stream(stream)))
 
+    def helrm_calibrate_alu(self, kind: int, prime_index: int = 0, stream=None) -> float:
+        v = ctypes.c_double()
+        _check(lib().helrm_calibrate_alu(self.h, kind, prime_index, _stream(stream), ctypes.byref(v)))
+        return v.value
+
     def helrm_lookup_packed_noalloc(self, plan: "Plan", sel, batch: int, out, stream=None):
         _check(lib().helrm_lookup_packed_noalloc(self.h, plan.h, _ptr(sel), batch, _ptr(out), _stream(stream)))
 
@@ -269,6 +282,28 @@ class Context:
         h = ctypes.c_void_p()
         _check(lib().helrm_batch_graph_create(self.h, arr, len(plans), _ptr(sel), batch, _ptr(out),
                                               ctypes.byref(h)))
+        return Graph(self, h, list(plans), sel, out)
+
+    def helrm_lookup_batch(self, plans: Sequence["Plan"], sel, out, stream=None):
+        """Element b of sel goes through plans[b]."""
+        arr = (_vp * len(plans))(*[p.h for p in plans])
+        _check(lib().helrm_lookup_batch(self.h, arr, _ptr(sel), len(plans), _ptr(out), _stream(stream)))
+
+    def helrm_footprint_batch(self, plans: Sequence["Plan"]) -> int:
+        arr = (_vp * len(plans))(*[p.h for p in plans])
+        v = ctypes.c_size_t()
+        _check(lib().helrm_footprint_batch(self.h, arr, len(plans), ctypes.byref(v)))
+        return v.value
+
+    def helrm_reserve_batch(self, plans: Sequence["Plan"], stream=None):
+        arr = (_vp * len(plans))(*[p.h for p in plans])
+        _check(lib().helrm_reserve_batch(self.h, arr, len(plans), _stream(stream)))
+
+    def helrm_batch_graph_create_mixed(self, plans: Sequence["Plan"], sel, out) -> "Graph":
+        """Element b goes through plans[b]; sel and out stay bound to the graph."""
+        arr = (_vp * len(plans))(*[p.h for p in plans])
+        h = ctypes.c_void_p()
+        _check(lib().helrm_batch_graph_create_mixed(self.h, arr, _ptr(sel), len(plans), _ptr(out), ctypes.byref(h)))
         return Graph(self, h, list(plans), sel, out)
 
     def helrm_mul_relin(self, a, b, level: int, out, batch: int, stream=None):

@@ -774,6 +774,219 @@ int run_matvec(helrm_ctx *ctx, const helrm_plan *const *ps, int n_in, const u64 
   return HELRM_OK;
 }
 
+// ---------------------------------------------------------------- mixed batches
+
+// A batch whose ciphertexts use different plans (uneven packings of the same
+// level, baby-step count n1 and rotation direction; the giant-step counts may
+// differ, and the per-element buffers are laid out for the largest).
+// The elements are taken in plan groups; groups with more fold stages come
+// first, so at every fold stage the elements still folding are a prefix of
+// the batch.
+struct PlanGroup {
+  const helrm_plan *p;
+  int start, count;
+};
+
+int mixed_groups(const helrm_ctx *c, const helrm_plan *const *plans, int batch, std::vector<PlanGroup> &groups,
+                 std::vector<int> &order) {
+  CHECK_ARG(plans && batch >= 1, "need one plan per batch element");
+  const helrm_plan *p0 = plans[0];
+  CHECK_ARG(p0 && p0->ctx == c, "NULL or foreign plan 0");
+  std::vector<const helrm_plan *> uniq;
+  for (int b = 0; b < batch; b++) {
+    const helrm_plan *q = plans[b];
+    CHECK_ARG(q && q->ctx == c, "NULL or foreign plan for element %d", b);
+    CHECK_ARG(q->level == p0->level && q->n1 == p0->n1 && q->sign == p0->sign,
+              "element %d: plans of one batch share level, n1 and rotation direction", b);
+    const bool g0 = q->giants.size() == 1 && q->giants[0] == 0, f0 = p0->giants.size() == 1 && p0->giants[0] == 0;
+    CHECK_ARG(g0 == f0, "element %d: either every plan or none has giant steps beyond g = 0", b);
+    if (std::find(uniq.begin(), uniq.end(), q) == uniq.end()) uniq.push_back(q);
+  }
+  std::stable_sort(uniq.begin(), uniq.end(), [](const helrm_plan *a, const helrm_plan *b) {
+    return a->stages.size() > b->stages.size();
+  });
+  groups.clear();
+  order.clear();
+  for (const helrm_plan *q : uniq) {
+    PlanGroup g{q, (int)order.size(), 0};
+    for (int b = 0; b < batch; b++)
+      if (plans[b] == q) {
+        order.push_back(b);
+        g.count++;
+      }
+    groups.push_back(g);
+  }
+  return HELRM_OK;
+}
+
+// The plan of a mixed batch with the most giant steps: the workspace is carved for it.
+const helrm_plan *widest(const std::vector<PlanGroup> &groups) {
+  const helrm_plan *w = groups[0].p;
+  for (auto &g : groups)
+    if (g.p->n2 > w->n2) w = g.p;
+  return w;
+}
+
+size_t mixed_ws_bytes(const helrm_ctx *c, const std::vector<PlanGroup> &groups, int batch) {
+  std::vector<const helrm_plan *> ps;
+  for (auto &g : groups) ps.push_back(g.p);
+  const size_t ngu = nonzero_giants(ps.data(), (int)ps.size());
+  const size_t N = c->N, lv = groups[0].p->level;
+  return matvec_ws_bytes(c, widest(groups), batch, true, ngu) + rnd((size_t)batch * 2 * (lv + 1) * N) +
+         rnd((size_t)batch * 2 * lv * N);
+}
+
+// The lookup of a mixed batch with the fused boundaries: the steps that do not
+// depend on the plan (ModUp, the ModDown boundaries, the rescale) run once
+// over the whole batch (or over the prefix still folding); the baby-step MAC
+// and the key-switch accumulations run once per plan group.  ct: the sorted
+// selectors ([batch][2][level+1]); rs_out: the sorted results ([batch][2][level]).
+int run_mixed(helrm_ctx *ctx, const std::vector<PlanGroup> &groups, const u64 *ct, u64 *rs_out, int batch,
+              MatvecWS &w, hipStream_t s) {
+  const helrm_plan *p0 = groups[0].p;
+  const int N = ctx->N, lv = p0->level, qn = lv + 1, pqn = lv + 1 + ctx->K, beta = ctx->n_digits(lv);
+  const int n2 = widest(groups)->n2;   // X, xg and Dg hold n2 giants per element; plan g uses its first g.p->n2
+  const size_t d_bs = (size_t)beta * pqn, f_bs = 2 * (size_t)qn + beta * pqn, ct_bs = 2 * (size_t)qn;
+  const size_t x_bs = (size_t)n2 * 2 * pqn, c_bs = 2 * (size_t)pqn, rs_bs = 2 * (size_t)lv;
+  u64 *const D = w.F + (size_t)2 * qn * N;
+  const bool only0 = p0->giants.size() == 1 && p0->giants[0] == 0;
+  // 1. hoisted ModUp of every c1
+  TRY(do_modup(ctx, lv, ct + (size_t)qn * N, (int)ct_bs, D, (int)f_bs, w.coef, batch, s));
+  // 2. fused baby steps + plaintext MAC, per plan group
+  for (const PlanGroup &g : groups)
+    for (int g0 = 0; g0 < g.p->n2; g0 += HELRM_MAX_GTILE) {
+      const int ng = std::min(HELRM_MAX_GTILE, g.p->n2 - g0);
+      TRY(launch_baby_mac(ctx, g.p, D + g.start * f_bs * N, f_bs * N, ct + g.start * ct_bs * N, ct_bs * N,
+                          w.X + (g.start * x_bs + (size_t)g0 * 2 * pqn) * N, x_bs * N, g0, ng, g.count, s, false,
+                          true));
+    }
+  // elements with no fold stage: the suffix of groups with stages == 0
+  auto stages_of = [&](const PlanGroup &g) { return (int)g.p->stages.size(); };
+  auto first_with_at_most = [&](int k) {   // first element whose plan has <= k stages
+    for (const PlanGroup &g : groups)
+      if (stages_of(g) <= k) return g.start;
+    return batch;
+  };
+  const u64 *src = w.X;   // what the first boundary reads: X_0 (only g = 0) or the giant accumulators
+  size_t src_bs = x_bs;
+  if (!only0) {
+    // 3. x_g = ModDown(X_g) for every giant of every element; 4. giant rotations
+    TRY(do_moddown(ctx, lv, w.X, 2 * pqn, w.xg, 2 * qn, w.mdP, w.mdT, batch * n2, s));
+    TRY(do_modup(ctx, lv, w.xg + (size_t)qn * N, 2 * qn, w.Dg, (int)d_bs, w.coef, batch * n2, s));
+    for (const PlanGroup &g : groups) {
+      std::vector<KsTerm> terms;
+      bool has0 = false;
+      for (int gi : g.p->giants) {
+        if (gi == 0) {
+          has0 = true;
+          continue;
+        }
+        KsTerm t;
+        t.digits = w.Dg + ((size_t)g.start * n2 + gi) * d_bs * N;
+        t.c0 = w.xg + ((size_t)g.start * n2 + gi) * 2 * qn * N;
+        TRY(key_for(ctx, (long)g.p->sign * g.p->n1 * gi, &t));
+        terms.push_back(t);
+      }
+      TRY(launch_ks_accumulate(ctx, lv, terms.data(), (int)terms.size(), (size_t)n2 * d_bs * N,
+                               (size_t)n2 * 2 * qn * N, has0 ? w.xg + (size_t)g.start * n2 * 2 * qn * N : nullptr,
+                               (size_t)n2 * 2 * qn * N, w.acc + g.start * c_bs * N, c_bs * N, g.count, s));
+    }
+    src = w.acc;
+    src_bs = c_bs;
+  }
+  // first boundary: ModDown -> rescale for the elements without fold stages,
+  // ModDown -> ModUp (z in zA, its digits in F) for the others
+  const int n_fold = first_with_at_most(0);
+  if (n_fold < batch)
+    TRY(do_moddown_rescale(ctx, lv, src + n_fold * src_bs * N, (int)src_bs, rs_out + n_fold * rs_bs * N,
+                           (int)rs_bs, w.F + n_fold * f_bs * N, w.C + n_fold * c_bs * N, batch - n_fold, s));
+  if (n_fold > 0)
+    TRY(do_moddown_modup(ctx, lv, src, (int)src_bs, w.zA, 2 * qn, w.F, (int)f_bs, w.C, n_fold, s));
+  // 5. fold stages: stage si runs for the prefix of elements with more than si stages
+  u64 *z = w.zA, *zn = w.zB;
+  const int max_st = stages_of(groups[0]);
+  for (int si = 0; si < max_st; si++) {
+    const int active = first_with_at_most(si);
+    for (const PlanGroup &g : groups) {
+      if (stages_of(g) <= si) break;
+      const int st = g.p->stages[si].first, r = g.p->stages[si].second;
+      std::vector<KsTerm> terms;
+      for (int t = 1; t < r; t++) {
+        KsTerm k;
+        k.digits = D + g.start * f_bs * N;
+        k.c0 = z + g.start * 2 * (size_t)qn * N;
+        TRY(key_for(ctx, (long)t * st, &k));
+        terms.push_back(k);
+      }
+      CHECK_ARG((int)terms.size() <= HELRM_MAX_TERMS, "fold radix above %d is not supported", HELRM_MAX_TERMS + 1);
+      TRY(launch_ks_accumulate(ctx, lv, terms.data(), (int)terms.size(), f_bs * N, 2 * (size_t)qn * N,
+                               z + g.start * 2 * (size_t)qn * N, 2 * (size_t)qn * N, w.acc + g.start * c_bs * N,
+                               c_bs * N, g.count, s));
+    }
+    // elements whose last stage this is: [done0, active); the rest go on
+    const int done0 = first_with_at_most(si + 1);
+    if (done0 < active)
+      TRY(do_moddown_rescale(ctx, lv, w.acc + done0 * c_bs * N, (int)c_bs, rs_out + done0 * rs_bs * N, (int)rs_bs,
+                             w.F + done0 * f_bs * N, w.C + done0 * c_bs * N, active - done0, s));
+    if (done0 > 0) {
+      TRY(do_moddown_modup(ctx, lv, w.acc, (int)c_bs, zn, 2 * qn, w.F, (int)f_bs, w.C, done0, s));
+      std::swap(z, zn);
+    }
+  }
+  return HELRM_OK;
+}
+
+// Selectors into plan-group order (sel -> dst) or results back (src -> out),
+// one copy per run of consecutive elements.
+int permute_elements(const std::vector<int> &order, const u64 *from, u64 *to, size_t words, bool gather,
+                     hipStream_t s) {
+  const int n = (int)order.size();
+  for (int i = 0; i < n;) {
+    int j = i + 1;
+    while (j < n && order[j] == order[j - 1] + 1) j++;
+    const size_t src = gather ? (size_t)order[i] : (size_t)i, dst = gather ? (size_t)i : (size_t)order[i];
+    HIP_TRY(hipMemcpyAsync(to + dst * words, from + src * words, (size_t)(j - i) * words * sizeof(u64),
+                           hipMemcpyDeviceToDevice, s));
+    i = j;
+  }
+  return HELRM_OK;
+}
+
+// Whole mixed-batch lookup on a workspace that mixed_ws_bytes sized.
+int lookup_mixed(helrm_ctx *c, const std::vector<PlanGroup> &groups, const std::vector<int> &order,
+                 const u64 *sel, int batch, u64 *out, char *base, hipStream_t s) {
+  const helrm_plan *p0 = widest(groups);
+  const size_t N = c->N, lv = p0->level, in_words = 2 * (lv + 1) * N, out_words = 2 * lv * N;
+  const bool fuse = c->tune_fuse_ks && fused_fits(c, (int)lv);
+  std::vector<const helrm_plan *> ps;
+  for (auto &g : groups) ps.push_back(g.p);
+  const size_t ngu = nonzero_giants(ps.data(), (int)ps.size());
+  MatvecWS w = carve_matvec(c, p0, batch, true, base, ngu);
+  bool ident = true;
+  for (int i = 0; i < batch; i++) ident = ident && order[i] == i;
+  u64 *s_sel = (u64 *)(base + matvec_ws_bytes(c, p0, batch, true, ngu));
+  u64 *s_out = (u64 *)((char *)s_sel + rnd((size_t)batch * in_words / N * N));
+  const u64 *in = sel;
+  u64 *res = out;
+  if (!ident) {
+    TRY(permute_elements(order, sel, s_sel, in_words, true, s));
+    in = s_sel;
+    res = s_out;
+  }
+  if (fuse) {
+    TRY(run_mixed(c, groups, in, res, batch, w, s));
+  } else {
+    // plain ModDown order: one lookup per plan group
+    for (const PlanGroup &g : groups) {
+      MatvecWS wg = carve_matvec(c, g.p, g.count, true, base);
+      TRY(run_matvec(c, &g.p, 1, in + g.start * in_words, 2 * (int)(lv + 1), wg.mv, res + g.start * out_words,
+                     g.count, wg, s));
+    }
+  }
+  if (!ident) TRY(permute_elements(order, s_out, out, out_words, false, s));
+  return HELRM_OK;
+}
+
 LimbList ll_from_primes(helrm_ctx *ctx, int n_limbs, const int32_t *prime_index, int off0) {
   LimbList ll = ll_make(n_limbs, n_limbs, n_limbs);
   for (int i = 0; i < n_limbs; i++) {
@@ -1359,6 +1572,51 @@ extern "C" int helrm_plan_create(helrm_ctx *c, const helrm_plan_desc *d, helrm_p
   if ((rc = launch_ntt(c, p->d_pt, p->d_pt, ll, d->n_diag, true, 0)) != HELRM_OK) return fail(rc);
   if ((rc = launch_to_mont(c, p->d_pt, ll, d->n_diag, 0)) != HELRM_OK) return fail(rc);
   if ((rc = launch_pack_pt(p->d_pt, p->pt_words, 0)) != HELRM_OK) return fail(rc);
+  // matrix-core operands for batched launches of plans with several giant
+  // steps: per giant tile of 8, the baby steps of the tile in the order the
+  // baby-step launch takes them (ascending, b = 0 first)
+  if (c->tune_ptm && d->n2 >= 2) {
+    const int tiles = (d->n2 + HELRM_MAX_GTILE - 1) / HELRM_MAX_GTILE;
+    std::vector<int> tab((size_t)tiles * 64 * 8, -1);
+    bool fits = true;
+    for (int T = 0; T < tiles; T++) {
+      int k = 0;
+      for (int b : p->babies) {
+        bool any = false;
+        for (int g = 0; g < 8; g++) {
+          const int G = T * 8 + g;
+          if (G < d->n2 && p->slot[(size_t)G * d->n1 + b] >= 0) any = true;
+        }
+        if (!any) continue;
+        if (k >= 64) { fits = false; break; }
+        for (int g = 0; g < 8; g++) {
+          const int G = T * 8 + g;
+          tab[((size_t)T * 64 + k) * 8 + g] = G < d->n2 ? p->slot[(size_t)G * d->n1 + b] : -1;
+        }
+        k++;
+      }
+    }
+    if (fits) {
+      int *dtab = nullptr;
+      const size_t bytes = (size_t)tiles * pqn * N * 4096;
+      if (hipMalloc(&p->d_ptm, bytes) != hipSuccess || hipMalloc(&dtab, tab.size() * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (dtab) (void)hipFree(dtab);
+        set_error("plan allocation failed (matrix-core operands)");
+        return fail(HELRM_ENOMEM);
+      }
+      p->ptm_tiles = tiles;
+      rc = hipMemcpy(dtab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess
+               ? launch_ptm_pack(c, p, dtab, 0)
+               : HELRM_EHIP;
+      if (rc == HELRM_OK && hipDeviceSynchronize() != hipSuccess) rc = HELRM_EHIP;
+      (void)hipFree(dtab);
+      if (rc != HELRM_OK) {
+        set_error("plan preparation failed (matrix-core operands)");
+        return fail(rc);
+      }
+    }
+  }
   if (hipDeviceSynchronize() != hipSuccess) {
     set_error("plan preparation failed on the device");
     return fail(HELRM_EHIP);
@@ -1376,6 +1634,7 @@ extern "C" int helrm_plan_destroy(helrm_plan *p) {
   (void)hipDeviceSynchronize();
   if (p->d_pt) (void)hipFree(p->d_pt);
   if (p->d_slot) (void)hipFree(p->d_slot);
+  if (p->d_ptm) (void)hipFree(p->d_ptm);
   delete p;
   return HELRM_OK;
   API_GUARD_END
@@ -1474,6 +1733,46 @@ extern "C" int helrm_lookup_multi(helrm_ctx *c, const helrm_plan *const *plans, 
   API_GUARD_END
 }
 
+extern "C" int helrm_lookup_batch(helrm_ctx *c, const helrm_plan *const *plans, const uint64_t *sel, int batch,
+                                  uint64_t *out, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(batch >= 0, "batch < 0");
+  if (batch == 0) return HELRM_OK;
+  CHECK_ARG(sel && out, "NULL buffer");
+  std::vector<PlanGroup> groups;
+  std::vector<int> order;
+  TRY(mixed_groups(c, plans, batch, groups, order));
+  CHECK_ARG(groups[0].p->level >= 1, "lookup needs plans at level >= 1");
+  hipStream_t s = as_stream(stream);
+  char *base;
+  TRY(ensure_ws(c, s, mixed_ws_bytes(c, groups, batch), &base));
+  return lookup_mixed(c, groups, order, sel, batch, out, base, s);
+  API_GUARD_END
+}
+
+extern "C" int helrm_footprint_batch(const helrm_ctx *c, const helrm_plan *const *plans, int batch, size_t *bytes) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && bytes && batch >= 1, "bad argument");
+  std::vector<PlanGroup> groups;
+  std::vector<int> order;
+  TRY(mixed_groups(c, plans, batch, groups, order));
+  *bytes = mixed_ws_bytes(c, groups, batch);
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_reserve_batch(helrm_ctx *c, const helrm_plan *const *plans, int batch, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && batch >= 1, "bad argument");
+  std::vector<PlanGroup> groups;
+  std::vector<int> order;
+  TRY(mixed_groups(c, plans, batch, groups, order));
+  char *base;
+  return ensure_ws(c, as_stream(stream), mixed_ws_bytes(c, groups, batch), &base);
+  API_GUARD_END
+}
+
 extern "C" int helrm_footprint(const helrm_ctx *c, const helrm_plan *p, int batch, size_t *bytes) {
   API_GUARD_BEGIN
   CHECK_ARG(c && p && bytes && batch >= 0, "bad argument");
@@ -1547,19 +1846,10 @@ extern "C" int helrm_batch_graph_destroy(helrm_graph *g) {
   API_GUARD_END
 }
 
-extern "C" int helrm_batch_graph_create(helrm_ctx *c, const helrm_plan *const *plans, int n_in,
-                                        const uint64_t *sel, int batch, uint64_t *out, helrm_graph **res) {
-  API_GUARD_BEGIN
-  CHECK_ARG(res, "NULL result pointer");
-  *res = nullptr;
-  TRY(check_multi_plans(c, plans, n_in));
-  const helrm_plan *p = plans[0];
-  CHECK_ARG(p->level >= 1, "lookup needs plans at level >= 1");
-  CHECK_ARG(batch >= 1, "batch must be >= 1");
-  CHECK_ARG(sel && out, "NULL buffer");
-  CHECK_ARG(!c->timing, "kernel timing is enabled: disable it before capturing a graph");
-  const size_t ngu = nonzero_giants(plans, n_in);
-  const size_t bytes = matvec_ws_bytes(c, p, batch, true, ngu);
+// Capture `body` (which enqueues one lookup on the given stream, on the graph's
+// own workspace of `bytes`) into g.
+template <class F>
+int capture_graph(helrm_ctx *c, size_t bytes, F body, helrm_graph **res) {
   helrm_graph *g = new helrm_graph();
   g->ctx = c;
   if (hipMalloc(&g->ws, bytes) != hipSuccess) {
@@ -1575,15 +1865,13 @@ extern "C" int helrm_batch_graph_create(helrm_ctx *c, const helrm_plan *const *p
     set_error("stream creation for the capture failed");
     return HELRM_EHIP;
   }
-  MatvecWS w = carve_matvec(c, p, batch, true, (char *)g->ws, ngu);
   int rc = HELRM_OK;
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
     set_error("hipStreamBeginCapture failed");
     rc = HELRM_EHIP;
   } else {
-    const int lv = p->level;
-    rc = run_matvec(c, plans, n_in, sel, n_in * 2 * (lv + 1), w.mv, out, batch, w, cs);
+    rc = body((char *)g->ws, cs);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &graph);
     if (rc == HELRM_OK && e != hipSuccess) {
@@ -1607,6 +1895,45 @@ extern "C" int helrm_batch_graph_create(helrm_ctx *c, const helrm_plan *const *p
   }
   *res = g;
   return HELRM_OK;
+}
+
+extern "C" int helrm_batch_graph_create(helrm_ctx *c, const helrm_plan *const *plans, int n_in,
+                                        const uint64_t *sel, int batch, uint64_t *out, helrm_graph **res) {
+  API_GUARD_BEGIN
+  CHECK_ARG(res, "NULL result pointer");
+  *res = nullptr;
+  TRY(check_multi_plans(c, plans, n_in));
+  const helrm_plan *p = plans[0];
+  CHECK_ARG(p->level >= 1, "lookup needs plans at level >= 1");
+  CHECK_ARG(batch >= 1, "batch must be >= 1");
+  CHECK_ARG(sel && out, "NULL buffer");
+  CHECK_ARG(!c->timing, "kernel timing is enabled: disable it before capturing a graph");
+  const size_t ngu = nonzero_giants(plans, n_in);
+  const size_t bytes = matvec_ws_bytes(c, p, batch, true, ngu);
+  return capture_graph(c, bytes, [&](char *base, hipStream_t cs) {
+    MatvecWS w = carve_matvec(c, p, batch, true, base, ngu);
+    const int lv = p->level;
+    return run_matvec(c, plans, n_in, sel, n_in * 2 * (lv + 1), w.mv, out, batch, w, cs);
+  }, res);
+  API_GUARD_END
+}
+
+extern "C" int helrm_batch_graph_create_mixed(helrm_ctx *c, const helrm_plan *const *plans, const uint64_t *sel,
+                                              int batch, uint64_t *out, helrm_graph **res) {
+  API_GUARD_BEGIN
+  CHECK_ARG(res, "NULL result pointer");
+  *res = nullptr;
+  CHECK_ARG(c, "NULL context");
+  CHECK_ARG(batch >= 1, "batch must be >= 1");
+  CHECK_ARG(sel && out, "NULL buffer");
+  CHECK_ARG(!c->timing, "kernel timing is enabled: disable it before capturing a graph");
+  std::vector<PlanGroup> groups;
+  std::vector<int> order;
+  TRY(mixed_groups(c, plans, batch, groups, order));
+  CHECK_ARG(groups[0].p->level >= 1, "lookup needs plans at level >= 1");
+  return capture_graph(c, mixed_ws_bytes(c, groups, batch), [&](char *base, hipStream_t cs) {
+    return lookup_mixed(c, groups, order, sel, batch, out, base, cs);
+  }, res);
   API_GUARD_END
 }
 
@@ -1615,6 +1942,19 @@ extern "C" int helrm_batch_graph_replay(helrm_graph *g, void *stream) {
   CHECK_ARG(g && g->exec, "NULL or empty graph");
   HIP_TRY(hipGraphLaunch(g->exec, as_stream(stream)));
   return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_calibrate_alu(helrm_ctx *c, int kind, int prime_index, void *stream, double *per_s) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && per_s, "NULL argument");
+  CHECK_ARG(kind >= HELRM_CAL_BUTTERFLY && kind <= HELRM_CAL_FMA_F64, "unknown calibration kind %d", kind);
+  hipStream_t s = as_stream(stream);
+  if (kind == HELRM_CAL_BUTTERFLY) {
+    CHECK_ARG(prime_index >= 0 && prime_index < c->nprimes, "prime_index %d out of range", prime_index);
+    return calibrate_butterflies(c, c->primes[prime_index], s, per_s);
+  }
+  return calibrate_instr(kind == HELRM_CAL_MAD_U64 ? 0 : 1, s, per_s);
   API_GUARD_END
 }
 
@@ -1686,6 +2026,12 @@ extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
   } else if (strcmp(knob, "conv_wgs") == 0) {
     CHECK_ARG(value >= 0, "conv_wgs must be >= 0");
     c->tune_conv_wgs = value;
+  } else if (strcmp(knob, "baby_mfma") == 0) {
+    CHECK_ARG(value >= 0, "baby_mfma must be >= 0");
+    c->tune_baby_mfma = value;
+  } else if (strcmp(knob, "ptm") == 0) {
+    CHECK_ARG(value == 0 || value == 1, "ptm must be 0 or 1");
+    c->tune_ptm = value;
   } else if (strcmp(knob, "baby_share") == 0) {
     CHECK_ARG(value == 1 || value == 2 || value == 4 || value == 8, "baby_share must be 1, 2, 4 or 8");
     c->tune_baby_share = value;

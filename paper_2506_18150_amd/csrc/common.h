@@ -398,6 +398,9 @@ struct helrm_ctx {
   int tune_fuse_ks = 1;       // ModDown fused with the ModUp or rescale that follows it (0 = off)
   int tune_fuse_conv = 1;   // fused boundary: c1's ModDown inside the ModUp conversions
   int tune_conv_wgs = 1536;  // base conversion: split outputs into chunks until a launch has this many workgroups (0 = off)
+  int tune_baby_mfma = 8;    // batches of at least this many ciphertexts take the matrix-core plaintext MAC
+                             // when the plan has its operands (0 = never)
+  int tune_ptm = 1;          // plans with several giant steps build matrix-core operands (0 = never)
   int tune_gen_key_a = 2;    // regenerate keys' a_j halves from their seeds where a kernel serves one
                              // ciphertext per thread and streams keys: 0 never, 1 on primes below
                              // 2^40, 2 on every prime (default)
@@ -430,6 +433,8 @@ struct helrm_plan {
   size_t pt_words = 0;                   // n_diag * L_pq * N
   int *d_slot = nullptr;                 // device copy of slot
   size_t pt_limb_stride;                 // limbs per stored diagonal (= level+1+K)
+  uint8_t *d_ptm = nullptr;              // matrix-core operands: [giant tile][L_pq][N] x 4 KiB (or null)
+  int ptm_tiles = 0;
 };
 
 // ---------------------------------------------------------------- timing
@@ -566,6 +571,16 @@ inline uint32_t galois_of_step(const helrm_ctx *ctx, long step) {
 
 // Plain a_j of a seeded key over every prime of PQ_L: out [L+1+K][N].
 int launch_key_uniform(helrm_ctx *ctx, u64 seed, int digit, u64 *out, hipStream_t s);
+
+// Matrix-core operands of a plan (giant tiles of 8, at most 64 baby steps
+// per tile): slot_tab [tiles][64][8] device array of stored diagonal indices.
+int launch_ptm_pack(helrm_ctx *ctx, const helrm_plan *plan, const int *slot_tab, hipStream_t s);
+
+// ALU calibration (measurement only; both block until done): butterflies per
+// second of the NTT arithmetic on prime q, and instructions per second of
+// v_mad_u64_u32 (kind 0) or fp64 FMA (kind 1), counted per lane.
+int calibrate_butterflies(helrm_ctx *ctx, u64 q, hipStream_t s, double *per_s);
+int calibrate_instr(int kind, hipStream_t s, double *per_s);
 // (d0, d1, d2) of two ciphertexts at `level` ([batch][2][level+1] -> [batch][3][level+1]).
 int launch_tensor(helrm_ctx *ctx, const u64 *a, const u64 *b, u64 *d, int level, int batch, hipStream_t s);
 // (c0 + pt, c1) with one plaintext [level+1] limbs for every ciphertext of the batch.

@@ -900,6 +900,258 @@ __global__ __launch_bounds__(64 * W) void baby_mac_shared_kernel(BabyArgs BA, Le
                                             dig_bs, ct, ct_bs, pt, ng, X, x_bs, accum);
 }
 
+// ---------------------------------------------------------------- matrix-core plaintext MAC
+//
+// For a batch, the plaintext MAC of the baby-step stage is a dense integer
+// contraction at every coefficient x of every limb:
+//   X_g[c] = sum_b pt_{g,b}[x] R_b[c][x]     (both polynomials of every c),
+// rows (ciphertext, polynomial), columns the giant outputs, depth the baby
+// steps.  It runs on the int8 matrix cores exactly: a residue v in [0, q) is
+// centred to (-q/2, q/2) and written with P balanced base-256 digits d_i in
+// [-128, 127] (P = 5 below 2^40, 8 otherwise), v = sum_i d_i 256^i; the bytes
+// of (v + OFF) xor OFF, OFF = 0x80 repeated P times, are exactly those digits.
+// Then sum_b pt R = sum_s 256^s sum_{i+j=s} sum_b pt_j R_i, and every inner
+// sum over the (at most 64) baby steps is one v_mfma_i32_16x16x64_i8 product
+// (|partial| < 2^22).  The columns are rebuilt into the exact signed 128-bit
+// sum and reduced with one Montgomery reduction (the plaintexts are in
+// Montgomery form), which gives the same canonical residue as the VALU kernels.
+//
+// Operand layouts (16x16x64, lane l = 16 h + n): A holds row n, depths
+// 16 h .. 16 h + 15 in its 16 bytes; B holds column n, the same depths; the
+// result holds column n, rows 4 h .. 4 h + 3.  A row is (ciphertext,
+// polynomial) = (n / 2, n % 2) of 8 ciphertexts; a column n is giant n % 8
+// and digit 2 jp + n / 8 of the plaintext word (two digits of B per product),
+// so result tile s = i + 2 jp holds the column sums s (n < 8) and s + 1
+// (n >= 8), which lanes n and n ^ 8 exchange.
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+template <int P>
+struct Balanced {
+  static constexpr u64 OFF = P == 8 ? 0x8080808080808080ull : 0x8080808080ull;
+  // P digits hold [-OFF, 256^P - OFF): for q near 2^40 that is narrower than
+  // (-q/2, q/2], so the values from min((q + 1) / 2, 256^P - OFF) on are
+  // taken as v - q (which is >= -OFF since q <= 256^P)
+  static constexpr u64 LIM = P == 8 ? 0x7F7F7F7F7F7F7F80ull : 0x7F7F7F7F80ull;
+  // v in [0, q) -> the P digit bytes of its signed representative
+  static __device__ __forceinline__ u64 of(u64 v, u64 q) {
+    const u64 thr = min((q + 1) >> 1, LIM);
+    const u64 c = v >= thr ? v - q : v;   // two's complement of the signed value
+    return (c + OFF) ^ OFF;
+  }
+};
+
+// Bytes p of four words, packed in order into one 32-bit word.
+__device__ __forceinline__ uint32_t byte_quad(u64 a, u64 b, u64 c, u64 d, int p) {
+  const int sh = 8 * (p & 3);
+  const uint32_t wa = (uint32_t)(p < 4 ? a : a >> 32), wb = (uint32_t)(p < 4 ? b : b >> 32);
+  const uint32_t wc = (uint32_t)(p < 4 ? c : c >> 32), wd = (uint32_t)(p < 4 ? d : d >> 32);
+  return ((wa >> sh) & 0xFFu) | (((wb >> sh) & 0xFFu) << 8) | (((wc >> sh) & 0xFFu) << 16) |
+         (((wd >> sh) & 0xFFu) << 24);
+}
+
+// Limbs of one matrix-core launch (those of one digit count P).
+struct LimbSel {
+  int n;
+  unsigned char r[HELRM_MAX_LIMBS];
+};
+
+constexpr int MF_XB = 8;    // coefficients per workgroup (one per wavefront in the products)
+constexpr int MF_CT = 8;    // ciphertexts per workgroup (16 rows)
+constexpr int MF_TPB = 512;
+
+// R_b of ciphertext c at coefficient x (both polynomials, canonical), for
+// depth index k of the launch: k = 0 is b = 0 when has0, then the rotations.
+template <int BETA, class M>
+__device__ __forceinline__ void form_r(const BabyArgs &BA, const LevelGeom &G, int k, int x, int r, int p,
+                                      const PrimeInfo &pi, const u64 *dg, const u64 *c, bool isq, u64 &RB,
+                                      u64 &RA) {
+  const int N = 1 << G.logn;
+  RB = RA = 0;
+  if (BA.has0 && k == 0) {
+    if (isq) {
+      RB = shoup(c[(size_t)r * N + x], pi.pmod, pi.pmod_p, pi.q);
+      RA = shoup(c[((size_t)(G.level + 1) + r) * N + x], pi.pmod, pi.pmod_p, pi.q);
+    }
+    return;
+  }
+  const int i = k - BA.has0;
+  if (i < 0 || i >= BA.nrot) return;
+  const unsigned src = galois_src(x, BA.gal[i], G.logn);
+  const u64 *kk = BA.key[i];
+  M ab, aa;
+  ab.zero();
+  aa.zero();
+#pragma unroll
+  for (int j = 0; j < BETA; j++) {
+    const auto d = M::prep(dg[((size_t)j * G.pqn + r) * N + src]);
+    ab.mac(d, M::prep(kk[((size_t)(2 * j) * G.keyl + p) * N + x]));
+    aa.mac(d, M::prep(kk[((size_t)(2 * j + 1) * G.keyl + p) * N + x]));
+  }
+  RB = ab.finish(pi.q, pi.qn);
+  RA = aa.finish(pi.q, pi.qn);
+  if (isq) RB = add_mod(RB, shoup(c[(size_t)r * N + src], pi.pmod, pi.pmod_p, pi.q), pi.q);
+}
+
+template <int BETA, int P, class M>
+__device__ __forceinline__ void baby_mfma_body(uint32_t *A, u64 *O, const BabyArgs &BA, const LevelGeom &G,
+                                               int batch, int xb, int r, int b0, int p, const PrimeInfo &pi,
+                                               const u64 *digits, size_t dig_bs, const u64 *ct, size_t ct_bs,
+                                               const uint8_t *ptm, int ng, u64 *X, size_t x_bs, int accum) {
+  constexpr int NJP = (P + 1) / 2;          // B operands: two digits each
+  constexpr int NS = P + 2 * (NJP - 1);     // result tiles s = i + 2 jp
+  const int N = 1 << G.logn;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const bool isq = r <= G.level;
+  // the plaintext operands of this wavefront's coefficient, in flight during step 1
+  v4i bop[NJP];
+  {
+    const uint8_t *bp = ptm + (((size_t)r * N + xb * MF_XB + w) * 4) * 1024 + lane * 16;
+#pragma unroll
+    for (int jp = 0; jp < NJP; jp++) bop[jp] = *(const v4i *)(bp + jp * 1024);
+  }
+  // 1. R_b for (coefficient xi, ciphertext ci, depths 8 w .. 8 w + 7), as
+  //    balanced digits into A[xi][digit][row][depth]
+  {
+    const int xi = t & 7, ci = (t >> 3) & 7, x = xb * MF_XB + xi, c = b0 + ci;
+    const bool ok = c < batch;
+    const u64 *dg = digits + (size_t)(ok ? c : b0) * dig_bs;
+    const u64 *cc = ct + (size_t)(ok ? c : b0) * ct_bs;
+#pragma unroll 1
+    for (int kq = 0; kq < 2; kq++) {
+      u64 rb[4], ra[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        rb[u] = ra[u] = 0;
+        if (ok) form_r<BETA, M>(BA, G, 8 * w + 4 * kq + u, x, r, p, pi, dg, cc, isq, rb[u], ra[u]);
+        rb[u] = Balanced<P>::of(rb[u], pi.q);
+        ra[u] = Balanced<P>::of(ra[u], pi.q);
+      }
+#pragma unroll
+      for (int d = 0; d < P; d++) {
+        uint32_t *row = A + ((xi * P + d) * 16 + 2 * ci) * 16 + 2 * w + kq;
+        row[0] = byte_quad(rb[0], rb[1], rb[2], rb[3], d);
+        row[16] = byte_quad(ra[0], ra[1], ra[2], ra[3], d);
+      }
+    }
+  }
+  __syncthreads();
+  // 2. coefficient xi = w: P x NJP products, column sums, exact sum, REDC
+  const int n = lane & 15, h = lane >> 4, hf = n >> 3, g = n & 7;
+  u64 res[2];
+  {
+    const int xi = w;
+    v4i acc[NS];
+#pragma unroll
+    for (int k = 0; k < NS; k++) acc[k] = v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < P; i++) {
+      const v4i aop = *(const v4i *)(A + ((xi * P + i) * 16 + n) * 16 + 4 * h);
+#pragma unroll
+      for (int jp = 0; jp < NJP; jp++)
+        acc[i + 2 * jp] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, bop[jp], acc[i + 2 * jp], 0, 0, 0);
+    }
+    // lanes n and n ^ 8 hold the two digit halves of one giant's column sums
+    // (tile s: column s for n < 8, column s + 1 for n >= 8).  Each lane
+    // finishes two rows (2 hf + vv): column c = own tile c (n < 8) or c - 1
+    // (n >= 8) plus what lane n ^ 8 sends for that row.
+#pragma unroll
+    for (int vv = 0; vv < 2; vv++) {
+      u128 S = 0;   // the exact signed sum (|S| < 2^126) in two's complement mod 2^128
+#pragma unroll
+      for (int cidx = 0; cidx <= NS; cidx++) {
+        const int lo_t = cidx < NS ? acc[cidx][vv] : 0, lo_o = cidx < NS ? acc[cidx][2 + vv] : 0;
+        const int up_t = cidx >= 1 ? acc[cidx - 1][vv] : 0, up_o = cidx >= 1 ? acc[cidx - 1][2 + vv] : 0;
+        // n < 8: own tile c at row vv, partner's tile c - 1 at row vv;
+        // n >= 8: own tile c - 1 at row 2 + vv, partner's tile c at row 2 + vv
+        const int own = hf ? up_o : lo_t;
+        const int send = hf ? up_t : lo_o;
+        const long long col = (long long)own + (long long)__shfl_xor(send, 8);
+        S += (u128)(__int128)col << (8 * cidx);
+      }
+      long long hi = (long long)(u64)(S >> 64);
+      const u64 lo = (u64)S;
+      const long long q = (long long)pi.q;
+      if (hi < 0) hi += q;
+      if (hi < 0) hi += q;
+      if (hi >= q) hi -= q;
+      res[vv] = redc(lo, (u64)hi, pi.q, pi.qn);
+    }
+  }
+  __syncthreads();   // every wave is done with A: its space stages the results
+#pragma unroll
+  for (int vv = 0; vv < 2; vv++) O[(w * 16 + 4 * h + 2 * hf + vv) * 8 + g] = res[vv];
+  __syncthreads();
+  // 3. results: runs of 8 coefficients per (ciphertext, giant, polynomial)
+  {
+    const int xi = t & 7, gg = (t >> 3) & 7, rq = t >> 6, x = xb * MF_XB + xi;
+    if (gg < ng) {
+#pragma unroll
+      for (int k = 0; k < 2; k++) {
+        const int row = 2 * rq + k, c = b0 + (row >> 1), pol = row & 1;
+        if (c >= batch) continue;
+        u64 v = O[(xi * 16 + row) * 8 + gg];
+        u64 *o = X + (size_t)c * x_bs + ((size_t)(gg * 2 + pol) * G.pqn + r) * N + x;
+        if (accum) v = add_mod(v, *o, pi.q);
+        *o = v;
+      }
+    }
+  }
+}
+
+template <int BETA, int P>
+__global__ __launch_bounds__(MF_TPB, 4) void baby_mfma_kernel(BabyArgs BA, LevelGeom G, int L, int batch,
+                                                               int ntiles, LimbSel ls, const u64 *digits,
+                                                               size_t dig_bs, const u64 *ct, size_t ct_bs,
+                                                               const uint8_t *ptm, int ng, u64 *X, size_t x_bs,
+                                                               int accum, const PrimeInfo *pinfo) {
+  __shared__ __align__(16) uint32_t A[MF_XB * P * 16 * 16];
+  static_assert(MF_XB * P * 16 * 16 * 4 >= MF_XB * 16 * 8 * 8, "result staging fits in A");
+  const int N = 1 << G.logn;
+  const TileMap tm = tile_map(blockIdx.x, N / MF_XB, ntiles, ls.n, G.limb_xcd);
+  const int r = ls.r[tm.r];
+  const int p = pq_prime_dev(r, G.level, L);
+  const PrimeInfo pi = pinfo[p];
+  if (P == 5)
+    baby_mfma_body<BETA, P, SplitMac>(A, (u64 *)A, BA, G, batch, tm.xb, r, tm.tile * MF_CT, p, pi, digits, dig_bs,
+                                      ct, ct_bs, ptm, ng, X, x_bs, accum);
+  else
+    baby_mfma_body<BETA, P, WideMac>(A, (u64 *)A, BA, G, batch, tm.xb, r, tm.tile * MF_CT, p, pi, digits, dig_bs,
+                                     ct, ct_bs, ptm, ng, X, x_bs, accum);
+}
+
+// B operands of the matrix-core MAC, built once per plan: for giant tile T,
+// limb r, coefficient x and digit pair jp, 64 lanes x 16 bytes where lane
+// l = 16 h + n holds the balanced digit 2 jp + n / 8 of pt_{8T + n % 8, b}[x]
+// for the depths k = 16 h .. 16 h + 15 (b = the k-th baby step of the tile,
+// slot_tab[T][k][g] gives its stored diagonal, -1 none).  4 KiB per (T, r, x).
+__global__ __launch_bounds__(256) void ptm_pack_kernel(const u64 *pt, const int *slot_tab, uint8_t *ptm, int pqn,
+                                                       int level, int L, int N, const PrimeInfo *pinfo) {
+  const size_t tid = (size_t)blockIdx.x * 256 + threadIdx.x;   // ((T pqn + r) N + x) 256 + jp 64 + l
+  const int l = tid & 63, jp = (tid >> 6) & 3;
+  const size_t trx = tid >> 8;
+  const int x = (int)(trx % N), r = (int)((trx / N) % pqn), T = (int)(trx / N / pqn);
+  const PrimeInfo pi = pinfo[pq_prime_dev(r, level, L)];
+  const int P = pi.q < SPLIT_MAC_LIMIT ? 5 : 8;
+  const int n = l & 15, h = l >> 4, g = n & 7, d = 2 * jp + (n >> 3);
+  uint32_t wv[4] = {0, 0, 0, 0};
+  if (d < P) {
+    for (int t = 0; t < 16; t++) {
+      const int slot = slot_tab[((size_t)T * 64 + 16 * h + t) * 8 + g];
+      if (slot < 0) continue;
+      const u64 v = pt[((size_t)slot * pqn + r) * N + x];
+      const u64 bal = P == 5 ? Balanced<5>::of(v, pi.q) : Balanced<8>::of(v, pi.q);
+      const uint32_t byte = (uint32_t)(bal >> (8 * d)) & 0xFFu;
+      wv[t >> 2] |= byte << (8 * (t & 3));
+    }
+  }
+  uint32_t *o = (uint32_t *)(ptm + (trx * 4 + jp) * 1024 + l * 16);
+  o[0] = wv[0];
+  o[1] = wv[1];
+  o[2] = wv[2];
+  o[3] = wv[3];
+}
+
 // Plain a_j of a seeded key (REDC of the Montgomery-form value) on every prime.
 __global__ __launch_bounds__(TPB) void key_uniform_kernel(u64 seed, int j, u64 *out, const PrimeInfo *pinfo,
                                                           int N) {
@@ -1237,6 +1489,15 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
   return HELRM_OK;
 }
 
+int launch_ptm_pack(helrm_ctx *ctx, const helrm_plan *plan, const int *slot_tab, hipStream_t s) {
+  const int pqn = plan->level + 1 + ctx->K;
+  const size_t threads = (size_t)plan->ptm_tiles * pqn * ctx->N * 256;
+  hipLaunchKernelGGL(ptm_pack_kernel, dim3((unsigned)(threads / 256)), dim3(256), 0, s, plan->d_pt, slot_tab,
+                     plan->d_ptm, pqn, plan->level, ctx->L, ctx->N, ctx->d_pinfo);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
 int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, size_t digits_bstride,
                     const u64 *ct, size_t ct_bstride, u64 *X, size_t x_bstride, int g0, int ng, int batch,
                     hipStream_t s, bool accum, bool force) {
@@ -1310,7 +1571,36 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   const double words = nrot * kl + pl * npt + qn * B * (nrot * (beta + 1) + 2 * has0 + xw * ng) +
                        K * B * (nrot * beta + xw * ng);
   KTimer tm(ctx, s);
-  if (ng >= 2 && batch >= 2 && ctx->tune_baby_share >= 2) {
+  const bool mfma = plan->d_ptm && ctx->tune_baby_mfma > 0 && batch >= ctx->tune_baby_mfma &&
+                    g0 % HELRM_MAX_GTILE == 0 && g0 / HELRM_MAX_GTILE < plan->ptm_tiles &&
+                    BA.nrot + BA.has0 <= 64;
+  if (mfma) {
+    // batched plaintext MAC on the matrix cores: one launch per digit count
+    const int ntiles = (batch + MF_CT - 1) / MF_CT;
+    const uint8_t *ptm = plan->d_ptm + (size_t)(g0 / HELRM_MAX_GTILE) * G.pqn * ctx->N * 4096;
+    for (int wide = 0; wide < 2; wide++) {
+      LimbSel ls;
+      ls.n = 0;
+      for (int r = 0; r < G.pqn; r++)
+        if ((ctx->primes[ctx->pq_prime(r, level)] >= SPLIT_MAC_LIMIT) == (wide == 1)) ls.r[ls.n++] = (unsigned char)r;
+      if (ls.n == 0) continue;
+      const int grid = (ctx->N / MF_XB) * ls.n * ntiles;
+#define BABYM(BETA_, P_)                                                                                 \
+  hipLaunchKernelGGL((baby_mfma_kernel<BETA_, P_>), dim3(grid), dim3(MF_TPB), 0, s, BA, G, ctx->L, batch,  \
+                     ntiles, ls, digits, digits_bstride, ct, ct_bstride, ptm, ng, X, x_bstride, accum ? 1 : 0, \
+                     ctx->d_pinfo)
+#define BABYM_P(BETA_) \
+  if (wide) BABYM(BETA_, 8); else BABYM(BETA_, 5);
+      switch (G.beta) {
+        case 1: BABYM_P(1); break;
+        case 2: BABYM_P(2); break;
+        case 3: BABYM_P(3); break;
+        default: BABYM_P(4); break;
+      }
+#undef BABYM_P
+#undef BABYM
+    }
+  } else if (ng >= 2 && batch >= 2 && ctx->tune_baby_share >= 2) {
     // several giant outputs and a batch: W ciphertexts per workgroup
     const int W = pick_bt(batch, ctx->tune_baby_share);
     const int gpw = (ng + W - 1) / W;
@@ -1395,4 +1685,96 @@ int launch_key_uniform(helrm_ctx *ctx, u64 seed, int digit, u64 *out, hipStream_
                      ctx->N);
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
+}
+
+// ---------------------------------------------------------------- ALU calibration
+//
+// Issue-rate ceilings of the two instructions the library's modular products
+// are built from: the 32x32->64 integer multiply-add (v_mad_u64_u32: every
+// Shoup, Montgomery and split product) and the fp64 FMA (the exact products
+// of the small-prime NTT).  Each thread runs 16 independent chains with no
+// memory access inside the loop; the result is written out so that nothing is
+// optimised away.
+__global__ __launch_bounds__(256) void calib_mad_kernel(const u64 *seed, u64 *out, int iters) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  u64 a[16];
+  uint32_t y[16];
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    a[k] = seed[(t + k) & 63];
+    y[k] = (uint32_t)seed[64 + ((t + 5 * k) & 63)] | 1u;
+  }
+  for (int it = 0; it < iters; it++) {
+#pragma unroll
+    for (int r = 0; r < 8; r++)
+#pragma unroll
+      for (int k = 0; k < 16; k++) a[k] = (u64)(uint32_t)a[k] * y[k] + a[k];
+  }
+  u64 acc = 0;
+#pragma unroll
+  for (int k = 0; k < 16; k++) acc ^= a[k];
+  out[t] = acc;
+}
+
+__global__ __launch_bounds__(256) void calib_fma_kernel(const u64 *seed, u64 *out, int iters) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double d[16], c[16];
+  const double m = 0.9990234375;   // d += c m: finite for any iteration count used here
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    d[k] = (double)(seed[(t + k) & 63] >> 40);
+    c[k] = (double)(seed[64 + ((t + 5 * k) & 63)] >> 44);
+  }
+  for (int it = 0; it < iters; it++) {
+#pragma unroll
+    for (int r = 0; r < 8; r++)
+#pragma unroll
+      for (int k = 0; k < 16; k++) d[k] = __fma_rn(c[k], m, d[k]);
+  }
+  u64 acc = 0;
+#pragma unroll
+  for (int k = 0; k < 16; k++) acc ^= (u64)__double_as_longlong(d[k]);
+  out[t] = acc;
+}
+
+int calibrate_instr(int kind, hipStream_t s, double *per_s) {
+  const int blocks = 256 * 16, iters = 256;
+  const size_t threads = (size_t)blocks * 256;
+  u64 *buf = nullptr;
+  HIP_TRY(hipMalloc(&buf, (128 + threads) * sizeof(u64)));
+  std::vector<u64> seed(128);
+  u64 z = 0x13198A2E03707344ull;
+  for (auto &v : seed) {
+    z = z * 6364136223846793005ull + 1442695040888963407ull;
+    v = z;
+  }
+  int rc = HELRM_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMemcpy(buf, seed.data(), 128 * sizeof(u64), hipMemcpyHostToDevice) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("calibration set-up failed");
+    rc = HELRM_EHIP;
+  } else {
+    for (int rep = 0; rep < 2; rep++) {
+      if (rep == 1) (void)hipEventRecord(e0, s);
+      if (kind == 0)
+        hipLaunchKernelGGL(calib_mad_kernel, dim3(blocks), dim3(256), 0, s, buf, buf + 128, iters);
+      else
+        hipLaunchKernelGGL(calib_fma_kernel, dim3(blocks), dim3(256), 0, s, buf, buf + 128, iters);
+    }
+    (void)hipEventRecord(e1, s);
+    float ms = 0;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess || ms <= 0) {
+      (void)hipGetLastError();
+      set_error("calibration launch failed");
+      rc = HELRM_EHIP;
+    } else {
+      *per_s = (double)threads * iters * 8 * 16 / (ms * 1e-3);
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  return rc;
 }

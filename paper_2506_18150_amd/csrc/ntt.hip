@@ -468,7 +468,129 @@ int launch_ntt_h(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, i
   return launch_ntt_hw<H, 16, 8>(ctx, src, dst, ll, batch, forward, s, epi);
 }
 
+// ---------------------------------------------------------------- ALU calibration
+//
+// The ALU ceiling of the butterfly arithmetic: every thread keeps 16 residues
+// and 16 twiddles in registers and repeats forward radix-16 phases (4 stages,
+// 32 butterflies each) with the policy the passes use, with no memory access
+// inside the loop.  The fp64 policy's magnitudes grow by at most 2q a stage,
+// so every 4 phases (16 stages, as in a forward transform) the registers are
+// brought back to [0, q], which the transform's last pass also does.  The
+// result is written out so that nothing is optimised away.
+struct RegTw {
+  template <class T>
+  struct Src {
+    const T (&t)[16];
+    __device__ __forceinline__ T operator()(int m, int j) const { return t[(m + j) & 15]; }
+  };
+};
+
+template <class A>
+__global__ __launch_bounds__(256) void calib_bfly_kernel(A ar, const u64 *seed, u64 *out, int iters) {
+  using V = typename A::V;
+  using T = typename A::T;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  V x[16];
+  T w[16];
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    x[k] = ar.load(seed[(t + k) & 63] % ar.q_int());
+    w[k] = ar.tw_of(seed[64 + ((t + 3 * k) & 63)] % ar.q_int(), seed[128 + ((t + 3 * k) & 63)]);
+  }
+  const RegTw::Src<T> src{w};
+  for (int it = 0; it < iters; it++) {
+#pragma unroll
+    for (int ph = 0; ph < 4; ph++) fwd_phase<4>(x, ar, src);
+    ar.renorm(x);
+  }
+  u64 acc = 0;
+#pragma unroll
+  for (int k = 0; k < 16; k++) acc ^= ar.bits(x[k]);
+  out[t] = acc;
+}
+
+// Integer policy with the calibration hooks (values stay in [0, 8q)).
+template <bool NEG>
+struct IntCal : IntA<NEG> {
+  __device__ __forceinline__ u64 q_int() const { return this->q; }
+  __device__ __forceinline__ TW tw_of(u64 w, u64 wp) const { return TW{w, wp}; }
+  __device__ __forceinline__ void renorm(u64 (&)[16]) const {}
+};
+
+struct FltCal : FltA {
+  u64 qi;
+  __device__ __forceinline__ u64 q_int() const { return qi; }
+  __device__ __forceinline__ double tw_of(u64 w, u64) const { return (double)w; }
+  __device__ __forceinline__ void renorm(double (&x)[16]) const {
+#pragma unroll
+    for (int k = 0; k < 16; k++) x[k] = reduce(x[k]);
+  }
+};
+
 }  // namespace
+
+// Butterflies per second of the register-resident loop above on prime q
+// (fp64 policy below 2^41, integer policy from 2^41): one launch of
+// blocks x 256 threads after one warm-up launch, timed with HIP events on s.
+int calibrate_butterflies(helrm_ctx *ctx, u64 q, hipStream_t s, double *per_s) {
+  const int blocks = 256 * 16, iters = 64;
+  const size_t threads = (size_t)blocks * 256;
+  u64 *buf = nullptr;
+  HIP_TRY(hipMalloc(&buf, (192 + threads) * sizeof(u64)));
+  std::vector<u64> seed(192);
+  u64 z = 0x243F6A8885A308D3ull;
+  for (auto &v : seed) {
+    z = z * 6364136223846793005ull + 1442695040888963407ull;
+    v = z;
+  }
+  // twiddle words below q with their Shoup quotients
+  for (int k = 0; k < 64; k++) {
+    seed[64 + k] %= q;
+    seed[128 + k] = (u64)(((unsigned __int128)seed[64 + k] << 64) / q);
+  }
+  int rc = HELRM_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMemcpy(buf, seed.data(), 192 * sizeof(u64), hipMemcpyHostToDevice) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("calibration set-up failed");
+    rc = HELRM_EHIP;
+  } else {
+    for (int rep = 0; rep < 2; rep++) {
+      if (rep == 1) (void)hipEventRecord(e0, s);
+      if (q < FLT_LIMIT) {
+        FltCal ar;
+        ar.q = (double)q;
+        ar.qinv = 1.0 / (double)q;
+        ar.tw = nullptr;
+        ar.qi = q;
+        hipLaunchKernelGGL(calib_bfly_kernel<FltCal>, dim3(blocks), dim3(256), 0, s, ar, buf, buf + 192, iters);
+      } else {
+        IntCal<true> ar;
+        ar.q = q;
+        ar.q4 = 4 * q;
+        ar.nq = 0 - q;
+        ar.nq4 = 0 - 4 * q;
+        ar.tw = nullptr;
+        hipLaunchKernelGGL(calib_bfly_kernel<IntCal<true>>, dim3(blocks), dim3(256), 0, s, ar, buf, buf + 192,
+                           iters);
+      }
+    }
+    (void)hipEventRecord(e1, s);
+    float ms = 0;
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess || ms <= 0) {
+      (void)hipGetLastError();
+      set_error("calibration launch failed");
+      rc = HELRM_EHIP;
+    } else {
+      *per_s = (double)threads * iters * 4 * 32 / (ms * 1e-3);
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  return rc;
+}
 
 int launch_ntt(helrm_ctx *ctx, const u64 *src, u64 *dst, const LimbList &ll, int batch, bool forward,
                hipStream_t s) {

@@ -12,9 +12,16 @@ of different table counts carry different amounts of work).  The server
   queues and, whenever one of its streams is free, launches a batch of up to
   ``max_batch`` units of the group whose oldest unit has waited longest --
   units of different requests share a batch, and batches on different
-  streams overlap on the device;
+  streams overlap on the device; with ``mix_groups`` a batch takes the oldest
+  units of any groups and one launch (helrm_lookup_batch) runs each through
+  its own group's plan;
 * completes a request when its last unit finishes and its results are on the
-  host; latency = completion - arrival.
+  host; latency = completion - arrival;
+* cancels a request whose ``deadline`` (seconds after arrival) passes before
+  it completes, or that the client withdraws (``cancel``): it leaves the
+  admission queue, its queued units leave the group queues and its device
+  bytes are released at once; units already running finish and their results
+  are dropped.
 
 The executor does the device work; ``GpuExecutor`` runs helrm_lookup_packed
 on HIP streams, ``FakeExecutor`` (with ``FakeClock``) models durations so the
@@ -35,13 +42,18 @@ class Request:
     rid: int
     arrival: float
     units: List[Tuple[int, Any]]            # (group, selector ciphertext payload)
-    deadline: Optional[float] = None
+    deadline: Optional[float] = None         # seconds after arrival; None = no deadline
     admitted_at: Optional[float] = None
     done_at: Optional[float] = None
     results: Dict[int, Any] = field(default_factory=dict)
     remaining: int = 0
     rejected: bool = False
+    cancelled: Optional[str] = None          # "deadline" or "client" once cancelled
     bytes_in_flight: int = 0
+
+    @property
+    def closed(self) -> bool:
+        return self.rejected or self.cancelled is not None
 
     @property
     def latency(self) -> Optional[float]:
@@ -83,6 +95,12 @@ class FakeClock:
 class Executor:
     n_streams: int
 
+    def admit(self, req: Request) -> None:
+        """Make an admitted request's selectors resident (device pool)."""
+
+    def release(self, req: Request) -> None:
+        """Free what admit() took for the request."""
+
     def unit_bytes(self, group: int) -> int: ...
     def static_bytes(self) -> int: ...
     def workspace_bytes(self, group: int, batch: int) -> int: ...
@@ -103,6 +121,13 @@ class FakeExecutor(Executor):
         self._ub, self._ws, self._static, self._fail = unit_bytes, ws_bytes, static, fail
         self.busy_until = [0.0] * n_streams
         self.launches: List[Tuple[int, int, int, float]] = []
+        self.resident: set = set()
+
+    def admit(self, req):
+        self.resident.add(req.rid)
+
+    def release(self, req):
+        self.resident.discard(req.rid)
 
     def unit_bytes(self, group):
         return self._ub
@@ -117,7 +142,7 @@ class FakeExecutor(Executor):
         if self._fail(group, len(units)):
             raise RuntimeError("injected launch failure")
         start = max(self.clock.now(), self.busy_until[stream])
-        end = start + self.cost(group, len(units))
+        end = start + self.cost(max(group, 0) if group >= 0 else max(u.group for u in units), len(units))
         self.busy_until[stream] = end
         self.launches.append((stream, group, len(units), start))
         return (end, [("result", u.req.rid, u.group, u.payload) for u in units])
@@ -135,8 +160,9 @@ class FakeExecutor(Executor):
 
 class Server:
     def __init__(self, executor: Executor, clock, n_groups: int, hbm_budget: int, max_batch: int = 16,
-                 admit_timeout: float = 10.0, max_queue: int = 100000):
+                 admit_timeout: float = 10.0, max_queue: int = 100000, mix_groups: bool = False):
         self.ex, self.clock = executor, clock
+        self.mix_groups = mix_groups
         self.n_groups, self.max_batch = n_groups, max_batch
         self.budget = hbm_budget
         self.admit_timeout, self.max_queue = admit_timeout, max_queue
@@ -146,9 +172,17 @@ class Server:
         self.running: List[Tuple[int, Any, List[Unit]]] = []
         self.in_flight = 0
         # every stream may hold a workspace for a full batch of the largest group
-        self.ws_reserved = executor.n_streams * max(executor.workspace_bytes(g, max_batch) for g in range(n_groups))
+        # (or, mixing groups, for a full batch over every group's plan)
+        if mix_groups:
+            self.ws_reserved = executor.n_streams * executor.workspace_bytes(-1, max_batch)
+        else:
+            self.ws_reserved = executor.n_streams * max(executor.workspace_bytes(g, max_batch)
+                                                        for g in range(n_groups))
         self.completed: List[Request] = []
         self.rejected: List[Request] = []
+        self.expired: List[Request] = []
+        self.cancelled: List[Request] = []
+        self.admitted: Dict[int, Request] = {}
         self.failed_batches = 0
         self.batch_sizes: List[int] = []
 
@@ -169,6 +203,9 @@ class Server:
     def _admit(self, now: float):
         while self.waiting:
             r = self.waiting[0]
+            if r.closed:
+                self.waiting.popleft()
+                continue
             if now - r.arrival > self.admit_timeout:
                 self.waiting.popleft()
                 r.rejected = True
@@ -179,8 +216,40 @@ class Server:
             self.waiting.popleft()
             self.in_flight += r.bytes_in_flight
             r.admitted_at = now
+            self.admitted[r.rid] = r
+            self.ex.admit(r)
             for g, payload in r.units:
                 self.queues[g].append(Unit(r, g, payload, now))
+
+    # ------------------------------------------------------------------ cancellation
+    def _close(self, r: Request, why: str) -> None:
+        """Cancel r: drop its queued units and release its device bytes now;
+        units already launched finish and their results are discarded."""
+        if r.closed or r.done_at is not None:
+            return
+        r.cancelled = why
+        (self.expired if why == "deadline" else self.cancelled).append(r)
+        if self.admitted.pop(r.rid, None) is not None:
+            self.in_flight -= r.bytes_in_flight
+            self.ex.release(r)
+            for q in self.queues:
+                if any(u.req is r for u in q):
+                    kept = [u for u in q if u.req is not r]
+                    q.clear()
+                    q.extend(kept)
+
+    def cancel(self, rid: int) -> bool:
+        """Client cancellation of a request that has not completed."""
+        for r in list(self.waiting) + list(self.admitted.values()):
+            if r.rid == rid and not r.closed and r.done_at is None:
+                self._close(r, "client")
+                return True
+        return False
+
+    def _expire(self, now: float) -> None:
+        for r in list(self.waiting) + list(self.admitted.values()):
+            if r.deadline is not None and not r.closed and now - r.arrival > r.deadline:
+                self._close(r, "deadline")
 
     # ------------------------------------------------------------------ completion
     def _finish(self, now: float):
@@ -189,13 +258,15 @@ class Server:
             if self.ex.done(handle):
                 outs = self.ex.results(handle)
                 for u, o in zip(units, outs):
-                    if u.req.rejected:
+                    if u.req.closed:
                         continue
                     u.req.results[u.group] = o
                     u.req.remaining -= 1
                     if u.req.remaining == 0:
                         u.req.done_at = self.clock.now()
                         self.in_flight -= u.req.bytes_in_flight
+                        self.admitted.pop(u.req.rid, None)
+                        self.ex.release(u.req)
                         self.completed.append(u.req)
                 self.free_streams.append(stream)
             else:
@@ -203,14 +274,27 @@ class Server:
         self.running = still
 
     # ------------------------------------------------------------------ dispatch
-    def _dispatch(self, now: float):
-        while self.free_streams:
+    def _take(self) -> Tuple[int, List[Unit]]:
+        """The next batch: up to max_batch units of the group whose oldest unit
+        has waited longest, or (mixing groups) the max_batch oldest units of
+        any groups, which one launch runs over their different plans."""
+        if not self.mix_groups:
+            _, g = min((q[0].enq, g) for g, q in enumerate(self.queues) if q)
+            q = self.queues[g]
+            return g, [q.popleft() for _ in range(min(self.max_batch, len(q)))]
+        units: List[Unit] = []
+        while len(units) < self.max_batch:
             cands = [(q[0].enq, g) for g, q in enumerate(self.queues) if q]
             if not cands:
+                break
+            units.append(self.queues[min(cands)[1]].popleft())
+        return (units[0].group if len({u.group for u in units}) == 1 else -1), units
+
+    def _dispatch(self, now: float):
+        while self.free_streams:
+            if not any(self.queues):
                 return
-            _, g = min(cands)
-            q = self.queues[g]
-            units = [q.popleft() for _ in range(min(self.max_batch, len(q)))]
+            g, units = self._take()
             stream = self.free_streams.pop(0)
             try:
                 handle = self.ex.launch(stream, g, units)
@@ -219,12 +303,14 @@ class Server:
                 self.failed_batches += 1
                 self.free_streams.append(stream)
                 for u in units:
-                    if not u.req.rejected:
+                    if not u.req.closed:
                         u.req.rejected = True
                         self.in_flight -= u.req.bytes_in_flight
+                        self.admitted.pop(u.req.rid, None)
+                        self.ex.release(u.req)
                         self.rejected.append(u.req)
                 for qq in self.queues:
-                    kept = [u for u in qq if not u.req.rejected]
+                    kept = [u for u in qq if not u.req.closed]
                     qq.clear()
                     qq.extend(kept)
                 continue
@@ -234,11 +320,12 @@ class Server:
     def step(self):
         now = self.clock.now()
         self._finish(now)
+        self._expire(now)
         self._admit(now)
         self._dispatch(now)
 
     def idle(self) -> bool:
-        return not self.waiting and not self.running and not any(self.queues)
+        return not any(not r.closed for r in self.waiting) and not self.running and not any(self.queues)
 
     def run(self, requests: Sequence[Request]) -> Dict:
         """Feed requests at their arrival times and run until all finish."""
@@ -258,6 +345,10 @@ class Server:
             nd = self.ex.next_done_time()
             if nd is not None:
                 nxt.append(nd)
+            dl = [r.arrival + r.deadline for r in list(self.waiting) + list(self.admitted.values())
+                  if r.deadline is not None and not r.closed]
+            if dl:
+                nxt.append(min(dl) + 1e-9)
             if nxt:
                 self.clock.sleep_until(min(nxt))
             elif self.running:
@@ -276,6 +367,8 @@ class Server:
         return {
             "completed": len(self.completed),
             "rejected": len(self.rejected),
+            "expired": len(self.expired),
+            "cancelled": len(self.cancelled),
             "failed_batches": self.failed_batches,
             "p50_ms": float(np.percentile(lat, 50) * 1e3) if len(lat) else None,
             "p99_ms": float(np.percentile(lat, 99) * 1e3) if len(lat) else None,
@@ -287,8 +380,11 @@ class Server:
 
 class GpuExecutor(Executor):
     """Runs batches of group selectors through helrm_lookup_packed on HIP
-    streams.  Selectors arrive as host tensors; each launch copies its batch to
-    the device, runs the lookup and copies results back, all on its stream."""
+    streams.  Selectors arrive as pinned host tensors; at admission they are
+    copied into device memory (a copy stream; the request's in-flight bytes
+    are then real HBM), each launch gathers its batch from there, runs the
+    lookup and copies the results back, all on its stream; completion or
+    cancellation frees the request's device copies."""
 
     def __init__(self, ctx, plans: Sequence, level: int, N: int, n_streams: int = 2, max_batch: int = 16,
                  static_bytes: int = 0):
@@ -297,7 +393,7 @@ class GpuExecutor(Executor):
         self.ctx, self.plans, self.level, self.N = ctx, list(plans), level, N
         self.n_streams = n_streams
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
-        self._static = static_bytes
+        self.copy_stream = torch.cuda.Stream()
         self.max_batch = max_batch
         ct_words = 2 * (level + 1) * N
         out_words = 2 * level * N
@@ -306,9 +402,29 @@ class GpuExecutor(Executor):
                         for _ in range(n_streams)]
         self.host_out = [torch.empty(max_batch, out_words, dtype=torch.int64, pin_memory=True)
                          for _ in range(n_streams)]
+        # keys and plans (given) plus the per-stream staging buffers
+        self._static = static_bytes + 8 * n_streams * max_batch * (ct_words + out_words)
+        self.resident: Dict[Tuple[int, int], Tuple[Any, Any]] = {}   # (rid, group) -> (device copy, ready event)
+        # a full batch over every group's plan bounds any mixed batch's workspace
+        self.mix_plans = [self.plans[k % len(self.plans)] for k in range(max_batch)]
         for s in range(n_streams):
             for p in self.plans:
                 ctx.helrm_reserve(p, max_batch, self.streams[s])
+            ctx.helrm_reserve_batch(self.mix_plans, self.streams[s])
+
+    def admit(self, req):
+        torch = self.torch
+        with torch.cuda.stream(self.copy_stream):
+            for g, payload in req.units:
+                d = torch.empty(payload.numel(), dtype=torch.int64, device="cuda")
+                d.copy_(payload.reshape(-1), non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(self.copy_stream)
+                self.resident[(req.rid, g)] = (d, ev)
+
+    def release(self, req):
+        for g, _ in req.units:
+            self.resident.pop((req.rid, g), None)
 
     def unit_bytes(self, group):
         return 8 * 2 * (self.level + 1) * self.N
@@ -317,6 +433,8 @@ class GpuExecutor(Executor):
         return self._static
 
     def workspace_bytes(self, group, batch):
+        if group < 0:
+            return self.ctx.helrm_footprint_batch([self.plans[k % len(self.plans)] for k in range(batch)])
         return self.ctx.helrm_footprint(self.plans[group], batch)
 
     def launch(self, stream, group, units):
@@ -325,10 +443,20 @@ class GpuExecutor(Executor):
         B = len(units)
         with torch.cuda.stream(s):
             for k, u in enumerate(units):
-                self.in_buf[stream][k].copy_(u.payload.reshape(-1), non_blocking=True)
+                res = self.resident.get((u.req.rid, u.group)) if u.req is not None else None
+                if res is not None:
+                    d, ev = res
+                    s.wait_event(ev)
+                    self.in_buf[stream][k].copy_(d, non_blocking=True)
+                    d.record_stream(s)
+                else:
+                    self.in_buf[stream][k].copy_(u.payload.reshape(-1), non_blocking=True)
             sel = self.in_buf[stream][:B]
             out = self.out_buf[stream][:B]
-            self.ctx.helrm_lookup_packed(self.plans[group], sel, B, out, s)
+            if group >= 0:
+                self.ctx.helrm_lookup_packed(self.plans[group], sel, B, out, s)
+            else:   # units of several groups: one launch over their plans
+                self.ctx.helrm_lookup_batch([self.plans[u.group] for u in units], sel, out, s)
             self.host_out[stream][:B].copy_(out, non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
