@@ -42,11 +42,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["ntt_fwd_col", "ntt_fwd_blk", "ntt_inv_blk", "ntt_inv_col", "conv", "ks_acc", "baby_mac", "sub_mul"]
+KERNELS = ["ntt_fwd_col", "ntt_fwd_blk", "ntt_inv_blk", "ntt_inv_col", "conv", "ks_acc", "baby_mac", "sub_mul",
+           "baby_mfma", "baby_fold"]
+BABY_CLASSES = ("baby_mac", "baby_mfma", "baby_fold")
 KERNEL_SYMBOL = {
     "ntt_fwd_col": "ntt_pass_kernel<4, true, true>", "ntt_fwd_blk": "ntt_pass_kernel<4, true, false>",
     "ntt_inv_blk": "ntt_pass_kernel<4, false, false>", "ntt_inv_col": "ntt_pass_kernel<4, false, true>",
     "conv": "conv_kernel", "ks_acc": "ks_acc_kernel", "baby_mac": "baby_mac_kernel", "sub_mul": "sub_mul_kernel",
+    "baby_mfma": "baby_mfma_kernel", "baby_fold": "fold_entries_kernel + baby_fold_kernel",
 }
 DEFAULTS = {"w2": dict(n1=16, radix=8, sign=-1, batch=1, level=23),
             "w3": dict(n1=64, radix=8, sign=-1, batch=64, level=23),
@@ -111,6 +114,7 @@ def parse():
     ap.add_argument("--threshold", type=int, default=50000,
                     help="w7: tables of at most this many rows stay uncompressed (selector slots grow)")
     ap.add_argument("--level", type=int, default=None, help="selector level (default 23; 1 for w6)")
+    ap.add_argument("--d", type=int, default=768, help="w6: embedding width (rows of the lookup; Table I: 768)")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--n1", type=int, default=None)
     ap.add_argument("--radix", type=int, default=None)
@@ -129,6 +133,8 @@ def parse():
     ap.add_argument("--graph", action="store_true", help="replay one captured HIP graph per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-fold", action="store_true",
+                    help="do not fold the keys into plans of several giant steps (batched matrix-core product)")
     ap.add_argument("--no-extras", action="store_true",
                     help="w2 only: skip the level sweep, the batched w3 leg and the served leg")
     ap.add_argument("--batched", type=int, default=8,
@@ -149,7 +155,7 @@ def parse():
     return ap.parse_args()
 
 
-def make_tables(workload: str, synth, planner, threshold: int = 256):
+def make_tables(workload: str, synth, planner, threshold: int = 256, d: int = 768):
     """Seeded synthetic tables.  w2: one 65,536-row table as two base-256
     digit tables.  w3: 26 tables with log-uniform row counts (the first seed
     whose total lies in [3.0e7, 3.8e7])."""
@@ -158,8 +164,8 @@ def make_tables(workload: str, synth, planner, threshold: int = 256):
         parts = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(2)]
         return [planner.Table(rows=65536, d=16, base=256, parts=parts)]
     if workload == "w6":
-        parts = [synth.uniform_table(g, 16, 768, -0.05, 0.05) for _ in range(32)]
-        return [planner.Table(rows=16 ** 32, d=768, base=16, parts=parts)]
+        parts = [synth.uniform_table(g, 16, d, -0.05, 0.05) for _ in range(32)]
+        return [planner.Table(rows=16 ** 32, d=d, base=16, parts=parts)]
     _, counts = synth.criteo_like_row_counts()
     tables = []
     limit = threshold if workload == "w7" else 256
@@ -173,7 +179,7 @@ def make_tables(workload: str, synth, planner, threshold: int = 256):
     return tables
 
 
-def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int, threads=(0,)):
+def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int, threads=(0,), d: int = 768):
     """The CPU oracle on one selector ciphertext of the same workload (keys,
     plan encoding and encryption untimed), once per entry of `threads` (0 =
     every host thread OpenMP sees)."""
@@ -189,8 +195,8 @@ def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int, thre
         C = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(2)]
         tables = [O.TableSpec(rows=65536, d=16, base=256, C=C)]
     elif workload == "w6":
-        C = [synth.uniform_table(g, 16, 768, -0.05, 0.05) for _ in range(32)]
-        tables = [O.TableSpec(rows=16 ** 32, d=768, base=16, C=C)]
+        C = [synth.uniform_table(g, 16, d, -0.05, 0.05) for _ in range(32)]
+        tables = [O.TableSpec(rows=16 ** 32, d=d, base=16, C=C)]
     else:
         _, counts = synth.criteo_like_row_counts()
         tables = []
@@ -323,7 +329,7 @@ def w3_batched(prm, batch: int, steps: int) -> dict:
         autotune.Schedule(dflt["n1"], dflt["radix"], dflt["sign"])
     key_fn = lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals)
     t0 = time.time()
-    sess = LookupSession(prm, tables, 23, sc.n1, sc.radix, key_fn, sign=sc.sign)
+    sess = LookupSession(prm, tables, 23, sc.n1, sc.radix, key_fn, sign=sc.sign, fold=True)
     setup_s = time.time() - t0
     qg = synth.rng(5)
     idx = [synth.indices(qg, [t.rows for t in tables]) for _ in range(batch)]
@@ -344,7 +350,7 @@ def w3_batched(prm, batch: int, steps: int) -> dict:
     torch.cuda.synchronize()
     plain_ms = e0.elapsed_time(e1) / n_plain
     # batched: the tuned knobs for this batch, one captured graph per call
-    for k in ("ks_tile", "baby_tile", "baby_share", "ntt_col_w", "ntt_blk_w", "baby_mfma"):
+    for k in ("ks_tile", "baby_tile", "baby_share", "ntt_col_w", "ntt_blk_w", "baby_mfma", "baby_fold"):
         sess.ctx.helrm_set_tuning(k, getattr(sc, k))
     out = sess.new_output(batch)
     g = sess.ctx.helrm_batch_graph_create([sess.plan], sel, batch, out)
@@ -376,13 +382,14 @@ def w3_batched(prm, batch: int, steps: int) -> dict:
                     "p50_ms": float(np.percentile(per, 50)), "p99_ms": float(np.percentile(per, 99)),
                     "graph": "helrm_batch_graph_create/replay", "steps": steps,
                     "knobs": {k: getattr(sc, k) for k in ("ks_tile", "baby_tile", "baby_share", "ntt_col_w",
-                                                          "ntt_blk_w", "baby_mfma")},
+                                                          "ntt_blk_w", "baby_mfma", "baby_fold")},
                     "key_switches_per_s": {"hoisted": n_hoisted * batch / (ms / 1e3),
                                            "full": n_full * batch / (ms / 1e3)},
                     "max_abs_err": err},
         "plain": {"lookups_per_s": lk / (plain_ms / 1e3), "ms_per_call": plain_ms, "steps": n_plain,
                   "max_abs_err": err1},
         "setup_s": round(setup_s, 2),
+        "folded_plan_bytes": sess.folded_bytes,
     }
     res["batched_vs_plain"] = res["batched"]["lookups_per_s"] / res["plain"]["lookups_per_s"]
     del sel, out, out1, sel1
@@ -601,7 +608,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     prm = params.n16()
-    tables = make_tables(args.workload, synth, planner, args.threshold)
+    tables = make_tables(args.workload, synth, planner, args.threshold, args.d)
     M = planner.packed_matrix(tables)
     dflt = DEFAULTS[args.workload]
     B = args.batch or dflt["batch"]
@@ -620,19 +627,21 @@ def main():
     if tune_rec is not None:
         b = tune_rec["best"]
         sched = autotune.Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b["baby_share"],
-                                  b["ntt_col_w"], b["ntt_blk_w"], b.get("baby_mfma", 8))
+                                  b["ntt_col_w"], b["ntt_blk_w"], b.get("baby_mfma", 8), b.get("baby_fold", 32))
     if sched is None:
         sched = autotune.Schedule(dflt["n1"], dflt["radix"], dflt["sign"])
     n1 = args.n1 or sched.n1
     radix = args.radix or sched.radix
     sign = args.sign or sched.sign
     t0 = time.time()
-    sess = LookupSession(prm, tables, args.level, n1, radix, key_fn, sign=sign)
+    sess = LookupSession(prm, tables, args.level, n1, radix, key_fn, sign=sign,
+                         fold=not args.no_fold and max(B, args.batched or 0) >= 8)
     sess.ctx.helrm_set_tuning("ks_tile", args.ks_tile or sched.ks_tile)
     sess.ctx.helrm_set_tuning("baby_tile", args.baby_tile or sched.baby_tile)
     share = args.baby_share or sched.baby_share
     sess.ctx.helrm_set_tuning("baby_share", share)
     sess.ctx.helrm_set_tuning("baby_mfma", sched.baby_mfma)
+    sess.ctx.helrm_set_tuning("baby_fold", sched.baby_fold)
     for knob, v in (("ntt_col_w", args.ntt_col_w if args.ntt_col_w is not None else sched.ntt_col_w),
                     ("ntt_blk_w", args.ntt_blk_w if args.ntt_blk_w is not None else sched.ntt_blk_w),
                     ("ntt_small_limbs", args.ntt_small_limbs)):
@@ -707,7 +716,8 @@ def main():
                    "name": args.workload, "level": args.level, "batch": B, "tables": len(tables), "n1": n1,
                    "radix": radix, "sign": sign, "fold_span": spec.span, "graph": args.graph,
                    "ks_tile": args.ks_tile or sched.ks_tile, "baby_tile": args.baby_tile or sched.baby_tile,
-                   "baby_share": share, "baby_mfma": sched.baby_mfma},
+                   "baby_share": share, "baby_mfma": sched.baby_mfma, "baby_fold": sched.baby_fold,
+                   "folded_plan_bytes": sess.folded_bytes},
         "latency_ms": {"p50": float(np.percentile(per, 50)), "p99": float(np.percentile(per, 99))},
         "key_switches_per_s": {"hoisted": n_hoisted * cts_per_s, "full": n_full * cts_per_s,
                                "per_ciphertext": {"hoisted": n_hoisted, "full": n_full}},
@@ -727,7 +737,7 @@ def main():
         bs = autotune.tuned_schedule(prm.N, prm.L, args.level, M.shape[0], M.shape[1], Bb)
         if bs is not None and (bs.n1, bs.radix, bs.sign) == (n1, radix, sign):
             for knob, v in (("ks_tile", bs.ks_tile), ("baby_tile", bs.baby_tile), ("baby_share", bs.baby_share),
-                            ("baby_mfma", bs.baby_mfma)):
+                            ("baby_mfma", bs.baby_mfma), ("baby_fold", bs.baby_fold)):
                 sess.ctx.helrm_set_tuning(knob, v)
         for _ in range(2):
             sess.lookup(bsel, bout, stream)
@@ -743,7 +753,7 @@ def main():
         brows = sess.decrypt_rows(bout)
         berr = max(float(np.max(np.abs(brows[b] - sess.cleartext(bidx[b])))) for b in range(Bb))
         for knob, v in (("ks_tile", args.ks_tile or sched.ks_tile), ("baby_tile", args.baby_tile or sched.baby_tile),
-                        ("baby_share", share), ("baby_mfma", sched.baby_mfma)):
+                        ("baby_share", share), ("baby_mfma", sched.baby_mfma), ("baby_fold", sched.baby_fold)):
             sess.ctx.helrm_set_tuning(knob, v)
         res["batched"] = {"batch": Bb, "steps": nb, "ms_per_step": bms,
                           "lookups_per_s": Bb * len(tables) / (bms / 1e3), "max_abs_err": berr,
@@ -776,10 +786,11 @@ def main():
             traffic = measured_traffic(symbol[k], pmc_cfg)
             ent = {"kernel": symbol[k], "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
                    "avg_us": d["avg_us"], "launches_per_step": d["launches_per_step"]}
-            if k in alg:
-                ach = alg[k] / (d["ms_per_step"] * 1e6)
+            ak = "baby_mac" if k in BABY_CLASSES else k
+            if ak in alg:
+                ach = alg[ak] / (d["ms_per_step"] * 1e6)
                 ent.update(achieved=ach, frac=ach / HBM_PEAK_GBS,
-                           algorithmic_bytes_per_launch=alg[k] / d["launches_per_step"])
+                           algorithmic_bytes_per_launch=alg[ak] / d["launches_per_step"])
             else:
                 ent.update(achieved=d["GB/s"], frac=d["GB/s"] / HBM_PEAK_GBS,
                            algorithmic_bytes_per_launch=d["bytes_per_launch"])
@@ -789,7 +800,7 @@ def main():
             ent["traffic_frac"] = (traffic / (d["avg_us"] * 1e3) / HBM_PEAK_GBS) if traffic else None
             return ent
 
-        res["roofline"] = hbm_entry(dom) if dom in ("baby_mac", "ks_acc") else {
+        res["roofline"] = hbm_entry(dom) if dom in BABY_CLASSES + ("ks_acc",) else {
             "kernel": symbol[dom], "bound": "alu", "note": "see roofline_ntt / roofline_conv"}
         if "ks_acc" in table:
             res["roofline_keyswitch"] = hbm_entry("ks_acc")
@@ -846,7 +857,7 @@ def main():
                          "served_vs_plain": row["served_vs_plain"],
                          "served_mixed_vs_plain": row["served_mixed_vs_plain"], "what": srv["what"]}
     if not args.no_cpu_baseline and args.workload != "w7":
-        cb = cpu_baseline(args.workload, args.level, n1, radix, sign, threads=(0, 1))
+        cb = cpu_baseline(args.workload, args.level, n1, radix, sign, threads=(0, 1), d=args.d)
         res["cpu_baseline"] = cb[0]
         res["cpu_baseline_single_thread"] = cb[1]
     print(json.dumps(res))

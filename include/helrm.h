@@ -227,6 +227,21 @@ typedef struct {
 int helrm_plan_create(helrm_ctx *ctx, const helrm_plan_desc *desc, helrm_plan **out);
 int helrm_plan_destroy(helrm_plan *plan);
 
+/* Fold the evaluation keys into the plan's plaintext diagonals for batched
+ * lookups (the product of Sec. III-B reassociated: sum_b pt_b sum_j
+ * sigma_b(d_j) k_{b,j} = sum_{b,j} sigma_b(d_j) (pt_b k_{b,j}), identical
+ * residues): the library builds and keeps W = pt_{g,b} k_{b,j} (and pt P for
+ * the c0 terms) as matrix-core operands, and lookups of at least `baby_fold`
+ * ciphertexts (helrm_set_tuning, default 32) then form no rotated ciphertext
+ * at all.  Needs the keys of every baby step loaded; a later
+ * helrm_load_eval_keys makes the folded words stale (lookups then use the
+ * other kernels until the plan is folded again).  Memory: per giant tile of
+ * 8, (level+1+K) N ceil(4 n_baby / 64) KiB times 5 (primes below 2^40) or 8
+ * digits; *bytes (may be NULL) receives the total.  At most 3 key-switching
+ * digits.  Blocks.  Errors: HELRM_EINVAL (foreign plan, missing key, more than
+ * 3 digits), HELRM_ENOMEM. */
+int helrm_plan_fold_keys(helrm_ctx *ctx, helrm_plan *plan, size_t *bytes);
+
 /* Galois steps the plan needs keys for (host query): writes up to `cap`
  * rotation steps into steps and their count into *n. */
 int helrm_plan_rotation_steps(const helrm_plan *plan, int32_t *steps, int cap, int *n);
@@ -357,11 +372,12 @@ int helrm_calibrate_alu(helrm_ctx *ctx, int kind, int prime_index, void *stream,
  * "ntt_fwd_col", "ntt_fwd_blk", "ntt_inv_blk", "ntt_inv_col" (the two passes
  * of each transform), "conv" (fast base conversion), "ks_acc" (key inner
  * product + automorphism), "baby_mac" (fused baby steps and plaintext MAC),
- * "sub_mul" (ModDown / rescale finish).  helrm_timing_read waits for the
+ * "sub_mul" (ModDown / rescale finish), "baby_mfma" (the same on the matrix
+ * cores) and "baby_fold" (the key-folded product and its entries pass).  helrm_timing_read waits for the
  * recorded launches of one class and returns their summed duration (ms), the
- * launch count, and the algorithmic bytes and modular products those launches
- * process (each kernel's minimum HBM traffic: every operand read once, every
- * result written once). */
+ * launch count, and the bytes and modular products those launches process
+ * (every operand read once, every result written once; for the matrix-core
+ * classes the bytes those kernels stream, see the kernel notes). */
 int helrm_timing_enable(helrm_ctx *ctx, int enable);
 int helrm_timing_read(helrm_ctx *ctx, const char *kernel, double *ms, int64_t *launches, double *bytes,
                       double *ops);

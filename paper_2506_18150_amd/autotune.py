@@ -39,6 +39,7 @@ class Schedule:
     ntt_col_w: int = 16
     ntt_blk_w: int = 4
     baby_mfma: int = 8
+    baby_fold: int = 32
 
 
 def library_revision() -> str:
@@ -81,7 +82,7 @@ def tuned_schedule(N: int, L: int, level: int, rows: int, cols: int, batch: int,
         return None
     b = rec["best"]
     return Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b.get("baby_share", 8),
-                    b.get("ntt_col_w", 16), b.get("ntt_blk_w", 4), b.get("baby_mfma", 8))
+                    b.get("ntt_col_w", 16), b.get("ntt_blk_w", 4), b.get("baby_mfma", 8), b.get("baby_fold", 32))
 
 
 def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
@@ -121,20 +122,28 @@ def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
     for sc, spec in specs:
         plan = ctx.helrm_plan_create(level, spec.m, spec.n1, spec.n2, spec.radix, spec.diag, spec.coeffs,
                                      spec.sign, spec.span)
+        folded = False
+        if batch >= 8 and spec.n2 >= 2 and prm.n_digits(level) <= 3:
+            plan.helrm_plan_fold_keys()
+            folded = True
         ctx.helrm_reserve(plan, batch, stream)
+        # (ks_tile, baby_tile, baby_share, baby_mfma, baby_fold)
         if batch == 1:
-            knobs = [(4, 4, 8, 0)]
+            knobs = [(4, 4, 8, 0, 0)]
         elif spec.n2 == 1:   # one giant output: the per-thread baby-step tile matters
-            knobs = [(a, b, 8, 0) for a in tiles for b in tiles]
+            knobs = [(a, b, 8, 0, 0) for a in tiles for b in tiles]
         else:                # several giant outputs: the workgroup-shared kernel's width, or the matrix cores
-            knobs = [(a, 4, c, 0) for a in tiles for c in shares]
+            knobs = [(a, 4, c, 0, 0) for a in tiles for c in shares]
             if batch >= 8:
-                knobs += [(a, 4, 8, 8) for a in tiles]
-        for kt, bt, sh, mf in knobs:
+                knobs += [(a, 4, 8, 8, 0) for a in tiles]
+                if folded:
+                    knobs += [(a, 4, 8, 8, 8) for a in tiles]
+        for kt, bt, sh, mf, fo in knobs:
             ctx.helrm_set_tuning("ks_tile", kt)
             ctx.helrm_set_tuning("baby_tile", bt)
             ctx.helrm_set_tuning("baby_share", sh)
             ctx.helrm_set_tuning("baby_mfma", mf)
+            ctx.helrm_set_tuning("baby_fold", fo)
             for _ in range(warmup):
                 ctx.helrm_lookup_packed(plan, sel, batch, out, stream)
             torch.cuda.synchronize()
@@ -146,7 +155,7 @@ def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
             rec = {"n1": sc.n1, "radix": sc.radix, "sign": sc.sign, "span": spec.span, "ks_tile": kt,
-                   "baby_tile": bt, "baby_share": sh, "baby_mfma": mf, "ms_per_batch": ms,
+                   "baby_tile": bt, "baby_share": sh, "baby_mfma": mf, "baby_fold": fo, "ms_per_batch": ms,
                    "lookups_per_s": batch * len(tables) / (ms / 1e3), "keys": len(spec.rotation_steps())}
             results.append(rec)
             if log:
@@ -158,7 +167,9 @@ def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,
     spec = next(sp for s_, sp in specs if (s_.n1, s_.radix, s_.sign) == (sc.n1, sc.radix, sc.sign))
     plan = ctx.helrm_plan_create(level, spec.m, spec.n1, spec.n2, spec.radix, spec.diag, spec.coeffs, spec.sign,
                                  spec.span)
-    for knob in ("ks_tile", "baby_tile", "baby_share", "baby_mfma"):
+    if best["baby_fold"]:
+        plan.helrm_plan_fold_keys()
+    for knob in ("ks_tile", "baby_tile", "baby_share", "baby_mfma", "baby_fold"):
         ctx.helrm_set_tuning(knob, best[knob])
     best_ntt = None
     for wc, wb in ((16, 4), (16, 8), (8, 4)):

@@ -58,7 +58,7 @@ EXPORTS = [
     "helrm_key_uniform", "helrm_footprint_multi", "helrm_reserve_multi", "helrm_batch_graph_create",
     "helrm_batch_graph_replay", "helrm_batch_graph_destroy", "helrm_lookup_packed_noalloc",
     "helrm_calibrate_alu", "helrm_lookup_batch", "helrm_footprint_batch", "helrm_reserve_batch",
-    "helrm_batch_graph_create_mixed",
+    "helrm_batch_graph_create_mixed", "helrm_plan_fold_keys",
 ]
 
 _lib = None
@@ -105,6 +105,7 @@ def lib() -> ctypes.CDLL:
     L.helrm_reserve_multi.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, _c_int, _vp]
     L.helrm_batch_graph_create.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, _vp, _c_int, _vp, ctypes.POINTER(_vp)]
     L.helrm_batch_graph_replay.argtypes = [_vp, _vp]
+    L.helrm_plan_fold_keys.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]
     L.helrm_lookup_batch.argtypes = [_vp, ctypes.POINTER(_vp), _vp, _c_int, _vp, _vp]
     L.helrm_footprint_batch.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.helrm_reserve_batch.argtypes = [_vp, ctypes.POINTER(_vp), _c_int, _vp]
@@ -333,6 +334,12 @@ class Plan:
     def __init__(self, ctx: Context, h, level, m, n1, n2, radix):
         self.ctx, self.h = ctx, h
         self.level, self.m, self.n1, self.n2, self.radix = level, m, n1, n2, radix
+
+    def helrm_plan_fold_keys(self) -> int:
+        """Fold the loaded keys into the plan (batched lookups); returns the bytes kept."""
+        v = ctypes.c_size_t()
+        _check(lib().helrm_plan_fold_keys(self.ctx.h, self.h, ctypes.byref(v)))
+        return v.value
 
     def rotation_steps(self):
         n = ctypes.c_int()

@@ -57,7 +57,8 @@ void timing_push(helrm_ctx *ctx, int k, hipEvent_t a, hipEvent_t b, double bytes
 }
 
 static const char *const kTimedNames[TK_COUNT] = {"ntt_fwd_col", "ntt_fwd_blk", "ntt_inv_blk", "ntt_inv_col",
-                                                  "conv",        "ks_acc",      "baby_mac",    "sub_mul"};
+                                                  "conv",        "ks_acc",      "baby_mac",    "sub_mul",
+                                                  "baby_mfma",   "baby_fold"};
 
 static void timing_clear(helrm_ctx *ctx) {
   std::vector<hipEvent_t> seen;
@@ -567,6 +568,7 @@ KsSizes ks_sizes(const helrm_ctx *ctx, int level, int batch, int n_pq) {
 // C: coefficient-form limbs of a ModDown input ([2][pqn] per element).
 struct MatvecWS {
   u64 *coef, *F, *C, *Dg, *X, *xg, *acc, *zA, *zB, *mdP, *mdT, *top, *V, *mv;
+  uint32_t *E;   // entries of the key-folded product (plans with folded operands), or null
 };
 
 // Non-zero giant steps of a plan, or of the union of several plans' giants.
@@ -599,6 +601,7 @@ size_t matvec_ws_bytes(const helrm_ctx *ctx, const helrm_plan *p, int batch, boo
     tot += rnd(B * 2 * lv * N);                 // V
     tot += rnd(B * 2 * qn * N);                 // matvec result
   }
+  if (p->d_wm) tot += rnd(B * fold_entry_words(ctx, (int)lv) / 2);   // E (32-bit words)
   return tot;
 }
 
@@ -626,6 +629,7 @@ MatvecWS carve_matvec(const helrm_ctx *ctx, const helrm_plan *p, int batch, bool
     w.V = a.take(B * 2 * lv * N);
     w.mv = a.take(B * 2 * qn * N);
   }
+  w.E = p->d_wm ? (uint32_t *)a.take(B * fold_entry_words(ctx, (int)lv) / 2) : nullptr;
   return w;
 }
 
@@ -663,7 +667,7 @@ int run_matvec(helrm_ctx *ctx, const helrm_plan *const *ps, int n_in, const u64 
       const bool force = c == 0 && n_in > 1;
       if (!any && !force) continue;
       TRY(launch_baby_mac(ctx, pc, D, (size_t)f_bs * N, ctc, (size_t)ct_bs * N, w.X + (size_t)g0 * 2 * pqn * N,
-                          x_bs * N, g0, ng, batch, s, c > 0, force));
+                          x_bs * N, g0, ng, batch, s, c > 0, force, pc->d_wm ? w.E : nullptr));
     }
     for (int g : pc->giants)
       if (std::find(giants.begin(), giants.end(), g) == giants.end()) giants.push_back(g);
@@ -858,7 +862,7 @@ int run_mixed(helrm_ctx *ctx, const std::vector<PlanGroup> &groups, const u64 *c
       const int ng = std::min(HELRM_MAX_GTILE, g.p->n2 - g0);
       TRY(launch_baby_mac(ctx, g.p, D + g.start * f_bs * N, f_bs * N, ct + g.start * ct_bs * N, ct_bs * N,
                           w.X + (g.start * x_bs + (size_t)g0 * 2 * pqn) * N, x_bs * N, g0, ng, g.count, s, false,
-                          true));
+                          true, w.E ? w.E + g.start * fold_entry_words(ctx, lv) : nullptr));
     }
   // elements with no fold stage: the suffix of groups with stages == 0
   auto stages_of = [&](const PlanGroup &g) { return (int)g.p->stages.size(); };
@@ -1246,6 +1250,7 @@ extern "C" int helrm_load_eval_keys(helrm_ctx *c, const uint32_t *galois, int n_
     TRY(launch_to_mont(c, d, ll, c->dnum * 2, 0));
     TRY(launch_pack_key(c, d, 0));
   }
+  if (n_keys > 0) c->keys_gen++;   // folded plan operands built from earlier keys are stale now
   HIP_TRY(hipDeviceSynchronize());
   return HELRM_OK;
   API_GUARD_END
@@ -1635,7 +1640,67 @@ extern "C" int helrm_plan_destroy(helrm_plan *p) {
   if (p->d_pt) (void)hipFree(p->d_pt);
   if (p->d_slot) (void)hipFree(p->d_slot);
   if (p->d_ptm) (void)hipFree(p->d_ptm);
+  if (p->d_wm) (void)hipFree(p->d_wm);
   delete p;
+  return HELRM_OK;
+  API_GUARD_END
+}
+
+extern "C" int helrm_plan_fold_keys(helrm_ctx *c, helrm_plan *p, size_t *bytes) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c && p && p->ctx == c, "NULL or foreign plan");
+  CHECK_ARG(c->n_digits(p->level) <= 3, "key folding supports at most 3 key-switching digits (level %d has %d)",
+            p->level, c->n_digits(p->level));
+  const int pqn = p->level + 1 + c->K, n1 = p->n1;
+  const int tiles = (p->n2 + HELRM_MAX_GTILE - 1) / HELRM_MAX_GTILE;
+  // depth: 4 entries per baby step of the tile, chunks of 64
+  int kc = 1;
+  for (int T = 0; T < tiles; T++) {
+    int ns = 0;
+    for (int b : p->babies) {
+      bool any = false;
+      for (int g = 0; g < HELRM_MAX_GTILE && T * HELRM_MAX_GTILE + g < p->n2; g++)
+        if (p->slot[(size_t)(T * HELRM_MAX_GTILE + g) * n1 + b] >= 0) any = true;
+      ns += any ? 1 : 0;
+    }
+    CHECK_ARG(ns <= HELRM_MAX_BABY, "key folding: at most %d baby steps per giant tile", HELRM_MAX_BABY);
+    kc = std::max(kc, (4 * ns + 63) / 64);
+  }
+  std::vector<int> planes(pqn), off(pqn);
+  int tot = 0;
+  for (int r = 0; r < pqn; r++) {
+    planes[r] = c->primes[c->pq_prime(r, p->level)] < SPLIT_MAC_LIMIT ? 5 : 8;
+    off[r] = tot;
+    tot += planes[r];
+  }
+  const size_t tile_bytes = (size_t)tot * c->N * kc * 1024;
+  if (p->d_wm) {
+    HIP_TRY(hipDeviceSynchronize());
+    (void)hipFree(p->d_wm);
+    p->d_wm = nullptr;
+  }
+  if (hipMalloc(&p->d_wm, tile_bytes * tiles) != hipSuccess) {
+    (void)hipGetLastError();
+    p->d_wm = nullptr;
+    set_error("folded operands: allocation of %zu bytes failed", tile_bytes * tiles);
+    return HELRM_ENOMEM;
+  }
+  p->wm_kc = kc;
+  p->wm_tiles = tiles;
+  p->wm_tile_bytes = tile_bytes;
+  p->wm_planes = planes;
+  p->wm_off = off;
+  for (int T = 0; T < tiles; T++) {
+    const int rc = launch_wfold_pack(c, p, T, 0);
+    if (rc != HELRM_OK) {
+      (void)hipFree(p->d_wm);
+      p->d_wm = nullptr;
+      return rc;
+    }
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  p->wm_keys_gen = c->keys_gen;
+  if (bytes) *bytes = tile_bytes * tiles;
   return HELRM_OK;
   API_GUARD_END
 }
@@ -2029,6 +2094,9 @@ extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
   } else if (strcmp(knob, "baby_mfma") == 0) {
     CHECK_ARG(value >= 0, "baby_mfma must be >= 0");
     c->tune_baby_mfma = value;
+  } else if (strcmp(knob, "baby_fold") == 0) {
+    CHECK_ARG(value >= 0, "baby_fold must be >= 0");
+    c->tune_baby_fold = value;
   } else if (strcmp(knob, "ptm") == 0) {
     CHECK_ARG(value == 0 || value == 1, "ptm must be 0 or 1");
     c->tune_ptm = value;

@@ -358,6 +358,8 @@ enum TimedKernel {
   TK_KS_ACC,
   TK_BABY_MAC,
   TK_SUB_MUL,
+  TK_BABY_MFMA,
+  TK_BABY_FOLD,
   TK_COUNT
 };
 
@@ -401,6 +403,9 @@ struct helrm_ctx {
   int tune_baby_mfma = 8;    // batches of at least this many ciphertexts take the matrix-core plaintext MAC
                              // when the plan has its operands (0 = never)
   int tune_ptm = 1;          // plans with several giant steps build matrix-core operands (0 = never)
+  int tune_baby_fold = 32;   // batches of at least this many ciphertexts take the key-folded matrix-core
+                             // product when the plan has folded operands (0 = never)
+  uint64_t keys_gen = 1;     // bumped by every helrm_load_eval_keys (folded operands of older keys are stale)
   int tune_gen_key_a = 2;    // regenerate keys' a_j halves from their seeds where a kernel serves one
                              // ciphertext per thread and streams keys: 0 never, 1 on primes below
                              // 2^40, 2 on every prime (default)
@@ -435,6 +440,14 @@ struct helrm_plan {
   size_t pt_limb_stride;                 // limbs per stored diagonal (= level+1+K)
   uint8_t *d_ptm = nullptr;              // matrix-core operands: [giant tile][L_pq][N] x 4 KiB (or null)
   int ptm_tiles = 0;
+  // key-folded operands (helrm_plan_fold_keys): per giant tile, limb r and
+  // coefficient x, wm_kc depth chunks of wm_planes[r] x 1 KiB; limb r starts
+  // at wm_off[r] KiB-units x N x wm_kc within the tile
+  uint8_t *d_wm = nullptr;
+  int wm_kc = 0, wm_tiles = 0;
+  size_t wm_tile_bytes = 0;
+  std::vector<int> wm_planes, wm_off;
+  uint64_t wm_keys_gen = 0;              // the context's key generation the operands were built from
 };
 
 // ---------------------------------------------------------------- timing
@@ -576,6 +589,17 @@ int launch_key_uniform(helrm_ctx *ctx, u64 seed, int digit, u64 *out, hipStream_
 // per tile): slot_tab [tiles][64][8] device array of stored diagonal indices.
 int launch_ptm_pack(helrm_ctx *ctx, const helrm_plan *plan, const int *slot_tab, hipStream_t s);
 
+// 32-bit words of the folded product's entry workspace per ciphertext at a
+// level (entries of the rotated steps, then of step 0): 2 N sum_r P_r.
+inline size_t fold_entry_words(const helrm_ctx *ctx, int level) {
+  size_t tot = 0;
+  for (int r = 0; r < level + 1 + ctx->K; r++) tot += ctx->primes[ctx->pq_prime(r, level)] < (1ull << 40) ? 5 : 8;
+  return 2 * tot * (size_t)ctx->N;
+}
+
+// Key-folded operands of giant tile T of a plan (helrm_plan_fold_keys).
+int launch_wfold_pack(helrm_ctx *ctx, helrm_plan *plan, int T, hipStream_t s);
+
 // ALU calibration (measurement only; both block until done): butterflies per
 // second of the NTT arithmetic on prime q, and instructions per second of
 // v_mad_u64_u32 (kind 0) or fp64 FMA (kind 1), counted per lane.
@@ -595,7 +619,10 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
 // Fused baby steps + plaintext MAC: X_g = sum_b pt_{g,b} (.) R_b for g in
 // [g0, g0+ng).
 // accum: add to what X holds; force: launch (writing zeros) even when no baby
-// step of this plan feeds giants g0..g0+ng-1.
+// step of this plan feeds giants g0..g0+ng-1; fold_ws: batch x
+// fold_entry_words(level) words of workspace for the key-folded product
+// (null: that product is not taken).
 int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, size_t digits_bstride,
                     const u64 *ct, size_t ct_bstride, u64 *X, size_t x_bstride, int g0, int ng,
-                    int batch, hipStream_t s, bool accum = false, bool force = false);
+                    int batch, hipStream_t s, bool accum = false, bool force = false,
+                    uint32_t *fold_ws = nullptr);

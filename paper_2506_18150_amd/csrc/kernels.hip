@@ -1120,6 +1120,272 @@ __global__ __launch_bounds__(MF_TPB, 4) void baby_mfma_kernel(BabyArgs BA, Level
                                      ct, ct_bs, ptm, ng, X, x_bs, accum);
 }
 
+// ---------------------------------------------------------------- key-folded matrix-core product
+//
+// With the keys folded into the plaintexts the whole baby-step stage of a
+// batch is one integer contraction per coefficient and limb:
+//   X_g[c] = sum_b pt_{g,b} R_b[c],  R_b = sum_j sigma_b(d_j) k_{b,j} (+ P sigma_b(c0))
+//          = sum_{b,e} sigma_b(y_e[c]) W_{g,b,e},   W_{g,b,e} = pt_{g,b} k_{b,e}
+// with y_e the digits d_0..d_{beta'-1} and c0 (whose "key" is P, on the Q
+// limbs), and for b = 0 the unrotated c0 and c1 with W = pt_{g,0} P on the
+// polynomial they feed: the same residues mod q (the sum is only
+// reassociated), with no per-rotation key switch left to form.  Rows are the
+// ciphertexts (16 per product), columns (giant, polynomial) (16), depth the
+// (baby step, entry) pairs, 4 entries per baby step (beta' <= 3; unused
+// entries are zero), in chunks of 64; the operands are balanced base-256
+// digits as in the MAC above, here P x P products per chunk (tile s = i + j
+// holds column s), rebuilt into the exact sum and reduced once.  The folded
+// words are built once per plan and key set (wfold_pack_kernel, 1 KiB per
+// digit, chunk, limb, coefficient and giant tile).
+
+struct FoldRun {
+  int nslot, has0, kc;                 // baby slots (b = 0 first when has0), depth chunks of 64
+  unsigned gal[HELRM_MAX_BABY];        // Galois element of rotation slot has0 + i
+  unsigned off[HELRM_MAX_PRIMES];      // limb r's block in the tile, in units of N * kc KiB
+};
+
+constexpr int FD_RS = 20;             // LDS dwords per ciphertext row (16 used): conflict-free 16-byte accesses
+
+template <int P>
+struct FoldLds {
+  static constexpr int PS = 16 * FD_RS;        // dwords per digit plane (16 ciphertexts)
+  static constexpr int XS = P * PS + 8;        // dwords per coefficient (offset 8 mod 64 banks)
+  static constexpr int WORDS = MF_XB * XS;
+};
+
+template <int P, int MP>
+__device__ __forceinline__ void baby_fold_body(uint32_t *A, const FoldRun &FR, const LevelGeom &G, int batch,
+                                               int xb, int r, const PrimeInfo &pi, const uint32_t *E, size_t e_bs,
+                                               size_t e_half, const uint8_t *wm, int ng, u64 *X, size_t x_bs,
+                                               int accum) {
+  using LD = FoldLds<P>;
+  constexpr int NS = 2 * P - 1;
+  const int N = 1 << G.logn;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int n = lane & 15, h = lane >> 4;
+  const uint8_t *wx = wm + ((size_t)FR.off[r] * N * FR.kc + (size_t)(xb * MF_XB + w) * FR.kc * P) * 1024 + lane * 16;
+  const int mtiles = (batch + 15) / 16;
+  // MP row tiles of 16 ciphertexts per pass share every folded operand load
+  for (int mt0 = 0; mt0 < mtiles; mt0 += MP) {
+    v4i acc[MP][NS];
+#pragma unroll
+    for (int m = 0; m < MP; m++)
+#pragma unroll
+      for (int k = 0; k < NS; k++) acc[m][k] = v4i{0, 0, 0, 0};
+    for (int kc = 0; kc < FR.kc; kc++) {
+      v4i wop[P];
+#pragma unroll
+      for (int j = 0; j < P; j++) wop[j] = *(const v4i *)(wx + ((size_t)kc * P + j) * 1024);
+#pragma unroll
+      for (int m = 0; m < MP; m++) {
+        const int mt = mt0 + m;
+        if (mt >= mtiles) break;
+        // stage the entries of (coefficient xi, ciphertext ci, slots 16 kc + 4 sq .. + 3): their
+        // balanced digits, packed per digit plane by fold_entries_kernel, gathered at the rotation's source
+        {
+          const int xi = t & 7, ci = (t >> 3) & 15, sq = t >> 7, x = xb * MF_XB + xi, c = mt * 16 + ci;
+          const bool ok = c < batch;
+          const uint32_t *ec = E + (size_t)(ok ? c : 0) * e_bs + (size_t)FR.off[r] * N;
+          uint32_t q4[P][4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const int sl = 16 * kc + 4 * sq + u;
+#pragma unroll
+            for (int d = 0; d < P; d++) q4[d][u] = 0;
+            if (ok && sl < FR.nslot) {
+              const bool zero = FR.has0 && sl == 0;
+              const unsigned src = zero ? (unsigned)x : galois_src(x, FR.gal[sl - FR.has0], G.logn);
+              const uint32_t *ep = ec + (zero ? e_half : 0) + (size_t)src * P;
+#pragma unroll
+              for (int d = 0; d < P; d++) q4[d][u] = ep[d];
+            }
+          }
+#pragma unroll
+          for (int d = 0; d < P; d++)
+            *(v4i *)(A + xi * LD::XS + d * LD::PS + ci * FD_RS + 4 * sq) =
+                v4i{(int)q4[d][0], (int)q4[d][1], (int)q4[d][2], (int)q4[d][3]};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < P; i++) {
+          const v4i aop = *(const v4i *)(A + w * LD::XS + i * LD::PS + n * FD_RS + 4 * h);
+#pragma unroll
+          for (int j = 0; j < P; j++)
+            acc[m][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, wop[j], acc[m][i + j], 0, 0, 0);
+        }
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < MP; m++) {
+      const int mt = mt0 + m;
+      if (mt >= mtiles) break;
+      // lane holds rows (ciphertexts) 4 h + v of column n = (giant n % 8, polynomial n / 8)
+      u64 res[4];
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        u128 S = 0;   // the exact signed sum in two's complement mod 2^128
+#pragma unroll
+        for (int cidx = 0; cidx < NS; cidx++) S += (u128)(__int128)(long long)acc[m][cidx][v] << (8 * cidx);
+        const long long hi = (long long)(u64)(S >> 64);
+        const u64 lo = (u64)S;
+        // |S| < 2^87 (P = 5) or 2^127 (P = 8): |hi| < 2^23, or below 8 q (q > 2^59)
+        u64 hm;
+        if (P == 5)
+          hm = hi < 0 ? (u64)(hi + (long long)pi.q) : (u64)hi;
+        else
+          hm = reduce64((u64)(hi + 8 * (long long)pi.q), pi.q, pi.mu);
+        res[v] = redc(lo, hm, pi.q, pi.qn);
+      }
+      u64 *O = (u64 *)A;   // the staging area is free: every wave passed the last barrier
+#pragma unroll
+      for (int v = 0; v < 4; v++) O[(w * 16 + 4 * h + v) * 16 + n] = res[v];
+      __syncthreads();
+      {
+        const int xi = t & 7, col = (t >> 3) & 15, rq = t >> 7, x = xb * MF_XB + xi;
+        const int gg = col & 7, pol = col >> 3;
+        if (gg < ng) {
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const int row = 4 * rq + k, c = mt * 16 + row;
+            if (c >= batch) continue;
+            u64 v = O[(xi * 16 + row) * 16 + col];
+            u64 *o = X + (size_t)c * x_bs + ((size_t)(gg * 2 + pol) * G.pqn + r) * N + x;
+            if (accum) v = add_mod(v, *o, pi.q);
+            *o = v;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(MF_TPB, 2) void baby_fold_kernel(FoldRun FR, LevelGeom G, int L, int batch,
+                                                               LimbSel ls, const uint32_t *E, size_t e_bs,
+                                                               size_t e_half, const uint8_t *wm, int ng, u64 *X,
+                                                               size_t x_bs, int accum, const PrimeInfo *pinfo) {
+  __shared__ __align__(16) uint32_t A[FoldLds<P>::WORDS];
+  static_assert(FoldLds<P>::WORDS * 4 >= MF_XB * 16 * 16 * 8, "result staging fits");
+  const int N = 1 << G.logn;
+  const TileMap tm = tile_map(blockIdx.x, N / MF_XB, 1, ls.n, G.limb_xcd);
+  const int r = ls.r[tm.r];
+  const PrimeInfo pi = pinfo[pq_prime_dev(r, G.level, L)];
+  // one row tile per pass: sharing the folded operand loads over several tiles
+  // (MP > 1) holds MP x (2P - 1) accumulator tiles, and the occupancy lost to
+  // them cost more than the repeated loads (measured at 8 and 64 ciphertexts)
+  baby_fold_body<P, 1>(A, FR, G, batch, tm.xb, r, pi, E, e_bs, e_half, wm, ng, X, x_bs, accum);
+}
+
+// The entries of every ciphertext once, before the folded product gathers
+// them per rotation: at limb r and coefficient x, P words whose bytes are
+// digit d of (d_0, .., d_{beta'-1}, c0, 0..) (E, the rotated steps; c0 on the
+// Q limbs only) and of (c0, c1, 0, 0) (E + e_half, step b = 0; Q limbs only),
+// limb r's words starting at off[r] N.
+template <int BETA>
+__global__ __launch_bounds__(256) void fold_entries_kernel(const u64 *digits, size_t dig_bs, const u64 *ct,
+                                                           size_t ct_bs, uint32_t *E, size_t e_bs, size_t e_half,
+                                                           FoldRun FR, LevelGeom G, int L, const PrimeInfo *pinfo) {
+  const int N = 1 << G.logn;
+  const size_t tid = (size_t)blockIdx.x * 256 + threadIdx.x;   // r N + x
+  const int c = blockIdx.y, x = (int)(tid % N), r = (int)(tid / N);
+  if (r >= G.pqn) return;
+  const PrimeInfo pi = pinfo[pq_prime_dev(r, G.level, L)];
+  const bool isq = r <= G.level, wide = pi.q >= SPLIT_MAC_LIMIT;
+  const u64 *dg = digits + (size_t)c * dig_bs;
+  const u64 *cc = ct + (size_t)c * ct_bs;
+  u64 e[4] = {0, 0, 0, 0}, z[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < BETA; j++) e[j] = dg[((size_t)j * G.pqn + r) * N + x];
+  if (isq) {
+    e[BETA] = z[0] = cc[(size_t)r * N + x];
+    z[1] = cc[((size_t)(G.level + 1) + r) * N + x];
+  }
+  uint32_t *o = E + (size_t)c * e_bs + (size_t)FR.off[r] * N;
+  if (wide) {
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      e[j] = Balanced<8>::of(e[j], pi.q);
+      z[j] = Balanced<8>::of(z[j], pi.q);
+    }
+#pragma unroll
+    for (int d = 0; d < 8; d++) {
+      o[(size_t)x * 8 + d] = byte_quad(e[0], e[1], e[2], e[3], d);
+      o[e_half + (size_t)x * 8 + d] = byte_quad(z[0], z[1], z[2], z[3], d);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      e[j] = Balanced<5>::of(e[j], pi.q);
+      z[j] = Balanced<5>::of(z[j], pi.q);
+    }
+#pragma unroll
+    for (int d = 0; d < 5; d++) {
+      o[(size_t)x * 5 + d] = byte_quad(e[0], e[1], e[2], e[3], d);
+      o[e_half + (size_t)x * 5 + d] = byte_quad(z[0], z[1], z[2], z[3], d);
+    }
+  }
+}
+
+// Folded operands of one giant tile: thread (r, x, chunk, digit, lane)
+// writes the 16 bytes of lane l = 16 h + n: digit `d` of W for column n
+// (giant n % 8, polynomial n / 8) at depths 64 kc + 16 h .. + 15, depth k =
+// 4 slot + entry.  W = REDC(pt_mont k_mont) (Montgomery form of pt k) for the
+// digit entries, pt_mont P for the c0 entry (Q limbs), and for slot 0 with
+// b = 0, pt_mont P on c0 (polynomial 0) and c1 (polynomial 1).
+struct FoldPack {
+  int nslot, has0, kc, beta, ng;
+  const u64 *key[HELRM_MAX_BABY];
+  short slot[HELRM_MAX_BABY + 1][8];   // stored diagonal of (slot, giant), -1: none
+  unsigned off[HELRM_MAX_PRIMES];
+  unsigned char planes[HELRM_MAX_PRIMES];
+};
+
+__global__ __launch_bounds__(256) void wfold_pack_kernel(const FoldPack FP, const u64 *pt, uint8_t *wm, int pqn,
+                                                         int level, int L, int logn, int keyl,
+                                                         const PrimeInfo *pinfo) {
+  const int N = 1 << logn;
+  // x: ((r N + x) 8 + d) 64 + l; y: the depth chunk (a grid holds fewer than 2^32 work-items per dimension)
+  const size_t tid = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const int l = tid & 63, d = (tid >> 6) & 7;
+  const int kci = blockIdx.y;
+  const size_t rx = tid >> 9;
+  const int x = (int)(rx % N), r = (int)(rx / N);
+  if (r >= pqn) return;
+  const int P = FP.planes[r];
+  if (d >= P) return;
+  const int p = pq_prime_dev(r, level, L);
+  const PrimeInfo pi = pinfo[p];
+  const bool isq = r <= level;
+  const int n = l & 15, h = l >> 4, g = n & 7, pol = n >> 3;
+  uint32_t wv[4] = {0, 0, 0, 0};
+  for (int tt = 0; tt < 16; tt++) {
+    const int k = 64 * kci + 16 * h + tt, sl = k >> 2, e = k & 3;
+    if (sl >= FP.nslot || g >= FP.ng) continue;
+    const int di = FP.slot[sl][g];
+    if (di < 0) continue;
+    const u64 ptm = pt[((size_t)di * pqn + r) * N + x];
+    u64 v = 0;
+    if (FP.has0 && sl == 0) {
+      if (isq && e == pol) v = shoup(ptm, pi.pmod, pi.pmod_p, pi.q);
+    } else if (e < FP.beta) {
+      const u64 kw = FP.key[sl - FP.has0][((size_t)(2 * e + pol) * keyl + p) * N + x];
+      const u128 prod = (u128)ptm * kw;
+      v = redc((u64)prod, (u64)(prod >> 64), pi.q, pi.qn);
+    } else if (e == FP.beta) {
+      if (isq && pol == 0) v = shoup(ptm, pi.pmod, pi.pmod_p, pi.q);
+    }
+    const u64 bal = P == 5 ? Balanced<5>::of(v, pi.q) : Balanced<8>::of(v, pi.q);
+    wv[tt >> 2] |= (uint32_t)((bal >> (8 * d)) & 0xFFu) << (8 * (tt & 3));
+  }
+  uint32_t *o = (uint32_t *)(wm + (((size_t)FP.off[r] * N * FP.kc + ((size_t)x * FP.kc + kci) * P + d) * 1024) + l * 16);
+  o[0] = wv[0];
+  o[1] = wv[1];
+  o[2] = wv[2];
+  o[3] = wv[3];
+}
+
 // B operands of the matrix-core MAC, built once per plan: for giant tile T,
 // limb r, coefficient x and digit pair jp, 64 lanes x 16 bytes where lane
 // l = 16 h + n holds the balanced digit 2 jp + n / 8 of pt_{8T + n % 8, b}[x]
@@ -1127,10 +1393,12 @@ __global__ __launch_bounds__(MF_TPB, 4) void baby_mfma_kernel(BabyArgs BA, Level
 // slot_tab[T][k][g] gives its stored diagonal, -1 none).  4 KiB per (T, r, x).
 __global__ __launch_bounds__(256) void ptm_pack_kernel(const u64 *pt, const int *slot_tab, uint8_t *ptm, int pqn,
                                                        int level, int L, int N, const PrimeInfo *pinfo) {
-  const size_t tid = (size_t)blockIdx.x * 256 + threadIdx.x;   // ((T pqn + r) N + x) 256 + jp 64 + l
+  // x: (r N + x) 256 + jp 64 + l; y: the giant tile T
+  const size_t tid = (size_t)blockIdx.x * 256 + threadIdx.x;
   const int l = tid & 63, jp = (tid >> 6) & 3;
-  const size_t trx = tid >> 8;
-  const int x = (int)(trx % N), r = (int)((trx / N) % pqn), T = (int)(trx / N / pqn);
+  const int T = blockIdx.y;
+  const size_t trx = (size_t)T * pqn * N + (tid >> 8);
+  const int x = (int)(trx % N), r = (int)((trx / N) % pqn);
   const PrimeInfo pi = pinfo[pq_prime_dev(r, level, L)];
   const int P = pi.q < SPLIT_MAC_LIMIT ? 5 : 8;
   const int n = l & 15, h = l >> 4, g = n & 7, d = 2 * jp + (n >> 3);
@@ -1491,16 +1759,63 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
 
 int launch_ptm_pack(helrm_ctx *ctx, const helrm_plan *plan, const int *slot_tab, hipStream_t s) {
   const int pqn = plan->level + 1 + ctx->K;
-  const size_t threads = (size_t)plan->ptm_tiles * pqn * ctx->N * 256;
-  hipLaunchKernelGGL(ptm_pack_kernel, dim3((unsigned)(threads / 256)), dim3(256), 0, s, plan->d_pt, slot_tab,
+  const size_t threads = (size_t)pqn * ctx->N * 256;
+  hipLaunchKernelGGL(ptm_pack_kernel, dim3((unsigned)(threads / 256), plan->ptm_tiles), dim3(256), 0, s, plan->d_pt,
+                     slot_tab,
                      plan->d_ptm, pqn, plan->level, ctx->L, ctx->N, ctx->d_pinfo);
+  HIP_TRY(hipGetLastError());
+  return HELRM_OK;
+}
+
+int launch_wfold_pack(helrm_ctx *ctx, helrm_plan *plan, int T, hipStream_t s) {
+  const int pqn = plan->level + 1 + ctx->K, n1 = plan->n1;
+  FoldPack FP;
+  memset(&FP, 0, sizeof FP);
+  FP.kc = plan->wm_kc;
+  FP.beta = ctx->n_digits(plan->level);
+  FP.ng = std::min(HELRM_MAX_GTILE, plan->n2 - T * HELRM_MAX_GTILE);
+  for (int r = 0; r < pqn; r++) {
+    FP.off[r] = (unsigned)plan->wm_off[r];
+    FP.planes[r] = (unsigned char)plan->wm_planes[r];
+  }
+  // the tile's baby steps, in the baby-step launch's order (b = 0 first)
+  int ns = 0;
+  for (int b : plan->babies) {
+    bool any = false;
+    for (int g = 0; g < FP.ng; g++)
+      if (plan->slot[(size_t)(T * HELRM_MAX_GTILE + g) * n1 + b] >= 0) any = true;
+    if (!any) continue;
+    if (ns > HELRM_MAX_BABY) {
+      set_error("key folding: too many baby steps in a giant tile");
+      return HELRM_EINVAL;
+    }
+    for (int g = 0; g < 8; g++)
+      FP.slot[ns][g] = g < FP.ng ? (short)plan->slot[(size_t)(T * HELRM_MAX_GTILE + g) * n1 + b] : (short)-1;
+    if (b == 0 && ns == 0) {
+      FP.has0 = 1;
+    } else {
+      const uint32_t gal = galois_of_step(ctx, (long)plan->sign * b);
+      auto it = ctx->keys.find(gal);
+      if (it == ctx->keys.end()) {
+        set_error("key folding: no evaluation key for rotation %d", b);
+        return HELRM_EINVAL;
+      }
+      FP.key[ns - FP.has0] = it->second.d;
+    }
+    ns++;
+  }
+  FP.nslot = ns;
+  const size_t threads = (size_t)pqn * ctx->N * 8 * 64;
+  hipLaunchKernelGGL(wfold_pack_kernel, dim3((unsigned)(threads / 256), FP.kc), dim3(256), 0, s, FP, plan->d_pt,
+                     plan->d_wm + (size_t)T * plan->wm_tile_bytes, pqn, plan->level, ctx->L, ctx->logn,
+                     ctx->L + 1 + ctx->K, ctx->d_pinfo);
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
 }
 
 int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, size_t digits_bstride,
                     const u64 *ct, size_t ct_bstride, u64 *X, size_t x_bstride, int g0, int ng, int batch,
-                    hipStream_t s, bool accum, bool force) {
+                    hipStream_t s, bool accum, bool force, uint32_t *fold_ws) {
   if (ng > HELRM_MAX_GTILE) {
     set_error("baby_mac: at most %d giant outputs per launch", HELRM_MAX_GTILE);
     return HELRM_EINVAL;
@@ -1571,10 +1886,50 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   const double words = nrot * kl + pl * npt + qn * B * (nrot * (beta + 1) + 2 * has0 + xw * ng) +
                        K * B * (nrot * beta + xw * ng);
   KTimer tm(ctx, s);
-  const bool mfma = plan->d_ptm && ctx->tune_baby_mfma > 0 && batch >= ctx->tune_baby_mfma &&
+  const bool fold = fold_ws && plan->d_wm && plan->wm_keys_gen == ctx->keys_gen && ctx->tune_baby_fold > 0 &&
+                    batch >= ctx->tune_baby_fold && g0 % HELRM_MAX_GTILE == 0 &&
+                    g0 / HELRM_MAX_GTILE < plan->wm_tiles && G.beta <= 3 && BA.nrot + BA.has0 <= 64;
+  const bool mfma = !fold && plan->d_ptm && ctx->tune_baby_mfma > 0 && batch >= ctx->tune_baby_mfma &&
                     g0 % HELRM_MAX_GTILE == 0 && g0 / HELRM_MAX_GTILE < plan->ptm_tiles &&
                     BA.nrot + BA.has0 <= 64;
-  if (mfma) {
+  if (fold) {
+    // key-folded product on the matrix cores: the entries of every ciphertext
+    // once, then one launch per digit count
+    FoldRun FR;
+    FR.nslot = BA.nrot + BA.has0;
+    FR.has0 = BA.has0;
+    FR.kc = plan->wm_kc;
+    for (int i = 0; i < BA.nrot; i++) FR.gal[i] = BA.gal[i];
+    for (int r = 0; r < G.pqn; r++) FR.off[r] = (unsigned)plan->wm_off[r];
+    const uint8_t *wm = plan->d_wm + (size_t)(g0 / HELRM_MAX_GTILE) * plan->wm_tile_bytes;
+    const size_t e_half = fold_entry_words(ctx, level) / 2, e_bs = 2 * e_half;
+    {
+      const size_t threads = (size_t)G.pqn * ctx->N;
+#define FENT(BETA_)                                                                                         \
+  hipLaunchKernelGGL((fold_entries_kernel<BETA_>), dim3((unsigned)((threads + 255) / 256), batch), dim3(256), 0, \
+                     s, digits, digits_bstride, ct, ct_bstride, fold_ws, e_bs, e_half, FR, G, ctx->L, ctx->d_pinfo)
+      switch (G.beta) {
+        case 1: FENT(1); break;
+        case 2: FENT(2); break;
+        default: FENT(3); break;
+      }
+#undef FENT
+    }
+    for (int wide = 0; wide < 2; wide++) {
+      LimbSel ls;
+      ls.n = 0;
+      for (int r = 0; r < G.pqn; r++)
+        if ((ctx->primes[ctx->pq_prime(r, level)] >= SPLIT_MAC_LIMIT) == (wide == 1)) ls.r[ls.n++] = (unsigned char)r;
+      if (ls.n == 0) continue;
+      const int grid = (ctx->N / MF_XB) * ls.n;
+      if (wide)
+        hipLaunchKernelGGL((baby_fold_kernel<8>), dim3(grid), dim3(MF_TPB), 0, s, FR, G, ctx->L, batch, ls, fold_ws,
+                           e_bs, e_half, wm, ng, X, x_bstride, accum ? 1 : 0, ctx->d_pinfo);
+      else
+        hipLaunchKernelGGL((baby_fold_kernel<5>), dim3(grid), dim3(MF_TPB), 0, s, FR, G, ctx->L, batch, ls, fold_ws,
+                           e_bs, e_half, wm, ng, X, x_bstride, accum ? 1 : 0, ctx->d_pinfo);
+    }
+  } else if (mfma) {
     // batched plaintext MAC on the matrix cores: one launch per digit count
     const int ntiles = (batch + MF_CT - 1) / MF_CT;
     const uint8_t *ptm = plan->d_ptm + (size_t)(g0 / HELRM_MAX_GTILE) * G.pqn * ctx->N * 4096;
@@ -1655,7 +2010,23 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
 #undef BABY_B
 #undef BABY
   }
-  tm.lap(TK_BABY_MAC, 8.0 * ctx->N * words, (2.0 * nrot * beta + 2.0 * npt) * ctx->N * B * (qn + K));
+  // bytes the matrix-core paths move: per ciphertext its digits (and c0) and
+  // giant outputs; the key-folded product streams the folded words once and
+  // the entries (written by the entries pass, read back once: the
+  // per-rotation gathers hit the caches); the other reads every rotation's
+  // key and the plaintext digits once per tile of 8 ciphertexts
+  const double Nd = ctx->N, pqn = qn + K, per_ct = Nd * 8.0 * (qn * (beta + 1) + K * beta + xw * ng * pqn);
+  const double ops = (2.0 * nrot * beta + 2.0 * npt) * Nd * B * pqn;
+  if (fold) {
+    tm.lap(TK_BABY_FOLD, (double)plan->wm_tile_bytes + B * (per_ct + 8.0 * fold_entry_words(ctx, level)), ops);
+  } else if (mfma) {
+    double njp = 0;
+    for (int r = 0; r < G.pqn; r++) njp += ctx->primes[ctx->pq_prime(r, level)] >= SPLIT_MAC_LIMIT ? 4 : 3;
+    const double tiles = (batch + MF_CT - 1) / MF_CT;
+    tm.lap(TK_BABY_MFMA, tiles * Nd * (16.0 * nrot * beta * pqn + 1024.0 * njp) + B * per_ct, ops);
+  } else {
+    tm.lap(TK_BABY_MAC, 8.0 * ctx->N * words, ops);
+  }
   HIP_TRY(hipGetLastError());
   return HELRM_OK;
 }

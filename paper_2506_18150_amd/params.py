@@ -58,6 +58,10 @@ class ParamSet:
     p: List[int]
     delta: float = 2.0 ** 40
 
+    def n_digits(self, level: int) -> int:
+        """Key-switching digits at this level: ceil((level + 1) / alpha)."""
+        return -(-(level + 1) // self.alpha)
+
     @property
     def N(self) -> int:
         return 1 << self.log_n

@@ -20,9 +20,11 @@ from .params import ParamSet
 
 class LookupSession:
     def __init__(self, prm: ParamSet, tables: Sequence[planner.Table], level: int, n1: int, radix: int,
-                 key_draws_fn, ctx: Optional[Context] = None, sign: int = -1):
+                 key_draws_fn, ctx: Optional[Context] = None, sign: int = -1, fold: bool = False):
         """key_draws_fn(galois_list) -> key draws (secret, public-key and
-        switching-key randomness) for those Galois elements."""
+        switching-key randomness) for those Galois elements.  fold: fold the
+        keys into the plans of several giant steps (batched lookups on the
+        matrix cores; helrm_plan_fold_keys)."""
         self.prm = prm
         self.tables = list(tables)
         self.level = level
@@ -40,6 +42,11 @@ class LookupSession:
         self.galois = [planner.galois(s, prm.N) for s in steps]
         self.client = Client(self.ctx, prm)
         self.client.keygen(key_draws_fn(self.galois), self.galois)
+        self.folded_bytes = 0
+        if fold and prm.n_digits(level) <= 3:
+            for p, sp in zip(self.plans, self.specs):
+                if sp.n2 >= 2:
+                    self.folded_bytes += p.helrm_plan_fold_keys()
 
     @property
     def out_slots(self) -> int:

@@ -27,8 +27,8 @@ from tests.gpu_helpers import (assert_bit_exact, context_for, empty, gpu_plan, l
 
 pytestmark = pytest.mark.gpu
 
-KNOBS = ("ks_tile", "baby_tile", "baby_share", "ntt_col_w", "ntt_blk_w", "baby_mfma")
-DEFAULT_KNOBS = dict(ks_tile=4, baby_tile=4, baby_share=8, ntt_col_w=16, ntt_blk_w=4, baby_mfma=8)
+KNOBS = ("ks_tile", "baby_tile", "baby_share", "ntt_col_w", "ntt_blk_w", "baby_mfma", "baby_fold")
+DEFAULT_KNOBS = dict(ks_tile=4, baby_tile=4, baby_share=8, ntt_col_w=16, ntt_blk_w=4, baby_mfma=8, baby_fold=32)
 
 
 def tuned(rows, cols, batch, level=23):
@@ -109,11 +109,10 @@ def _w3_specs():
 @pytest.mark.timeout(1200)
 def test_batching_workload_full_size_bit_exact():
     """26 tables in one selector ciphertext per query (m = 512, n1 = 64, n2 =
-    8, radix 8, sign -1, level 23: three digits), batch 64 through the
-    captured graph with the batch-64 knobs (workgroup-shared baby-step kernel
-    over 4 ciphertexts, key-switch tiles of 2) and the first 8 eagerly with
-    the batch-8 knobs: queries 0 and 63 bit-exact against the oracle, query 0
-    the same in both runs."""
+    8, radix 8, sign -1, level 23: three digits), the plan's keys folded as
+    the benchmark does, batch 64 through the captured graph with the batch-64
+    knobs and the first 8 eagerly with the batch-8 knobs: queries 0 and 63
+    bit-exact against the oracle, query 0 the same in both runs."""
     import torch
     prm = O.config2_params()
     specs = _w3_specs()
@@ -124,6 +123,7 @@ def test_batching_workload_full_size_bit_exact():
     ctx = context_for(prm)
     load_keys(ctx, w.keys)
     plan = gpu_plan(ctx, w.plan)
+    plan.helrm_plan_fold_keys()   # as the benchmark's session does for batches
     sel = to_dev(np.stack(w.cts))
     sc64 = tuned(416, 13962, 64)
     assert (sc64.n1, sc64.radix, sc64.sign) == (64, 8, -1)
