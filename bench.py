@@ -265,6 +265,27 @@ def sect8d_bytes(prm, level: int, spec, batch: int) -> dict:
     return {"baby_mac": float(baby), "ks_acc": float(ks)}
 
 
+def kernel_table(ctx, run, steps: int):
+    """Per kernel class, over `steps` calls of run() with the library's event
+    timing on: ms per step, launches, average launch, and the rates of the
+    bytes and modular products the library counts for those launches."""
+    import torch
+    ctx.helrm_timing_enable(True)
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    kt = {k: ctx.helrm_timing_read(k) for k in KERNELS}
+    ctx.helrm_timing_enable(False)
+    table = {}
+    for k, v in kt.items():
+        if v["launches"] == 0:
+            continue
+        table[k] = {"ms_per_step": v["ms"] / steps, "launches_per_step": v["launches"] / steps,
+                    "avg_us": 1e3 * v["ms"] / v["launches"], "GB/s": v["bytes"] / (v["ms"] * 1e6),
+                    "Gmodmul/s": v["ops"] / (v["ms"] * 1e6), "bytes_per_launch": v["bytes"] / v["launches"]}
+    return table, kt
+
+
 def alu_peaks(ctx, prm) -> dict:
     """ALU ceilings measured by the library's calibration kernels on this GPU:
     butterflies/s of the NTT arithmetic on a 60-bit prime (integer Shoup
@@ -370,6 +391,19 @@ def w3_batched(prm, batch: int, steps: int) -> dict:
     err1 = float(np.max(np.abs(rows1[0] - sess.cleartext(idx[0]))))
     g.close()
     spec = sess.spec
+    # the same batch once eagerly with every launch timed: the dominant class
+    # against HBM, in the scope table's bytes and in the bytes it streams
+    sess.ctx.helrm_reserve(sess.plan, batch, stream)
+    table, _ = kernel_table(sess.ctx, lambda: sess.lookup(sel, out, stream), 1)
+    dom = max(table, key=lambda k: table[k]["ms_per_step"])
+    alg = sect8d_bytes(prm, 23, spec, batch)
+    ak = "baby_mac" if dom in BABY_CLASSES else dom
+    roof = {"kernel": KERNEL_SYMBOL[dom], "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "ms_per_call": table[dom]["ms_per_step"], "moved_GBps": table[dom]["GB/s"],
+            "moved_bytes_per_call": table[dom]["bytes_per_launch"] * table[dom]["launches_per_step"]}
+    if ak in alg:
+        roof.update(achieved=alg[ak] / (table[dom]["ms_per_step"] * 1e6), algorithmic_bytes_per_call=alg[ak])
+        roof["frac"] = roof["achieved"] / HBM_PEAK_GBS
     n_hoisted = sum(1 for b in sorted({k % spec.n1 for k in spec.diag}) if b)
     n_full = sum(1 for g_ in sorted({k // spec.n1 for k in spec.diag}) if g_) + sum(r - 1 for _, r in spec.stages)
     lk = len(tables)
@@ -385,7 +419,9 @@ def w3_batched(prm, batch: int, steps: int) -> dict:
                                                           "ntt_blk_w", "baby_mfma", "baby_fold")},
                     "key_switches_per_s": {"hoisted": n_hoisted * batch / (ms / 1e3),
                                            "full": n_full * batch / (ms / 1e3)},
-                    "max_abs_err": err},
+                    "max_abs_err": err,
+                    "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in table.items()},
+                    "roofline": roof},
         "plain": {"lookups_per_s": lk / (plain_ms / 1e3), "ms_per_call": plain_ms, "steps": n_plain,
                   "max_abs_err": err1},
         "setup_s": round(setup_s, 2),
@@ -620,14 +656,14 @@ def main():
         if args.workload == "w3":
             cands = [autotune.Schedule(n1, r, -1) for n1 in (32, 64) for r in (4, 8)]
         tune_rec = autotune.tune(prm, tables, args.level, B, key_fn, lambda: synth.enc_draws(eg, prm.N),
-                                 schedules=cands)
+                                 schedules=cands, log=lambda r: print(json.dumps(r), file=sys.stderr, flush=True))
         if args.autotune_out:
             autotune.record(tune_rec, args.autotune_out)
     sched = autotune.tuned_schedule(prm.N, prm.L, args.level, M.shape[0], M.shape[1], B)
     if tune_rec is not None:
         b = tune_rec["best"]
         sched = autotune.Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b["baby_share"],
-                                  b["ntt_col_w"], b["ntt_blk_w"], b.get("baby_mfma", 8), b.get("baby_fold", 32))
+                                  b["ntt_col_w"], b["ntt_blk_w"], b.get("baby_mfma", 8), b.get("baby_fold", 8))
     if sched is None:
         sched = autotune.Schedule(dflt["n1"], dflt["radix"], dflt["sign"])
     n1 = args.n1 or sched.n1
@@ -647,9 +683,9 @@ def main():
                     ("ntt_small_limbs", args.ntt_small_limbs)):
         if v is not None:
             sess.ctx.helrm_set_tuning(knob, v)
-    for kv in args.knob:
-        name, v = kv.split("=")
-        sess.ctx.helrm_set_tuning(name, int(v))
+    extra_knobs = tuple((kv.split("=")[0], int(kv.split("=")[1])) for kv in args.knob)
+    for name, v in extra_knobs:
+        sess.ctx.helrm_set_tuning(name, v)
     setup_s = time.time() - t0
     qg = synth.rng(1)
     idx = [synth.indices(qg, [t.rows for t in tables]) for _ in range(B)]
@@ -735,10 +771,12 @@ def main():
         bout = sess.new_output(Bb)
         sess.ctx.helrm_reserve(sess.plan, Bb, stream)
         bs = autotune.tuned_schedule(prm.N, prm.L, args.level, M.shape[0], M.shape[1], Bb)
+        bb_knobs = []
         if bs is not None and (bs.n1, bs.radix, bs.sign) == (n1, radix, sign):
-            for knob, v in (("ks_tile", bs.ks_tile), ("baby_tile", bs.baby_tile), ("baby_share", bs.baby_share),
-                            ("baby_mfma", bs.baby_mfma), ("baby_fold", bs.baby_fold)):
-                sess.ctx.helrm_set_tuning(knob, v)
+            bb_knobs = [("ks_tile", bs.ks_tile), ("baby_tile", bs.baby_tile), ("baby_share", bs.baby_share),
+                        ("baby_mfma", bs.baby_mfma), ("baby_fold", bs.baby_fold)]
+        for knob, v in bb_knobs + list(extra_knobs):
+            sess.ctx.helrm_set_tuning(knob, v)
         for _ in range(2):
             sess.lookup(bsel, bout, stream)
         torch.cuda.synchronize()
@@ -752,28 +790,25 @@ def main():
         bms = e0.elapsed_time(e1) / nb
         brows = sess.decrypt_rows(bout)
         berr = max(float(np.max(np.abs(brows[b] - sess.cleartext(bidx[b])))) for b in range(Bb))
-        for knob, v in (("ks_tile", args.ks_tile or sched.ks_tile), ("baby_tile", args.baby_tile or sched.baby_tile),
-                        ("baby_share", share), ("baby_mfma", sched.baby_mfma), ("baby_fold", sched.baby_fold)):
+        restore_knobs = (("ks_tile", args.ks_tile or sched.ks_tile), ("baby_tile", args.baby_tile or sched.baby_tile),
+                         ("baby_share", share), ("baby_mfma", sched.baby_mfma), ("baby_fold", sched.baby_fold))
+        for knob, v in restore_knobs + extra_knobs:
             sess.ctx.helrm_set_tuning(knob, v)
         res["batched"] = {"batch": Bb, "steps": nb, "ms_per_step": bms,
                           "lookups_per_s": Bb * len(tables) / (bms / 1e3), "max_abs_err": berr,
                           "vs_plain": (Bb * len(tables) / (bms / 1e3)) / value}
+        if not args.no_kernel_timing:
+            # the same batch once more, eagerly, with every launch timed
+            for knob, v in bb_knobs + list(extra_knobs):
+                sess.ctx.helrm_set_tuning(knob, v)
+            bt, _ = kernel_table(sess.ctx, lambda: sess.lookup(bsel, bout, stream), 1)
+            res["batched"]["kernels"] = {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in bt.items()}
+            for knob, v in restore_knobs + extra_knobs:
+                sess.ctx.helrm_set_tuning(knob, v)
         del bsel, bout
 
     if not args.no_kernel_timing:
-        sess.ctx.helrm_timing_enable(True)
-        for _ in range(args.steps):
-            sess.lookup(sel, out, stream)
-        torch.cuda.synchronize()
-        kt = {k: sess.ctx.helrm_timing_read(k) for k in KERNELS}
-        sess.ctx.helrm_timing_enable(False)
-        table = {}
-        for k, v in kt.items():
-            if v["launches"] == 0:
-                continue
-            table[k] = {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
-                        "avg_us": 1e3 * v["ms"] / v["launches"], "GB/s": v["bytes"] / (v["ms"] * 1e6),
-                        "Gmodmul/s": v["ops"] / (v["ms"] * 1e6), "bytes_per_launch": v["bytes"] / v["launches"]}
+        table, kt = kernel_table(sess.ctx, lambda: sess.lookup(sel, out, stream), args.steps)
         dom = max(table, key=lambda k: table[k]["ms_per_step"])
         symbol = dict(KERNEL_SYMBOL)
         if B >= 2 and spec.n2 >= 2 and share >= 2:

@@ -232,7 +232,7 @@ int helrm_plan_destroy(helrm_plan *plan);
  * sigma_b(d_j) k_{b,j} = sum_{b,j} sigma_b(d_j) (pt_b k_{b,j}), identical
  * residues): the library builds and keeps W = pt_{g,b} k_{b,j} (and pt P for
  * the c0 terms) as matrix-core operands, and lookups of at least `baby_fold`
- * ciphertexts (helrm_set_tuning, default 32) then form no rotated ciphertext
+ * ciphertexts (helrm_set_tuning, default 8) then form no rotated ciphertext
  * at all.  Needs the keys of every baby step loaded; a later
  * helrm_load_eval_keys makes the folded words stale (lookups then use the
  * other kernels until the plan is folded again).  Memory: per giant tile of
@@ -445,7 +445,15 @@ int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *o
  * ModDown runs inside the ModUp conversions (one conversion launch instead
  * of two).  "conv_wgs" (>= 0, default 1536): a base conversion launch with fewer
  * workgroups than this splits its outputs into chunks (at least four outputs
- * each) until it has that many; 0 never splits.
+ * each) until it has that many; 0 never splits.  "baby_mfma" (>= 0, default
+ * 8): batches of at least this many ciphertexts run the plaintext MAC of the
+ * baby steps on the matrix cores (0: never).  "baby_fold" (>= 0, default 8):
+ * batches of at least this many use a plan's folded keys
+ * (helrm_plan_fold_keys; 0: never).  "ptm" (1, default, or 0): plans keep the
+ * plaintexts' matrix-core operands.  "block_chain" (1, default, or 0): the
+ * key-folded product takes its coefficient blocks in the order in which the
+ * baby-step rotations shift them (rotated words then come from L2), or in
+ * plain order.
  * Errors: HELRM_EINVAL for an unknown knob or value. */
 int helrm_set_tuning(helrm_ctx *ctx, const char *knob, int value);
 

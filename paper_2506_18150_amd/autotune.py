@@ -39,7 +39,7 @@ class Schedule:
     ntt_col_w: int = 16
     ntt_blk_w: int = 4
     baby_mfma: int = 8
-    baby_fold: int = 32
+    baby_fold: int = 8
 
 
 def library_revision() -> str:
@@ -82,7 +82,7 @@ def tuned_schedule(N: int, L: int, level: int, rows: int, cols: int, batch: int,
         return None
     b = rec["best"]
     return Schedule(b["n1"], b["radix"], b["sign"], b["ks_tile"], b["baby_tile"], b.get("baby_share", 8),
-                    b.get("ntt_col_w", 16), b.get("ntt_blk_w", 4), b.get("baby_mfma", 8), b.get("baby_fold", 32))
+                    b.get("ntt_col_w", 16), b.get("ntt_blk_w", 4), b.get("baby_mfma", 8), b.get("baby_fold", 8))
 
 
 def tune(prm, tables, level: int, batch: int, key_draws_fn, enc_draws_fn,

@@ -1146,6 +1146,34 @@ extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
     if (qinv.empty()) qinv.push_back(TW{0, 0});
     off_qinv[lv] = cb.add_tw(qinv);
   }
+  // blocks of 8 coefficients in chain order: position s N/16 + i holds the
+  // block whose exponents e = 2 brv(x) + 1 are (-1)^s 5^i modulo 2N/8
+  size_t off_chain = 0;
+  {
+    const int lb = c->logn - 3;   // bits of a block index
+    const u64 mask = (2ull << c->logn) / 8 - 1, half = (u64)c->N / 16;
+    std::vector<u64> chain(c->N / 8);
+    std::vector<char> seen(c->N / 8, 0);
+    u64 pw = 1;
+    bool ok = true;
+    for (u64 i = 0; i < half; i++) {
+      for (int sg = 0; sg < 2; sg++) {
+        const u64 e = sg ? (0 - pw) & mask : pw;
+        u64 v = (e - 1) / 2, m = 0;
+        for (int k = 0; k < lb; k++) m |= ((v >> k) & 1) << (lb - 1 - k);
+        chain[sg * half + i] = m;
+        ok = ok && !seen[m];
+        seen[m] = 1;
+      }
+      pw = (pw * 5) & mask;
+    }
+    if (!ok) {
+      set_error("internal: coefficient block chain is not a permutation");
+      delete c;
+      return HELRM_EINVAL;
+    }
+    off_chain = cb.add_u64(chain);
+  }
   auto fail = [&](int code) {
     helrm_destroy(c);
     return code;
@@ -1179,6 +1207,7 @@ extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
     c->moddown_tabs[f.level].hat_inv = (const TW *)(c->d_const + f.inv);
     c->moddown_tabs[f.level].hat_mont = c->d_const + f.mont;
   }
+  c->d_block_chain = c->d_const + off_chain;
   c->moddown_pinv.resize(c->L + 1);
   c->rescale_qinv.resize(c->L + 1);
   for (int lv = 0; lv <= c->L; lv++) {
@@ -2076,6 +2105,9 @@ extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
   } else if (strcmp(knob, "fuse_conv") == 0) {
     CHECK_ARG(value == 0 || value == 1, "fuse_conv must be 0 or 1");
     c->tune_fuse_conv = value;
+  } else if (strcmp(knob, "block_chain") == 0) {
+    CHECK_ARG(value == 0 || value == 1, "block_chain must be 0 or 1");
+    c->tune_block_chain = value;
   } else if (strcmp(knob, "ntt_small_limbs") == 0) {
     CHECK_ARG(value >= 0, "ntt_small_limbs must be >= 0");
     c->ntt_small_limbs = value;

@@ -396,6 +396,8 @@ struct helrm_ctx {
   int tune_ntt_col_w = 16;   // NTT column-pass columns per workgroup (8, 16; 0 = by launch size)
   int tune_ntt_blk_w = 4;    // NTT block-pass blocks per workgroup (4, 8; 0 = by launch size)
   int ntt_small_limbs = 48;  // launches of fewer limbs take the narrow shapes when a width is 0
+  int tune_block_chain = 1;   // key-folded product: workgroups in chain order of the coefficient blocks
+  const u64 *d_block_chain = nullptr;   // [N/8]: coefficient block at chain position i (inside d_const)
   int tune_limb_xcd = 0;      // key-switching kernels: whole limbs per XCD (1) or blocks dealt over the XCDs (0)
   int tune_fuse_ks = 1;       // ModDown fused with the ModUp or rescale that follows it (0 = off)
   int tune_fuse_conv = 1;   // fused boundary: c1's ModDown inside the ModUp conversions
@@ -403,7 +405,7 @@ struct helrm_ctx {
   int tune_baby_mfma = 8;    // batches of at least this many ciphertexts take the matrix-core plaintext MAC
                              // when the plan has its operands (0 = never)
   int tune_ptm = 1;          // plans with several giant steps build matrix-core operands (0 = never)
-  int tune_baby_fold = 32;   // batches of at least this many ciphertexts take the key-folded matrix-core
+  int tune_baby_fold = 8;   // batches of at least this many ciphertexts take the key-folded matrix-core
                              // product when the plan has folded operands (0 = never)
   uint64_t keys_gen = 1;     // bumped by every helrm_load_eval_keys (folded operands of older keys are stale)
   int tune_gen_key_a = 2;    // regenerate keys' a_j halves from their seeds where a kernel serves one

@@ -398,6 +398,30 @@ __device__ __forceinline__ TileMap tile_map(int L, int nx, int ntiles, int nr, i
   return m;
 }
 
+// Workgroup order of the key-folded product (and, given a chain, of the
+// matrix-core MAC, where it measured 5 % slower at 8 ciphertexts and is not
+// used).  A block of 8 consecutive
+// coefficients (evaluation points with exponents e = 2 brv(x) + 1) is one
+// class of e modulo 2N/8, and every Galois map sends a block onto a block.
+// With a chain (the blocks in the order of the classes ±5^i, i = 0, 1, ..),
+// the rotation by 5^b sends the block at chain position i to the one at
+// i ± b; XCD x takes the x-th eighth of the (limb, chain position, tile)
+// triples in order, so the workgroups resident on one XCD at a time gather
+// their rotated words from a window of about twice the baby-step count of
+// blocks, which stays in that XCD's L2 for every rotation and every
+// ciphertext tile.  Without a chain: the key-switching kernels' order.
+__device__ __forceinline__ TileMap chain_map(int L, int nx, int ntiles, int nr, int limb_xcd, const u64 *chain) {
+  if (!chain) return tile_map(L, nx, ntiles, nr, limb_xcd);
+  const long per = (long)nx * nr * ntiles / 8;   // nx is a multiple of 8
+  const long q = (L & 7) * per + (L >> 3);
+  const long g = q / ntiles;
+  TileMap m;
+  m.tile = (int)(q % ntiles);
+  m.r = (int)(g / nx);
+  m.xb = (int)chain[g % nx];
+  return m;
+}
+
 constexpr int MAXBETA = 4;   // digits per key switch handled in registers
 
 // Multiply-accumulate policy of limbs with primes of 40 bits and more: the
@@ -1104,11 +1128,12 @@ __global__ __launch_bounds__(MF_TPB, 4) void baby_mfma_kernel(BabyArgs BA, Level
                                                                int ntiles, LimbSel ls, const u64 *digits,
                                                                size_t dig_bs, const u64 *ct, size_t ct_bs,
                                                                const uint8_t *ptm, int ng, u64 *X, size_t x_bs,
-                                                               int accum, const PrimeInfo *pinfo) {
+                                                               int accum, const PrimeInfo *pinfo,
+                                                               const u64 *chain) {
   __shared__ __align__(16) uint32_t A[MF_XB * P * 16 * 16];
   static_assert(MF_XB * P * 16 * 16 * 4 >= MF_XB * 16 * 8 * 8, "result staging fits in A");
   const int N = 1 << G.logn;
-  const TileMap tm = tile_map(blockIdx.x, N / MF_XB, ntiles, ls.n, G.limb_xcd);
+  const TileMap tm = chain_map(blockIdx.x, N / MF_XB, ntiles, ls.n, G.limb_xcd, chain);
   const int r = ls.r[tm.r];
   const int p = pq_prime_dev(r, G.level, L);
   const PrimeInfo pi = pinfo[p];
@@ -1149,8 +1174,11 @@ constexpr int FD_RS = 20;             // LDS dwords per ciphertext row (16 used)
 template <int P>
 struct FoldLds {
   static constexpr int PS = 16 * FD_RS;        // dwords per digit plane (16 ciphertexts)
-  static constexpr int XS = P * PS + 8;        // dwords per coefficient (offset 8 mod 64 banks)
+  // dwords per coefficient: 4 mod 32, so the 8 coefficients that one
+  // 16-byte store instruction's lanes write land in 8 distinct bank groups
+  static constexpr int XS = P * PS + 4;
   static constexpr int WORDS = MF_XB * XS;
+  static constexpr int OS = 16 * 16 + 2;       // result staging: u64 per coefficient (2 mod 16)
 };
 
 template <int P, int MP>
@@ -1239,7 +1267,7 @@ __device__ __forceinline__ void baby_fold_body(uint32_t *A, const FoldRun &FR, c
       }
       u64 *O = (u64 *)A;   // the staging area is free: every wave passed the last barrier
 #pragma unroll
-      for (int v = 0; v < 4; v++) O[(w * 16 + 4 * h + v) * 16 + n] = res[v];
+      for (int v = 0; v < 4; v++) O[w * LD::OS + (4 * h + v) * 16 + n] = res[v];
       __syncthreads();
       {
         const int xi = t & 7, col = (t >> 3) & 15, rq = t >> 7, x = xb * MF_XB + xi;
@@ -1249,7 +1277,7 @@ __device__ __forceinline__ void baby_fold_body(uint32_t *A, const FoldRun &FR, c
           for (int k = 0; k < 4; k++) {
             const int row = 4 * rq + k, c = mt * 16 + row;
             if (c >= batch) continue;
-            u64 v = O[(xi * 16 + row) * 16 + col];
+            u64 v = O[xi * LD::OS + row * 16 + col];
             u64 *o = X + (size_t)c * x_bs + ((size_t)(gg * 2 + pol) * G.pqn + r) * N + x;
             if (accum) v = add_mod(v, *o, pi.q);
             *o = v;
@@ -1265,11 +1293,12 @@ template <int P>
 __global__ __launch_bounds__(MF_TPB, 2) void baby_fold_kernel(FoldRun FR, LevelGeom G, int L, int batch,
                                                                LimbSel ls, const uint32_t *E, size_t e_bs,
                                                                size_t e_half, const uint8_t *wm, int ng, u64 *X,
-                                                               size_t x_bs, int accum, const PrimeInfo *pinfo) {
+                                                               size_t x_bs, int accum, const PrimeInfo *pinfo,
+                                                               const u64 *chain) {
   __shared__ __align__(16) uint32_t A[FoldLds<P>::WORDS];
-  static_assert(FoldLds<P>::WORDS * 4 >= MF_XB * 16 * 16 * 8, "result staging fits");
+  static_assert(FoldLds<P>::WORDS * 4 >= MF_XB * FoldLds<P>::OS * 8, "result staging fits");
   const int N = 1 << G.logn;
-  const TileMap tm = tile_map(blockIdx.x, N / MF_XB, 1, ls.n, G.limb_xcd);
+  const TileMap tm = chain_map(blockIdx.x, N / MF_XB, 1, ls.n, G.limb_xcd, chain);
   const int r = ls.r[tm.r];
   const PrimeInfo pi = pinfo[pq_prime_dev(r, G.level, L)];
   // one row tile per pass: sharing the folded operand loads over several tiles
@@ -1922,12 +1951,13 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
         if ((ctx->primes[ctx->pq_prime(r, level)] >= SPLIT_MAC_LIMIT) == (wide == 1)) ls.r[ls.n++] = (unsigned char)r;
       if (ls.n == 0) continue;
       const int grid = (ctx->N / MF_XB) * ls.n;
+      const u64 *chain = ctx->tune_block_chain ? ctx->d_block_chain : nullptr;
       if (wide)
         hipLaunchKernelGGL((baby_fold_kernel<8>), dim3(grid), dim3(MF_TPB), 0, s, FR, G, ctx->L, batch, ls, fold_ws,
-                           e_bs, e_half, wm, ng, X, x_bstride, accum ? 1 : 0, ctx->d_pinfo);
+                           e_bs, e_half, wm, ng, X, x_bstride, accum ? 1 : 0, ctx->d_pinfo, chain);
       else
         hipLaunchKernelGGL((baby_fold_kernel<5>), dim3(grid), dim3(MF_TPB), 0, s, FR, G, ctx->L, batch, ls, fold_ws,
-                           e_bs, e_half, wm, ng, X, x_bstride, accum ? 1 : 0, ctx->d_pinfo);
+                           e_bs, e_half, wm, ng, X, x_bstride, accum ? 1 : 0, ctx->d_pinfo, chain);
     }
   } else if (mfma) {
     // batched plaintext MAC on the matrix cores: one launch per digit count
@@ -1943,7 +1973,7 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
 #define BABYM(BETA_, P_)                                                                                 \
   hipLaunchKernelGGL((baby_mfma_kernel<BETA_, P_>), dim3(grid), dim3(MF_TPB), 0, s, BA, G, ctx->L, batch,  \
                      ntiles, ls, digits, digits_bstride, ct, ct_bstride, ptm, ng, X, x_bstride, accum ? 1 : 0, \
-                     ctx->d_pinfo)
+                     ctx->d_pinfo, nullptr)
 #define BABYM_P(BETA_) \
   if (wide) BABYM(BETA_, 8); else BABYM(BETA_, 5);
       switch (G.beta) {

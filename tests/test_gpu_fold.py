@@ -29,7 +29,7 @@ def _run(ctx, plan, cts, level, N, knobs):
         ctx.helrm_lookup_packed(plan, to_dev(np.stack(cts)), B, out)
         return to_host(out).reshape(B, 2, level, N)
     finally:
-        ctx.helrm_set_tuning("baby_fold", 32)
+        ctx.helrm_set_tuning("baby_fold", 8)
         ctx.helrm_set_tuning("baby_mfma", 8)
 
 
@@ -130,4 +130,33 @@ def test_fold_n16_level23_group():
     plan = gpu_plan(ctx, w.plan)
     plan.helrm_plan_fold_keys()
     _check(ctx, w, plan, [0, 16], "level 23 group")
+    ctx.close()
+
+
+def test_block_chain_order_off():
+    """The matrix-core kernels with the workgroups in plain block order (knob
+    block_chain = 0) give the same residues as in chain order: the folded
+    product and the matrix-core MAC, toy ring at level 2, batch 17."""
+    prm = O.config1_params()
+    g = synth.rng(0)
+    t = W.compressed_table(g, 256, 16, 16, -1.0, 1.0)
+    w = W.build(prm, [t], level=2, n1=4, radix=2, n_queries=17)
+    ctx = context_for(prm)
+    load_keys(ctx, w.keys)
+    plan = gpu_plan(ctx, w.plan)
+    plan.helrm_plan_fold_keys()
+    MFMA = dict(baby_fold=0, baby_mfma=8)
+    outs = {}
+    try:
+        for chain in (1, 0):
+            ctx.helrm_set_tuning("block_chain", chain)
+            for what, knobs in (("fold", FOLD), ("mfma", MFMA)):
+                say(f"block_chain {chain}: {what}")
+                outs[(chain, what)] = _run(ctx, plan, w.cts, w.level, prm.N, knobs)
+    finally:
+        ctx.helrm_set_tuning("block_chain", 1)
+    for k, v in outs.items():
+        assert_bit_exact(v, outs[(1, "fold")], f"block_chain {k}")
+    pts = O.plan_residues(prm, w.plan)
+    assert_bit_exact(outs[(0, "fold")][0], O.lookup(prm, w.keys, w.plan, w.cts[0], pts), "query 0")
     ctx.close()

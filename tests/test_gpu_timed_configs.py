@@ -28,7 +28,7 @@ from tests.gpu_helpers import (assert_bit_exact, context_for, empty, gpu_plan, l
 pytestmark = pytest.mark.gpu
 
 KNOBS = ("ks_tile", "baby_tile", "baby_share", "ntt_col_w", "ntt_blk_w", "baby_mfma", "baby_fold")
-DEFAULT_KNOBS = dict(ks_tile=4, baby_tile=4, baby_share=8, ntt_col_w=16, ntt_blk_w=4, baby_mfma=8, baby_fold=32)
+DEFAULT_KNOBS = dict(ks_tile=4, baby_tile=4, baby_share=8, ntt_col_w=16, ntt_blk_w=4, baby_mfma=8, baby_fold=8)
 
 
 def tuned(rows, cols, batch, level=23):
