@@ -435,7 +435,7 @@ def w3_batched(prm, batch: int, steps: int) -> dict:
 
 
 def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int = 16, radix: int = 8,
-                sign: int = -1, streams: int = 2, max_batch: int = 16, seed: int = 12) -> dict:
+                sign: int = -1, streams: int = 2, max_batch: int = 16, seed: int = 12, knobs=()) -> dict:
     """The request loop on the 26-table set: tables in fixed groups of
     group_size, one selector ciphertext per touched group, Poisson arrivals,
     each request touching r ~ U{1..26} distinct tables.  Selector ciphertexts
@@ -454,6 +454,8 @@ def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int =
     t0 = time.time()
     dep = GroupedDeployment(prm, tables, group_size, level, n1, radix,
                             lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals), sign=sign)
+    for name, v in knobs:
+        dep.ctx.helrm_set_tuning(name, v)
     eg = synth.rng(11)
     pool = []
     for g, grp in enumerate(dep.groups):
@@ -515,7 +517,8 @@ def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int =
 def serve_bench(args):
     """--serve: the request loop at several arrival rates (one JSON line)."""
     out = serving_run(args.level, [float(x) for x in args.rates.split(",")], args.requests, args.group_size,
-                      args.n1 or 16, args.radix or 8, args.sign or -1, args.streams, args.max_batch)
+                      args.n1 or 16, args.radix or 8, args.sign or -1, args.streams, args.max_batch,
+                      knobs=tuple((kv.split("=")[0], int(kv.split("=")[1])) for kv in args.knob))
     best = max(out["rates"], key=lambda r: r["served"]["lookups_per_s"])
     res = {
         "metric": "served encrypted lookups/s",

@@ -434,9 +434,11 @@ int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *o
  * of the NTT's column and block passes; 0 picks the narrow shape for launches
  * of fewer than "ntt_small_limbs" limbs (default 48).  Results do not depend
  * on the knobs.  "gen_key_a" lets kernels that use every key word once
- * regenerate seeded keys' a_j halves instead of reading them: 0 never, 1 on
- * primes below 2^40 (one generator output per word), 2 (default) on every
- * prime.
+ * regenerate seeded keys' a_j halves instead of reading them: 0 never, 1
+ * (default) on primes below 2^40, 2 on every prime.
+ * "ks_chain" (1, default, or 0): the key-switching kernels take their
+ * coefficient blocks in the order in which the rotations shift them, each XCD
+ * an eighth of every limb (rotated words then come from L2).  With 0,
  * "limb_xcd" (0, default, or 1): the key-switching kernels deal coefficient
  * blocks over all 8 XCDs, or give each XCD whole limbs (a limb's rotated words
  * are then re-read from one L2: less HBM traffic, less even load).  "fuse_ks" (1, default, or 0): a
@@ -447,7 +449,8 @@ int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *o
  * workgroups than this splits its outputs into chunks (at least four outputs
  * each) until it has that many; 0 never splits.  "baby_mfma" (>= 0, default
  * 8): batches of at least this many ciphertexts run the plaintext MAC of the
- * baby steps on the matrix cores (0: never).  "baby_fold" (>= 0, default 8):
+ * baby steps on the matrix cores (0: never), for plans with at least
+ * "mfma_min_slots" (0..64, default 33) baby steps (b = 0 included).  "baby_fold" (>= 0, default 8):
  * batches of at least this many use a plan's folded keys
  * (helrm_plan_fold_keys; 0: never).  "ptm" (1, default, or 0): plans keep the
  * plaintexts' matrix-core operands.  "block_chain" (1, default, or 0): the

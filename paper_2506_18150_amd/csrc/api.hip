@@ -1016,6 +1016,34 @@ int check_primes(const helrm_ctx *ctx, int n_limbs, const int32_t *prime_index) 
 
 static int check_multi_plans(const helrm_ctx *c, const helrm_plan *const *plans, int n_in);
 
+// Blocks of 2^lb consecutive coefficients in chain order.  Coefficient x is
+// the evaluation at the exponent e = 2 brv(x) + 1 (mod 2N); the block of x
+// is the class of e modulo 2N / 2^lb, so every Galois map sends a block onto
+// a block, and the rotation by 5^b sends the class (-1)^s 5^i to (-1)^s
+// 5^(i+b).  Position s n/2 + i of the chain (n = N / 2^lb blocks) holds the
+// block of class (-1)^s 5^i.  Returns false unless that is a permutation.
+static bool block_chain(int logn, int lb, std::vector<u64> &chain) {
+  const int bits = logn - lb;                     // bits of a block index
+  const u64 nblk = 1ull << bits, half = nblk / 2;
+  const u64 mask = (2ull << bits) - 1;            // exponents modulo 2N / 2^lb
+  chain.assign(nblk, 0);
+  std::vector<char> seen(nblk, 0);
+  u64 pw = 1;
+  for (u64 i = 0; i < half; i++) {
+    for (int sg = 0; sg < 2; sg++) {
+      const u64 e = sg ? (0 - pw) & mask : pw;
+      const u64 v = (e - 1) / 2;
+      u64 m = 0;
+      for (int k = 0; k < bits; k++) m |= ((v >> k) & 1) << (bits - 1 - k);
+      if (m >= nblk || seen[m]) return false;
+      seen[m] = 1;
+      chain[sg * half + i] = m;
+    }
+    pw = (pw * 5) & mask;
+  }
+  return true;
+}
+
 extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
   API_GUARD_BEGIN
   CHECK_ARG(prm && out, "NULL argument");
@@ -1146,33 +1174,19 @@ extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
     if (qinv.empty()) qinv.push_back(TW{0, 0});
     off_qinv[lv] = cb.add_tw(qinv);
   }
-  // blocks of 8 coefficients in chain order: position s N/16 + i holds the
-  // block whose exponents e = 2 brv(x) + 1 are (-1)^s 5^i modulo 2N/8
-  size_t off_chain = 0;
+  // coefficient blocks in chain order (blocks of 8, 64 and 256)
+  size_t off_chain[3];
   {
-    const int lb = c->logn - 3;   // bits of a block index
-    const u64 mask = (2ull << c->logn) / 8 - 1, half = (u64)c->N / 16;
-    std::vector<u64> chain(c->N / 8);
-    std::vector<char> seen(c->N / 8, 0);
-    u64 pw = 1;
-    bool ok = true;
-    for (u64 i = 0; i < half; i++) {
-      for (int sg = 0; sg < 2; sg++) {
-        const u64 e = sg ? (0 - pw) & mask : pw;
-        u64 v = (e - 1) / 2, m = 0;
-        for (int k = 0; k < lb; k++) m |= ((v >> k) & 1) << (lb - 1 - k);
-        chain[sg * half + i] = m;
-        ok = ok && !seen[m];
-        seen[m] = 1;
+    const int lbs[3] = {3, 6, 8};
+    for (int k = 0; k < 3; k++) {
+      std::vector<u64> chain;
+      if (!block_chain(c->logn, lbs[k], chain)) {
+        set_error("internal: coefficient block chain is not a permutation");
+        delete c;
+        return HELRM_EINVAL;
       }
-      pw = (pw * 5) & mask;
+      off_chain[k] = cb.add_u64(chain);
     }
-    if (!ok) {
-      set_error("internal: coefficient block chain is not a permutation");
-      delete c;
-      return HELRM_EINVAL;
-    }
-    off_chain = cb.add_u64(chain);
   }
   auto fail = [&](int code) {
     helrm_destroy(c);
@@ -1207,7 +1221,9 @@ extern "C" int helrm_create(const helrm_params *prm, helrm_ctx **out) {
     c->moddown_tabs[f.level].hat_inv = (const TW *)(c->d_const + f.inv);
     c->moddown_tabs[f.level].hat_mont = c->d_const + f.mont;
   }
-  c->d_block_chain = c->d_const + off_chain;
+  c->d_block_chain = c->d_const + off_chain[0];
+  c->d_chain64 = c->d_const + off_chain[1];
+  c->d_chain256 = c->d_const + off_chain[2];
   c->moddown_pinv.resize(c->L + 1);
   c->rescale_qinv.resize(c->L + 1);
   for (int lv = 0; lv <= c->L; lv++) {
@@ -2105,6 +2121,12 @@ extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
   } else if (strcmp(knob, "fuse_conv") == 0) {
     CHECK_ARG(value == 0 || value == 1, "fuse_conv must be 0 or 1");
     c->tune_fuse_conv = value;
+  } else if (strcmp(knob, "mfma_min_slots") == 0) {
+    CHECK_ARG(value >= 0 && value <= 64, "mfma_min_slots must be in 0..64");
+    c->tune_mfma_min_slots = value;
+  } else if (strcmp(knob, "ks_chain") == 0) {
+    CHECK_ARG(value == 0 || value == 1, "ks_chain must be 0 or 1");
+    c->tune_ks_chain = value;
   } else if (strcmp(knob, "block_chain") == 0) {
     CHECK_ARG(value == 0 || value == 1, "block_chain must be 0 or 1");
     c->tune_block_chain = value;

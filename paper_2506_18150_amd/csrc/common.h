@@ -396,8 +396,12 @@ struct helrm_ctx {
   int tune_ntt_col_w = 16;   // NTT column-pass columns per workgroup (8, 16; 0 = by launch size)
   int tune_ntt_blk_w = 4;    // NTT block-pass blocks per workgroup (4, 8; 0 = by launch size)
   int ntt_small_limbs = 48;  // launches of fewer limbs take the narrow shapes when a width is 0
+  int tune_mfma_min_slots = 33;   // matrix-core MAC only for plans with at least this many baby steps
   int tune_block_chain = 1;   // key-folded product: workgroups in chain order of the coefficient blocks
-  const u64 *d_block_chain = nullptr;   // [N/8]: coefficient block at chain position i (inside d_const)
+  const u64 *d_block_chain = nullptr;   // [N/8]: block of 8 coefficients at chain position i (in d_const)
+  const u64 *d_chain64 = nullptr;       // [N/64]: the same for blocks of 64 coefficients
+  const u64 *d_chain256 = nullptr;      // [N/256]: and of 256
+  int tune_ks_chain = 1;     // key-switching kernels: workgroups in chain order of their coefficient blocks
   int tune_limb_xcd = 0;      // key-switching kernels: whole limbs per XCD (1) or blocks dealt over the XCDs (0)
   int tune_fuse_ks = 1;       // ModDown fused with the ModUp or rescale that follows it (0 = off)
   int tune_fuse_conv = 1;   // fused boundary: c1's ModDown inside the ModUp conversions
@@ -408,7 +412,7 @@ struct helrm_ctx {
   int tune_baby_fold = 8;   // batches of at least this many ciphertexts take the key-folded matrix-core
                              // product when the plan has folded operands (0 = never)
   uint64_t keys_gen = 1;     // bumped by every helrm_load_eval_keys (folded operands of older keys are stale)
-  int tune_gen_key_a = 2;    // regenerate keys' a_j halves from their seeds where a kernel serves one
+  int tune_gen_key_a = 1;    // regenerate keys' a_j halves from their seeds where a kernel serves one
                              // ciphertext per thread and streams keys: 0 never, 1 on primes below
                              // 2^40, 2 on every prime (default)
   bool timing = false;

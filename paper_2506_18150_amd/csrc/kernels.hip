@@ -357,6 +357,7 @@ struct LevelGeom {
   int keyd;       // digits of a stored key (dnum), for the 40-bit planes of its b halves
   int limb_xcd;   // tile_map: whole limbs per XCD (1) or blocks dealt over the XCDs (0)
   int gen_wide;   // kernels that regenerate key halves do so on primes >= 2^40 too (1)
+  const u64 *chain = nullptr;   // workgroup order (chain_map) of the launch's coefficient blocks, or none
 };
 
 __device__ __forceinline__ int pq_prime_dev(int r, int level, int L) {
@@ -398,27 +399,28 @@ __device__ __forceinline__ TileMap tile_map(int L, int nx, int ntiles, int nr, i
   return m;
 }
 
-// Workgroup order of the key-folded product (and, given a chain, of the
-// matrix-core MAC, where it measured 5 % slower at 8 ciphertexts and is not
-// used).  A block of 8 consecutive
-// coefficients (evaluation points with exponents e = 2 brv(x) + 1) is one
-// class of e modulo 2N/8, and every Galois map sends a block onto a block.
-// With a chain (the blocks in the order of the classes ±5^i, i = 0, 1, ..),
-// the rotation by 5^b sends the block at chain position i to the one at
-// i ± b; XCD x takes the x-th eighth of the (limb, chain position, tile)
-// triples in order, so the workgroups resident on one XCD at a time gather
-// their rotated words from a window of about twice the baby-step count of
-// blocks, which stays in that XCD's L2 for every rotation and every
-// ciphertext tile.  Without a chain: the key-switching kernels' order.
+// Workgroup order along a chain of coefficient blocks.  A block of 2^k
+// consecutive coefficients (evaluation points with exponents e = 2 brv(x) +
+// 1) is one class of e modulo 2N / 2^k, and every Galois map sends a block
+// onto a block; the rotation by 5^b sends the block of class ±5^i to that of
+// ±5^(i+b).  The chain lists the blocks in the order of i (the two signs one
+// after the other), so a rotation shifts chain positions by b.  XCD x takes
+// the x-th eighth of the chain positions of every limb, limb by limb (and
+// the ciphertext tiles of a position back to back): the workgroups resident
+// on one XCD then gather their rotated words from a window of a few times
+// the rotation count of blocks, which stays in that XCD's L2, and every XCD
+// gets the same mix of cheap and costly (wide-prime) limbs.  Without a
+// chain: the key-switching kernels' order above.
 __device__ __forceinline__ TileMap chain_map(int L, int nx, int ntiles, int nr, int limb_xcd, const u64 *chain) {
   if (!chain) return tile_map(L, nx, ntiles, nr, limb_xcd);
-  const long per = (long)nx * nr * ntiles / 8;   // nx is a multiple of 8
-  const long q = (L & 7) * per + (L >> 3);
-  const long g = q / ntiles;
+  const int xcd = L & 7, k = L >> 3;
+  const int pe = nx >> 3;                 // chain positions per XCD and limb (nx is a multiple of 8)
+  const int per_limb = pe * ntiles;
+  const int w = k % per_limb;
   TileMap m;
-  m.tile = (int)(q % ntiles);
-  m.r = (int)(g / nx);
-  m.xb = (int)chain[g % nx];
+  m.r = k / per_limb;
+  m.tile = w % ntiles;
+  m.xb = (int)chain[xcd * pe + w / ntiles];
   return m;
 }
 
@@ -535,7 +537,7 @@ __global__ __launch_bounds__(TPB) void ks_acc_kernel(KsArgs T, LevelGeom G, int 
                                                      size_t base_bs, u64 *out, size_t out_bs,
                                                      const PrimeInfo *pinfo) {
   const int N = 1 << G.logn;
-  const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles, G.pqn, G.limb_xcd);
+  const TileMap tm = chain_map(blockIdx.x, N / TPB, ntiles, G.pqn, G.limb_xcd, G.chain);
   const int x = tm.xb * TPB + threadIdx.x;
   const int p = pq_prime_dev(tm.r, G.level, L);
   const PrimeInfo pi = pinfo[p];
@@ -711,7 +713,7 @@ __global__ __launch_bounds__(TPB, (GT * BT == 1 ? 5 : 1)) void baby_mac_kernel(
     BabyArgs BA, LevelGeom G, int L, int batch, int ntiles, const u64 *digits, size_t dig_bs, const u64 *ct,
     size_t ct_bs, const u64 *pt, size_t pt_words, int ng, u64 *X, size_t x_bs, int accum, const PrimeInfo *pinfo) {
   const int N = 1 << G.logn;
-  const TileMap tm = tile_map(blockIdx.x, N / TPB, ntiles, G.pqn, G.limb_xcd);
+  const TileMap tm = chain_map(blockIdx.x, N / TPB, ntiles, G.pqn, G.limb_xcd, G.chain);
   const int x = tm.xb * TPB + threadIdx.x;
   const int p = pq_prime_dev(tm.r, G.level, L);
   const PrimeInfo pi = pinfo[p];
@@ -911,7 +913,7 @@ __global__ __launch_bounds__(64 * W) void baby_mac_shared_kernel(BabyArgs BA, Le
                                                                  const PrimeInfo *pinfo) {
   __shared__ u64 R[2][W][2][64];
   const int N = 1 << G.logn;
-  const TileMap tm = tile_map(blockIdx.x, N / 64, ntiles, G.pqn, G.limb_xcd);
+  const TileMap tm = chain_map(blockIdx.x, N / 64, ntiles, G.pqn, G.limb_xcd, G.chain);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int x = tm.xb * 64 + lane;
   const int p = pq_prime_dev(tm.r, G.level, L);
@@ -1185,16 +1187,16 @@ template <int P, int MP>
 __device__ __forceinline__ void baby_fold_body(uint32_t *A, const FoldRun &FR, const LevelGeom &G, int batch,
                                                int xb, int r, const PrimeInfo &pi, const uint32_t *E, size_t e_bs,
                                                size_t e_half, const uint8_t *wm, int ng, u64 *X, size_t x_bs,
-                                               int accum) {
+                                               int accum, int mt_begin, int mt_end) {
   using LD = FoldLds<P>;
   constexpr int NS = 2 * P - 1;
   const int N = 1 << G.logn;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int n = lane & 15, h = lane >> 4;
   const uint8_t *wx = wm + ((size_t)FR.off[r] * N * FR.kc + (size_t)(xb * MF_XB + w) * FR.kc * P) * 1024 + lane * 16;
-  const int mtiles = (batch + 15) / 16;
+  const int mtiles = mt_end;
   // MP row tiles of 16 ciphertexts per pass share every folded operand load
-  for (int mt0 = 0; mt0 < mtiles; mt0 += MP) {
+  for (int mt0 = mt_begin; mt0 < mtiles; mt0 += MP) {
     v4i acc[MP][NS];
 #pragma unroll
     for (int m = 0; m < MP; m++)
@@ -1301,10 +1303,13 @@ __global__ __launch_bounds__(MF_TPB, 2) void baby_fold_kernel(FoldRun FR, LevelG
   const TileMap tm = chain_map(blockIdx.x, N / MF_XB, 1, ls.n, G.limb_xcd, chain);
   const int r = ls.r[tm.r];
   const PrimeInfo pi = pinfo[pq_prime_dev(r, G.level, L)];
-  // one row tile per pass: sharing the folded operand loads over several tiles
-  // (MP > 1) holds MP x (2P - 1) accumulator tiles, and the occupancy lost to
-  // them cost more than the repeated loads (measured at 8 and 64 ciphertexts)
-  baby_fold_body<P, 1>(A, FR, G, batch, tm.xb, r, pi, E, e_bs, e_half, wm, ng, X, x_bs, accum);
+  // one workgroup takes every row tile of its coefficient block, one tile per
+  // pass: sharing the folded operand loads over several tiles (MP > 1) holds
+  // MP x (2P - 1) accumulator tiles, and the occupancy lost to them cost more
+  // than the repeated loads; so did dealing the row tiles over workgroups
+  // (measured at 8 and 64 ciphertexts)
+  baby_fold_body<P, 1>(A, FR, G, batch, tm.xb, r, pi, E, e_bs, e_half, wm, ng, X, x_bs, accum, 0,
+                       (batch + 15) / 16);
 }
 
 // The entries of every ciphertext once, before the folded product gathers
@@ -1718,7 +1723,7 @@ int launch_ks_accumulate(helrm_ctx *ctx, int level, const KsTerm *terms, int n_t
                          size_t digits_bstride, size_t c0_bstride, const u64 *base, size_t base_bstride,
                          u64 *out, size_t out_bstride, int batch, hipStream_t s) {
   LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn, ctx->dnum, ctx->tune_limb_xcd,
-               ctx->tune_gen_key_a == 2 ? 1 : 0};
+               ctx->tune_gen_key_a == 2 ? 1 : 0, ctx->tune_ks_chain ? ctx->d_chain256 : nullptr};
   if (G.beta > MAXBETA || G.beta < 1) {
     set_error("key switching with %d digits (1 to %d supported)", G.beta, MAXBETA);
     return HELRM_EINVAL;
@@ -1890,7 +1895,7 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   }
   const int level = plan->level;
   LevelGeom G{level, ctx->n_digits(level), level + 1 + ctx->K, ctx->L + 1 + ctx->K, ctx->logn, ctx->dnum, ctx->tune_limb_xcd,
-               ctx->tune_gen_key_a == 2 ? 1 : 0};
+               ctx->tune_gen_key_a == 2 ? 1 : 0, ctx->tune_ks_chain ? ctx->d_chain256 : nullptr};
   if (G.beta > MAXBETA || G.beta < 1) {
     set_error("key switching with %d digits (1 to %d supported)", G.beta, MAXBETA);
     return HELRM_EINVAL;
@@ -1918,9 +1923,11 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
   const bool fold = fold_ws && plan->d_wm && plan->wm_keys_gen == ctx->keys_gen && ctx->tune_baby_fold > 0 &&
                     batch >= ctx->tune_baby_fold && g0 % HELRM_MAX_GTILE == 0 &&
                     g0 / HELRM_MAX_GTILE < plan->wm_tiles && G.beta <= 3 && BA.nrot + BA.has0 <= 64;
+  // the matrix-core MAC reads its plaintext operands padded to 64 baby steps
+  // and 8 giant outputs: plans with few baby steps stay on the VALU kernels
   const bool mfma = !fold && plan->d_ptm && ctx->tune_baby_mfma > 0 && batch >= ctx->tune_baby_mfma &&
                     g0 % HELRM_MAX_GTILE == 0 && g0 / HELRM_MAX_GTILE < plan->ptm_tiles &&
-                    BA.nrot + BA.has0 <= 64;
+                    BA.nrot + BA.has0 <= 64 && BA.nrot + BA.has0 >= ctx->tune_mfma_min_slots;
   if (fold) {
     // key-folded product on the matrix cores: the entries of every ciphertext
     // once, then one launch per digit count
@@ -1986,7 +1993,8 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
 #undef BABYM
     }
   } else if (ng >= 2 && batch >= 2 && ctx->tune_baby_share >= 2) {
-    // several giant outputs and a batch: W ciphertexts per workgroup
+    // several giant outputs and a batch: W ciphertexts per workgroup (blocks of 64 coefficients)
+    G.chain = ctx->tune_ks_chain ? ctx->d_chain64 : nullptr;
     const int W = pick_bt(batch, ctx->tune_baby_share);
     const int gpw = (ng + W - 1) / W;
     const int ntiles = (batch + W - 1) / W;

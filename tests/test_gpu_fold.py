@@ -160,3 +160,4 @@ def test_block_chain_order_off():
     pts = O.plan_residues(prm, w.plan)
     assert_bit_exact(outs[(0, "fold")][0], O.lookup(prm, w.keys, w.plan, w.cts[0], pts), "query 0")
     ctx.close()
+

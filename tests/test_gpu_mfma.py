@@ -18,6 +18,14 @@ from tests.gpu_helpers import assert_bit_exact, context_for, empty, gpu_plan, lo
 pytestmark = pytest.mark.gpu
 
 
+def _mfma_ctx(prm):
+    """A context whose matrix-core MAC also takes plans with few baby steps
+    (by default those stay on the VALU kernels)."""
+    ctx = context_for(prm)
+    ctx.helrm_set_tuning("mfma_min_slots", 1)
+    return ctx
+
+
 def _lookup(ctx, plan, cts, level, N, mfma):
     ctx.helrm_set_tuning("baby_mfma", 8 if mfma else 0)
     try:
@@ -53,7 +61,7 @@ def test_mfma_toy_ring_ragged(level):
     g = synth.rng(0)
     t = W.compressed_table(g, 256, 16, 16, -1.0, 1.0)
     w = W.build(prm, [t], level=level, n1=4, radix=2, n_queries=9)
-    ctx = context_for(prm)
+    ctx = _mfma_ctx(prm)
     load_keys(ctx, w.keys)
     _both_and_oracle(ctx, w, gpu_plan(ctx, w.plan), [0, 7, 8], f"toy level {level}")
     ctx.close()
@@ -65,7 +73,7 @@ def test_mfma_table1_shape_giant_tiles():
     prm = O.config1_params()
     w = W.table1_shape(prm, 1, n_queries=8)
     assert w.plan.n2 == 32
-    ctx = context_for(prm)
+    ctx = _mfma_ctx(prm)
     load_keys(ctx, w.keys)
     _both_and_oracle(ctx, w, gpu_plan(ctx, w.plan), [0, 5], "Table I shape")
     ctx.close()
@@ -75,7 +83,7 @@ def test_mfma_multi_ciphertext_accumulates():
     """Two selector ciphertexts per query on the toy ring (the second block's
     products are added to the first's giant accumulators), batch 8."""
     prm = O.config1_params()
-    ctx = context_for(prm)
+    ctx = _mfma_ctx(prm)
     g = synth.rng(9)
     tables = [W.uncompressed_table(g, 1000, 16, -1, 1) for _ in range(3)]
     w = W.build_multi(prm, tables, level=2, n1=16, radix=4, n_queries=8)
@@ -106,7 +114,7 @@ def test_mfma_n16_multitable_batch17():
               W.compressed_table(g, 300000, 16, 256, -0.05, 0.05),
               W.compressed_table(g, 1000, 16, 256, -0.05, 0.05)]
     w = W.build(prm, tables, level=1, n1=16, radix=8, n_queries=17, sign=-1)
-    ctx = context_for(prm)
+    ctx = _mfma_ctx(prm)
     load_keys(ctx, w.keys)
     _both_and_oracle(ctx, w, gpu_plan(ctx, w.plan), [0, 16], "N=2^16 level 1 batch 17")
     ctx.close()
@@ -129,7 +137,7 @@ def test_mfma_n16_level23_group():
             specs.append(O.TableSpec(rows=k, d=16, base=256, C=C))
     w = W.build(prm, specs, level=23, n1=16, radix=8, n_queries=8, sign=-1)
     assert w.plan.n2 == 4 and prm.n_digits(23) == 3
-    ctx = context_for(prm)
+    ctx = _mfma_ctx(prm)
     load_keys(ctx, w.keys)
     _both_and_oracle(ctx, w, gpu_plan(ctx, w.plan), [0, 7], "level 23 group")
     ctx.close()

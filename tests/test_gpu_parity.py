@@ -94,6 +94,34 @@ def test_ntt_parity_other_shapes(which, wc, wb, p1, p2, ctx1, ctx2):
         ctx.helrm_set_tuning("ntt_blk_w", 4)
 
 
+@pytest.mark.parametrize("n1,batch", [(16, 1), (4, 3)])
+def test_lookup_ks_chain(n1, batch, p2, ctx2):
+    """The key-switching kernels with their workgroups in chain order of the
+    coefficient blocks (knob ks_chain): a lookup at N=2^16, level 4, on the
+    per-thread baby-step kernel (n1 = 16, one giant output, batch 1) and on
+    the workgroup-shared one (n1 = 4, four giant outputs, batch 3), bit-exact
+    against the oracle and equal to the plain order."""
+    g = synth.rng(3)
+    t = W.compressed_table(g, 65536, 16, 256, -0.05, 0.05)
+    w = W.build(p2, [t], level=4, n1=n1, radix=4, n_queries=batch, sign=-1)
+    load_keys(ctx2, w.keys)
+    plan = gpu_plan(ctx2, w.plan)
+    outs = []
+    try:
+        for chain in (1, 0):
+            ctx2.helrm_set_tuning("ks_chain", chain)
+            say(f"lookup N=2^16 level 4 n1={n1} batch {batch}, ks_chain {chain}")
+            out = empty(batch, 2, 4, p2.N)
+            ctx2.helrm_lookup_packed(plan, to_dev(np.stack(w.cts)), batch, out)
+            outs.append(to_host(out).reshape(batch, 2, 4, p2.N))
+    finally:
+        ctx2.helrm_set_tuning("ks_chain", 1)
+    assert_bit_exact(outs[0], outs[1], "ks_chain 1 vs 0")
+    pts = O.plan_residues(p2, w.plan)
+    for k in range(batch):
+        assert_bit_exact(outs[0][k], O.lookup(p2, w.keys, w.plan, w.cts[k], pts), f"ks_chain query {k}")
+
+
 @pytest.mark.parametrize("which", ["cfg1", "cfg2"])
 def test_key_uniform_parity(which, p1, p2, ctx1, ctx2):
     """Seeded key polynomials expanded on the GPU equal the oracle's expansion,
@@ -141,10 +169,13 @@ def test_tuning_knobs_validate(p1):
     ctx = context_for(p1)
     good = {"ks_tile": [1, 2, 4], "baby_tile": [1, 2, 4], "baby_share": [1, 2, 4, 8], "ntt_col_w": [0, 8, 16],
             "ntt_blk_w": [0, 4, 8], "ntt_small_limbs": [0, 48], "gen_key_a": [0, 1, 2], "limb_xcd": [0, 1],
-            "fuse_ks": [0, 1], "fuse_conv": [0, 1], "conv_wgs": [0, 2048]}
+            "fuse_ks": [0, 1], "fuse_conv": [0, 1], "conv_wgs": [0, 2048], "ks_chain": [0, 1],
+            "block_chain": [0, 1], "baby_mfma": [0, 8], "baby_fold": [0, 8], "ptm": [0, 1],
+            "mfma_min_slots": [0, 64, 33]}
     bad = {"ks_tile": [0, 3, 8], "baby_tile": [0, 3], "baby_share": [0, 3, 16], "ntt_col_w": [4, 32],
            "ntt_blk_w": [2, 16], "ntt_small_limbs": [-1], "gen_key_a": [-1, 3], "limb_xcd": [2],
-           "fuse_ks": [2], "fuse_conv": [2, -1], "conv_wgs": [-1]}
+           "fuse_ks": [2], "fuse_conv": [2, -1], "conv_wgs": [-1], "ks_chain": [2, -1], "block_chain": [2],
+           "baby_mfma": [-1], "baby_fold": [-1], "ptm": [2], "mfma_min_slots": [-1, 65]}
     for knob, vals in good.items():
         for v in vals:
             ctx.helrm_set_tuning(knob, v)
@@ -347,7 +378,7 @@ def test_lookup_regenerated_key_halves_cfg2(ctx2):
             ctx2.helrm_set_tuning("gen_key_a", gen)
             _check_lookup(ctx2, w, plan, [0])
     finally:
-        ctx2.helrm_set_tuning("gen_key_a", 2)
+        ctx2.helrm_set_tuning("gen_key_a", 1)
 
 
 def test_lookup_batched_ragged_cfg2(ctx2):
