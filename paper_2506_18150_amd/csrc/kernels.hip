@@ -1304,10 +1304,10 @@ __global__ __launch_bounds__(MF_TPB, 2) void baby_fold_kernel(FoldRun FR, LevelG
   const int r = ls.r[tm.r];
   const PrimeInfo pi = pinfo[pq_prime_dev(r, G.level, L)];
   // one workgroup takes every row tile of its coefficient block, one tile per
-  // pass: sharing the folded operand loads over several tiles (MP > 1) holds
-  // MP x (2P - 1) accumulator tiles, and the occupancy lost to them cost more
-  // than the repeated loads; so did dealing the row tiles over workgroups
-  // (measured at 8 and 64 ciphertexts)
+  // pass.  Sharing the folded operand loads over 2 or 4 tiles per pass (MP)
+  // holds MP x (2P - 1) accumulator tiles; the occupancy lost to them cost
+  // more than the repeated loads (at 64 ciphertexts: 53.5 ms with one tile,
+  // 58-61 ms with 2 or 4), and so did dealing the row tiles over workgroups
   baby_fold_body<P, 1>(A, FR, G, batch, tm.xb, r, pi, E, e_bs, e_half, wm, ng, X, x_bs, accum, 0,
                        (batch + 15) / 16);
 }
