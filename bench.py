@@ -75,9 +75,12 @@ def kernel_source(path: str, name: str) -> str:
 
 
 def kernel_hash(rec) -> str:
-    """sha256 over the kernel's own text plus the shared device header."""
+    """sha256 over the kernel's own text (each kernel's, for a record of a
+    kernel class) plus the shared device header."""
     import hashlib
-    h = hashlib.sha256(kernel_source(rec["kernel_file"], rec["kernel"]).encode())
+    h = hashlib.sha256()
+    for name in rec.get("kernels", [rec["kernel"]]):
+        h.update(kernel_source(rec["kernel_file"], name).encode())
     for p in rec["headers"]:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
@@ -404,6 +407,10 @@ def w3_batched(prm, batch: int, steps: int) -> dict:
     if ak in alg:
         roof.update(achieved=alg[ak] / (table[dom]["ms_per_step"] * 1e6), algorithmic_bytes_per_call=alg[ak])
         roof["frac"] = roof["achieved"] / HBM_PEAK_GBS
+    traffic = measured_traffic(KERNEL_SYMBOL[dom], dict(workload="w3", level=23, radix=spec.radix, n1=spec.n1,
+                                                        batch=batch, sign=spec.sign))
+    roof["traffic"] = traffic
+    roof["traffic_frac"] = (traffic / (table[dom]["ms_per_step"] * 1e6) / HBM_PEAK_GBS) if traffic else None
     n_hoisted = sum(1 for b in sorted({k % spec.n1 for k in spec.diag}) if b)
     n_full = sum(1 for g_ in sorted({k // spec.n1 for k in spec.diag}) if g_) + sum(r - 1 for _, r in spec.stages)
     lk = len(tables)

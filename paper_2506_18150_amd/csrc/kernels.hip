@@ -1183,111 +1183,125 @@ struct FoldLds {
   static constexpr int OS = 16 * 16 + 2;       // result staging: u64 per coefficient (2 mod 16)
 };
 
-template <int P, int MP>
-__device__ __forceinline__ void baby_fold_body(uint32_t *A, const FoldRun &FR, const LevelGeom &G, int batch,
-                                               int xb, int r, const PrimeInfo &pi, const uint32_t *E, size_t e_bs,
-                                               size_t e_half, const uint8_t *wm, int ng, u64 *X, size_t x_bs,
-                                               int accum, int mt_begin, int mt_end) {
+// One workgroup: coefficient block xb (8 coefficients, one per wave) of limb
+// r, row tiles [mt_begin, mt_end) of 16 ciphertexts, each over FR.kc depth
+// chunks.  The (tile, chunk) steps are software-pipelined: the gathers of
+// the next step's entries and the loads of its folded operands are issued
+// before this step's barrier and products, so their latency overlaps the
+// matrix-core work instead of following it.
+template <int P>
+__device__ __forceinline__ void baby_fold_body(uint32_t *A, const unsigned *sgal, const FoldRun &FR,
+                                               const LevelGeom &G, int batch, int xb, int r, const PrimeInfo &pi,
+                                               const uint32_t *E, size_t e_bs, size_t e_half, const uint8_t *wm, int ng,
+                                               u64 *X, size_t x_bs, int accum, int mt_begin, int mt_end) {
   using LD = FoldLds<P>;
   constexpr int NS = 2 * P - 1;
   const int N = 1 << G.logn;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int n = lane & 15, h = lane >> 4;
   const uint8_t *wx = wm + ((size_t)FR.off[r] * N * FR.kc + (size_t)(xb * MF_XB + w) * FR.kc * P) * 1024 + lane * 16;
-  const int mtiles = mt_end;
-  // MP row tiles of 16 ciphertexts per pass share every folded operand load
-  for (int mt0 = mt_begin; mt0 < mtiles; mt0 += MP) {
-    v4i acc[MP][NS];
+  const int K = FR.kc, steps = (mt_end - mt_begin) * K;
+  // staging role of this thread: coefficient xi, ciphertext ci of the tile,
+  // slots 16 kc + 4 sq .. + 3
+  const int sxi = t & 7, sci = (t >> 3) & 15, sq = t >> 7, sx = xb * MF_XB + sxi;
+  const uint32_t *elimb = E + (size_t)FR.off[r] * N;
+  uint32_t q4[P][4];
+  unsigned qmask = 0;   // slots of the gathered step that hold entries (the others stage as 0)
+  // the entries of step `it`: balanced digits packed per digit plane by
+  // fold_entries_kernel, gathered at the rotation's source.  Branch-free: an
+  // absent ciphertext or slot loads valid words of ciphertext 0 / coefficient
+  // x and is masked out when staged, so the loads stay in flight across the
+  // barrier and the products that follow
+  auto gather = [&](int it) {
+    const int mt = mt_begin + it / K, kc = it % K, c = mt * 16 + sci;
+    const bool ok = c < batch;
+    const uint32_t *ec = elimb + (size_t)(ok ? c : 0) * e_bs;
+    qmask = 0;
 #pragma unroll
-    for (int m = 0; m < MP; m++)
+    for (int u = 0; u < 4; u++) {
+      const int sl = 16 * kc + 4 * sq + u;
+      const bool zero = FR.has0 && sl == 0;
+      const int gi = min(max(sl - FR.has0, 0), FR.nslot - FR.has0 - 1);
+      const unsigned src = zero || gi < 0 ? (unsigned)sx : galois_src(sx, sgal[gi < 0 ? 0 : gi], G.logn);
+      const uint32_t *ep = ec + (zero ? e_half : 0) + (size_t)src * P;
 #pragma unroll
-      for (int k = 0; k < NS; k++) acc[m][k] = v4i{0, 0, 0, 0};
-    for (int kc = 0; kc < FR.kc; kc++) {
-      v4i wop[P];
+      for (int d = 0; d < P; d++) q4[d][u] = ep[d];
+      qmask |= (ok && sl < FR.nslot) ? 1u << u : 0u;
+    }
+  };
+  v4i wop[P];
+  auto load_w = [&](int it) {
+    const int kc = it % K;
 #pragma unroll
-      for (int j = 0; j < P; j++) wop[j] = *(const v4i *)(wx + ((size_t)kc * P + j) * 1024);
+    for (int j = 0; j < P; j++) wop[j] = *(const v4i *)(wx + ((size_t)kc * P + j) * 1024);
+  };
+  v4i acc[NS];
 #pragma unroll
-      for (int m = 0; m < MP; m++) {
-        const int mt = mt0 + m;
-        if (mt >= mtiles) break;
-        // stage the entries of (coefficient xi, ciphertext ci, slots 16 kc + 4 sq .. + 3): their
-        // balanced digits, packed per digit plane by fold_entries_kernel, gathered at the rotation's source
-        {
-          const int xi = t & 7, ci = (t >> 3) & 15, sq = t >> 7, x = xb * MF_XB + xi, c = mt * 16 + ci;
-          const bool ok = c < batch;
-          const uint32_t *ec = E + (size_t)(ok ? c : 0) * e_bs + (size_t)FR.off[r] * N;
-          uint32_t q4[P][4];
+  for (int k = 0; k < NS; k++) acc[k] = v4i{0, 0, 0, 0};
+  if (steps > 0) {
+    load_w(0);
+    gather(0);
+  }
+  for (int it = 0; it < steps; it++) {
+    const int mt = mt_begin + it / K, kc = it % K;
 #pragma unroll
-          for (int u = 0; u < 4; u++) {
-            const int sl = 16 * kc + 4 * sq + u;
+    for (int d = 0; d < P; d++)
+      *(v4i *)(A + sxi * LD::XS + d * LD::PS + sci * FD_RS + 4 * sq) =
+          v4i{(int)(qmask & 1 ? q4[d][0] : 0u), (int)(qmask & 2 ? q4[d][1] : 0u), (int)(qmask & 4 ? q4[d][2] : 0u),
+              (int)(qmask & 8 ? q4[d][3] : 0u)};
+    // unconditional (the last step re-reads its own words): every iteration
+    // issues the same loads, so the waits before their first use stay exact
+    gather(min(it + 1, steps - 1));
+    __syncthreads();
 #pragma unroll
-            for (int d = 0; d < P; d++) q4[d][u] = 0;
-            if (ok && sl < FR.nslot) {
-              const bool zero = FR.has0 && sl == 0;
-              const unsigned src = zero ? (unsigned)x : galois_src(x, FR.gal[sl - FR.has0], G.logn);
-              const uint32_t *ep = ec + (zero ? e_half : 0) + (size_t)src * P;
+    for (int i = 0; i < P; i++) {
+      const v4i aop = *(const v4i *)(A + w * LD::XS + i * LD::PS + n * FD_RS + 4 * h);
 #pragma unroll
-              for (int d = 0; d < P; d++) q4[d][u] = ep[d];
-            }
-          }
+      for (int j = 0; j < P; j++) acc[i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, wop[j], acc[i + j], 0, 0, 0);
+    }
+    load_w(min(it + 1, steps - 1));
+    __syncthreads();
+    if (kc < K - 1) continue;
+    // tile mt done: lane holds rows (ciphertexts) 4 h + v of column n = (giant
+    // n % 8, polynomial n / 8)
+    u64 res[4];
 #pragma unroll
-          for (int d = 0; d < P; d++)
-            *(v4i *)(A + xi * LD::XS + d * LD::PS + ci * FD_RS + 4 * sq) =
-                v4i{(int)q4[d][0], (int)q4[d][1], (int)q4[d][2], (int)q4[d][3]};
-        }
-        __syncthreads();
+    for (int v = 0; v < 4; v++) {
+      u128 S = 0;   // the exact signed sum in two's complement mod 2^128
 #pragma unroll
-        for (int i = 0; i < P; i++) {
-          const v4i aop = *(const v4i *)(A + w * LD::XS + i * LD::PS + n * FD_RS + 4 * h);
-#pragma unroll
-          for (int j = 0; j < P; j++)
-            acc[m][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, wop[j], acc[m][i + j], 0, 0, 0);
-        }
-        __syncthreads();
-      }
+      for (int cidx = 0; cidx < NS; cidx++) S += (u128)(__int128)(long long)acc[cidx][v] << (8 * cidx);
+      const long long hi = (long long)(u64)(S >> 64);
+      const u64 lo = (u64)S;
+      // |S| < 2^87 (P = 5) or 2^127 (P = 8): |hi| < 2^23, or below 8 q (q > 2^59)
+      u64 hm;
+      if (P == 5)
+        hm = hi < 0 ? (u64)(hi + (long long)pi.q) : (u64)hi;
+      else
+        hm = reduce64((u64)(hi + 8 * (long long)pi.q), pi.q, pi.mu);
+      res[v] = redc(lo, hm, pi.q, pi.qn);
     }
 #pragma unroll
-    for (int m = 0; m < MP; m++) {
-      const int mt = mt0 + m;
-      if (mt >= mtiles) break;
-      // lane holds rows (ciphertexts) 4 h + v of column n = (giant n % 8, polynomial n / 8)
-      u64 res[4];
+    for (int k = 0; k < NS; k++) acc[k] = v4i{0, 0, 0, 0};
+    u64 *O = (u64 *)A;   // the staging area is free: every wave passed the last barrier
 #pragma unroll
-      for (int v = 0; v < 4; v++) {
-        u128 S = 0;   // the exact signed sum in two's complement mod 2^128
+    for (int v = 0; v < 4; v++) O[w * LD::OS + (4 * h + v) * 16 + n] = res[v];
+    __syncthreads();
+    {
+      const int xi = t & 7, col = (t >> 3) & 15, rq = t >> 7, x = xb * MF_XB + xi;
+      const int gg = col & 7, pol = col >> 3;
+      if (gg < ng) {
 #pragma unroll
-        for (int cidx = 0; cidx < NS; cidx++) S += (u128)(__int128)(long long)acc[m][cidx][v] << (8 * cidx);
-        const long long hi = (long long)(u64)(S >> 64);
-        const u64 lo = (u64)S;
-        // |S| < 2^87 (P = 5) or 2^127 (P = 8): |hi| < 2^23, or below 8 q (q > 2^59)
-        u64 hm;
-        if (P == 5)
-          hm = hi < 0 ? (u64)(hi + (long long)pi.q) : (u64)hi;
-        else
-          hm = reduce64((u64)(hi + 8 * (long long)pi.q), pi.q, pi.mu);
-        res[v] = redc(lo, hm, pi.q, pi.qn);
-      }
-      u64 *O = (u64 *)A;   // the staging area is free: every wave passed the last barrier
-#pragma unroll
-      for (int v = 0; v < 4; v++) O[w * LD::OS + (4 * h + v) * 16 + n] = res[v];
-      __syncthreads();
-      {
-        const int xi = t & 7, col = (t >> 3) & 15, rq = t >> 7, x = xb * MF_XB + xi;
-        const int gg = col & 7, pol = col >> 3;
-        if (gg < ng) {
-#pragma unroll
-          for (int k = 0; k < 4; k++) {
-            const int row = 4 * rq + k, c = mt * 16 + row;
-            if (c >= batch) continue;
-            u64 v = O[xi * LD::OS + row * 16 + col];
-            u64 *o = X + (size_t)c * x_bs + ((size_t)(gg * 2 + pol) * G.pqn + r) * N + x;
-            if (accum) v = add_mod(v, *o, pi.q);
-            *o = v;
-          }
+        for (int k = 0; k < 4; k++) {
+          const int row = 4 * rq + k, c = mt * 16 + row;
+          if (c >= batch) continue;
+          u64 v = O[xi * LD::OS + row * 16 + col];
+          u64 *o = X + (size_t)c * x_bs + ((size_t)(gg * 2 + pol) * G.pqn + r) * N + x;
+          if (accum) v = add_mod(v, *o, pi.q);
+          *o = v;
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 }
 
@@ -1298,8 +1312,11 @@ __global__ __launch_bounds__(MF_TPB, 2) void baby_fold_kernel(FoldRun FR, LevelG
                                                                size_t x_bs, int accum, const PrimeInfo *pinfo,
                                                                const u64 *chain) {
   __shared__ __align__(16) uint32_t A[FoldLds<P>::WORDS];
+  __shared__ unsigned sgal[HELRM_MAX_BABY];   // the rotations' Galois elements, read with LDS latency
   static_assert(FoldLds<P>::WORDS * 4 >= MF_XB * FoldLds<P>::OS * 8, "result staging fits");
   const int N = 1 << G.logn;
+  if (threadIdx.x < HELRM_MAX_BABY) sgal[threadIdx.x] = FR.gal[threadIdx.x];
+  __syncthreads();
   const TileMap tm = chain_map(blockIdx.x, N / MF_XB, 1, ls.n, G.limb_xcd, chain);
   const int r = ls.r[tm.r];
   const PrimeInfo pi = pinfo[pq_prime_dev(r, G.level, L)];
@@ -1308,8 +1325,8 @@ __global__ __launch_bounds__(MF_TPB, 2) void baby_fold_kernel(FoldRun FR, LevelG
   // holds MP x (2P - 1) accumulator tiles; the occupancy lost to them cost
   // more than the repeated loads (at 64 ciphertexts: 53.5 ms with one tile,
   // 58-61 ms with 2 or 4), and so did dealing the row tiles over workgroups
-  baby_fold_body<P, 1>(A, FR, G, batch, tm.xb, r, pi, E, e_bs, e_half, wm, ng, X, x_bs, accum, 0,
-                       (batch + 15) / 16);
+  baby_fold_body<P>(A, sgal, FR, G, batch, tm.xb, r, pi, E, e_bs, e_half, wm, ng, X, x_bs, accum, 0,
+                    (batch + 15) / 16);
 }
 
 // The entries of every ciphertext once, before the folded product gathers
