@@ -456,7 +456,9 @@ int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *o
  * plaintexts' matrix-core operands.  "block_chain" (1, default, or 0): the
  * key-folded product takes its coefficient blocks in the order in which the
  * baby-step rotations shift them (rotated words then come from L2), or in
- * plain order.
+ * plain order.  "fold_mp" (0..3, default 2): batches of more than 16
+ * ciphertexts let one load of the folded operands serve two tiles of 16
+ * ciphertexts on primes below 2^40 (bit 0) and on the wider ones (bit 1).
  * Errors: HELRM_EINVAL for an unknown knob or value. */
 int helrm_set_tuning(helrm_ctx *ctx, const char *knob, int value);
 

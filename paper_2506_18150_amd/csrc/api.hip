@@ -2124,6 +2124,9 @@ extern "C" int helrm_set_tuning(helrm_ctx *c, const char *knob, int value) {
   } else if (strcmp(knob, "mfma_min_slots") == 0) {
     CHECK_ARG(value >= 0 && value <= 64, "mfma_min_slots must be in 0..64");
     c->tune_mfma_min_slots = value;
+  } else if (strcmp(knob, "fold_mp") == 0) {
+    CHECK_ARG(value >= 0 && value <= 3, "fold_mp must be 0..3");
+    c->tune_fold_mp = value;
   } else if (strcmp(knob, "ks_chain") == 0) {
     CHECK_ARG(value == 0 || value == 1, "ks_chain must be 0 or 1");
     c->tune_ks_chain = value;

@@ -397,6 +397,7 @@ struct helrm_ctx {
   int tune_ntt_blk_w = 4;    // NTT block-pass blocks per workgroup (4, 8; 0 = by launch size)
   int ntt_small_limbs = 48;  // launches of fewer limbs take the narrow shapes when a width is 0
   int tune_mfma_min_slots = 33;   // matrix-core MAC only for plans with at least this many baby steps
+  int tune_fold_mp = 2;      // key-folded product: 2 row tiles per operand load (bit 0: 40-bit, bit 1: wide primes)
   int tune_block_chain = 1;   // key-folded product: workgroups in chain order of the coefficient blocks
   const u64 *d_block_chain = nullptr;   // [N/8]: block of 8 coefficients at chain position i (in d_const)
   const u64 *d_chain64 = nullptr;       // [N/64]: the same for blocks of 64 coefficients

@@ -1184,12 +1184,14 @@ struct FoldLds {
 };
 
 // One workgroup: coefficient block xb (8 coefficients, one per wave) of limb
-// r, row tiles [mt_begin, mt_end) of 16 ciphertexts, each over FR.kc depth
-// chunks.  The (tile, chunk) steps are software-pipelined: the gathers of
-// the next step's entries and the loads of its folded operands are issued
-// before this step's barrier and products, so their latency overlaps the
-// matrix-core work instead of following it.
-template <int P>
+// r, row tiles [mt_begin, mt_end) of 16 ciphertexts in groups of MP, each
+// group over FR.kc depth chunks; a chunk's folded operands are loaded once
+// and serve the MP tiles of the group (MP x (2P - 1) accumulator tiles).
+// The sub-steps (group, chunk, tile) are software-pipelined: the gathers of
+// the next sub-step's entries are issued before this one's barrier and
+// products, the next chunk's folded operands right after the products of a
+// chunk's last tile, so their latency overlaps the matrix-core work.
+template <int P, int MP>
 __device__ __forceinline__ void baby_fold_body(uint32_t *A, const unsigned *sgal, const FoldRun &FR,
                                                const LevelGeom &G, int batch, int xb, int r, const PrimeInfo &pi,
                                                const uint32_t *E, size_t e_bs, size_t e_half, const uint8_t *wm, int ng,
@@ -1200,20 +1202,21 @@ __device__ __forceinline__ void baby_fold_body(uint32_t *A, const unsigned *sgal
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int n = lane & 15, h = lane >> 4;
   const uint8_t *wx = wm + ((size_t)FR.off[r] * N * FR.kc + (size_t)(xb * MF_XB + w) * FR.kc * P) * 1024 + lane * 16;
-  const int K = FR.kc, steps = (mt_end - mt_begin) * K;
+  const int K = FR.kc, groups = (mt_end - mt_begin + MP - 1) / MP;
+  if (groups <= 0) return;
   // staging role of this thread: coefficient xi, ciphertext ci of the tile,
   // slots 16 kc + 4 sq .. + 3
   const int sxi = t & 7, sci = (t >> 3) & 15, sq = t >> 7, sx = xb * MF_XB + sxi;
   const uint32_t *elimb = E + (size_t)FR.off[r] * N;
   uint32_t q4[P][4];
-  unsigned qmask = 0;   // slots of the gathered step that hold entries (the others stage as 0)
-  // the entries of step `it`: balanced digits packed per digit plane by
-  // fold_entries_kernel, gathered at the rotation's source.  Branch-free: an
-  // absent ciphertext or slot loads valid words of ciphertext 0 / coefficient
-  // x and is masked out when staged, so the loads stay in flight across the
-  // barrier and the products that follow
-  auto gather = [&](int it) {
-    const int mt = mt_begin + it / K, kc = it % K, c = mt * 16 + sci;
+  unsigned qmask = 0;   // slots of the gathered sub-step that hold entries (the others stage as 0)
+  // the entries of tile mt, chunk kc: balanced digits packed per digit plane
+  // by fold_entries_kernel, gathered at the rotation's source.  Branch-free:
+  // an absent ciphertext (a tile past the batch included) or slot loads valid
+  // words of ciphertext 0 / coefficient x and is masked out when staged, so
+  // the loads stay in flight across the barrier and the products that follow
+  auto gather = [&](int mt, int kc) {
+    const int c = mt * 16 + sci;
     const bool ok = c < batch;
     const uint32_t *ec = elimb + (size_t)(ok ? c : 0) * e_bs;
     qmask = 0;
@@ -1230,87 +1233,109 @@ __device__ __forceinline__ void baby_fold_body(uint32_t *A, const unsigned *sgal
     }
   };
   v4i wop[P];
-  auto load_w = [&](int it) {
-    const int kc = it % K;
+  auto load_w = [&](int kc) {
 #pragma unroll
     for (int j = 0; j < P; j++) wop[j] = *(const v4i *)(wx + ((size_t)kc * P + j) * 1024);
   };
-  v4i acc[NS];
+  v4i acc[MP][NS];
 #pragma unroll
-  for (int k = 0; k < NS; k++) acc[k] = v4i{0, 0, 0, 0};
-  if (steps > 0) {
-    load_w(0);
-    gather(0);
-  }
-  for (int it = 0; it < steps; it++) {
-    const int mt = mt_begin + it / K, kc = it % K;
+  for (int m = 0; m < MP; m++)
 #pragma unroll
-    for (int d = 0; d < P; d++)
-      *(v4i *)(A + sxi * LD::XS + d * LD::PS + sci * FD_RS + 4 * sq) =
-          v4i{(int)(qmask & 1 ? q4[d][0] : 0u), (int)(qmask & 2 ? q4[d][1] : 0u), (int)(qmask & 4 ? q4[d][2] : 0u),
-              (int)(qmask & 8 ? q4[d][3] : 0u)};
-    // unconditional (the last step re-reads its own words): every iteration
-    // issues the same loads, so the waits before their first use stay exact
-    gather(min(it + 1, steps - 1));
-    __syncthreads();
+    for (int k = 0; k < NS; k++) acc[m][k] = v4i{0, 0, 0, 0};
+  load_w(0);
+  gather(mt_begin, 0);
+  for (int g = 0; g < groups; g++) {
+    const int mt0 = mt_begin + g * MP;
+    for (int kc = 0; kc < K; kc++) {
 #pragma unroll
-    for (int i = 0; i < P; i++) {
-      const v4i aop = *(const v4i *)(A + w * LD::XS + i * LD::PS + n * FD_RS + 4 * h);
+      for (int m = 0; m < MP; m++) {
 #pragma unroll
-      for (int j = 0; j < P; j++) acc[i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, wop[j], acc[i + j], 0, 0, 0);
-    }
-    load_w(min(it + 1, steps - 1));
-    __syncthreads();
-    if (kc < K - 1) continue;
-    // tile mt done: lane holds rows (ciphertexts) 4 h + v of column n = (giant
-    // n % 8, polynomial n / 8)
-    u64 res[4];
-#pragma unroll
-    for (int v = 0; v < 4; v++) {
-      u128 S = 0;   // the exact signed sum in two's complement mod 2^128
-#pragma unroll
-      for (int cidx = 0; cidx < NS; cidx++) S += (u128)(__int128)(long long)acc[cidx][v] << (8 * cidx);
-      const long long hi = (long long)(u64)(S >> 64);
-      const u64 lo = (u64)S;
-      // |S| < 2^87 (P = 5) or 2^127 (P = 8): |hi| < 2^23, or below 8 q (q > 2^59)
-      u64 hm;
-      if (P == 5)
-        hm = hi < 0 ? (u64)(hi + (long long)pi.q) : (u64)hi;
-      else
-        hm = reduce64((u64)(hi + 8 * (long long)pi.q), pi.q, pi.mu);
-      res[v] = redc(lo, hm, pi.q, pi.qn);
-    }
-#pragma unroll
-    for (int k = 0; k < NS; k++) acc[k] = v4i{0, 0, 0, 0};
-    u64 *O = (u64 *)A;   // the staging area is free: every wave passed the last barrier
-#pragma unroll
-    for (int v = 0; v < 4; v++) O[w * LD::OS + (4 * h + v) * 16 + n] = res[v];
-    __syncthreads();
-    {
-      const int xi = t & 7, col = (t >> 3) & 15, rq = t >> 7, x = xb * MF_XB + xi;
-      const int gg = col & 7, pol = col >> 3;
-      if (gg < ng) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-          const int row = 4 * rq + k, c = mt * 16 + row;
-          if (c >= batch) continue;
-          u64 v = O[xi * LD::OS + row * 16 + col];
-          u64 *o = X + (size_t)c * x_bs + ((size_t)(gg * 2 + pol) * G.pqn + r) * N + x;
-          if (accum) v = add_mod(v, *o, pi.q);
-          *o = v;
+        for (int d = 0; d < P; d++)
+          *(v4i *)(A + sxi * LD::XS + d * LD::PS + sci * FD_RS + 4 * sq) =
+              v4i{(int)(qmask & 1 ? q4[d][0] : 0u), (int)(qmask & 2 ? q4[d][1] : 0u),
+                  (int)(qmask & 4 ? q4[d][2] : 0u), (int)(qmask & 8 ? q4[d][3] : 0u)};
+        // the next sub-step's entries (unconditional: the last re-reads its
+        // own), so every sub-step issues the same loads
+        {
+          int nm = mt0 + m + 1, nk = kc;
+          if (m + 1 == MP) {
+            nm = mt0;
+            nk = kc + 1;
+            if (nk == K) {
+              nk = 0;
+              nm = g + 1 < groups ? mt0 + MP : mt0 + m;
+              if (g + 1 == groups) nk = kc;
+            }
+          }
+          gather(nm, nk);
         }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < P; i++) {
+          const v4i aop = *(const v4i *)(A + w * LD::XS + i * LD::PS + n * FD_RS + 4 * h);
+#pragma unroll
+          for (int j = 0; j < P; j++)
+            acc[m][i + j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aop, wop[j], acc[m][i + j], 0, 0, 0);
+        }
+        if (m + 1 == MP) load_w(kc + 1 < K ? kc + 1 : 0);
+        __syncthreads();
       }
     }
-    __syncthreads();
+    // group done: lane holds rows (ciphertexts) 4 h + v of column n = (giant
+    // n % 8, polynomial n / 8) of every tile of the group
+#pragma unroll
+    for (int m = 0; m < MP; m++) {
+      const int mt = mt0 + m;
+      u64 res[4];
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        u128 S = 0;   // the exact signed sum in two's complement mod 2^128
+#pragma unroll
+        for (int cidx = 0; cidx < NS; cidx++) S += (u128)(__int128)(long long)acc[m][cidx][v] << (8 * cidx);
+        const long long hi = (long long)(u64)(S >> 64);
+        const u64 lo = (u64)S;
+        // |S| < 2^87 (P = 5) or 2^127 (P = 8): |hi| < 2^23, or below 8 q (q > 2^59)
+        u64 hm;
+        if (P == 5)
+          hm = hi < 0 ? (u64)(hi + (long long)pi.q) : (u64)hi;
+        else
+          hm = reduce64((u64)(hi + 8 * (long long)pi.q), pi.q, pi.mu);
+        res[v] = redc(lo, hm, pi.q, pi.qn);
+      }
+#pragma unroll
+      for (int k = 0; k < NS; k++) acc[m][k] = v4i{0, 0, 0, 0};
+      u64 *O = (u64 *)A;   // the staging area is free: every wave passed the last barrier
+#pragma unroll
+      for (int v = 0; v < 4; v++) O[w * LD::OS + (4 * h + v) * 16 + n] = res[v];
+      __syncthreads();
+      {
+        const int xi = t & 7, col = (t >> 3) & 15, rq = t >> 7, x = xb * MF_XB + xi;
+        const int gg = col & 7, pol = col >> 3;
+        if (gg < ng) {
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const int row = 4 * rq + k, c = mt * 16 + row;
+            if (c >= batch) continue;
+            u64 v = O[xi * LD::OS + row * 16 + col];
+            u64 *o = X + (size_t)c * x_bs + ((size_t)(gg * 2 + pol) * G.pqn + r) * N + x;
+            if (accum) v = add_mod(v, *o, pi.q);
+            *o = v;
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
 }
 
-template <int P>
-__global__ __launch_bounds__(MF_TPB, 2) void baby_fold_kernel(FoldRun FR, LevelGeom G, int L, int batch,
-                                                               LimbSel ls, const uint32_t *E, size_t e_bs,
-                                                               size_t e_half, const uint8_t *wm, int ng, u64 *X,
-                                                               size_t x_bs, int accum, const PrimeInfo *pinfo,
-                                                               const u64 *chain) {
+template <int P, int MP>
+__global__ __launch_bounds__(MF_TPB, MP == 1 ? 2 : 1) void baby_fold_kernel(FoldRun FR, LevelGeom G, int L,
+                                                                             int batch, LimbSel ls,
+                                                                             const uint32_t *E, size_t e_bs,
+                                                                             size_t e_half, const uint8_t *wm,
+                                                                             int ng, u64 *X, size_t x_bs, int accum,
+                                                                             const PrimeInfo *pinfo,
+                                                                             const u64 *chain) {
   __shared__ __align__(16) uint32_t A[FoldLds<P>::WORDS];
   __shared__ unsigned sgal[HELRM_MAX_BABY];   // the rotations' Galois elements, read with LDS latency
   static_assert(FoldLds<P>::WORDS * 4 >= MF_XB * FoldLds<P>::OS * 8, "result staging fits");
@@ -1320,13 +1345,9 @@ __global__ __launch_bounds__(MF_TPB, 2) void baby_fold_kernel(FoldRun FR, LevelG
   const TileMap tm = chain_map(blockIdx.x, N / MF_XB, 1, ls.n, G.limb_xcd, chain);
   const int r = ls.r[tm.r];
   const PrimeInfo pi = pinfo[pq_prime_dev(r, G.level, L)];
-  // one workgroup takes every row tile of its coefficient block, one tile per
-  // pass.  Sharing the folded operand loads over 2 or 4 tiles per pass (MP)
-  // holds MP x (2P - 1) accumulator tiles; the occupancy lost to them cost
-  // more than the repeated loads (at 64 ciphertexts: 53.5 ms with one tile,
-  // 58-61 ms with 2 or 4), and so did dealing the row tiles over workgroups
-  baby_fold_body<P>(A, sgal, FR, G, batch, tm.xb, r, pi, E, e_bs, e_half, wm, ng, X, x_bs, accum, 0,
-                    (batch + 15) / 16);
+  // one workgroup takes every row tile of its coefficient block
+  baby_fold_body<P, MP>(A, sgal, FR, G, batch, tm.xb, r, pi, E, e_bs, e_half, wm, ng, X, x_bs, accum, 0,
+                        (batch + 15) / 16);
 }
 
 // The entries of every ciphertext once, before the folded product gathers
@@ -1976,12 +1997,17 @@ int launch_baby_mac(helrm_ctx *ctx, const helrm_plan *plan, const u64 *digits, s
       if (ls.n == 0) continue;
       const int grid = (ctx->N / MF_XB) * ls.n;
       const u64 *chain = ctx->tune_block_chain ? ctx->d_block_chain : nullptr;
-      if (wide)
-        hipLaunchKernelGGL((baby_fold_kernel<8>), dim3(grid), dim3(MF_TPB), 0, s, FR, G, ctx->L, batch, ls, fold_ws,
-                           e_bs, e_half, wm, ng, X, x_bstride, accum ? 1 : 0, ctx->d_pinfo, chain);
-      else
-        hipLaunchKernelGGL((baby_fold_kernel<5>), dim3(grid), dim3(MF_TPB), 0, s, FR, G, ctx->L, batch, ls, fold_ws,
-                           e_bs, e_half, wm, ng, X, x_bstride, accum ? 1 : 0, ctx->d_pinfo, chain);
+      // row tiles per group (knob), 1 when the batch has a single tile
+      const bool two = batch > 16 && ((ctx->tune_fold_mp >> wide) & 1);
+#define FOLDK(P_, MP_)                                                                                       \
+  hipLaunchKernelGGL((baby_fold_kernel<P_, MP_>), dim3(grid), dim3(MF_TPB), 0, s, FR, G, ctx->L, batch, ls,  \
+                     fold_ws, e_bs, e_half, wm, ng, X, x_bstride, accum ? 1 : 0, ctx->d_pinfo, chain)
+      if (wide) {
+        if (two) FOLDK(8, 2); else FOLDK(8, 1);
+      } else {
+        if (two) FOLDK(5, 2); else FOLDK(5, 1);
+      }
+#undef FOLDK
     }
   } else if (mfma) {
     // batched plaintext MAC on the matrix cores: one launch per digit count

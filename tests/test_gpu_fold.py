@@ -161,3 +161,36 @@ def test_block_chain_order_off():
     assert_bit_exact(outs[(0, "fold")][0], O.lookup(prm, w.keys, w.plan, w.cts[0], pts), "query 0")
     ctx.close()
 
+
+
+@pytest.mark.parametrize("shape", ["toy", "table1"])
+def test_fold_two_tiles_per_operand_load(shape):
+    """Two row tiles of 16 ciphertexts per load of the folded operands (knob
+    fold_mp on both digit counts) give the residues of one tile per load: toy
+    ring at level 2, batch 40 (tiles 16, 16, 8: the second group holds a
+    partial and an absent tile), and the Table I shape at level 1, batch 33
+    (two depth chunks); the last query against the oracle."""
+    prm = O.config1_params()
+    if shape == "toy":
+        g = synth.rng(0)
+        t = W.compressed_table(g, 256, 16, 16, -1.0, 1.0)
+        w = W.build(prm, [t], level=2, n1=4, radix=2, n_queries=40)
+    else:
+        w = W.table1_shape(prm, 1, n_queries=33)
+    ctx = context_for(prm)
+    load_keys(ctx, w.keys)
+    plan = gpu_plan(ctx, w.plan)
+    plan.helrm_plan_fold_keys()
+    outs = {}
+    try:
+        for mp in (0, 3):
+            ctx.helrm_set_tuning("fold_mp", mp)
+            say(f"{shape}: fold_mp {mp}, batch {len(w.cts)}")
+            outs[mp] = _run(ctx, plan, w.cts, w.level, prm.N, FOLD)
+    finally:
+        ctx.helrm_set_tuning("fold_mp", 2)
+    assert_bit_exact(outs[3], outs[0], "fold_mp 3 vs 0")
+    last = len(w.cts) - 1
+    pts = O.plan_residues(prm, w.plan)
+    assert_bit_exact(outs[3][last], O.lookup(prm, w.keys, w.plan, w.cts[last], pts), f"query {last}")
+    ctx.close()

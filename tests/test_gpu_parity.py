@@ -171,11 +171,11 @@ def test_tuning_knobs_validate(p1):
             "ntt_blk_w": [0, 4, 8], "ntt_small_limbs": [0, 48], "gen_key_a": [0, 1, 2], "limb_xcd": [0, 1],
             "fuse_ks": [0, 1], "fuse_conv": [0, 1], "conv_wgs": [0, 2048], "ks_chain": [0, 1],
             "block_chain": [0, 1], "baby_mfma": [0, 8], "baby_fold": [0, 8], "ptm": [0, 1],
-            "mfma_min_slots": [0, 64, 33]}
+            "mfma_min_slots": [0, 64, 33], "fold_mp": [0, 3, 2]}
     bad = {"ks_tile": [0, 3, 8], "baby_tile": [0, 3], "baby_share": [0, 3, 16], "ntt_col_w": [4, 32],
            "ntt_blk_w": [2, 16], "ntt_small_limbs": [-1], "gen_key_a": [-1, 3], "limb_xcd": [2],
            "fuse_ks": [2], "fuse_conv": [2, -1], "conv_wgs": [-1], "ks_chain": [2, -1], "block_chain": [2],
-           "baby_mfma": [-1], "baby_fold": [-1], "ptm": [2], "mfma_min_slots": [-1, 65]}
+           "baby_mfma": [-1], "baby_fold": [-1], "ptm": [2], "mfma_min_slots": [-1, 65], "fold_mp": [-1, 4]}
     for knob, vals in good.items():
         for v in vals:
             ctx.helrm_set_tuning(knob, v)
