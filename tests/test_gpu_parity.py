@@ -488,6 +488,23 @@ def test_lookup_multi_ciphertext_n16(ctx2):
     _check_multi(ctx2, w, [gpu_plan(ctx2, p) for p in w.plans], [0, 1])
 
 
+@pytest.mark.parametrize("n_ct,rows,batch", [(18, 12288, 2), (85, 58000, 1)])
+def test_lookup_multi_ciphertext_paper_scale(n_ct, rows, batch, p1):
+    """Selectors as wide as the paper's multi-ciphertext models (18 and 85
+    input ciphertexts, Sec. V-D and Table II) on the toy ring: three
+    uncompressed tables of `rows` rows each, every column block's products
+    summed into the same giant accumulators; bit-exact against the oracle and
+    decrypted against the cleartext rows."""
+    ctx = context_for(p1)
+    g = synth.rng(21)
+    tables = [W.uncompressed_table(g, rows, 16, -1, 1) for _ in range(3)]
+    w = W.build_multi(p1, tables, level=2, n1=16, radix=4, n_queries=batch)
+    assert len(w.plans) == n_ct
+    load_keys(ctx, w.keys)
+    _check_multi(ctx, w, [gpu_plan(ctx, p) for p in w.plans], list(range(batch)))
+    ctx.close()
+
+
 def test_graph_capture_replays(ctx1, w1):
     """The batched lookup captured in a HIP graph: every replay (with eager
     work and synchronisation between replays) equals the eager result."""
