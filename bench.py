@@ -482,6 +482,7 @@ def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int =
         for b in range(1, max_batch + 1):
             wx.launch(0, g, [Unit(None, g, pool[g][k % len(pool[g])], 0.0) for k in range(b)])
     torch.cuda.synchronize()
+    wx.close()
     del wx
     out = {"rates": []}
     rg = synth.rng(seed)
@@ -504,6 +505,7 @@ def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int =
             looked = sum(specs[r.rid][1] for r in srv.completed)
             rep["lookups_per_s"] = looked / rep["span_s"] if rep["span_s"] > 0 else 0.0
             row[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in rep.items()}
+            ex.close()
             del ex, srv
             torch.cuda.synchronize()
         for mode in ("served", "served_mixed"):

@@ -295,6 +295,14 @@ int helrm_footprint(const helrm_ctx *ctx, const helrm_plan *plan, int batch, siz
  * it stay valid until helrm_destroy. */
 int helrm_reserve(helrm_ctx *ctx, const helrm_plan *plan, int batch, void *stream);
 
+/* Give back the workspace of `stream` (for callers that retire a stream, such
+ * as a serving executor that is replaced): waits for the stream, then frees
+ * its workspace; a workspace that a graph capture used is kept until
+ * helrm_destroy instead, since the graph may still be replayed.  A later call
+ * on the stream allocates afresh.  No-op for a stream without a workspace.
+ * Errors: HELRM_ESTATE while the stream is being captured, HELRM_EHIP. */
+int helrm_release_stream(helrm_ctx *ctx, void *stream);
+
 /* helrm_footprint / helrm_reserve for helrm_lookup_multi: the workspace of
  * one call with these plans (the same checks as helrm_lookup_multi), which
  * also holds the ModUp digits of every giant step in the union of the plans'.

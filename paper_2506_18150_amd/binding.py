@@ -53,7 +53,8 @@ EXPORTS = [
     "helrm_ntt", "helrm_intt", "helrm_automorph", "helrm_poly_op", "helrm_mul_scalar",
     "helrm_from_signed", "helrm_keyswitch_hoisted", "helrm_rescale", "helrm_plan_create",
     "helrm_plan_destroy", "helrm_plan_rotation_steps", "helrm_ptxt_ct_matvec_diag",
-    "helrm_lookup_packed", "helrm_footprint", "helrm_reserve", "helrm_timing_enable", "helrm_timing_read",
+    "helrm_lookup_packed", "helrm_footprint", "helrm_reserve", "helrm_release_stream", "helrm_timing_enable",
+    "helrm_timing_read",
     "helrm_set_tuning", "helrm_mul_relin", "helrm_add_plain", "helrm_mod_drop", "helrm_lookup_multi",
     "helrm_key_uniform", "helrm_footprint_multi", "helrm_reserve_multi", "helrm_batch_graph_create",
     "helrm_batch_graph_replay", "helrm_batch_graph_destroy", "helrm_lookup_packed_noalloc",
@@ -95,6 +96,7 @@ def lib() -> ctypes.CDLL:
     L.helrm_calibrate_alu.argtypes = [_vp, _c_int, _c_int, _vp, ctypes.POINTER(ctypes.c_double)]
     L.helrm_footprint.argtypes = [_vp, _vp, _c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.helrm_reserve.argtypes = [_vp, _vp, _c_int, _vp]
+    L.helrm_release_stream.argtypes = [_vp, _vp]
     L.helrm_timing_enable.argtypes = [_vp, _c_int]
     L.helrm_set_tuning.argtypes = [_vp, ctypes.c_char_p, _c_int]
     L.helrm_mul_relin.argtypes = [_vp, _vp, _vp, _c_int, _vp, _c_int, _vp]
@@ -265,6 +267,9 @@ class Context:
 
     def helrm_reserve(self, plan: "Plan", batch: int, stream=None):
         _check(lib().helrm_reserve(self.h, plan.h, batch, _stream(stream)))
+
+    def helrm_release_stream(self, stream=None):
+        _check(lib().helrm_release_stream(self.h, _stream(stream)))
 
     def helrm_footprint_multi(self, plans: Sequence["Plan"], batch: int) -> int:
         arr = (_vp * len(plans))(*[p.h for p in plans])

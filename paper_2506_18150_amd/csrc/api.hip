@@ -1899,6 +1899,36 @@ extern "C" int helrm_reserve(helrm_ctx *c, const helrm_plan *p, int batch, void 
   API_GUARD_END
 }
 
+extern "C" int helrm_release_stream(helrm_ctx *c, void *stream) {
+  API_GUARD_BEGIN
+  CHECK_ARG(c, "NULL context");
+  const hipStream_t s = as_stream(stream);
+  std::lock_guard<std::mutex> lk(c->ws_mu);
+  auto it = c->ws.find(s);
+  if (it == c->ws.end()) return HELRM_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    cs = hipStreamCaptureStatusNone;
+  }
+  if (cs != hipStreamCaptureStatusNone) {
+    set_error("the stream is being captured: its workspace cannot be released");
+    return HELRM_ESTATE;
+  }
+  Workspace &w = it->second;
+  if (w.ptr) {
+    if (w.captured) {
+      c->ws_retired.push_back(w.ptr);   // a captured graph may still use it
+    } else {
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipFree(w.ptr));
+    }
+  }
+  c->ws.erase(it);
+  return HELRM_OK;
+  API_GUARD_END
+}
+
 // Plans of one multi-ciphertext lookup: same context, level, m, n1, n2,
 // direction, fold radix and span.
 static int check_multi_plans(const helrm_ctx *c, const helrm_plan *const *plans, int n_in) {

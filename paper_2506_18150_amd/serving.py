@@ -412,6 +412,15 @@ class GpuExecutor(Executor):
                 ctx.helrm_reserve(p, max_batch, self.streams[s])
             ctx.helrm_reserve_batch(self.mix_plans, self.streams[s])
 
+    def close(self):
+        """Wait for this executor's streams and give their workspaces back to
+        the library (an executor that is replaced by another would otherwise
+        leave them allocated until the context is destroyed)."""
+        for st in self.streams:
+            st.synchronize()
+            self.ctx.helrm_release_stream(st)
+        self.resident.clear()
+
     def admit(self, req):
         torch = self.torch
         with torch.cuda.stream(self.copy_stream):

@@ -61,3 +61,14 @@ def test_results_same_alone_and_in_the_mix():
             got = dep.decrypt_group(gg, r.results[gg].cuda())
             want = dep.cleartext_group(gg, touched_of[r.rid])
             assert np.max(np.abs(got - want)) < 1e-4
+    say("serving: executor closed (workspaces released); a new one with mixed groups serves the requests again")
+    ex.close()
+    ex2 = GpuExecutor(dep.ctx, dep.plans, level, prm.N, n_streams=2, max_batch=4)
+    srv2 = Server(ex2, RealClock(), len(dep.groups), hbm_budget=200 << 30, max_batch=4, mix_groups=True)
+    reqs2 = [Request(rid=r.rid, arrival=r.arrival, units=r.units) for r in reqs]
+    rep2 = srv2.run(reqs2)
+    assert rep2["completed"] == 12
+    for r, r2 in zip(reqs, reqs2):
+        for gg, _ in r.units:
+            assert torch.equal(r2.results[gg].reshape(-1), r.results[gg].reshape(-1)), f"request {r.rid} group {gg}"
+    ex2.close()
