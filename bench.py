@@ -118,6 +118,8 @@ def parse():
                     help="w7: tables of at most this many rows stay uncompressed (selector slots grow)")
     ap.add_argument("--level", type=int, default=None, help="selector level (default 23; 1 for w6)")
     ap.add_argument("--d", type=int, default=768, help="w6: embedding width (rows of the lookup; Table I: 768)")
+    ap.add_argument("--vocab", type=int, default=0,
+                    help="w6: a token-embedding table of this many rows (base-256 digits) instead of the Table I shape")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--n1", type=int, default=None)
     ap.add_argument("--radix", type=int, default=None)
@@ -158,14 +160,21 @@ def parse():
     return ap.parse_args()
 
 
-def make_tables(workload: str, synth, planner, threshold: int = 256, d: int = 768):
+def make_tables(workload: str, synth, planner, threshold: int = 256, d: int = 768, vocab: int = 0):
     """Seeded synthetic tables.  w2: one 65,536-row table as two base-256
     digit tables.  w3: 26 tables with log-uniform row counts (the first seed
-    whose total lies in [3.0e7, 3.8e7])."""
+    whose total lies in [3.0e7, 3.8e7]).  w6: the Table I shape (32 base-16
+    digit tables of 16 x d), or with `vocab` a token-embedding table of that
+    many rows as base-256 digit tables of 256 x d (50,257 rows: 2 digits, 512
+    selector slots)."""
     g = synth.rng(0)
     if workload == "w2":
         parts = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(2)]
         return [planner.Table(rows=65536, d=16, base=256, parts=parts)]
+    if workload == "w6" and vocab:
+        nd = planner.n_digits(vocab, 256)
+        parts = [synth.uniform_table(g, 256, d, -0.05, 0.05) for _ in range(nd)]
+        return [planner.Table(rows=vocab, d=d, base=256, parts=parts)]
     if workload == "w6":
         parts = [synth.uniform_table(g, 16, d, -0.05, 0.05) for _ in range(32)]
         return [planner.Table(rows=16 ** 32, d=d, base=16, parts=parts)]
@@ -656,7 +665,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     prm = params.n16()
-    tables = make_tables(args.workload, synth, planner, args.threshold, args.d)
+    tables = make_tables(args.workload, synth, planner, args.threshold, args.d, args.vocab)
     M = planner.packed_matrix(tables)
     dflt = DEFAULTS[args.workload]
     B = args.batch or dflt["batch"]
@@ -758,6 +767,8 @@ def main():
         "config": {"workload": f"{args.workload}: N=2^16, L=23, dnum=3, K=8; {len(tables)} table(s), packed "
                                f"{M.shape[0]}x{M.shape[1]}"
                                + (f" in {sess.n_in} selector ciphertexts" if sess.n_in > 1 else "")
+                               + (f" (a {args.vocab}-token embedding table, d={args.d}, base-256 digits)"
+                                  if args.workload == "w6" and args.vocab else "")
                                + f"; selector at level {args.level}; n1={n1}, fold radix "
                                f"{radix}, rotation sign {sign} (fold span {spec.span}); batch {B} ciphertext(s) per "
                                f"call" + (", HIP graph replay" if args.graph else ""),
