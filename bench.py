@@ -137,6 +137,8 @@ def parse():
     ap.add_argument("--autotune-out", default=None, help="write the tuning record to this file")
     ap.add_argument("--graph", action="store_true", help="replay one captured HIP graph per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", default="0,1",
+                    help="host threads of the oracle timings (0 = all; the first is cpu_baseline)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-fold", action="store_true",
                     help="do not fold the keys into plans of several giant steps (batched matrix-core product)")
@@ -191,7 +193,8 @@ def make_tables(workload: str, synth, planner, threshold: int = 256, d: int = 76
     return tables
 
 
-def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int, threads=(0,), d: int = 768):
+def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int, threads=(0,), d: int = 768,
+                 vocab: int = 0):
     """The CPU oracle on one selector ciphertext of the same workload (keys,
     plan encoding and encryption untimed), once per entry of `threads` (0 =
     every host thread OpenMP sees)."""
@@ -206,6 +209,9 @@ def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int, thre
     if workload == "w2":
         C = [synth.uniform_table(g, 256, 16, -0.05, 0.05) for _ in range(2)]
         tables = [O.TableSpec(rows=65536, d=16, base=256, C=C)]
+    elif workload == "w6" and vocab:
+        C = [synth.uniform_table(g, 256, d, -0.05, 0.05) for _ in range(O.num_digits(vocab, 256))]
+        tables = [O.TableSpec(rows=vocab, d=d, base=256, C=C)]
     elif workload == "w6":
         C = [synth.uniform_table(g, 16, d, -0.05, 0.05) for _ in range(32)]
         tables = [O.TableSpec(rows=16 ** 32, d=d, base=16, C=C)]
@@ -220,11 +226,13 @@ def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int, thre
                 tables.append(O.TableSpec(rows=k, d=16, base=256, C=C))
     plan = O.make_plan(prm, O.pack_tables(tables), level, n1, radix, sign)
     gals = [O.galois_for_step(k, prm) for k in plan.rotation_steps()]
+    print(f"cpu baseline: oracle keys for {len(gals)} rotations", file=sys.stderr, flush=True)
     keys = O.keygen(prm, synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals))
     qg = synth.rng(1)
     idx = synth.indices(qg, [t.rows for t in tables])
     ct = O.encrypt(prm, keys, O.encode(O.pack_selector(tables, idx), prm.delta, prm), level,
                    synth.enc_draws(qg, prm.N))
+    print("cpu baseline: oracle plan residues", file=sys.stderr, flush=True)
     pts = O.plan_residues(prm, plan)
     rows = sum(t.d for t in tables)
     ref = np.concatenate([t.lookup(i) for t, i in zip(tables, idx)])
@@ -234,6 +242,7 @@ def cpu_baseline(workload: str, level: int, n1: int, radix: int, sign: int, thre
     for nt in threads:
         nt = all_cores if nt == 0 else nt
         O.set_threads(nt)
+        print(f"cpu baseline: oracle lookup on {nt} thread(s)", file=sys.stderr, flush=True)
         with threadpool_limits(limits=nt):
             t0 = time.perf_counter()
             out = O.lookup(prm, keys, plan, ct, pts)
@@ -915,9 +924,11 @@ def main():
                          "served_vs_plain": row["served_vs_plain"],
                          "served_mixed_vs_plain": row["served_mixed_vs_plain"], "what": srv["what"]}
     if not args.no_cpu_baseline and args.workload != "w7":
-        cb = cpu_baseline(args.workload, args.level, n1, radix, sign, threads=(0, 1), d=args.d)
+        cb = cpu_baseline(args.workload, args.level, n1, radix, sign,
+                          threads=tuple(int(x) for x in args.cpu_threads.split(",")), d=args.d, vocab=args.vocab)
         res["cpu_baseline"] = cb[0]
-        res["cpu_baseline_single_thread"] = cb[1]
+        if len(cb) > 1:
+            res["cpu_baseline_" + ("single_thread" if cb[1]["cores"] == 1 else "threads_%d" % cb[1]["cores"])] = cb[1]
     print(json.dumps(res))
 
 
