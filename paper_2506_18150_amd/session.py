@@ -43,10 +43,21 @@ class LookupSession:
         self.client = Client(self.ctx, prm)
         self.client.keygen(key_draws_fn(self.galois), self.galois)
         self.folded_bytes = 0
+        self.folded_plans = 0
         if fold and prm.n_digits(level) <= 3:
+            from .binding import HelrmError
             for p, sp in zip(self.plans, self.specs):
-                if sp.n2 >= 2:
+                if sp.n2 < 2:
+                    continue
+                try:
                     self.folded_bytes += p.helrm_plan_fold_keys()
+                    self.folded_plans += 1
+                except HelrmError as e:
+                    if e.code != -2:   # HELRM_ENOMEM
+                        raise
+                    # out of device memory (a selector of many column blocks):
+                    # the remaining plans stay unfolded and take the other kernels
+                    break
 
     @property
     def out_slots(self) -> int:
