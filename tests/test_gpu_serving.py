@@ -65,7 +65,9 @@ def test_results_same_alone_and_in_the_mix():
     ex.close()
     ex2 = GpuExecutor(dep.ctx, dep.plans, level, prm.N, n_streams=2, max_batch=4)
     srv2 = Server(ex2, RealClock(), len(dep.groups), hbm_budget=200 << 30, max_batch=4, mix_groups=True)
-    reqs2 = [Request(rid=r.rid, arrival=r.arrival, units=r.units) for r in reqs]
+    # fresh requests with the original relative arrival times (a run turns
+    # each request's arrival into an absolute clock time)
+    reqs2 = [Request(rid=r.rid, arrival=0.0005 * r.rid, units=r.units) for r in reqs]
     rep2 = srv2.run(reqs2)
     assert rep2["completed"] == 12
     for r, r2 in zip(reqs, reqs2):
