@@ -461,7 +461,8 @@ int helrm_mod_drop(helrm_ctx *ctx, const uint64_t *in, int level_in, uint64_t *o
  * "mfma_min_slots" (0..64, default 33) baby steps (b = 0 included).  "baby_fold" (>= 0, default 8):
  * batches of at least this many use a plan's folded keys
  * (helrm_plan_fold_keys; 0: never).  "ptm" (1, default, or 0): plans keep the
- * plaintexts' matrix-core operands.  "block_chain" (1, default, or 0): the
+ * plaintexts' matrix-core operands (only plans created while their baby-step
+ * count is at least "mfma_min_slots": the others would never use them).  "block_chain" (1, default, or 0): the
  * key-folded product takes its coefficient blocks in the order in which the
  * baby-step rotations shift them (rotated words then come from L2), or in
  * plain order.  "fold_mp" (0..3, default 2): batches of more than 16

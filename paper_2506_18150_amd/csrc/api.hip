@@ -1624,8 +1624,10 @@ extern "C" int helrm_plan_create(helrm_ctx *c, const helrm_plan_desc *d, helrm_p
   if ((rc = launch_pack_pt(p->d_pt, p->pt_words, 0)) != HELRM_OK) return fail(rc);
   // matrix-core operands for batched launches of plans with several giant
   // steps: per giant tile of 8, the baby steps of the tile in the order the
-  // baby-step launch takes them (ascending, b = 0 first)
-  if (c->tune_ptm && d->n2 >= 2) {
+  // baby-step launch takes them (ascending, b = 0 first).  Plans with fewer
+  // baby steps than the matrix-core MAC's floor (mfma_min_slots, read here)
+  // would never use them and keep none
+  if (c->tune_ptm && d->n2 >= 2 && (int)p->babies.size() >= c->tune_mfma_min_slots) {
     const int tiles = (d->n2 + HELRM_MAX_GTILE - 1) / HELRM_MAX_GTILE;
     std::vector<int> tab((size_t)tiles * 64 * 8, -1);
     bool fits = true;

@@ -142,6 +142,9 @@ def test_block_chain_order_off():
     t = W.compressed_table(g, 256, 16, 16, -1.0, 1.0)
     w = W.build(prm, [t], level=2, n1=4, radix=2, n_queries=17)
     ctx = context_for(prm)
+    # four baby steps: below the matrix-core MAC's default floor, so lower it
+    # before the plan is made (the plan keeps matrix-core operands only then)
+    ctx.helrm_set_tuning("mfma_min_slots", 1)
     load_keys(ctx, w.keys)
     plan = gpu_plan(ctx, w.plan)
     plan.helrm_plan_fold_keys()
