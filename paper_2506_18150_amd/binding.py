@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libhelrm.so")
 
 HELRM_OK = 0
+HELRM_EINVAL, HELRM_ENOMEM, HELRM_EHIP, HELRM_ESTATE = -1, -2, -3, -4
 HELRM_OP_ADD, HELRM_OP_SUB, HELRM_OP_MUL, HELRM_OP_NEG = 0, 1, 2, 3
 HELRM_BASIS_Q, HELRM_BASIS_PQ = 0, 1
 HELRM_CAL_BUTTERFLY, HELRM_CAL_MAD_U64, HELRM_CAL_FMA_F64 = 0, 1, 2

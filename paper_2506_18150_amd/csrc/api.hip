@@ -1923,7 +1923,10 @@ extern "C" int helrm_release_stream(helrm_ctx *c, void *stream) {
       c->ws_retired.push_back(w.ptr);   // a captured graph may still use it
     } else {
       HIP_TRY(hipStreamSynchronize(s));
-      HIP_TRY(hipFree(w.ptr));
+      void *p = w.ptr;
+      c->ws.erase(it);   // forgotten before the free, so a failed free is never repeated
+      HIP_TRY(hipFree(p));
+      return HELRM_OK;
     }
   }
   c->ws.erase(it);

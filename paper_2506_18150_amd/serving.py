@@ -328,7 +328,10 @@ class Server:
         return not any(not r.closed for r in self.waiting) and not self.running and not any(self.queues)
 
     def run(self, requests: Sequence[Request]) -> Dict:
-        """Feed requests at their arrival times and run until all finish."""
+        """Feed requests at their arrival times (seconds after the call) and run
+        until all finish.  The requests are consumed: each one's arrival is
+        moved onto the server clock and its results, times and state are
+        filled in, so a second run takes fresh Request objects."""
         pending = sorted(requests, key=lambda r: r.arrival)
         i = 0
         t0 = self.clock.now()

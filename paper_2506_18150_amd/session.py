@@ -45,7 +45,7 @@ class LookupSession:
         self.folded_bytes = 0
         self.folded_plans = 0
         if fold and prm.n_digits(level) <= 3:
-            from .binding import HelrmError
+            from .binding import HELRM_ENOMEM, HelrmError
             for p, sp in zip(self.plans, self.specs):
                 if sp.n2 < 2:
                     continue
@@ -53,7 +53,7 @@ class LookupSession:
                     self.folded_bytes += p.helrm_plan_fold_keys()
                     self.folded_plans += 1
                 except HelrmError as e:
-                    if e.code != -2:   # HELRM_ENOMEM
+                    if e.code != HELRM_ENOMEM:
                         raise
                     # out of device memory (a selector of many column blocks):
                     # the remaining plans stay unfolded and take the other kernels
