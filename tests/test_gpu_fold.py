@@ -133,6 +133,24 @@ def test_fold_n16_level23_group():
     ctx.close()
 
 
+@pytest.mark.timeout(900)
+def test_fold_one_digit_n16_level1():
+    """One key-switching digit: the Table I shape (d = 768 from 32 base-16
+    digit tables, m = 1024 diagonals, n1 = 32, 32 giant outputs in four
+    tiles) at N=2^16 with the selector at level 1 (two Q primes, one digit,
+    the level of the token-embedding runs), batch 17 (row tiles of 16 and 1;
+    the wide primes share each operand load between the two)."""
+    prm = O.config2_params()
+    assert prm.n_digits(1) == 1
+    w = W.table1_shape(prm, 1, n_queries=17)
+    ctx = context_for(prm)
+    load_keys(ctx, w.keys)
+    plan = gpu_plan(ctx, w.plan)
+    assert plan.helrm_plan_fold_keys() > 0
+    _check(ctx, w, plan, [0, 16], "N=2^16 level 1")
+    ctx.close()
+
+
 def test_block_chain_order_off():
     """The matrix-core kernels with the workgroups in plain block order (knob
     block_chain = 0) give the same residues as in chain order: the folded
