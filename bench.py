@@ -15,8 +15,9 @@ Workloads (seeded synthetic data of the paper's shapes):
   w7  the w3 tables with the threshold rule of Table II: tables of at most
       --threshold rows stay uncompressed, so the packed selector spans several
       ciphertexts (50,000: 3 ciphertexts; 500,000: 20), selector at level 4.
-Other modes: --serve (continuous-batching request loop on the w3 tables in
-groups), --dlrm (batched end-to-end small DLRM).
+Other modes: --serve (continuous-batching request loop on the w3 tables: one
+packed plan for all 26, or --group-size tables per plan), --dlrm (batched
+end-to-end small DLRM).
 A step is one helrm_lookup_packed call over one batch of selector ciphertexts
 already resident in HBM; a lookup is one (query, table) embedding row.
 
@@ -37,6 +38,7 @@ import json
 import os
 import sys
 import time
+from typing import Optional
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -148,9 +150,10 @@ def parse():
                     help="also time this batch size on the same plan and keys (0 to skip)")
     ap.add_argument("--serve", action="store_true",
                     help="run the request loop (26 tables in groups, Poisson arrivals) instead of the step loop")
-    ap.add_argument("--rates", default="5,20,50,100,200", help="arrival rates (requests/s) for --serve")
+    ap.add_argument("--rates", default="50,100,200,400", help="arrival rates (requests/s) for --serve")
     ap.add_argument("--requests", type=int, default=200, help="requests per rate for --serve")
-    ap.add_argument("--group-size", type=int, default=4)
+    ap.add_argument("--group-size", type=int, default=26,
+                    help="--serve: tables per packed plan (26: one plan and one ciphertext per request)")
     ap.add_argument("--max-batch", type=int, default=16)
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--dlrm", action="store_true",
@@ -459,14 +462,19 @@ def w3_batched(prm, batch: int, steps: int) -> dict:
     return res
 
 
-def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int = 16, radix: int = 8,
-                sign: int = -1, streams: int = 2, max_batch: int = 16, seed: int = 12, knobs=()) -> dict:
+def serving_run(level: int, rates, requests: int, group_size: int = 26, n1: Optional[int] = None, radix: int = 8,
+                sign: int = -1, streams: int = 2, max_batch: int = 16, seed: int = 12, knobs=(),
+                fold: bool = True) -> dict:
     """The request loop on the 26-table set: tables in fixed groups of
-    group_size, one selector ciphertext per touched group, Poisson arrivals,
-    each request touching r ~ U{1..26} distinct tables.  Selector ciphertexts
-    wait in pinned host memory (a pool per group, encrypted before the run:
-    cost is data-oblivious) and are copied in and out by the loop.  Compared
-    with the plain per-request path: one stream, one ciphertext per call."""
+    group_size (26: one plan for the whole set, one ciphertext per request),
+    one selector ciphertext per touched group, Poisson arrivals, each request
+    touching r ~ U{1..26} distinct tables.  Selector ciphertexts wait in
+    pinned host memory (a pool per group, encrypted before the run: cost is
+    data-oblivious) and are copied in and out by the loop.  Compared with the
+    plain per-request path: one stream, one ciphertext per call.  fold: keys
+    folded into the plans of several giant steps (batches of 8 and more).
+    n1 (baby steps) defaults to 64 for the one plan of all 26 tables (the
+    batching workload's tuned value) and 16 for the smaller group plans."""
     import torch
 
     import synth
@@ -476,11 +484,16 @@ def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int =
 
     prm = params.n16()
     tables = make_tables("w3", synth, planner)
+    if n1 is None:
+        n1 = 64 if group_size >= len(tables) else 16
     t0 = time.time()
     dep = GroupedDeployment(prm, tables, group_size, level, n1, radix,
-                            lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals), sign=sign)
+                            lambda gals: synth.key_draws(0, prm.N, prm.q, prm.p, prm.dnum, gals), sign=sign,
+                            fold=fold and max_batch >= 8)
     for name, v in knobs:
         dep.ctx.helrm_set_tuning(name, v)
+    print(f"serve: {len(dep.groups)} group plan(s) at level {level}, {dep.folded_plans} folded, "
+          f"{time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     eg = synth.rng(11)
     pool = []
     for g, grp in enumerate(dep.groups):
@@ -492,7 +505,7 @@ def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int =
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     total = torch.cuda.get_device_properties(0).total_memory
-    static = dep.key_bytes + dep.plan_bytes
+    static = dep.key_bytes + dep.plan_bytes + dep.folded_bytes
     # warm-up: every group at every batch size the served mode can form, so
     # that no first launch of a kernel falls inside a measured span
     wx = GpuExecutor(dep.ctx, dep.plans, level, prm.N, n_streams=1, max_batch=max_batch, static_bytes=static)
@@ -515,6 +528,7 @@ def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int =
         row = {"rate": rate}
         for mode, ns, mb, mix in (("served", streams, max_batch, False), ("served_mixed", streams, max_batch, True),
                                   ("plain", 1, 1, False)):
+            print(f"serve: rate {rate}, {mode}", file=sys.stderr, flush=True)
             ex = GpuExecutor(dep.ctx, dep.plans, level, prm.N, n_streams=ns, max_batch=mb, static_bytes=static)
             srv = Server(ex, RealClock(), len(dep.groups), hbm_budget=int(total * 0.9), max_batch=mb,
                          admit_timeout=30.0, mix_groups=mix)
@@ -531,9 +545,12 @@ def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int =
                                        if row["plain"]["lookups_per_s"] else None)
         out["rates"].append(row)
     out.update(setup_s=round(setup_s, 1), groups=len(dep.groups), level=level, group_size=group_size,
-               requests=requests, resident_bytes={"keys": dep.key_bytes, "plans": dep.plan_bytes},
+               requests=requests, n1=min(n1, max(sp.m for sp in dep.specs)), radix=radix, sign=sign,
+               folded_plans=dep.folded_plans,
+               resident_bytes={"keys": dep.key_bytes, "plans": dep.plan_bytes, "folded": dep.folded_bytes},
                what=(f"w5: 26 tables (w3 set) in {len(dep.groups)} groups of {group_size}, selectors at level "
-                     f"{level}, Poisson arrivals, {requests} requests per rate, r ~ U{{1..26}} tables per request; "
+                     f"{level}, Poisson arrivals, {requests} requests per rate, r ~ U{{1..26}} tables per request, "
+                     f"one selector ciphertext per touched group; "
                      f"served: {streams} streams, batches of up to {max_batch} units of one group; served_mixed: the "
                      f"same with units of any groups in one launch (helrm_lookup_batch); plain: 1 stream, 1 "
                      f"ciphertext per call; latency = arrival to result on the host"))
@@ -544,8 +561,9 @@ def serving_run(level: int, rates, requests: int, group_size: int = 4, n1: int =
 def serve_bench(args):
     """--serve: the request loop at several arrival rates (one JSON line)."""
     out = serving_run(args.level, [float(x) for x in args.rates.split(",")], args.requests, args.group_size,
-                      args.n1 or 16, args.radix or 8, args.sign or -1, args.streams, args.max_batch,
-                      knobs=tuple((kv.split("=")[0], int(kv.split("=")[1])) for kv in args.knob))
+                      args.n1, args.radix or 8, args.sign or -1, args.streams, args.max_batch,
+                      knobs=tuple((kv.split("=")[0], int(kv.split("=")[1])) for kv in args.knob),
+                      fold=not args.no_fold)
     best = max(out["rates"], key=lambda r: r["served"]["lookups_per_s"])
     res = {
         "metric": "served encrypted lookups/s",
@@ -916,7 +934,7 @@ def main():
         res["level_sweep"] = level_sweep(prm, tables, [4, 1], n1, radix, sign, key_fn, max(10, args.steps))
         res["level_sweep"]["23"] = {"lookups_per_s": value, "ms_per_lookup": ms_per_step, "max_abs_err": err}
         res["batched_w3"] = w3_batched(prm, 64, 3)
-        srv = serving_run(23, [100.0], 240)
+        srv = serving_run(23, [400.0], 240)
         row = srv["rates"][0]
         keep = ("lookups_per_s", "p50_ms", "p99_ms", "mean_batch", "completed", "rejected", "span_s")
         res["served"] = {"rate_per_s": row["rate"], "requests": srv["requests"],

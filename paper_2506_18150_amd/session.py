@@ -109,7 +109,10 @@ class GroupedDeployment:
     get an all-zero one-hot block (their rows come out as zeros)."""
 
     def __init__(self, prm: ParamSet, tables: Sequence[planner.Table], group_size: int, level: int, n1: int,
-                 radix: int, key_draws_fn, sign: int = -1):
+                 radix: int, key_draws_fn, sign: int = -1, fold: bool = False):
+        """fold: fold the keys into the plans of several giant steps, for
+        batches of 8 and more on the matrix cores (helrm_plan_fold_keys);
+        plans that no longer fit in device memory stay unfolded."""
         self.prm, self.level = prm, level
         self.tables = list(tables)
         self.groups = [list(range(i, min(i + group_size, len(tables)))) for i in range(0, len(tables), group_size)]
@@ -131,6 +134,20 @@ class GroupedDeployment:
         # per key: Montgomery-form words plus the 40-bit planes of the b halves
         self.key_bytes = len(self.galois) * prm.dnum * kl * prm.N * (16 + 5)
         self.plan_bytes = sum(len(sp.diag) * (level + 1 + prm.K) * prm.N * (8 + 5) for sp in self.specs)
+        self.folded_bytes = 0
+        self.folded_plans = 0
+        if fold and prm.n_digits(level) <= 3:
+            from .binding import HELRM_ENOMEM, HelrmError
+            for p, sp in zip(self.plans, self.specs):
+                if sp.n2 < 2:
+                    continue
+                try:
+                    self.folded_bytes += p.helrm_plan_fold_keys()
+                    self.folded_plans += 1
+                except HelrmError as e:
+                    if e.code != HELRM_ENOMEM:
+                        raise
+                    break
 
     def group_of(self, table: int) -> int:
         for g, grp in enumerate(self.groups):
