@@ -41,6 +41,9 @@
  *     stream, grown on demand (growing synchronises that stream).  Work for
  *     one context on one stream is serialised; different streams get
  *     different workspaces and may overlap.
+ *   - An empty call (batch 0, or no limbs or rotations) checks the context
+ *     and sizes, may take NULL buffers, enqueues nothing and returns HELRM_OK;
+ *     a batch graph needs at least one element (HELRM_EINVAL).
  *   - Return value: HELRM_OK (0) or a negative code; helrm_last_error()
  *     returns a thread-local description of the last failure.  No C++
  *     exception crosses this interface and the library never aborts.

@@ -1334,7 +1334,7 @@ extern "C" int helrm_automorph(helrm_ctx *c, const uint64_t *in, uint64_t *out, 
   CHECK_ARG(n_limbs >= 0 && batch >= 0, "negative size");
   CHECK_ARG(n_limbs * batch == 0 || (in && out), "NULL buffer");
   CHECK_ARG((galois & 1u) && galois < 2u * c->N, "galois element must be odd and < 2N");
-  CHECK_ARG(in != out, "in and out must differ");
+  CHECK_ARG(n_limbs * batch == 0 || in != out, "in and out must differ");
   return launch_automorph(c, in, out, galois, n_limbs, batch, as_stream(stream));
   API_GUARD_END
 }
@@ -1364,6 +1364,7 @@ extern "C" int helrm_mul_scalar(helrm_ctx *c, const uint64_t *a, const uint64_t 
   CHECK_ARG(batch >= 0, "batch < 0");
   TRY(check_primes(c, n_limbs, pidx));
   CHECK_ARG(n_limbs * batch == 0 || (a && out && scalars), "NULL buffer");
+  if (n_limbs * batch == 0) return HELRM_OK;   // before the scalars are read: they may be NULL
   for (int i0 = 0; i0 < n_limbs; i0 += 64) {
     const int n = std::min(64, n_limbs - i0);
     LimbList ll = ll_from_primes(c, n, pidx + i0, i0);

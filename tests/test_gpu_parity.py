@@ -162,6 +162,51 @@ def test_automorph_parity(p1, p2, ctx1, ctx2):
                 assert_bit_exact(got[b], O.automorph_ntt(x[b], g, prm.N), "automorph")
 
 
+def test_empty_calls_enqueue_nothing(ctx1, w1):
+    """Every call that takes a batch accepts an empty one (batch 0, or no
+    limbs or rotations) with NULL buffers and returns HELRM_OK without
+    enqueueing work; a batch graph needs an element.  The context keeps
+    working: a lookup afterwards matches the oracle."""
+    import ctypes
+    from paper_2506_18150_amd import binding as B
+    L = B.lib()
+    h, lv = ctx1.h, w1.level
+    pidx = np.arange(3, dtype=np.int32)
+    pp = pidx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    steps = np.array([1], dtype=np.int32)
+    sp = steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    plan = gpu_plan(ctx1, w1.plan)
+    plans = (ctypes.c_void_p * 1)(plan.h.value if hasattr(plan.h, "value") else plan.h)
+    calls = {
+        "ntt, batch 0": lambda: L.helrm_ntt(h, None, 3, pp, 0, None),
+        "ntt, no limbs": lambda: L.helrm_ntt(h, None, 0, None, 4, None),
+        "intt, batch 0": lambda: L.helrm_intt(h, None, 3, pp, 0, None),
+        "automorph": lambda: L.helrm_automorph(h, None, None, 5, 3, 0, None),
+        "poly_op": lambda: L.helrm_poly_op(h, B.HELRM_OP_ADD, None, None, None, 3, pp, 0, None),
+        "mul_scalar": lambda: L.helrm_mul_scalar(h, None, None, None, 3, pp, 0, None),
+        "from_signed": lambda: L.helrm_from_signed(h, None, None, 3, pp, 0, None),
+        "keyswitch_hoisted, batch 0": lambda: L.helrm_keyswitch_hoisted(h, None, lv, sp, 1, None, 1, 0, None),
+        "keyswitch_hoisted, no rotations": lambda: L.helrm_keyswitch_hoisted(h, None, lv, None, 0, None, 1, 2,
+                                                                             None),
+        "rescale": lambda: L.helrm_rescale(h, None, lv, None, 0, None),
+        "mul_relin": lambda: L.helrm_mul_relin(h, None, None, lv, None, 0, None),
+        "add_plain": lambda: L.helrm_add_plain(h, None, None, lv, None, 0, None),
+        "mod_drop": lambda: L.helrm_mod_drop(h, None, lv, None, 1, 0, None),
+        "ptxt_ct_matvec_diag": lambda: L.helrm_ptxt_ct_matvec_diag(h, plan.h, None, None, 0, None),
+        "lookup_packed": lambda: L.helrm_lookup_packed(h, plan.h, None, 0, None, None),
+        "lookup_packed_noalloc": lambda: L.helrm_lookup_packed_noalloc(h, plan.h, None, 0, None, None),
+        "lookup_multi": lambda: L.helrm_lookup_multi(h, plans, 1, None, 0, None, None),
+        "lookup_batch": lambda: L.helrm_lookup_batch(h, plans, None, 0, None, None),
+    }
+    for what, call in calls.items():
+        say(f"empty call: {what}")
+        assert call() == B.HELRM_OK, f"{what}: {L.helrm_last_error()}"
+    g = ctypes.c_void_p()
+    assert L.helrm_batch_graph_create(h, plans, 1, None, 0, None, ctypes.byref(g)) == B.HELRM_EINVAL
+    say("empty calls done; a lookup on the same context")
+    _check_lookup(ctx1, w1, plan, [0])
+
+
 def test_tuning_knobs_validate(p1):
     """Every schedule knob accepts its documented values and rejects the
     others (and unknown names) with HELRM_EINVAL, leaving the context usable."""
