@@ -149,7 +149,7 @@ def parse():
     ap.add_argument("--batched", type=int, default=8,
                     help="also time this batch size on the same plan and keys (0 to skip)")
     ap.add_argument("--serve", action="store_true",
-                    help="run the request loop (26 tables in groups, Poisson arrivals) instead of the step loop")
+                    help="run the request loop (the 26 tables, Poisson arrivals) instead of the step loop")
     ap.add_argument("--rates", default="50,100,200,400", help="arrival rates (requests/s) for --serve")
     ap.add_argument("--requests", type=int, default=200, help="requests per rate for --serve")
     ap.add_argument("--group-size", type=int, default=26,
