@@ -7,7 +7,7 @@ draws); everything else is this package's own arithmetic.
 from __future__ import annotations
 
 from dataclasses import dataclass
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -16,6 +16,28 @@ from . import encoding, planner
 from .binding import Context, Plan
 from .client import Client
 from .params import ParamSet
+
+
+def fold_plans(prm: ParamSet, level: int, plans: Sequence[Plan], specs) -> Tuple[int, int]:
+    """Fold the keys into every plan with several giant steps (the batched
+    matrix-core product; at most 3 key-switching digits).  Stops at the first
+    plan that no longer fits in device memory: the rest stay unfolded and
+    take the other kernels.  Returns (bytes, plans folded)."""
+    from .binding import HELRM_ENOMEM, HelrmError
+    if prm.n_digits(level) > 3:
+        return 0, 0
+    total = count = 0
+    for p, sp in zip(plans, specs):
+        if sp.n2 < 2:
+            continue
+        try:
+            total += p.helrm_plan_fold_keys()
+            count += 1
+        except HelrmError as e:
+            if e.code != HELRM_ENOMEM:
+                raise
+            break
+    return total, count
 
 
 class LookupSession:
@@ -42,22 +64,7 @@ class LookupSession:
         self.galois = [planner.galois(s, prm.N) for s in steps]
         self.client = Client(self.ctx, prm)
         self.client.keygen(key_draws_fn(self.galois), self.galois)
-        self.folded_bytes = 0
-        self.folded_plans = 0
-        if fold and prm.n_digits(level) <= 3:
-            from .binding import HELRM_ENOMEM, HelrmError
-            for p, sp in zip(self.plans, self.specs):
-                if sp.n2 < 2:
-                    continue
-                try:
-                    self.folded_bytes += p.helrm_plan_fold_keys()
-                    self.folded_plans += 1
-                except HelrmError as e:
-                    if e.code != HELRM_ENOMEM:
-                        raise
-                    # out of device memory (a selector of many column blocks):
-                    # the remaining plans stay unfolded and take the other kernels
-                    break
+        self.folded_bytes, self.folded_plans = fold_plans(prm, level, self.plans, self.specs) if fold else (0, 0)
 
     @property
     def out_slots(self) -> int:
@@ -134,20 +141,7 @@ class GroupedDeployment:
         # per key: Montgomery-form words plus the 40-bit planes of the b halves
         self.key_bytes = len(self.galois) * prm.dnum * kl * prm.N * (16 + 5)
         self.plan_bytes = sum(len(sp.diag) * (level + 1 + prm.K) * prm.N * (8 + 5) for sp in self.specs)
-        self.folded_bytes = 0
-        self.folded_plans = 0
-        if fold and prm.n_digits(level) <= 3:
-            from .binding import HELRM_ENOMEM, HelrmError
-            for p, sp in zip(self.plans, self.specs):
-                if sp.n2 < 2:
-                    continue
-                try:
-                    self.folded_bytes += p.helrm_plan_fold_keys()
-                    self.folded_plans += 1
-                except HelrmError as e:
-                    if e.code != HELRM_ENOMEM:
-                        raise
-                    break
+        self.folded_bytes, self.folded_plans = fold_plans(prm, level, self.plans, self.specs) if fold else (0, 0)
 
     def group_of(self, table: int) -> int:
         for g, grp in enumerate(self.groups):
