@@ -111,8 +111,10 @@ def test_batching_workload_full_size_bit_exact():
     """26 tables in one selector ciphertext per query (m = 512, n1 = 64, n2 =
     8, radix 8, sign -1, level 23: three digits), the plan's keys folded as
     the benchmark does, batch 64 through the captured graph with the batch-64
-    knobs and the first 8 eagerly with the batch-8 knobs: queries 0 and 63
-    bit-exact against the oracle, query 0 the same in both runs."""
+    knobs, the first 8 eagerly with the batch-8 knobs, query 63 alone with the
+    batch-1 knobs, and the first 3 and 12 with the default knobs (the request
+    loop's batches on this plan): queries 0 and 63 bit-exact against the
+    oracle, every other run equal to the batch-64 one on its queries."""
     import torch
     prm = O.config2_params()
     specs = _w3_specs()
@@ -143,9 +145,29 @@ def test_batching_workload_full_size_bit_exact():
     out8 = empty(8, 2, 23, prm.N)
     ctx.helrm_lookup_packed(plan, sel[:8].contiguous(), 8, out8)
     got8 = to_host(out8).reshape(8, 2, 23, prm.N)
+    sc1 = tuned(416, 13962, 1)
+    set_knobs(ctx, sc1)
+    say("batching workload: query 63 alone with the batch-1 knobs")
+    out1 = empty(1, 2, 23, prm.N)
+    ctx.helrm_lookup_packed(plan, sel[B - 1:].contiguous(), 1, out1)
+    got1 = to_host(out1).reshape(1, 2, 23, prm.N)
     reset_knobs(ctx)
-    del sel, out, out8
+    # the request loop's batches on this plan with the library's default
+    # knobs: 3 (workgroup-shared VALU kernel) and 12 (folded product, one
+    # partial row tile)
+    loop = {}
+    for b in (3, 12):
+        say(f"batching workload: eager batch {b}, default knobs")
+        ob = empty(b, 2, 23, prm.N)
+        ctx.helrm_lookup_packed(plan, sel[:b].contiguous(), b, ob)
+        loop[b] = to_host(ob).reshape(b, 2, 23, prm.N)
+        del ob
+    del sel, out, out8, out1
     assert_bit_exact(got8[0], got[0], "query 0: batch 8 eager vs batch 64 graph")
+    assert_bit_exact(got1[0], got[B - 1], "query 63: batch 1 vs batch 64 graph")
+    for b, res in loop.items():
+        for k in range(b):
+            assert_bit_exact(res[k], got[k], f"query {k}: batch {b} vs batch 64 graph")
     say("batching workload: oracle lookups of queries 0 and 63")
     pts = O.plan_residues(prm, w.plan)
     for k in (0, B - 1):
