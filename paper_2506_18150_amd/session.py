@@ -18,6 +18,22 @@ from .client import Client
 from .params import ParamSet
 
 
+def plan_device_bytes(prm: ParamSet, level: int, spec, mfma_min_slots: int = 33) -> int:
+    """Device bytes a plan made from spec holds (helrm_plan_create): every
+    stored diagonal's residues over PQ_level at 13 bytes a word (the 8-byte
+    word plus the 5-byte plane the 40-bit primes keep), and, for a plan with
+    several giant steps whose baby-step count reaches the matrix-core MAC's
+    floor (knob mfma_min_slots), its matrix-core operands: 4 KiB per limb,
+    coefficient and giant tile of 8.  Folded keys are not included
+    (helrm_plan_fold_keys reports those)."""
+    pqn = level + 1 + prm.K
+    total = len(spec.diag) * pqn * prm.N * (8 + 5)
+    babies = len({k % spec.n1 for k in spec.diag})
+    if spec.n2 >= 2 and babies >= mfma_min_slots:
+        total += -(-spec.n2 // 8) * pqn * prm.N * 4096
+    return total
+
+
 def fold_plans(prm: ParamSet, level: int, plans: Sequence[Plan], specs) -> Tuple[int, int]:
     """Fold the keys into every plan with several giant steps (the batched
     matrix-core product; at most 3 key-switching digits).  Stops at the first
@@ -140,7 +156,7 @@ class GroupedDeployment:
         kl = prm.L + 1 + prm.K
         # per key: Montgomery-form words plus the 40-bit planes of the b halves
         self.key_bytes = len(self.galois) * prm.dnum * kl * prm.N * (16 + 5)
-        self.plan_bytes = sum(len(sp.diag) * (level + 1 + prm.K) * prm.N * (8 + 5) for sp in self.specs)
+        self.plan_bytes = sum(plan_device_bytes(prm, level, sp) for sp in self.specs)
         self.folded_bytes, self.folded_plans = fold_plans(prm, level, self.plans, self.specs) if fold else (0, 0)
 
     def group_of(self, table: int) -> int:

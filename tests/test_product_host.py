@@ -112,3 +112,27 @@ def test_multi_plan_matches_oracle():
         assert (sp.m, sp.n1, sp.n2, sp.span, sp.stages) == (p.m, p.n1, p.n2, p.span, p.stages)
         assert sp.diag == sorted(gg * p.n1 + b for (gg, b) in p.coeffs)
         assert sp.rotation_steps() == p.rotation_steps()
+
+
+def test_plan_device_bytes():
+    """Plan memory as the request loop counts it: 13 bytes per stored word
+    over PQ_level, plus the matrix-core operands (4 KiB per limb, coefficient
+    and giant tile of 8) only for plans with several giant steps and at least
+    33 distinct baby steps among their stored diagonals."""
+    from types import SimpleNamespace
+
+    from paper_2506_18150_amd.session import plan_device_bytes
+    prm = params.n16()
+    pqn = 24 + prm.K
+    word = pqn * prm.N
+    w2 = SimpleNamespace(diag=list(range(16)), n1=16, n2=1)
+    assert plan_device_bytes(prm, 23, w2) == 16 * word * 13
+    w3 = SimpleNamespace(diag=list(range(512)), n1=64, n2=8)
+    assert plan_device_bytes(prm, 23, w3) == 512 * word * 13 + word * 4096
+    group = SimpleNamespace(diag=list(range(64)), n1=16, n2=4)
+    assert plan_device_bytes(prm, 23, group) == 64 * word * 13
+    wide = SimpleNamespace(diag=[g * 40 + b for g in range(9) for b in range(33)], n1=40, n2=9)
+    assert plan_device_bytes(prm, 23, wide) == 9 * 33 * word * 13 + 2 * word * 4096
+    few = SimpleNamespace(diag=[g * 40 + b for g in range(9) for b in range(32)], n1=40, n2=9)
+    assert plan_device_bytes(prm, 23, few) == 9 * 32 * word * 13
+    assert plan_device_bytes(prm, 4, w2) == 16 * (5 + prm.K) * prm.N * 13
